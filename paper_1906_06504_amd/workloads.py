@@ -1,0 +1,218 @@
+"""Seeded synthetic inputs for the heap workloads.
+
+This module only draws random numbers and lays out operation lists; it holds
+none of the heap's arithmetic (no ordering, merging or tree logic), so the
+oracle-side tests and the GPU side can both use it.
+
+Randomness comes from SplitMix64 (Steele, Lea and Flood, "Fast splittable
+pseudorandom number generators", OOPSLA 2014), written here from its published
+definition and used in counter mode: draw i of stream `seed` is
+mix(seed + (i + 1) * golden_gamma).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+GOLDEN_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+OP_INSERT = 0
+OP_DELETE_MIN = 1
+ENTRY_MAX = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def splitmix64(seed: int, start: int, count: int) -> np.ndarray:
+    """Draws start .. start+count-1 of the SplitMix64 stream `seed`."""
+    with np.errstate(over="ignore"):
+        i = np.arange(start + 1, start + count + 1, dtype=np.uint64)
+        z = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + i * GOLDEN_GAMMA
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+class Stream:
+    """Sequential reader over one SplitMix64 stream."""
+
+    def __init__(self, seed: int):
+        self.seed = int(seed)
+        self.pos = 0
+
+    def u64(self, count: int) -> np.ndarray:
+        out = splitmix64(self.seed, self.pos, count)
+        self.pos += count
+        return out
+
+    def u32(self, count: int) -> np.ndarray:
+        return (self.u64(count) >> np.uint64(32)).astype(np.uint32)
+
+    def uniform_int(self, lo: int, hi: int, count: int) -> np.ndarray:
+        """Integers uniform on [lo, hi] (multiply-shift of the top 32 bits)."""
+        span = np.uint64(hi - lo + 1)
+        r = self.u64(count) >> np.uint64(32)
+        return (np.uint64(lo) + ((r * span) >> np.uint64(32))).astype(np.int64)
+
+    def unit(self, count: int) -> np.ndarray:
+        """Doubles uniform on [0, 1) from the top 53 bits."""
+        return (self.u64(count) >> np.uint64(11)).astype(np.float64) * (1.0 / (1 << 53))
+
+
+def pack(keys: np.ndarray, ids: np.ndarray) -> np.ndarray:
+    """(u32 key, u32 id) -> u64 entry key<<32 | id (id 0xFFFFFFFF is reserved)."""
+    return (keys.astype(np.uint64) << np.uint64(32)) | ids.astype(np.uint64)
+
+
+@dataclass
+class OpList:
+    """A list of heap operations in submission order.
+
+    kind[i]  0 = insert, 1 = deleteMin
+    n[i]     insert: number of entries; deleteMin: 0
+    off[i]   insert: offset into `keys`; deleteMin: offset of its k-entry slot
+             in the output buffer
+    heap[i]  heap index (0 for single-heap lists)
+    arrival  optional earliest start time per op, in nanoseconds from launch
+    """
+
+    kind: np.ndarray
+    n: np.ndarray
+    off: np.ndarray
+    keys: np.ndarray
+    out_entries: int
+    heap: np.ndarray | None = None
+    arrival: np.ndarray | None = None
+    meta: dict = field(default_factory=dict)
+
+    def __len__(self):
+        return int(self.kind.size)
+
+    def heap_ids(self) -> np.ndarray:
+        return self.heap if self.heap is not None else np.zeros(self.kind.size, dtype=np.uint32)
+
+    def seq(self) -> np.ndarray:
+        """Rank of each op among the list's ops on the same heap."""
+        h = self.heap_ids().astype(np.int64)
+        order = np.argsort(h, kind="stable")
+        hs = h[order]
+        starts = np.r_[0, np.flatnonzero(np.diff(hs)) + 1]
+        run_start = np.repeat(starts, np.diff(np.r_[starts, hs.size]))
+        rank = np.empty(h.size, dtype=np.int64)
+        rank[order] = np.arange(h.size) - run_start
+        return rank.astype(np.uint32)
+
+
+def build_oplist(kinds, sizes, key_source, k: int, heap=None, arrival=None) -> OpList:
+    """Lay out an op list; inserts take their keys from `key_source(count)` in
+    op order, deleteMin ops each get a k-entry output slot."""
+    kinds = np.asarray(kinds, dtype=np.uint8)
+    sizes = np.asarray(sizes, dtype=np.int64)
+    n = np.where(kinds == OP_INSERT, sizes, 0).astype(np.uint32)
+    ins_off = np.cumsum(n.astype(np.uint64)) - n.astype(np.uint64)
+    del_rank = np.cumsum(kinds == OP_DELETE_MIN) - (kinds == OP_DELETE_MIN)
+    off = np.where(kinds == OP_INSERT, ins_off, del_rank.astype(np.uint64) * np.uint64(k)).astype(np.uint64)
+    total_in = int(n.astype(np.uint64).sum())
+    keys = key_source(total_in)
+    out_entries = int((kinds == OP_DELETE_MIN).sum()) * k
+    return OpList(kinds, n, off, keys, out_entries,
+                  None if heap is None else np.asarray(heap, dtype=np.uint32),
+                  None if arrival is None else np.asarray(arrival, dtype=np.uint64))
+
+
+def _keys_with_ids(stream: Stream, first_id: int):
+    state = {"next": first_id}
+
+    def src(count: int) -> np.ndarray:
+        keys = stream.u32(count)
+        ids = np.arange(state["next"], state["next"] + count, dtype=np.uint64)
+        state["next"] += count
+        if ids.size and int(ids[-1]) >= 0xFFFFFFFF:
+            raise ValueError("id space exhausted")
+        return pack(keys, ids)
+
+    return src
+
+
+# ---------------------------------------------------------------------------
+# Workload recipes
+# ---------------------------------------------------------------------------
+
+def insert_then_drain(total: int, k: int, batch: int, seed: int) -> OpList:
+    """Insert `total` uniform u32 keys (ids 0..total-1) in batches of `batch`,
+    then deleteMin until the heap is empty (one extra deleteMin returns 0)."""
+    st = Stream(seed)
+    n_ins = -(-total // batch)
+    sizes = [batch] * (total // batch) + ([total % batch] if total % batch else [])
+    n_del = -(-total // k) + 1
+    kinds = [OP_INSERT] * n_ins + [OP_DELETE_MIN] * n_del
+    sizes = sizes + [0] * n_del
+    return build_oplist(kinds, sizes, _keys_with_ids(st, 0), k)
+
+
+def prefill_ops(nkeys: int, k: int, seed: int, first_id: int = 0) -> OpList:
+    """`nkeys` uniform u32 keys inserted as full batches of k."""
+    st = Stream(seed)
+    sizes = [k] * (nkeys // k) + ([nkeys % k] if nkeys % k else [])
+    kinds = [OP_INSERT] * len(sizes)
+    return build_oplist(kinds, sizes, _keys_with_ids(st, first_id), k)
+
+
+def mixed_ops(total_requested: int, k: int, seed: int, first_id: int,
+              max_insert: int | None = None, p_insert: float = 0.5) -> OpList:
+    """Random interleave: each op is an insert of U[1, max_insert] fresh keys
+    (probability p_insert) or a deleteMin(k), drawn until the requested keys
+    (insert sizes plus k per deleteMin) reach `total_requested`."""
+    max_insert = k if max_insert is None else max_insert
+    st = Stream(seed)
+    kinds, sizes = [], []
+    acc = 0
+    chunk = 4096
+    while acc < total_requested:
+        coin = st.unit(chunk)
+        sz = st.uniform_int(1, max_insert, chunk)
+        for c, s in zip(coin, sz):
+            if acc >= total_requested:
+                break
+            if c < p_insert:
+                kinds.append(OP_INSERT)
+                sizes.append(int(s))
+                acc += int(s)
+            else:
+                kinds.append(OP_DELETE_MIN)
+                sizes.append(0)
+                acc += k
+    key_stream = Stream(seed ^ 0x5A5A5A5A5A5A5A5A)
+    return build_oplist(kinds, sizes, _keys_with_ids(key_stream, first_id), k)
+
+
+def concat(a: OpList, b: OpList, k: int) -> OpList:
+    """Ops of a followed by ops of b (b's offsets shifted past a's buffers)."""
+    kind = np.concatenate([a.kind, b.kind])
+    n = np.concatenate([a.n, b.n])
+    boff = b.off.copy()
+    boff[b.kind == OP_INSERT] += np.uint64(a.keys.size)
+    boff[b.kind == OP_DELETE_MIN] += np.uint64(a.out_entries)
+    off = np.concatenate([a.off, boff])
+    keys = np.concatenate([a.keys, b.keys])
+    return OpList(kind, n, off, keys, a.out_entries + b.out_entries)
+
+
+CONFIG_SEED = {1: 0x5EED0001, 2: 0x5EED0002, 3: 0x5EED0003, 4: 0x5EED0004, 5: 0x5EED0005}
+
+
+def config1(scale: int = 1 << 16) -> tuple[OpList, int]:
+    """Plain heap, k = 64: insert 2^16 keys in batches of 64, then drain."""
+    k = 64
+    return insert_then_drain(scale, k, 64, CONFIG_SEED[1]), k
+
+
+def config2(prefill: int = 1 << 22, requested: int = 1 << 24, k: int = 1024):
+    """Plain heap, k = 1024: prefill `prefill` keys as full batches, then a
+    50/50 interleave of inserts of U[1, 1024] keys and deleteMin(1024) until
+    `requested` keys have been requested.  Returns (prefill ops, mixed ops, k)."""
+    pre = prefill_ops(prefill, k, CONFIG_SEED[2])
+    mix = mixed_ops(requested, k, CONFIG_SEED[2] + 1, first_id=prefill)
+    return pre, mix, k

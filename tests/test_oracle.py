@@ -1,0 +1,255 @@
+"""Pins for the CPU oracle, against facts fixed outside the oracle itself.
+
+* brute force: a deleteMin returns exactly the min(k, size) smallest live
+  entries in ascending order (the root holds the k smallest by Properties 1
+  and 3, Sec. 3.1; the partial buffer is read only when no node exists,
+  Sec. 3.3.2), checked against a sorted Python list on small random traces;
+* Properties 1-3 and the closed form m = size // k, s = size % k after every
+  operation (the partial buffer never reaches k entries, Sec. 3.1);
+* k = 1 reduces to the conventional heap (Sec. 3.1, note after Property 3):
+  pop order equals Python's heapq;
+* insert-all-then-drain returns the fully sorted sequence;
+* the bit-reversal target order (Sec. 4.3) against an independent string
+  reversal, and the stated property that consecutive insert paths share
+  only the root;
+* MergeAndSort (Sec. 3.2.1 display equation) against sorted();
+* planted mistakes: variants of the oracle with one plausible error each must
+  fail these pins.
+"""
+import heapq
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+
+MAXE = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    oracle.build(force=False)
+
+
+def random_trace(rng, k, nops, key_range, max_ins=None):
+    """Random op sequence: ('ins', array) or ('del',)."""
+    max_ins = max_ins or 3 * k
+    ops = []
+    for _ in range(nops):
+        if rng.random() < 0.55:
+            n = int(rng.integers(0, max_ins + 1))
+            ops.append(("ins", rng.integers(0, key_range, n).astype(np.uint64)))
+        else:
+            ops.append(("del",))
+    return ops
+
+
+def run_against_brute_force(k, ops, lib=None):
+    """Returns None if the oracle matches brute force on every op, else a
+    string describing the first mismatch."""
+    h = oracle.OracleHeap(k, lib=lib)
+    live = []
+    for i, op in enumerate(ops):
+        if op[0] == "ins":
+            h.insert(op[1])
+            live = sorted(live + [int(v) for v in op[1]])
+        else:
+            got = h.delete_min()
+            c = min(k, len(live))
+            want = live[:c]
+            live = live[c:]
+            if [int(v) for v in got] != want:
+                return "op %d: deleteMin mismatch" % i
+        rc = h.check()
+        if rc:
+            return "op %d: invariant code %d" % (i, rc)
+        if h.size != len(live) or h.m != len(live) // k or h.s != len(live) % k:
+            return "op %d: size bookkeeping" % i
+    return None
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 8, 16])
+def test_brute_force_random_traces(k):
+    rng = np.random.default_rng(1000 + k)
+    for trial in range(60):
+        key_range = 50 if trial % 3 == 0 else 1 << 40   # duplicates and distinct
+        ops = random_trace(rng, k, int(rng.integers(5, 80)), key_range)
+        msg = run_against_brute_force(k, ops)
+        assert msg is None, "k=%d trial=%d %s" % (k, trial, msg)
+
+
+def test_k1_matches_heapq_order():
+    rng = np.random.default_rng(7)
+    h = oracle.OracleHeap(1)
+    ref = []
+    for step in range(3000):
+        if rng.random() < 0.6:
+            v = int(rng.integers(0, 1000))
+            h.insert([v])
+            heapq.heappush(ref, v)
+        else:
+            got = h.delete_min()
+            if ref:
+                assert list(got) == [heapq.heappop(ref)]
+            else:
+                assert got.size == 0
+        assert h.check() == 0
+
+
+@pytest.mark.parametrize("k,batch,total", [(64, 64, 1 << 16), (32, 17, 5000), (7, 100, 3001)])
+def test_insert_all_then_drain_is_sorted(k, batch, total):
+    rng = np.random.default_rng(k)
+    keys = rng.integers(0, 1 << 32, total).astype(np.uint64) << np.uint64(32) | np.arange(total, dtype=np.uint64)
+    h = oracle.OracleHeap(k)
+    for i in range(0, total, batch):
+        h.insert(keys[i:i + batch])
+    assert h.check() == 0
+    outs = []
+    while True:
+        o = h.delete_min()
+        if o.size == 0:
+            break
+        assert o.size == k or h.size == 0
+        outs.append(o)
+    assert np.array_equal(np.concatenate(outs), np.sort(keys))
+
+
+def _rev_by_string(p):
+    l = p.bit_length() - 1
+    if l == 0:
+        return 1
+    off = p - (1 << l)
+    return (1 << l) + int(format(off, "0%db" % l)[::-1], 2)
+
+
+def test_bit_reversal_order():
+    for p in range(1, 5000):
+        assert oracle.idx(p) == _rev_by_string(p)
+        assert oracle.idx(oracle.idx(p)) == p
+    for l in range(0, 13):
+        level = list(range(1 << l, 1 << (l + 1)))
+        assert sorted(oracle.idx(p) for p in level) == level
+
+
+def _path(t):
+    out = []
+    while t >= 1:
+        out.append(t)
+        t //= 2
+    return set(out)
+
+
+def test_consecutive_insert_paths_share_only_root():
+    for p in range(2, 5000):
+        shared = _path(oracle.idx(p)) & _path(oracle.idx(p + 1))
+        assert shared == {1}, p
+
+
+def test_merge_and_sort_matches_sorted():
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        na, nb = int(rng.integers(0, 40)), int(rng.integers(0, 40))
+        a = np.sort(rng.integers(0, 30, na).astype(np.uint64))
+        b = np.sort(rng.integers(0, 30, nb).astype(np.uint64))
+        hi, lo = oracle.merge_and_sort(a, b)
+        allv = sorted([int(x) for x in a] + [int(x) for x in b])
+        assert [int(x) for x in hi] == allv[:na]
+        assert [int(x) for x in lo] == allv[na:]
+
+
+def test_delete_on_empty_and_pb_only():
+    h = oracle.OracleHeap(8)
+    assert h.delete_min().size == 0
+    h.insert([5, 3, 9])
+    assert h.m == 0 and h.s == 3
+    assert list(h.delete_min()) == [3, 5, 9]
+    assert h.size == 0
+
+
+def test_replay_matches_step_by_step():
+    from paper_1906_06504_amd import workloads as W
+    ops = W.mixed_ops(20000, 16, seed=11, first_id=0)
+    h1 = oracle.OracleHeap(16)
+    out, counts = h1.replay(ops.kind, ops.n, ops.off, ops.keys, ops.out_entries, check=True)
+    h2 = oracle.OracleHeap(16)
+    for i in range(len(ops)):
+        if ops.kind[i] == 0:
+            h2.insert(ops.keys[int(ops.off[i]):int(ops.off[i]) + int(ops.n[i])])
+        else:
+            got = h2.delete_min()
+            o = int(ops.off[i])
+            assert counts[i] == got.size
+            assert np.array_equal(out[o:o + got.size], got)
+
+
+# ---------------------------------------------------------------------------
+# planted mistakes: each must be caught by the pins above
+# ---------------------------------------------------------------------------
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "gheap_oracle.c")
+
+MUTANTS = {
+    "no_pb_merge_on_delete": (
+        "    if (h->s > 0)\n        merge_and_sort(h, node_at(h, 1), k, h->pb, h->s, node_at(h, 1), h->pb);\n    /* sift down */",
+        "    /* sift down */"),
+    "lo_to_smaller_max_child": (
+        "uint64_t big = (L[k - 1] > R[k - 1]) ? l : r;",
+        "uint64_t big = (L[k - 1] > R[k - 1]) ? r : l;"),
+    "early_stop_on_min": (
+        "if (cur[k - 1] <= cmin) break;",
+        "if (cur[0] <= cmin) break;"),
+    "partial_insert_skips_root_merge": (
+        "        if (h->m >= 1)\n            merge_and_sort(h, node_at(h, 1), k, h->pb, h->s, node_at(h, 1), h->pb);\n        free(merged);",
+        "        free(merged);"),
+    "pb_capacity_k": (
+        "if (n + h->s <= k - 1) {",
+        "if (n + h->s <= k) {"),
+    "no_max_fill": (
+        "    for (uint64_t i = 0; i < k; i++) node_at(h, last)[i] = GHO_MAX;\n    h->m -= 1;",
+        "    h->m -= 1;"),
+    "insert_path_skips_root": (
+        "for (int j = 0; j < L; j++) {",
+        "for (int j = 1; j < L; j++) {"),
+    "one_child_no_merge": (
+        "            if (cur[k - 1] <= X[0]) break;",
+        "            break;"),
+    "full_batch_takes_largest": (
+        "    memcpy(F, merged, k * sizeof(gho_ent));\n    memcpy(h->pb, merged + k, rest * sizeof(gho_ent));",
+        "    memcpy(F, merged + rest, k * sizeof(gho_ent));\n    memcpy(h->pb, merged, rest * sizeof(gho_ent));"),
+}
+
+
+def _build_mutant(name, tmpdir):
+    before, after = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(before) == 1, "mutation anchor for %s not found exactly once" % name
+    path = os.path.join(tmpdir, name + ".c")
+    with open(path, "w") as f:
+        f.write(src.replace(before, after))
+    so = os.path.join(tmpdir, name + ".so")
+    apps = os.path.join(os.path.dirname(SRC), "apps_oracle.c")
+    subprocess.check_call(["gcc", "-O1", "-std=c11", "-shared", "-fPIC", "-w", "-o", so, path, apps])
+    return oracle.load(so)
+
+
+def _mutant_caught(lib):
+    rng = np.random.default_rng(99)
+    for k in (1, 2, 3, 4, 8):
+        for trial in range(40):
+            ops = random_trace(rng, k, 60, 1 << 40 if trial % 2 else 40)
+            try:
+                if run_against_brute_force(k, ops, lib=lib) is not None:
+                    return True
+            except Exception:
+                return True
+    return False
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(name):
+    with tempfile.TemporaryDirectory() as d:
+        lib = _build_mutant(name, d)
+        assert _mutant_caught(lib), "planted mistake %s was not detected" % name
