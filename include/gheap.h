@@ -1,0 +1,202 @@
+/*
+ * gheap.h -- C ABI of libgheap.so, a generalized concurrent min-heap for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The heap is the generalized heap of Chen et al., "Accelerating Concurrent
+ * Heap on GPUs" (Sec. 3): every node holds a sorted batch of k entries, a
+ * partial buffer holds fewer than k entries that are all >= the root's
+ * (Sec. 3.1, Properties 1-3), deleteMin returns the root batch, and insert
+ * and deleteMin run top-down under per-node locks with many operations in
+ * flight (Sec. 3.3, TD-INS/TD-DEL heap).
+ *
+ * Entries.  An entry is an unsigned 64-bit integer and entries are ordered as
+ * integers.  The all-ones value (UINT64_MAX) is reserved as the empty-slot
+ * filler and must never be inserted.  (key, id) pairs are packed by the
+ * caller, e.g. (uint64_t)key << 32 | id with id != 0xFFFFFFFF; equal entries
+ * are indistinguishable, so results are unique even with repeated keys.
+ *
+ * Memory and streams.  Every pointer named d_* is a device pointer on the
+ * current HIP device.  The caller owns all device buffers, including the
+ * arena that holds the heap state (size from heap_arena_bytes); the library
+ * owns only the handle.  All calls are ordered on the stream given at
+ * creation (a hipStream_t passed as void*, NULL = the legacy default stream)
+ * and return before the device work finishes, except where noted.  Input
+ * buffers must stay valid and unmodified, and output buffers untouched, until
+ * the stream has passed the call.  A handle must not be used from two host
+ * threads at once.
+ *
+ * Errors.  Functions return GH_OK (0) or a negative GH_E* code.  Argument
+ * errors are reported synchronously and leave the heap unchanged.  Errors
+ * found on the device (capacity exceeded inside a multi-op submission, a
+ * lock wait over the watchdog limit) are sticky: they are reported by
+ * heap_sync, heap_size and heap_destroy, and every later operation on the
+ * handle returns the same code.
+ *
+ * Linearization.  Every operation takes a ticket when it acquires the root;
+ * the root is the linearization point of the TD-INS/TD-DEL heap (Sec. 3.3.3,
+ * Theorem 1), so applying the operations one at a time in ticket order on a
+ * sequential generalized heap reproduces every deleteMin result exactly.
+ * Within one heap, tickets follow submission order.
+ */
+#ifndef GHEAP_H
+#define GHEAP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GH_OK 0
+#define GH_EINVAL (-1)     /* bad argument: null pointer, unsupported k, ... */
+#define GH_ENOMEM (-2)     /* arena too small, or an insert exceeds capacity */
+#define GH_ETIMEDOUT (-3)  /* a device lock wait exceeded the watchdog limit */
+#define GH_EDEVICE (-4)    /* a HIP runtime call failed */
+#define GH_ESTATE (-5)     /* the heap set was left inconsistent by an earlier error */
+
+#define GH_OP_INSERT 0u
+#define GH_OP_DELETE_MIN 1u
+
+/* Opaque handle to a set of one or more heaps that share k, an arena and a
+ * stream.  heap_create makes a set of one heap. */
+typedef struct gh_heap *gh_heap_t;
+
+/* One operation of a multi-operation submission (32 bytes, device memory).
+ *   heap   index of the heap within the set, < nheaps
+ *   kind   GH_OP_INSERT or GH_OP_DELETE_MIN
+ *   n      insert: number of entries, 1..k; deleteMin: ignored
+ *   seq    rank of this operation among the submission's operations on the
+ *          same heap: 0, 1, 2, ... in the order they must take the root
+ *   off    insert: entry offset of its keys in d_in; deleteMin: entry offset
+ *          of its k-entry output slot in d_out
+ *   arrival_ns  earliest start, in nanoseconds after the submission starts
+ *          on the device (0 = immediately); operations must appear in
+ *          non-decreasing arrival order */
+typedef struct gh_op {
+    uint32_t heap;
+    uint32_t kind;
+    uint32_t n;
+    uint32_t seq;
+    uint64_t off;
+    uint64_t arrival_ns;
+} gh_op;
+
+/* Per-operation record written by a submission (32 bytes, device memory).
+ *   ticket   root ticket of the operation on its heap (linearization order)
+ *   count    insert: n; deleteMin: entries returned (min(k, heap size))
+ *   levels   insert: depth of the target node reached (0 if the keys stayed
+ *            in the partial buffer); deleteMin: sift-down levels that merged
+ *   kind     GH_OP_INSERT or GH_OP_DELETE_MIN
+ *   flags    bit 0: a full batch was created; bit 1: an insert handed its
+ *            batch to a deleteMin that took its target; bit 2: a deleteMin
+ *            took the batch of an in-flight insert
+ *   t_root   device wall clock (ticks) when the root was acquired
+ *   t_done   device wall clock (ticks) when the operation finished */
+typedef struct gh_logrec {
+    uint64_t ticket;
+    uint32_t count;
+    uint16_t levels;
+    uint8_t kind;
+    uint8_t flags;
+    uint64_t t_root;
+    uint64_t t_done;
+} gh_logrec;
+
+/* Launch shape of a submission: workgroups = number of operations in flight
+ * (0 = library default), threads = workgroup size (0 = library default; must
+ * be one of the shapes heap_supported_shape accepts for k). */
+typedef struct gh_tuning {
+    uint32_t workgroups;
+    uint32_t threads;
+} gh_tuning;
+
+/* Bytes of arena needed for nheaps heaps of node capacity k, heap i holding
+ * up to max_keys[i] entries (max_keys == NULL: every heap holds up to
+ * max_keys_each).  Returns 0 if k is unsupported. */
+uint64_t heap_arena_bytes(uint32_t k, uint32_t nheaps, const uint64_t *max_keys,
+                          uint64_t max_keys_each);
+
+/* Nonzero if the library has a kernel for node capacity k with workgroups
+ * of `threads` threads.  Supported k: 32, 64, 128, 256, 512, 1024. */
+int heap_supported_shape(uint32_t k, uint32_t threads);
+
+/* Create one heap (Sec. 3.1) of node capacity k holding up to max_keys
+ * entries in the caller's arena d_arena (arena_bytes >= heap_arena_bytes;
+ * 256-byte aligned; borrowed, must outlive the handle).  Initializes the
+ * arena on `stream`.  Errors: GH_EINVAL, GH_ENOMEM (arena too small),
+ * GH_EDEVICE. */
+int heap_create(gh_heap_t *out, uint32_t k, uint64_t max_keys, void *d_arena,
+                uint64_t arena_bytes, void *stream);
+
+/* Create a set of nheaps independent heaps of node capacity k; heap i holds
+ * up to max_keys[i] entries.  Same arena and stream rules as heap_create. */
+int heap_create_many(gh_heap_t *out, uint32_t k, uint32_t nheaps,
+                     const uint64_t *max_keys, void *d_arena,
+                     uint64_t arena_bytes, void *stream);
+
+/* Insert n entries from d_keys (device, n * 8 bytes) into heap 0 of the set:
+ * ceil(n / k) insert operations of up to k entries each, full chunks first
+ * (Sec. 3.2.2 footnote), each run top-down (Sec. 3.3.2).  n = 0 is a no-op.
+ * Errors: GH_EINVAL (null, reserved entry is not checked), GH_ENOMEM (the
+ * heap would exceed max_keys; nothing is inserted). */
+int heap_insert(gh_heap_t h, const uint64_t *d_keys, uint64_t n);
+
+/* deleteMin on heap 0 of the set (Sec. 3.2.1, Sec. 3.3.2): writes the
+ * min(k, size) smallest entries in ascending order to d_out (device, room for
+ * k entries) and that number to *d_count (device).  An empty heap gives
+ * *d_count = 0, not an error.  k must equal the heap's node capacity.
+ * Errors: GH_EINVAL. */
+int heap_delete_min(gh_heap_t h, uint64_t *d_out, uint32_t k, uint32_t *d_count);
+
+/* Run nops operations (d_ops, device) on the set's heaps in one persistent
+ * launch with many operations in flight (Sec. 3.3): each workgroup claims the
+ * next operation in list order, waits for its arrival time, takes the heap's
+ * root in `seq` order, and runs the operation top-down under node locks.
+ * Inserts read d_in, deleteMins write d_out and d_counts[i] (device, one
+ * uint32 per operation; inserts get 0); d_log (device, nops records, may be
+ * NULL) receives one gh_logrec per operation.  Capacity overruns are
+ * detected on the device (sticky GH_ENOMEM). */
+int heap_submit(gh_heap_t h, const gh_op *d_ops, uint32_t nops,
+                const uint64_t *d_in, uint64_t *d_out, uint32_t *d_counts,
+                gh_logrec *d_log, const gh_tuning *tuning);
+
+/* Like heap_submit, but records the launch into a HIP graph once and returns
+ * it as *graph_out (a hipGraphExec_t passed as void*); heap_graph_launch
+ * replays it on the set's stream with the same arguments, and
+ * heap_graph_destroy frees it. */
+int heap_submit_graph(gh_heap_t h, const gh_op *d_ops, uint32_t nops,
+                      const uint64_t *d_in, uint64_t *d_out, uint32_t *d_counts,
+                      gh_logrec *d_log, const gh_tuning *tuning, void **graph_out);
+int heap_graph_launch(gh_heap_t h, void *graph);
+int heap_graph_destroy(void *graph);
+
+/* Wait for the set's stream; return the sticky device error (GH_OK if none). */
+int heap_sync(gh_heap_t h);
+
+/* Synchronous: wait for the stream and write heap i's entry count to
+ * *out_host (host memory). */
+int heap_size(gh_heap_t h, uint32_t i, uint64_t *out_host);
+
+/* Synchronous: copy heap i's state to host memory for inspection:
+ * meta_host[0..3] = {nodes in use m, partial-buffer size s, tickets served,
+ * node capacity}; nodes_host (may be NULL) receives max_nodes * k entries,
+ * slot p-1 holding the node added p-th (bit-reversal order, Sec. 4.3);
+ * pb_host (may be NULL) receives s entries. */
+int heap_read_state(gh_heap_t h, uint32_t i, uint64_t *meta_host,
+                    uint64_t *nodes_host, uint64_t *pb_host);
+
+/* Synchronous: wait for the stream, release the handle, and return the
+ * sticky device error.  The arena may be freed afterwards. */
+int heap_destroy(gh_heap_t h);
+
+/* Static description of an error code. */
+const char *heap_strerror(int code);
+
+/* Device wall-clock frequency in Hz (for gh_logrec timestamps). */
+uint64_t heap_clock_hz(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GHEAP_H */

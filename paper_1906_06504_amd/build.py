@@ -1,0 +1,65 @@
+"""Build libgheap.so (HIP, gfx950) in-tree with hipcc.
+
+Usage: python -m paper_1906_06504_amd.build   (or call build()).
+Each supported node capacity k gets its own object of gh_kernels.hip so the
+objects compile in parallel.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libgheap.so")
+KS = (32, 64, 128, 256, 512, 1024)
+ARCH = os.environ.get("GHEAP_ARCH", "gfx950")
+
+HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+COMMON = [
+    "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function",
+]
+
+
+def _run(cmd):
+    p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    out = "\n".join(l for l in p.stdout.splitlines()
+                    if "packed-fp32-ops" not in l and l.strip())
+    if p.returncode != 0:
+        raise RuntimeError("command failed: %s\n%s" % (" ".join(cmd), out))
+    return out
+
+
+def build(jobs: int | None = None, verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    jobs = jobs or min(8, os.cpu_count() or 4)
+    tasks = []
+    for k in KS:
+        obj = os.path.join(BUILD, "gh_kernels_k%d.o" % k)
+        tasks.append([HIPCC] + COMMON + ["-DGH_K=%d" % k, "-c",
+                                         os.path.join(CSRC, "gh_kernels.hip"), "-o", obj])
+    tasks.append([HIPCC] + COMMON + ["-c", os.path.join(CSRC, "gh_setup.hip"),
+                                     "-o", os.path.join(BUILD, "gh_setup.o")])
+    tasks.append([HIPCC] + COMMON + ["-x", "hip", "-c", os.path.join(CSRC, "gheap_api.cpp"),
+                                     "-o", os.path.join(BUILD, "gheap_api.o")])
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        outs = list(ex.map(_run, tasks))
+    if verbose:
+        for o in outs:
+            if o:
+                print(o)
+    objs = [t[t.index("-o") + 1] for t in tasks]
+    tmp = LIB + ".tmp%d" % os.getpid()
+    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

@@ -1,0 +1,353 @@
+// gh_device.h -- device-side building blocks of the generalized heap:
+// heap-state layout, node lock words, memory-ordering helpers, bit-reversal
+// node order, and LDS-staged merge-path merge and sort for one workgroup.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gh {
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+
+constexpr u64 ENT_MAX = ~0ull;  // reserved filler; never a live entry
+
+// ---------------------------------------------------------------------------
+// Heap state in device memory
+// ---------------------------------------------------------------------------
+
+// Root metadata of one heap.  `serving` sits alone in its own 128-byte line
+// because every operation waiting for the root polls it.
+struct alignas(256) HeapMeta {
+  u64 serving;        // ticket allowed to take the root now
+  u64 pad0[15];
+  u64 base;           // ticket of seq 0 in the current submission
+  u64 m;              // nodes in use (guarded by the root)
+  u64 s;              // partial-buffer size (guarded by the root)
+  u64 pad1[13];
+};
+static_assert(sizeof(HeapMeta) == 256, "meta layout");
+
+// Where one heap lives.  Node storage is indexed by the order in which nodes
+// are added (position p >= 1 at nodes + (p-1)*k), so a heap of m nodes
+// occupies the first m slots; tree navigation uses node indices (root 1,
+// children 2c and 2c+1) and converts with the bit-reversal map.
+struct alignas(64) HeapDesc {
+  u64* nodes;         // max_nodes * k entries
+  u64* locks;         // lock word per position, [0] unused, [1..max_nodes]
+  u64* pb;            // partial buffer, k entries
+  HeapMeta* meta;
+  u32 max_nodes;
+  u32 k;
+  u64 pad[2];
+};
+static_assert(sizeof(HeapDesc) == 64, "desc layout");
+
+// Per-set control block.
+struct alignas(256) Ctl {
+  u32 next_op;        // claim counter of the running submission
+  u32 pad0[31];
+  u64 t0;             // device clock when the submission started
+  u64 timeout_ticks;  // watchdog limit for one lock wait
+  u32 status;         // sticky error code (0 = ok), first error wins
+  u32 abort;          // nonzero: every workgroup leaves as soon as it can
+  u32 pad1[26];
+};
+static_assert(sizeof(Ctl) == 256, "ctl layout");
+
+// Error codes stored in Ctl::status (negated GH_E* codes).
+constexpr u32 ERR_INVAL = 1;
+constexpr u32 ERR_NOMEM = 2;
+constexpr u32 ERR_TIMEOUT = 3;
+constexpr u32 ERR_STATE = 5;
+
+// ---------------------------------------------------------------------------
+// Node lock words: the multi-state lock of the TD-INS/TD-DEL heap (Sec. 3.3.2)
+// Low 3 bits hold the state, the rest the ticket of the operation that set it.
+// ---------------------------------------------------------------------------
+constexpr u64 ST_AVAIL = 0;   // free
+constexpr u64 ST_INUSE = 1;   // held by one operation (Lemma 1)
+constexpr u64 ST_TARGET = 2;  // reserved target of an in-flight insert
+constexpr u64 ST_MARKED = 3;  // a deleteMin asked that insert for its batch
+constexpr u64 ST_HANDED = 4;  // the insert left its batch in the target slot
+
+__device__ __forceinline__ u64 lockword(u64 st, u64 ticket) { return (ticket << 3) | st; }
+__device__ __forceinline__ u64 lw_state(u64 w) { return w & 7; }
+__device__ __forceinline__ u64 lw_ticket(u64 w) { return w >> 3; }
+
+// ---------------------------------------------------------------------------
+// Memory ordering.  Node payloads move with ordinary loads and stores; lock
+// words and the root ticket use agent-scope atomics.  A holder publishes its
+// stores with a release fence in every thread before the barrier that
+// precedes the releasing store; an acquirer's thread 0 takes the lock with an
+// acquire, and the workgroup barrier orders the other threads' loads after it.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ u64 ld_relaxed(const u64* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ u32 ld_relaxed32(const u32* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_release(u64* p, u64 v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool cas_relaxed(u64* p, u64 expect, u64 desired) {
+  return __hip_atomic_compare_exchange_strong(p, &expect, desired, __ATOMIC_RELAXED,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+__device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+
+// All threads: make this workgroup's prior global stores visible at agent
+// scope, then meet at a barrier.  After it, thread 0 may release locks.
+__device__ __forceinline__ void publish() {
+  fence_release();
+  __syncthreads();
+}
+
+__device__ __forceinline__ u64 now_ticks() { return wall_clock64(); }
+
+// Sticky error: the first code wins; every waiting workgroup then leaves.
+__device__ __forceinline__ void raise_error(Ctl* ctl, u32 code) {
+  u32 zero = 0;
+  __hip_atomic_compare_exchange_strong(&ctl->status, &zero, code, __ATOMIC_RELAXED,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sticky error that leaves the heap consistent: record it, keep running.
+__device__ __forceinline__ void note_error(Ctl* ctl, u32 code) {
+  u32 zero = 0;
+  __hip_atomic_compare_exchange_strong(&ctl->status, &zero, code, __ATOMIC_RELAXED,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bounded wait step for thread 0: sleeps a little, checks the abort flag and
+// the watchdog.  Returns false when the wait must be abandoned.
+struct Waiter {
+  u64 start;
+  u32 iters;
+  __device__ __forceinline__ Waiter() : start(0), iters(0) {}
+  __device__ __forceinline__ bool step(Ctl* ctl, u32 sleep = 1) {
+    ++iters;
+    if ((iters & 31) == 1) {
+      u64 t = now_ticks();
+      if (iters == 1) start = t;
+      else if (t - start > ctl->timeout_ticks) {
+        raise_error(ctl, ERR_TIMEOUT);
+        return false;
+      }
+      if (ld_relaxed32(&ctl->abort)) return false;
+    }
+    if (sleep <= 1) __builtin_amdgcn_s_sleep(1);
+    else if (sleep <= 4) __builtin_amdgcn_s_sleep(4);
+    else __builtin_amdgcn_s_sleep(16);
+    return true;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Bit-reversal node order (Sec. 4.3).  The p-th node added (p >= 1) is on
+// level l = floor(log2 p) at offset reverse_l(p - 2^l); the map is an
+// involution, so the same function turns a node index into its position.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int level_of(u32 c) { return 31 - __builtin_clz(c); }
+__device__ __forceinline__ u32 bitrev_pos(u32 c) {
+  int l = level_of(c);
+  if (l == 0) return 1;
+  u32 off = c - (1u << l);
+  return (1u << l) | (__builtin_bitreverse32(off) >> (32 - l));
+}
+
+// Does node index c exist in a heap of m nodes?  (c may be up to 2^32 - 1.)
+__device__ __forceinline__ bool node_exists(u64 c, u64 m) {
+  if (c == 0 || c > 0xFFFFFFFFull) return false;
+  return (u64)bitrev_pos((u32)c) <= m;
+}
+
+template <int K>
+__device__ __forceinline__ u64* node_ptr(const HeapDesc& H, u32 c) {
+  return H.nodes + (u64)(bitrev_pos(c) - 1) * K;
+}
+__device__ __forceinline__ u64* lock_ptr(const HeapDesc& H, u32 c) {
+  return H.locks + bitrev_pos(c);
+}
+
+// ---------------------------------------------------------------------------
+// Coalesced node transfers between global memory and LDS (16 bytes a lane).
+// ---------------------------------------------------------------------------
+template <int K, int T>
+__device__ __forceinline__ void load_node(u64* __restrict__ lds, const u64* __restrict__ g) {
+  for (int i = threadIdx.x * 2; i < K; i += 2 * T) {
+    ulonglong2 v = *reinterpret_cast<const ulonglong2*>(g + i);
+    *reinterpret_cast<ulonglong2*>(lds + i) = v;
+  }
+}
+template <int K, int T>
+__device__ __forceinline__ void store_node(u64* __restrict__ g, const u64* __restrict__ lds) {
+  for (int i = threadIdx.x * 2; i < K; i += 2 * T) {
+    ulonglong2 v = *reinterpret_cast<const ulonglong2*>(lds + i);
+    *reinterpret_cast<ulonglong2*>(g + i) = v;
+  }
+}
+// n entries, any n, 8 bytes a lane
+template <int T>
+__device__ __forceinline__ void load_n(u64* __restrict__ lds, const u64* __restrict__ g, u32 n) {
+  for (u32 i = threadIdx.x; i < n; i += T) lds[i] = g[i];
+}
+template <int T>
+__device__ __forceinline__ void store_n(u64* __restrict__ g, const u64* __restrict__ lds, u32 n) {
+  for (u32 i = threadIdx.x; i < n; i += T) g[i] = lds[i];
+}
+template <int T>
+__device__ __forceinline__ void copy_n(u64* __restrict__ dst, const u64* __restrict__ src, u32 n) {
+  for (u32 i = threadIdx.x; i < n; i += T) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// Merge path (Green, McColl and Bader, "GPU merge path", cited in Sec. 4.2):
+// output positions [d, d+E) of the stable merge of sorted A[0,na) and
+// B[0,nb) (A first on ties), found by a binary search along the diagonal and
+// a short sequential merge.  Positions past na+nb yield ENT_MAX.
+// ---------------------------------------------------------------------------
+template <int E>
+__device__ __forceinline__ void merge_path(const u64* A, int na, const u64* B, int nb, int d,
+                                           u64 (&v)[E]) {
+  const int total = na + nb;
+  if (d >= total) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = ENT_MAX;
+    return;
+  }
+  int lo = d > nb ? d - nb : 0;
+  int hi = d < na ? d : na;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (A[mid] <= B[d - 1 - mid]) lo = mid + 1;
+    else hi = mid;
+  }
+  int i = lo, j = d - lo;
+  u64 a = i < na ? A[i] : ENT_MAX;
+  u64 b = j < nb ? B[j] : ENT_MAX;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    if (a <= b) {
+      v[e] = a;
+      ++i;
+      a = i < na ? A[i] : ENT_MAX;
+    } else {
+      v[e] = b;
+      ++j;
+      b = j < nb ? B[j] : ENT_MAX;
+    }
+  }
+}
+
+// Destinations for merge output: LDS or global, written E entries a thread.
+struct Sink {
+  u64* p;
+  __device__ __forceinline__ void put1(int off, u64 x) const { p[off] = x; }
+  template <int E>
+  __device__ __forceinline__ void put_range(int off, const u64 (&v)[E]) const {
+    u64* q = p + off;
+    if constexpr (E % 2 == 0) {
+      if ((reinterpret_cast<uintptr_t>(q) & 15) == 0) {
+#pragma unroll
+        for (int e = 0; e < E; e += 2) {
+          ulonglong2 w;
+          w.x = v[e];
+          w.y = v[e + 1];
+          *reinterpret_cast<ulonglong2*>(q + e) = w;
+        }
+        return;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) q[e] = v[e];
+  }
+};
+
+// Workgroup-wide MergeAndSort (Sec. 3.2.1 display equation, generalized to
+// unequal sizes): the stable merge of A[0,na) and B[0,nb) is split at
+// `split`; positions < split go to lo[p], the rest to hi[p - split].  Inputs
+// must be in LDS and must not overlap the outputs.  No barrier inside: the
+// caller synchronizes before reusing inputs or reading outputs.
+template <int E, int T>
+__device__ __forceinline__ void merge_split(const u64* A, int na, const u64* B, int nb, int split,
+                                            Sink lo, Sink hi) {
+  const int total = na + nb;
+  for (int d = threadIdx.x * E; d < total; d += T * E) {
+    u64 v[E];
+    merge_path<E>(A, na, B, nb, d, v);
+    if (d + E <= total && d + E <= split) {
+      lo.put_range<E>(d, v);
+    } else if (d + E <= total && d >= split) {
+      hi.put_range<E>(d - split, v);
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        int p = d + e;
+        if (p < total) {
+          if (p < split) lo.put1(p, v[e]);
+          else hi.put1(p - split, v[e]);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup merge sort of up to K entries in LDS (sorts the insert batch,
+// Sec. 4.1): every thread sorts EPT entries in registers, then rounds of
+// merge path double the sorted run length.  A holds the n inputs; it is
+// padded with ENT_MAX to a power of two.  Returns the buffer (A or B) that
+// holds the sorted result.
+// ---------------------------------------------------------------------------
+template <int K, int T>
+__device__ u64* block_sort(u64* A, u64* B, int n) {
+  constexpr int EPT = (K >= T) ? (K / T) : 1;
+  int np = EPT;
+  while (np < n) np <<= 1;
+  for (int i = n + threadIdx.x; i < np; i += T) A[i] = ENT_MAX;
+  __syncthreads();
+  const int active = np / EPT;
+  const int tid = threadIdx.x;
+  if (tid < active) {
+    u64 v[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) v[e] = A[tid * EPT + e];
+    // odd-even transposition sort of EPT registers
+#pragma unroll
+    for (int r = 0; r < EPT; ++r) {
+#pragma unroll
+      for (int e = (r & 1); e + 1 < EPT; e += 2) {
+        u64 x = v[e], y = v[e + 1];
+        v[e] = x < y ? x : y;
+        v[e + 1] = x < y ? y : x;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) A[tid * EPT + e] = v[e];
+  }
+  __syncthreads();
+  u64* src = A;
+  u64* dst = B;
+  for (int w = EPT; w < np; w <<= 1) {
+    if (tid < active) {
+      int d0 = tid * EPT;
+      int base = d0 & ~(2 * w - 1);
+      u64 v[EPT];
+      merge_path<EPT>(src + base, w, src + base + w, w, d0 - base, v);
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) dst[d0 + e] = v[e];
+    }
+    __syncthreads();
+    u64* t = src;
+    src = dst;
+    dst = t;
+  }
+  return src;
+}
+
+}  // namespace gh

@@ -1,0 +1,377 @@
+// gheap_api.cpp -- host side of libgheap.so: arena layout, handle
+// management, launches, graphs and error reporting for the C ABI declared in
+// include/gheap.h.
+#include <hip/hip_runtime.h>
+
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "gh_launch.h"
+
+using namespace gh;
+
+namespace gh {
+hipError_t launch_init(HeapDesc* descs_dev, const HeapDesc* descs_host, u32 nheaps, Ctl* ctl,
+                       u64 timeout_ticks, hipStream_t st);
+hipError_t launch_prep(const HeapDesc* descs, u32 nheaps, Ctl* ctl, hipStream_t st);
+}  // namespace gh
+
+struct gh_heap {
+  u32 k;
+  u32 nheaps;
+  hipStream_t stream;
+  unsigned char* arena;
+  u64 arena_bytes;
+  Ctl* ctl;                        // device
+  HeapDesc* descs;                 // device
+  std::vector<HeapDesc> host_descs;
+  std::vector<u64> max_keys;
+  u64 size0;                       // host-tracked entry count of heap 0
+  bool size0_known;
+  int sticky;                      // last device error seen by the host
+  u32 clock_mhz;
+};
+
+namespace {
+
+constexpr u64 ALIGN = 256;
+inline u64 align_up(u64 x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
+
+bool k_supported(u32 k) {
+  return k == 32 || k == 64 || k == 128 || k == 256 || k == 512 || k == 1024;
+}
+
+u32 default_threads(u32 k) {
+  switch (k) {
+    case 32: return 64;
+    case 64: return 64;
+    case 128: return 128;
+    case 256: return 128;
+    case 512: return 256;
+    default: return 256;
+  }
+}
+
+u64 max_nodes_for(u64 max_keys, u32 k) { return max_keys / k + 1; }
+
+struct Layout {
+  u64 ctl_off, desc_off, total;
+  std::vector<u64> meta_off, pb_off, lock_off, node_off, max_nodes;
+};
+
+bool make_layout(u32 k, u32 nheaps, const u64* max_keys, u64 each, Layout& L) {
+  L.ctl_off = 0;
+  L.desc_off = align_up(sizeof(Ctl));
+  u64 off = align_up(L.desc_off + (u64)nheaps * sizeof(HeapDesc));
+  L.meta_off.resize(nheaps);
+  L.pb_off.resize(nheaps);
+  L.lock_off.resize(nheaps);
+  L.node_off.resize(nheaps);
+  L.max_nodes.resize(nheaps);
+  for (u32 i = 0; i < nheaps; ++i) {
+    u64 mk = max_keys ? max_keys[i] : each;
+    u64 mn = max_nodes_for(mk, k);
+    if (mn >= 0x7FFFFFFFull) return false;
+    L.max_nodes[i] = mn;
+    L.meta_off[i] = off;
+    off = align_up(off + sizeof(HeapMeta));
+    L.pb_off[i] = off;
+    off = align_up(off + (u64)k * 8);
+    L.lock_off[i] = off;
+    off = align_up(off + (mn + 1) * 8);
+    L.node_off[i] = off;
+    off = align_up(off + mn * (u64)k * 8);
+  }
+  L.total = off;
+  return true;
+}
+
+int from_status(u32 st) {
+  switch (st) {
+    case 0: return GH_OK;
+    case ERR_INVAL: return GH_EINVAL;
+    case ERR_NOMEM: return GH_ENOMEM;
+    case ERR_TIMEOUT: return GH_ETIMEDOUT;
+    default: return GH_ESTATE;
+  }
+}
+
+hipError_t launch_ops(const gh_heap* h, const LaunchArgs& a) {
+  switch (h->k) {
+    case 32: return launch_ops_k<32>(a);
+    case 64: return launch_ops_k<64>(a);
+    case 128: return launch_ops_k<128>(a);
+    case 256: return launch_ops_k<256>(a);
+    case 512: return launch_ops_k<512>(a);
+    case 1024: return launch_ops_k<1024>(a);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+u32 clock_mhz_of_device() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 100;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+    return 100;
+  return (u32)(khz / 1000);
+}
+
+u64 watchdog_ticks(u32 clock_mhz) {
+  u64 ms = 5000;
+  if (const char* e = std::getenv("GHEAP_WATCHDOG_MS")) {
+    long long v = std::atoll(e);
+    if (v > 0) ms = (u64)v;
+  }
+  return ms * 1000ull * clock_mhz;
+}
+
+// Launch the prep kernel (ticket bases, claim counter, start clock) and the
+// operation loop on the set's stream.
+int run_ops(gh_heap* h, const gh_op* d_ops, u32 nops, const OpParams& p, const u64* d_in,
+            u64* d_out, u32* d_counts, gh_logrec* d_log, const gh_tuning* t) {
+  if (nops == 0) return GH_OK;
+  u32 threads = (t && t->threads) ? t->threads : default_threads(h->k);
+  if (!heap_supported_shape(h->k, threads)) return GH_EINVAL;
+  u32 wg = (t && t->workgroups) ? t->workgroups : 256;
+  if (wg > nops) wg = nops;
+  if (wg == 0) wg = 1;
+  if (launch_prep(h->descs, h->nheaps, h->ctl, h->stream) != hipSuccess) return GH_EDEVICE;
+  LaunchArgs a;
+  a.descs = h->descs;
+  a.ops = d_ops;
+  a.nops = nops;
+  a.direct = p;
+  a.direct.clock_mhz = h->clock_mhz;
+  a.direct.nheaps = h->nheaps;
+  a.in = d_in;
+  a.out = d_out;
+  a.counts = d_counts;
+  a.log = d_log;
+  a.ctl = h->ctl;
+  a.workgroups = wg;
+  a.threads = threads;
+  a.stream = h->stream;
+  if (launch_ops(h, a) != hipSuccess) return GH_EDEVICE;
+  return GH_OK;
+}
+
+int refresh_status(gh_heap* h) {
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return GH_EDEVICE;
+  u32 st = 0;
+  if (hipMemcpy(&st, &h->ctl->status, sizeof(u32), hipMemcpyDeviceToHost) != hipSuccess)
+    return GH_EDEVICE;
+  int rc = from_status(st);
+  if (rc != GH_OK) h->sticky = rc;
+  return h->sticky;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t heap_arena_bytes(uint32_t k, uint32_t nheaps, const uint64_t* max_keys,
+                          uint64_t max_keys_each) {
+  if (!k_supported(k) || nheaps == 0) return 0;
+  Layout L;
+  if (!make_layout(k, nheaps, max_keys, max_keys_each, L)) return 0;
+  return L.total;
+}
+
+int heap_supported_shape(uint32_t k, uint32_t threads) {
+  return k_supported(k) && shape_ok((int)k, (int)threads) ? 1 : 0;
+}
+
+int heap_create_many(gh_heap_t* out, uint32_t k, uint32_t nheaps, const uint64_t* max_keys,
+                     void* d_arena, uint64_t arena_bytes, void* stream) {
+  if (!out || !d_arena || !max_keys || nheaps == 0 || !k_supported(k)) return GH_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(d_arena) & (ALIGN - 1)) != 0) return GH_EINVAL;
+  Layout L;
+  if (!make_layout(k, nheaps, max_keys, 0, L)) return GH_EINVAL;
+  if (arena_bytes < L.total) return GH_ENOMEM;
+  gh_heap* h = new (std::nothrow) gh_heap();
+  if (!h) return GH_ENOMEM;
+  h->k = k;
+  h->nheaps = nheaps;
+  h->stream = reinterpret_cast<hipStream_t>(stream);
+  h->arena = reinterpret_cast<unsigned char*>(d_arena);
+  h->arena_bytes = arena_bytes;
+  h->ctl = reinterpret_cast<Ctl*>(h->arena + L.ctl_off);
+  h->descs = reinterpret_cast<HeapDesc*>(h->arena + L.desc_off);
+  h->max_keys.assign(max_keys, max_keys + nheaps);
+  h->size0 = 0;
+  h->size0_known = true;
+  h->sticky = GH_OK;
+  h->clock_mhz = clock_mhz_of_device();
+  h->host_descs.resize(nheaps);
+  for (u32 i = 0; i < nheaps; ++i) {
+    HeapDesc& d = h->host_descs[i];
+    std::memset(&d, 0, sizeof(d));
+    d.meta = reinterpret_cast<HeapMeta*>(h->arena + L.meta_off[i]);
+    d.pb = reinterpret_cast<u64*>(h->arena + L.pb_off[i]);
+    d.locks = reinterpret_cast<u64*>(h->arena + L.lock_off[i]);
+    d.nodes = reinterpret_cast<u64*>(h->arena + L.node_off[i]);
+    d.max_nodes = (u32)L.max_nodes[i];
+    d.k = k;
+  }
+  if (launch_init(h->descs, h->host_descs.data(), nheaps, h->ctl, watchdog_ticks(h->clock_mhz),
+                  h->stream) != hipSuccess) {
+    delete h;
+    return GH_EDEVICE;
+  }
+  *out = h;
+  return GH_OK;
+}
+
+int heap_create(gh_heap_t* out, uint32_t k, uint64_t max_keys, void* d_arena,
+                uint64_t arena_bytes, void* stream) {
+  return heap_create_many(out, k, 1, &max_keys, d_arena, arena_bytes, stream);
+}
+
+int heap_insert(gh_heap_t h, const uint64_t* d_keys, uint64_t n) {
+  if (!h) return GH_EINVAL;
+  if (h->sticky != GH_OK) return h->sticky;
+  if (n == 0) return GH_OK;
+  if (!d_keys) return GH_EINVAL;
+  if (!h->size0_known) {
+    uint64_t sz = 0;
+    int rc = heap_size(h, 0, &sz);
+    if (rc != GH_OK) return rc;
+  }
+  if (h->size0 + n > h->max_keys[0]) return GH_ENOMEM;
+  u64 nops = (n + h->k - 1) / h->k;
+  if (nops > 0xFFFFFFFFull) return GH_EINVAL;
+  OpParams p{GH_OP_INSERT, 0, n, 0, 0};
+  gh_tuning t{(u32)(nops < 64 ? nops : 64), 0};
+  int rc = run_ops(h, nullptr, (u32)nops, p, d_keys, nullptr, nullptr, nullptr, &t);
+  if (rc == GH_OK) h->size0 += n;
+  return rc;
+}
+
+int heap_delete_min(gh_heap_t h, uint64_t* d_out, uint32_t k, uint32_t* d_count) {
+  if (!h || !d_out || !d_count || k != h->k) return GH_EINVAL;
+  if (h->sticky != GH_OK) return h->sticky;
+  OpParams p{GH_OP_DELETE_MIN, 0, 0, 0, 0};
+  gh_tuning t{1, 0};
+  int rc = run_ops(h, nullptr, 1, p, nullptr, d_out, d_count, nullptr, &t);
+  if (rc == GH_OK && h->size0_known) h->size0 -= (h->size0 < h->k ? h->size0 : h->k);
+  return rc;
+}
+
+int heap_submit(gh_heap_t h, const gh_op* d_ops, uint32_t nops, const uint64_t* d_in,
+                uint64_t* d_out, uint32_t* d_counts, gh_logrec* d_log, const gh_tuning* tuning) {
+  if (!h) return GH_EINVAL;
+  if (h->sticky != GH_OK) return h->sticky;
+  if (nops == 0) return GH_OK;
+  if (!d_ops) return GH_EINVAL;
+  h->size0_known = false;
+  OpParams p{GH_OP_INSERT, 0, 0, 0, 0};
+  return run_ops(h, d_ops, nops, p, d_in, d_out, d_counts, d_log, tuning);
+}
+
+int heap_submit_graph(gh_heap_t h, const gh_op* d_ops, uint32_t nops, const uint64_t* d_in,
+                      uint64_t* d_out, uint32_t* d_counts, gh_logrec* d_log,
+                      const gh_tuning* tuning, void** graph_out) {
+  if (!h || !graph_out || !d_ops || nops == 0) return GH_EINVAL;
+  if (h->sticky != GH_OK) return h->sticky;
+  if (h->stream == nullptr) return GH_EINVAL;  // the legacy stream cannot be captured
+  h->size0_known = false;
+  if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return GH_EDEVICE;
+  OpParams p{GH_OP_INSERT, 0, 0, 0, 0};
+  int rc = run_ops(h, d_ops, nops, p, d_in, d_out, d_counts, d_log, tuning);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(h->stream, &g);
+  if (rc != GH_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess || !g) return GH_EDEVICE;
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return GH_EDEVICE;
+  *graph_out = reinterpret_cast<void*>(ex);
+  return GH_OK;
+}
+
+int heap_graph_launch(gh_heap_t h, void* graph) {
+  if (!h || !graph) return GH_EINVAL;
+  if (h->sticky != GH_OK) return h->sticky;
+  h->size0_known = false;
+  if (hipGraphLaunch(reinterpret_cast<hipGraphExec_t>(graph), h->stream) != hipSuccess)
+    return GH_EDEVICE;
+  return GH_OK;
+}
+
+int heap_graph_destroy(void* graph) {
+  if (!graph) return GH_EINVAL;
+  return hipGraphExecDestroy(reinterpret_cast<hipGraphExec_t>(graph)) == hipSuccess ? GH_OK
+                                                                                     : GH_EDEVICE;
+}
+
+int heap_sync(gh_heap_t h) {
+  if (!h) return GH_EINVAL;
+  return refresh_status(h);
+}
+
+int heap_size(gh_heap_t h, uint32_t i, uint64_t* out_host) {
+  if (!h || !out_host || i >= h->nheaps) return GH_EINVAL;
+  int rc = refresh_status(h);
+  if (rc == GH_EDEVICE) return rc;
+  u64 ms[2];
+  const HeapDesc& d = h->host_descs[i];
+  if (hipMemcpy(ms, &d.meta->m, sizeof(ms), hipMemcpyDeviceToHost) != hipSuccess) return GH_EDEVICE;
+  *out_host = ms[0] * h->k + ms[1];
+  if (i == 0 && rc == GH_OK) {
+    h->size0 = *out_host;
+    h->size0_known = true;
+  }
+  return rc;
+}
+
+int heap_read_state(gh_heap_t h, uint32_t i, uint64_t* meta_host, uint64_t* nodes_host,
+                    uint64_t* pb_host) {
+  if (!h || !meta_host || i >= h->nheaps) return GH_EINVAL;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return GH_EDEVICE;
+  const HeapDesc& d = h->host_descs[i];
+  HeapMeta m;
+  if (hipMemcpy(&m, d.meta, sizeof(m), hipMemcpyDeviceToHost) != hipSuccess) return GH_EDEVICE;
+  meta_host[0] = m.m;
+  meta_host[1] = m.s;
+  meta_host[2] = m.serving;
+  meta_host[3] = d.max_nodes;
+  if (nodes_host &&
+      hipMemcpy(nodes_host, d.nodes, (u64)d.max_nodes * h->k * 8, hipMemcpyDeviceToHost) !=
+          hipSuccess)
+    return GH_EDEVICE;
+  if (pb_host && m.s > 0 &&
+      hipMemcpy(pb_host, d.pb, m.s * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    return GH_EDEVICE;
+  return GH_OK;
+}
+
+int heap_destroy(gh_heap_t h) {
+  if (!h) return GH_EINVAL;
+  int rc = refresh_status(h);
+  delete h;
+  return rc;
+}
+
+const char* heap_strerror(int code) {
+  switch (code) {
+    case GH_OK: return "success";
+    case GH_EINVAL: return "invalid argument";
+    case GH_ENOMEM: return "out of heap capacity or arena space";
+    case GH_ETIMEDOUT: return "a device lock wait exceeded the watchdog limit";
+    case GH_EDEVICE: return "HIP runtime error";
+    case GH_ESTATE: return "heap left inconsistent by an earlier error";
+    default: return "unknown error";
+  }
+}
+
+uint64_t heap_clock_hz(void) { return (uint64_t)clock_mhz_of_device() * 1000000ull; }
+
+}  // extern "C"

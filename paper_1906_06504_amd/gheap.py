@@ -1,0 +1,273 @@
+"""Python binding of libgheap.so (ctypes).  Argument marshalling only: every
+step of the heap runs in the HIP library; PyTorch supplies device memory and
+streams.
+
+The library must have been built (``python -m paper_1906_06504_amd.build``);
+importing this module without it raises ImportError -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgheap.so")
+
+GH_OK = 0
+GH_EINVAL = -1
+GH_ENOMEM = -2
+GH_ETIMEDOUT = -3
+GH_EDEVICE = -4
+GH_ESTATE = -5
+
+OP_INSERT = 0
+OP_DELETE_MIN = 1
+SUPPORTED_K = (32, 64, 128, 256, 512, 1024)
+ENTRY_MAX = 0xFFFFFFFFFFFFFFFF
+
+# struct gh_op / gh_logrec layouts (include/gheap.h)
+OP_DTYPE = np.dtype([("heap", "<u4"), ("kind", "<u4"), ("n", "<u4"), ("seq", "<u4"),
+                     ("off", "<u8"), ("arrival_ns", "<u8")])
+LOG_DTYPE = np.dtype([("ticket", "<u8"), ("count", "<u4"), ("levels", "<u2"), ("kind", "u1"),
+                      ("flags", "u1"), ("t_root", "<u8"), ("t_done", "<u8")])
+assert OP_DTYPE.itemsize == 32 and LOG_DTYPE.itemsize == 32
+
+FLAG_FULL = 1
+FLAG_HANDOFF = 2
+FLAG_TOOK = 4
+FLAG_REJECTED = 0x40
+FLAG_ABORTED = 0x80
+
+EXPORTS = ("heap_arena_bytes", "heap_supported_shape", "heap_create", "heap_create_many",
+           "heap_insert", "heap_delete_min", "heap_submit", "heap_submit_graph",
+           "heap_graph_launch", "heap_graph_destroy", "heap_sync", "heap_size",
+           "heap_read_state", "heap_destroy", "heap_strerror", "heap_clock_hz")
+
+
+class GHeapError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__("%s failed: %s (%d)" % (what, strerror(code), code))
+
+
+_lib = None
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("workgroups", ctypes.c_uint32), ("threads", ctypes.c_uint32)]
+
+
+def load_library(path: str = LIB_PATH):
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libgheap.so is not built at %s; run "
+                          "`python -m paper_1906_06504_amd.build`" % path)
+    lib = ctypes.CDLL(path)
+    vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    sig = {
+        "heap_arena_bytes": (u64, [u32, u32, vp, u64]),
+        "heap_supported_shape": (i32, [u32, u32]),
+        "heap_create": (i32, [ctypes.POINTER(vp), u32, u64, vp, u64, vp]),
+        "heap_create_many": (i32, [ctypes.POINTER(vp), u32, u32, vp, vp, u64, vp]),
+        "heap_insert": (i32, [vp, vp, u64]),
+        "heap_delete_min": (i32, [vp, vp, u32, vp]),
+        "heap_submit": (i32, [vp, vp, u32, vp, vp, vp, vp, ctypes.POINTER(_Tuning)]),
+        "heap_submit_graph": (i32, [vp, vp, u32, vp, vp, vp, vp, ctypes.POINTER(_Tuning),
+                                    ctypes.POINTER(vp)]),
+        "heap_graph_launch": (i32, [vp, vp]),
+        "heap_graph_destroy": (i32, [vp]),
+        "heap_sync": (i32, [vp]),
+        "heap_size": (i32, [vp, u32, ctypes.POINTER(u64)]),
+        "heap_read_state": (i32, [vp, u32, vp, vp, vp]),
+        "heap_destroy": (i32, [vp]),
+        "heap_strerror": (ctypes.c_char_p, [i32]),
+        "heap_clock_hz": (u64, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load_library().heap_strerror(code).decode()
+
+
+def _check(rc: int, what: str):
+    if rc != GH_OK:
+        raise GHeapError(rc, what)
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return t.data_ptr()
+
+
+def to_device_u64(a: np.ndarray, device="cuda") -> torch.Tensor:
+    """uint64 numpy array -> int64 device tensor holding the same bits."""
+    a = np.ascontiguousarray(a, dtype=np.uint64)
+    return torch.from_numpy(a.view(np.int64)).to(device)
+
+
+def to_host_u64(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint64)
+
+
+def arena_bytes(k: int, max_keys) -> int:
+    lib = load_library()
+    mk = np.ascontiguousarray(np.atleast_1d(np.asarray(max_keys, dtype=np.uint64)))
+    return int(lib.heap_arena_bytes(k, mk.size, mk.ctypes.data, 0))
+
+
+def supported_shape(k: int, threads: int) -> bool:
+    return bool(load_library().heap_supported_shape(k, threads))
+
+
+def clock_hz() -> int:
+    return int(load_library().heap_clock_hz())
+
+
+class HeapSet:
+    """One or more device heaps sharing node capacity k, an arena and a stream."""
+
+    def __init__(self, k: int, max_keys, device: str | torch.device = "cuda",
+                 stream: torch.cuda.Stream | None = None):
+        self.lib = load_library()
+        self.k = int(k)
+        mk = np.ascontiguousarray(np.atleast_1d(np.asarray(max_keys, dtype=np.uint64)))
+        self.nheaps = int(mk.size)
+        self.max_keys = mk
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = int(self.lib.heap_arena_bytes(self.k, self.nheaps, mk.ctypes.data, 0))
+        if nbytes == 0:
+            raise GHeapError(GH_EINVAL, "heap_arena_bytes")
+        # 256-byte alignment: torch's caching allocator returns 512-aligned blocks
+        self.arena = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        rc = self.lib.heap_create_many(ctypes.byref(h), self.k, self.nheaps, mk.ctypes.data,
+                                       self.arena.data_ptr(), nbytes,
+                                       ctypes.c_void_p(self.stream.cuda_stream))
+        _check(rc, "heap_create_many")
+        self.h = h
+        self._graphs = []
+
+    # -- single-heap calls (heap 0) -------------------------------------
+    def insert(self, keys: torch.Tensor) -> None:
+        """Insert a 1-D int64/uint64 device tensor of entries into heap 0."""
+        _check(self.lib.heap_insert(self.h, _ptr(keys), keys.numel()), "heap_insert")
+
+    def delete_min(self, out: torch.Tensor | None = None, count: torch.Tensor | None = None):
+        """deleteMin on heap 0; returns (out[k] int64 tensor, count int32 tensor)."""
+        if out is None:
+            out = torch.empty(self.k, dtype=torch.int64, device=self.device)
+        if count is None:
+            count = torch.zeros(1, dtype=torch.int32, device=self.device)
+        _check(self.lib.heap_delete_min(self.h, _ptr(out), self.k, _ptr(count)),
+               "heap_delete_min")
+        return out, count
+
+    # -- submissions -------------------------------------------------------
+    def submit(self, ops: torch.Tensor, nops: int, d_in: torch.Tensor | None,
+               d_out: torch.Tensor | None, counts: torch.Tensor | None = None,
+               log: torch.Tensor | None = None, workgroups: int = 0, threads: int = 0):
+        t = _Tuning(workgroups, threads)
+        rc = self.lib.heap_submit(self.h, _ptr(ops), nops, _ptr(d_in), _ptr(d_out),
+                                  _ptr(counts), _ptr(log), ctypes.byref(t))
+        _check(rc, "heap_submit")
+
+    def submit_graph(self, ops, nops, d_in, d_out, counts=None, log=None, workgroups=0,
+                     threads=0) -> int:
+        t = _Tuning(workgroups, threads)
+        g = ctypes.c_void_p()
+        rc = self.lib.heap_submit_graph(self.h, _ptr(ops), nops, _ptr(d_in), _ptr(d_out),
+                                        _ptr(counts), _ptr(log), ctypes.byref(t),
+                                        ctypes.byref(g))
+        _check(rc, "heap_submit_graph")
+        self._graphs.append(g.value)
+        return g.value
+
+    def graph_launch(self, g: int) -> None:
+        _check(self.lib.heap_graph_launch(self.h, ctypes.c_void_p(g)), "heap_graph_launch")
+
+    def sync(self) -> int:
+        return int(self.lib.heap_sync(self.h))
+
+    def size(self, i: int = 0) -> int:
+        v = ctypes.c_uint64()
+        _check(self.lib.heap_size(self.h, i, ctypes.byref(v)), "heap_size")
+        return int(v.value)
+
+    def read_state(self, i: int = 0):
+        """(m, s, served, max_nodes, nodes[max_nodes, k] uint64, pb[s] uint64)."""
+        meta = np.zeros(4, dtype=np.uint64)
+        _check(self.lib.heap_read_state(self.h, i, meta.ctypes.data, None, None),
+               "heap_read_state")
+        nodes = np.empty(int(meta[3]) * self.k, dtype=np.uint64)
+        pb = np.empty(max(int(meta[1]), 1), dtype=np.uint64)
+        _check(self.lib.heap_read_state(self.h, i, meta.ctypes.data, nodes.ctypes.data,
+                                        pb.ctypes.data), "heap_read_state")
+        return (int(meta[0]), int(meta[1]), int(meta[2]), int(meta[3]),
+                nodes.reshape(int(meta[3]), self.k), pb[: int(meta[1])].copy())
+
+    def close(self) -> int:
+        rc = GH_OK
+        if getattr(self, "h", None):
+            for g in self._graphs:
+                self.lib.heap_graph_destroy(ctypes.c_void_p(g))
+            self._graphs = []
+            rc = int(self.lib.heap_destroy(self.h))
+            self.h = None
+        return rc
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Heap(HeapSet):
+    """A single device heap (heap_create)."""
+
+    def __init__(self, k: int, max_keys: int, device="cuda", stream=None):
+        super().__init__(k, [max_keys], device=device, stream=stream)
+
+
+def ops_to_device(oplist, device="cuda"):
+    """Pack a workloads.OpList into gh_op records on the device.
+    Returns (ops tensor, nops, keys tensor, out tensor, counts tensor)."""
+    n = len(oplist)
+    rec = np.zeros(n, dtype=OP_DTYPE)
+    rec["heap"] = oplist.heap_ids()
+    rec["kind"] = oplist.kind
+    rec["n"] = oplist.n
+    rec["seq"] = oplist.seq()
+    rec["off"] = oplist.off
+    if oplist.arrival is not None:
+        rec["arrival_ns"] = oplist.arrival
+    ops = torch.from_numpy(rec.view(np.uint8).copy()).to(device)
+    keys = to_device_u64(oplist.keys if oplist.keys.size else np.zeros(1, np.uint64), device)
+    out = torch.full((max(oplist.out_entries, 1),), -1, dtype=torch.int64, device=device)
+    counts = torch.zeros(max(n, 1), dtype=torch.int32, device=device)
+    return ops, n, keys, out, counts
+
+
+def new_log(nops: int, device="cuda") -> torch.Tensor:
+    return torch.zeros(max(nops, 1) * LOG_DTYPE.itemsize, dtype=torch.uint8, device=device)
+
+
+def log_to_host(log: torch.Tensor, nops: int) -> np.ndarray:
+    return log.cpu().numpy().view(LOG_DTYPE)[:nops].copy()

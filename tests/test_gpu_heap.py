@@ -1,0 +1,171 @@
+"""GPU parity tests: the HIP heap (through the C ABI) against the CPU oracle,
+bit for bit, on seeded inputs.
+
+Every deleteMin result of a submission is compared with the oracle replaying
+the submission's ticket log in ticket order (the root is the linearization
+point, Sec. 3.3.3 Theorem 1); quiescent GPU states are checked against
+Properties 1-3 (Sec. 3.1) and against the live multiset.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1906_06504_amd import workloads as W
+
+from heap_harness import (MAXE, check_gpu_state, gpu_state_by_index, replay_and_compare,
+                          run_gpu)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1906_06504_amd import gheap
+    gheap.load_library()
+    oracle.build(force=False)
+    return gheap
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+def test_single_calls_insert_then_drain(G):
+    """heap_insert / heap_delete_min one call at a time, k = 64."""
+    k, total = 64, 5000
+    st = W.Stream(1)
+    keys = W.pack(st.u32(total), np.arange(total, dtype=np.uint64))
+    h = G.Heap(k, total)
+    dk = G.to_device_u64(keys)
+    h.insert(dk[:1000])
+    h.insert(dk[1000:1001])
+    h.insert(dk[1001:])
+    assert h.size() == total
+    outs = []
+    out = torch.empty(k, dtype=torch.int64, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    while True:
+        h.delete_min(out, cnt)
+        c = int(cnt.item())
+        if c == 0:
+            break
+        outs.append(G.to_host_u64(out)[:c].copy())
+    assert np.array_equal(np.concatenate(outs), np.sort(keys))
+    assert h.close() == G.GH_OK
+
+
+@pytest.mark.parametrize("k", [32, 64, 128, 256, 512, 1024])
+def test_serialized_state_equals_oracle(G, k):
+    """One operation in flight: after a mixed trace the GPU node array and
+    partial buffer equal the oracle's exactly (same bit-reversal order)."""
+    ops = W.mixed_ops(60 * k, k, seed=100 + k, first_id=0)
+    _print("serialized k=%d ops=%d" % (k, len(ops)))
+    hs, out, counts, log = run_gpu(ops, k, max_keys=60 * k, workgroups=1)
+    oh = replay_and_compare(ops, k, out, counts, log)
+    m, s, byidx, pb = gpu_state_by_index(hs, 0, k)
+    assert (m, s) == (oh.m, oh.s)
+    onodes, opb = oh.export()
+    assert np.array_equal(pb, opb)
+    for c, row in byidx.items():
+        assert np.array_equal(row, onodes[c - 1]), "node %d differs" % c
+    hs.close()
+
+
+@pytest.mark.parametrize("k,wg", [(32, 64), (64, 128), (128, 64), (256, 32), (1024, 16)])
+def test_concurrent_replay(G, k, wg):
+    """Many operations in flight on one heap: ticket-log replay is exact."""
+    pre = W.prefill_ops(40 * k, k, seed=7 + k)
+    mix = W.mixed_ops(200 * k, k, seed=8 + k, first_id=40 * k)
+    allops = W.concat(pre, mix, k)
+    _print("concurrent k=%d wg=%d ops=%d" % (k, wg, len(allops)))
+    hs, out, counts, log = run_gpu(allops, k, max_keys=400 * k, workgroups=wg)
+    oh = replay_and_compare(allops, k, out, counts, log)
+    live = check_gpu_state(hs, 0, k)
+    onodes, opb = oh.export()
+    olive = np.sort(np.concatenate([onodes[oracle.idx(p) - 1] for p in range(1, oh.m + 1)] + [opb])) \
+        if oh.m else np.sort(opb)
+    assert np.array_equal(live, olive)
+    hs.close()
+
+
+def test_concurrent_small_k_heavy_contention(G):
+    """k = 32, 512 workgroups on a small heap: many cooperations and absent
+    children; the replay must still be exact."""
+    k = 32
+    ops = W.mixed_ops(20000 * k // 32, k, seed=99, first_id=0, p_insert=0.6)
+    _print("contention ops=%d" % len(ops))
+    hs, out, counts, log = run_gpu(ops, k, max_keys=len(ops) * k, workgroups=512)
+    replay_and_compare(ops, k, out, counts, log)
+    check_gpu_state(hs, 0, k)
+    hs.close()
+
+
+def test_config1_full_size(G):
+    """k = 64: insert 2^16 keys in batches of 64, drain; the deleteMin
+    sequence is the fully sorted input."""
+    ops, k = W.config1()
+    _print("config1 ops=%d" % len(ops))
+    hs, out, counts, log = run_gpu(ops, k, max_keys=1 << 16, workgroups=128)
+    dels = np.flatnonzero(ops.kind == W.OP_DELETE_MIN)
+    # deleteMins follow all inserts in ticket order, so their outputs in
+    # ticket order concatenate to the sorted keys
+    order = dels[np.argsort(log["ticket"][dels])]
+    got = np.concatenate([out[int(ops.off[i]):int(ops.off[i]) + int(counts[i])] for i in order])
+    assert np.array_equal(got, np.sort(ops.keys))
+    assert counts[order[-1]] == 0
+    replay_and_compare(ops, k, out, counts, log)
+    hs.close()
+
+
+def test_config2_reduced(G):
+    """k = 1024, prefill 2^18, then a 50/50 mix requesting 2^20 keys."""
+    pre, mix, k = W.config2(prefill=1 << 18, requested=1 << 20)
+    allops = W.concat(pre, mix, k)
+    _print("config2-reduced ops=%d" % len(allops))
+    hs, out, counts, log = run_gpu(allops, k, max_keys=(1 << 18) + (1 << 20), workgroups=128)
+    replay_and_compare(allops, k, out, counts, log)
+    check_gpu_state(hs, 0, k)
+    hs.close()
+
+
+def test_edge_cases(G):
+    k = 64
+    h = G.Heap(k, 200)
+    out, cnt = h.delete_min()
+    assert int(cnt.item()) == 0                      # empty heap
+    h.insert(torch.empty(0, dtype=torch.int64, device="cuda"))   # n = 0 no-op
+    keys = np.array([9, 3, 7], dtype=np.uint64)
+    h.insert(G.to_device_u64(keys))                 # partial buffer only
+    out, cnt = h.delete_min()
+    assert int(cnt.item()) == 3
+    assert np.array_equal(G.to_host_u64(out)[:3], np.sort(keys))
+    big = np.arange(1, 202, dtype=np.uint64)
+    with pytest.raises(G.GHeapError) as ei:
+        h.insert(G.to_device_u64(big))              # over capacity: rejected whole
+    assert ei.value.code == G.GH_ENOMEM
+    assert h.size() == 0
+    lib = G.load_library()
+    o = torch.empty(k, dtype=torch.int64, device="cuda")
+    c = torch.zeros(1, dtype=torch.int32, device="cuda")
+    assert lib.heap_delete_min(h.h, o.data_ptr(), k + 1, c.data_ptr()) == G.GH_EINVAL
+    assert lib.heap_delete_min(h.h, None, k, c.data_ptr()) == G.GH_EINVAL
+    assert h.close() == G.GH_OK
+
+
+def test_capacity_overrun_in_submission_is_sticky(G):
+    """An insert that needs a node beyond max_keys inside a submission is
+    rejected on the device; the heap stays consistent and the error sticks."""
+    k = 64
+    ops = W.prefill_ops(10 * k, k, seed=5)
+    hs = G.HeapSet(k, [5 * k])
+    d_ops, n, keys, out, counts = G.ops_to_device(ops)
+    hs.submit(d_ops, n, keys, out, counts, workgroups=4)
+    assert hs.sync() == G.GH_ENOMEM
+    check_gpu_state(hs, 0, k)
+    with pytest.raises(G.GHeapError):
+        hs.insert(keys[:1])
+    assert hs.close() == G.GH_ENOMEM

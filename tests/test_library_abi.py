@@ -1,0 +1,80 @@
+"""CPU-side checks of the C ABI: the library loads and exports every function
+include/gheap.h declares; host-only calls (no device work) behave as
+documented; the Python binding mirrors the header's struct layouts."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gheap.h")
+LIB = os.path.join(ROOT, "paper_1906_06504_amd", "libgheap.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_ ]*\*?\s*\b(heap_[a-z_]+)\s*\(",
+                      text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_1906_06504_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_exports_every_declared_function(lib):
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), "missing export " + n
+
+
+def test_binding_lists_every_export():
+    from paper_1906_06504_amd import gheap
+    assert sorted(gheap.EXPORTS) == declared_functions()
+
+
+def test_host_only_calls(lib):
+    lib.heap_arena_bytes.restype = ctypes.c_uint64
+    lib.heap_arena_bytes.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint64]
+    assert lib.heap_arena_bytes(1000, 1, None, 100) == 0          # unsupported k
+    a = lib.heap_arena_bytes(1024, 1, None, 1 << 22)
+    b = lib.heap_arena_bytes(1024, 1, None, 1 << 23)
+    assert a > (1 << 22) * 8 and b > a
+    lib.heap_supported_shape.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+    assert lib.heap_supported_shape(1024, 256) == 1
+    assert lib.heap_supported_shape(1024, 64) == 0
+    assert lib.heap_supported_shape(32, 64) == 1
+    assert lib.heap_supported_shape(48, 64) == 0
+    lib.heap_strerror.restype = ctypes.c_char_p
+    assert b"capacity" in lib.heap_strerror(-2)
+    for fn in ("heap_insert", "heap_sync", "heap_destroy"):
+        f = getattr(lib, fn)
+        f.restype = ctypes.c_int
+    lib.heap_insert.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64]
+    assert lib.heap_insert(None, None, 5) == -1
+    lib.heap_destroy.argtypes = [ctypes.c_void_p]
+    assert lib.heap_destroy(None) == -1
+
+
+def test_struct_layouts_match_header():
+    from paper_1906_06504_amd import gheap
+    text = open(HEADER).read()
+    assert "uint64_t arrival_ns;" in text and gheap.OP_DTYPE.names[-1] == "arrival_ns"
+    assert gheap.OP_DTYPE.itemsize == 32 and gheap.LOG_DTYPE.itemsize == 32
+    assert list(gheap.LOG_DTYPE.names) == ["ticket", "count", "levels", "kind", "flags",
+                                           "t_root", "t_done"]
+
+
+def test_oplist_seq_ranks():
+    from paper_1906_06504_amd import workloads as W
+    ops = W.OpList(np.zeros(6, np.uint8), np.ones(6, np.uint32), np.zeros(6, np.uint64),
+                   np.zeros(6, np.uint64), 0, heap=np.array([2, 0, 2, 1, 0, 2], np.uint32))
+    assert list(ops.seq()) == [0, 0, 1, 0, 1, 2]
