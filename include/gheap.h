@@ -89,17 +89,26 @@ typedef struct gh_op {
  *   kind     GH_OP_INSERT or GH_OP_DELETE_MIN
  *   flags    bit 0: a full batch was created; bit 1: an insert handed its
  *            batch to a deleteMin that took its target; bit 2: a deleteMin
- *            took the batch of an in-flight insert
- *   t_root   device wall clock (ticks) when the root was acquired
- *   t_done   device wall clock (ticks) when the operation finished */
+ *            took the batch of an in-flight insert; bit 3: the heap had at
+ *            least one node when the root was taken; bit 4: a deleteMin
+ *            refilled the root from the last node; bit 6: the operation
+ *            was rejected (capacity or malformed record); bit 7: abandoned
+ *            after a device error
+ *   pb       partial-buffer size when the root was taken
+ *   t_claim, t_root, t_done  device wall clock in ticks (heap_clock_hz)
+ *            relative to the submission's start, when a workgroup claimed
+ *            the operation, took the root, and finished (32-bit, wraps) */
 typedef struct gh_logrec {
     uint64_t ticket;
     uint32_t count;
     uint16_t levels;
     uint8_t kind;
     uint8_t flags;
-    uint64_t t_root;
-    uint64_t t_done;
+    uint16_t pb;
+    uint16_t reserved;
+    uint32_t t_claim;
+    uint32_t t_root;
+    uint32_t t_done;
 } gh_logrec;
 
 /* Launch shape of a submission: workgroups = number of operations in flight

@@ -28,6 +28,7 @@ __global__ __launch_bounds__(T) void k_ops(const HeapDesc* __restrict__ descs,
       u32 i = atomicAdd(&ctl->next_op, 1u);
       if (ld_relaxed32(&ctl->abort)) i = nops;
       sh.op = i;
+      sh.t_claim = now_ticks();
     }
     __syncthreads();
     const u32 i = sh.op;
@@ -52,7 +53,7 @@ __global__ __launch_bounds__(T) void k_ops(const HeapDesc* __restrict__ descs,
         if (log) {
           gh_logrec rec{};
           rec.kind = (uint8_t)op.kind;
-          rec.flags = 0x40;
+          rec.flags = (uint8_t)F_REJECT;
           log[i] = rec;
         }
       }
@@ -77,7 +78,7 @@ __global__ __launch_bounds__(T) void k_ops(const HeapDesc* __restrict__ descs,
     if (malformed || (op.kind == GH_OP_INSERT && op.n == 0)) {
       if (malformed && tid == 0) note_error(ctl, ERR_INVAL);
       r = op_pass_root(H, ticket, sh, ctl);
-      if (malformed) r.flags |= 0x40;
+      if (malformed) r.flags |= F_REJECT;
     } else if (op.kind == GH_OP_INSERT) {
       r = op_insert<K, T>(H, ticket, in + op.off, op.n, lds, sh, ctl);
     } else {
@@ -86,14 +87,18 @@ __global__ __launch_bounds__(T) void k_ops(const HeapDesc* __restrict__ descs,
     if (tid == 0) {
       if (counts) counts[i] = op.kind == GH_OP_INSERT ? 0u : r.count;
       if (log) {
+        const u64 t0 = ctl->t0;
         gh_logrec rec;
         rec.ticket = ticket;
         rec.count = r.count;
         rec.levels = (uint16_t)r.levels;
         rec.kind = (uint8_t)op.kind;
-        rec.flags = (uint8_t)(r.flags | (r.ok ? 0u : 0x80u));
-        rec.t_root = sh.t_root;
-        rec.t_done = now_ticks();
+        rec.flags = (uint8_t)(r.flags | (r.ok ? 0u : F_ABORT));
+        rec.pb = (uint16_t)sh.s;
+        rec.reserved = 0;
+        rec.t_claim = (u32)(sh.t_claim - t0);
+        rec.t_root = (u32)(sh.t_root - t0);
+        rec.t_done = (u32)(now_ticks() - t0);
         log[i] = rec;
       }
     }

@@ -29,6 +29,7 @@ namespace gh {
 
 struct OpShared {
   u64 m, s;            // root metadata read at root acquire
+  u64 t_claim;         // clock when the operation was claimed
   u64 t_root;          // clock at root acquire
   u32 flag0, flag1;    // broadcast results from thread 0
   u32 ok;
@@ -42,7 +43,8 @@ struct OpResult {
   bool ok;
 };
 
-constexpr u32 F_FULL = 1, F_HANDOFF = 2, F_TOOK = 4;
+constexpr u32 F_FULL = 1, F_HANDOFF = 2, F_TOOK = 4, F_ROOT = 8, F_REFILL = 16, F_REJECT = 0x40,
+              F_ABORT = 0x80;
 
 // --- thread-0 lock primitives (return false when the wait is abandoned) ---
 
@@ -142,6 +144,7 @@ __device__ __forceinline__ OpResult op_pass_root(const HeapDesc& H, u64 ticket, 
   if (threadIdx.x == 0) {
     sh.ok = root_acquire(H.meta, ticket, ctl) ? 1u : 0u;
     sh.t_root = now_ticks();
+    sh.s = 0;
     if (sh.ok) st_release(&H.meta->serving, ticket + 1);
   }
   __syncthreads();
@@ -184,6 +187,7 @@ __device__ OpResult op_insert(const HeapDesc& H, u64 ticket, const u64* __restri
   if (!sh.ok) { res.ok = false; return res; }
   const u64 m = sh.m;
   const u32 s = (u32)sh.s;
+  if (m >= 1) res.flags |= F_ROOT;
   if (n + s >= (u32)K && m + 1 > H.max_nodes) {
     // no room for another node: reject the insert, leave the heap unchanged
     if (tid == 0) {
@@ -191,7 +195,7 @@ __device__ OpResult op_insert(const HeapDesc& H, u64 ticket, const u64* __restri
       st_release(&meta->serving, ticket + 1);
     }
     res.count = 0;
-    res.flags |= 0x40;
+    res.flags |= F_REJECT;
     return res;
   }
 
@@ -349,6 +353,7 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
   if (!sh.ok) { res.ok = false; return res; }
   const u64 m = sh.m;
   const u32 s = (u32)sh.s;
+  if (m >= 1) res.flags |= F_ROOT;
 
   if (m == 0) {
     // no node: the partial buffer is the whole heap
@@ -376,6 +381,7 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
   }
 
   // refill the root from the last node (Sec. 3.2.1), MAX-marking that node
+  res.flags |= F_REFILL;
   const u64 m2 = m - 1;
   u64* llock = H.locks + m;
   u64* lastp = H.nodes + (m - 1) * (u64)K;

@@ -32,12 +32,15 @@ ENTRY_MAX = 0xFFFFFFFFFFFFFFFF
 OP_DTYPE = np.dtype([("heap", "<u4"), ("kind", "<u4"), ("n", "<u4"), ("seq", "<u4"),
                      ("off", "<u8"), ("arrival_ns", "<u8")])
 LOG_DTYPE = np.dtype([("ticket", "<u8"), ("count", "<u4"), ("levels", "<u2"), ("kind", "u1"),
-                      ("flags", "u1"), ("t_root", "<u8"), ("t_done", "<u8")])
+                      ("flags", "u1"), ("pb", "<u2"), ("reserved", "<u2"), ("t_claim", "<u4"),
+                      ("t_root", "<u4"), ("t_done", "<u4")])
 assert OP_DTYPE.itemsize == 32 and LOG_DTYPE.itemsize == 32
 
 FLAG_FULL = 1
 FLAG_HANDOFF = 2
 FLAG_TOOK = 4
+FLAG_ROOT = 8
+FLAG_REFILL = 16
 FLAG_REJECTED = 0x40
 FLAG_ABORTED = 0x80
 

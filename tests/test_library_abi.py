@@ -69,8 +69,8 @@ def test_struct_layouts_match_header():
     text = open(HEADER).read()
     assert "uint64_t arrival_ns;" in text and gheap.OP_DTYPE.names[-1] == "arrival_ns"
     assert gheap.OP_DTYPE.itemsize == 32 and gheap.LOG_DTYPE.itemsize == 32
-    assert list(gheap.LOG_DTYPE.names) == ["ticket", "count", "levels", "kind", "flags",
-                                           "t_root", "t_done"]
+    assert list(gheap.LOG_DTYPE.names) == ["ticket", "count", "levels", "kind", "flags", "pb",
+                                           "reserved", "t_claim", "t_root", "t_done"]
 
 
 def test_oplist_seq_ranks():
