@@ -164,7 +164,7 @@ int heap_delete_min(gh_heap_t h, uint64_t *d_out, uint32_t k, uint32_t *d_count)
  * Inserts read d_in, deleteMins write d_out and d_counts[i] (device, one
  * uint32 per operation; inserts get 0); d_log (device, nops records, may be
  * NULL) receives one gh_logrec per operation.  Capacity overruns are
- * detected on the device (sticky GH_ENOMEM). */
+ * detected on the device (sticky GH_ENOMEM).  nops < 2^24. */
 int heap_submit(gh_heap_t h, const gh_op *d_ops, uint32_t nops,
                 const uint64_t *d_in, uint64_t *d_out, uint32_t *d_counts,
                 gh_logrec *d_log, const gh_tuning *tuning);

@@ -17,16 +17,26 @@ constexpr u64 ENT_MAX = ~0ull;  // reserved filler; never a live entry
 // Heap state in device memory
 // ---------------------------------------------------------------------------
 
-// Root metadata of one heap.  `serving` sits alone in its own 128-byte line
-// because every operation waiting for the root polls it.
+// Root metadata of one heap.  The word every waiting operation polls also
+// carries the root-guarded counters, so the operation that gets the root
+// learns m and s without another round trip:
+//   root = (ticket allowed at the root, low 24 bits) << 40 | m << 10 | s
+// (m < 2^30 nodes, s < 1024 partial-buffer entries).  `base` is the full
+// ticket of seq 0 in the current submission.
 struct alignas(256) HeapMeta {
-  u64 serving;        // ticket allowed to take the root now
+  u64 root;
   u64 pad0[15];
-  u64 base;           // ticket of seq 0 in the current submission
-  u64 m;              // nodes in use (guarded by the root)
-  u64 s;              // partial-buffer size (guarded by the root)
-  u64 pad1[13];
+  u64 base;
+  u64 pad1[15];
 };
+constexpr u64 RW_TICKET_MASK = 0xFFFFFFull;
+constexpr u64 RW_M_MASK = (1ull << 30) - 1;
+__host__ __device__ __forceinline__ u64 rootword(u64 ticket, u64 m, u64 s) {
+  return ((ticket & RW_TICKET_MASK) << 40) | ((m & RW_M_MASK) << 10) | (s & 1023);
+}
+__host__ __device__ __forceinline__ u64 rw_ticket(u64 w) { return w >> 40; }
+__host__ __device__ __forceinline__ u64 rw_m(u64 w) { return (w >> 10) & RW_M_MASK; }
+__host__ __device__ __forceinline__ u64 rw_s(u64 w) { return w & 1023; }
 static_assert(sizeof(HeapMeta) == 256, "meta layout");
 
 // Where one heap lives.  Node storage is indexed by the order in which nodes
@@ -71,17 +81,26 @@ constexpr u64 ST_INUSE = 1;   // held by one operation (Lemma 1)
 constexpr u64 ST_TARGET = 2;  // reserved target of an in-flight insert
 constexpr u64 ST_MARKED = 3;  // a deleteMin asked that insert for its batch
 constexpr u64 ST_HANDED = 4;  // the insert left its batch in the target slot
+constexpr u64 ST_REMOVED = 5; // a deleteMin took this node's batch as the last node
 
 __device__ __forceinline__ u64 lockword(u64 st, u64 ticket) { return (ticket << 3) | st; }
 __device__ __forceinline__ u64 lw_state(u64 w) { return w & 7; }
 __device__ __forceinline__ u64 lw_ticket(u64 w) { return w >> 3; }
 
 // ---------------------------------------------------------------------------
-// Memory ordering.  Node payloads move with ordinary loads and stores; lock
-// words and the root ticket use agent-scope atomics.  A holder publishes its
-// stores with a release fence in every thread before the barrier that
-// precedes the releasing store; an acquirer's thread 0 takes the lock with an
-// acquire, and the workgroup barrier orders the other threads' loads after it.
+// Memory ordering across the XCDs (each has its own L2).
+//
+// Node payloads move with ordinary loads and stores; lock words and the root
+// word are agent-scope atomics.  A holder publishes with publish(): every
+// wave waits for its stores, the workgroup meets at a barrier, and thread 0
+// writes the XCD's L2 back to memory and waits for that write-back before it
+// issues any releasing store.  An acquirer invalidates its XCD's L2 after
+// taking the lock and before reading the protected data.
+//
+// The two cache operations are written out with their waits: the compiler's
+// own release sequence can omit the wait after the L2 write-back when it
+// sees no other outstanding memory operation, which lets the releasing store
+// overtake the write-back.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ u64 ld_relaxed(const u64* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -89,21 +108,38 @@ __device__ __forceinline__ u64 ld_relaxed(const u64* p) {
 __device__ __forceinline__ u32 ld_relaxed32(const u32* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void st_release(u64* p, u64 v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ void st_relaxed(u64* p, u64 v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ bool cas_relaxed(u64* p, u64 expect, u64 desired) {
   return __hip_atomic_compare_exchange_strong(p, &expect, desired, __ATOMIC_RELAXED,
                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
-__device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+// compare-and-swap returning the previous value (== expect on success)
+__device__ __forceinline__ u64 cas_old(u64* p, u64 expect, u64 desired) {
+  __hip_atomic_compare_exchange_strong(p, &expect, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+  return expect;
+}
+__device__ __forceinline__ u64 xchg_relaxed(u64* p, u64 v) {
+  return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
-// All threads: make this workgroup's prior global stores visible at agent
-// scope, then meet at a barrier.  After it, thread 0 may release locks.
+// write the XCD's L2 back to memory and wait until it is done
+__device__ __forceinline__ void l2_writeback() {
+  asm volatile("s_waitcnt vmcnt(0)\n\tbuffer_wbl2 sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
+}
+// acquire side: after the lock atomic returned, drop stale L2 and L1 lines
+__device__ __forceinline__ void fence_acquire() {
+  asm volatile("s_waitcnt vmcnt(0)\n\tbuffer_inv sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
+}
+
+// All threads: make this workgroup's global stores visible at agent scope.
+// Afterwards thread 0 may release locks with relaxed atomic stores.
 __device__ __forceinline__ void publish() {
-  fence_release();
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
+  if (threadIdx.x == 0) l2_writeback();
 }
 
 __device__ __forceinline__ u64 now_ticks() { return wall_clock64(); }
@@ -191,6 +227,28 @@ __device__ __forceinline__ void store_node(u64* __restrict__ g, const u64* __res
     *reinterpret_cast<ulonglong2*>(g + i) = v;
   }
 }
+// A node's share per thread held in registers, so that several node loads
+// (and lock atomics) can be in flight before anything is written to LDS.
+template <int K, int T>
+struct NodeRegs {
+  static constexpr int C = (K / 2 + T - 1) / T;  // 16-byte chunks per thread
+  ulonglong2 v[C];
+  __device__ __forceinline__ void load(const u64* __restrict__ g) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int i = (threadIdx.x + c * T) * 2;
+      if (i < K) v[c] = *reinterpret_cast<const ulonglong2*>(g + i);
+    }
+  }
+  __device__ __forceinline__ void store(u64* __restrict__ lds) const {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int i = (threadIdx.x + c * T) * 2;
+      if (i < K) *reinterpret_cast<ulonglong2*>(lds + i) = v[c];
+    }
+  }
+};
+
 // n entries, any n, 8 bytes a lane
 template <int T>
 __device__ __forceinline__ void load_n(u64* __restrict__ lds, const u64* __restrict__ g, u32 n) {
@@ -207,10 +265,48 @@ __device__ __forceinline__ void copy_n(u64* __restrict__ dst, const u64* __restr
 
 // ---------------------------------------------------------------------------
 // Merge path (Green, McColl and Bader, "GPU merge path", cited in Sec. 4.2):
-// output positions [d, d+E) of the stable merge of sorted A[0,na) and
-// B[0,nb) (A first on ties), found by a binary search along the diagonal and
-// a short sequential merge.  Positions past na+nb yield ENT_MAX.
+// output positions [d, d+E) of the merge of sorted A[0,na) and B[0,nb) are
+// the E smallest entries of A[i, i+E) and B[j, j+E), where (i, j) is where
+// the merge path crosses diagonal d.  The crossing is found with a 4-ary
+// search (three independent LDS probes per round); the two E-entry windows
+// are read at once and merged in registers by a bitonic network.  Positions
+// past na+nb yield ENT_MAX.  Equal entries are indistinguishable, so the
+// result equals the stable merge.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ u64 umin64(u64 a, u64 b) { return a < b ? a : b; }
+__device__ __forceinline__ u64 umax64(u64 a, u64 b) { return a < b ? b : a; }
+
+// number of A entries among the first d outputs
+__device__ __forceinline__ int merge_path_split(const u64* A, int na, const u64* B, int nb, int d) {
+  int lo = d > nb ? d - nb : 0;
+  int hi = d < na ? d : na;
+  // p(x) = A[x] <= B[d-1-x] holds for x < answer and fails from it on
+  while (hi - lo > 3) {
+    const int q = (hi - lo) >> 2;
+    const int m1 = lo + q, m2 = lo + 2 * q, m3 = lo + 3 * q;
+    const bool t1 = A[m1] <= B[d - 1 - m1];
+    const bool t2 = A[m2] <= B[d - 1 - m2];
+    const bool t3 = A[m3] <= B[d - 1 - m3];
+    if (t3) {
+      lo = m3 + 1;
+    } else if (t2) {
+      lo = m2 + 1;
+      hi = m3;
+    } else if (t1) {
+      lo = m1 + 1;
+      hi = m2;
+    } else {
+      hi = m1;
+    }
+  }
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (A[mid] <= B[d - 1 - mid]) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
 template <int E>
 __device__ __forceinline__ void merge_path(const u64* A, int na, const u64* B, int nb, int d,
                                            u64 (&v)[E]) {
@@ -220,26 +316,27 @@ __device__ __forceinline__ void merge_path(const u64* A, int na, const u64* B, i
     for (int e = 0; e < E; ++e) v[e] = ENT_MAX;
     return;
   }
-  int lo = d > nb ? d - nb : 0;
-  int hi = d < na ? d : na;
-  while (lo < hi) {
-    int mid = (lo + hi) >> 1;
-    if (A[mid] <= B[d - 1 - mid]) lo = mid + 1;
-    else hi = mid;
-  }
-  int i = lo, j = d - lo;
-  u64 a = i < na ? A[i] : ENT_MAX;
-  u64 b = j < nb ? B[j] : ENT_MAX;
+  const int i = merge_path_split(A, na, B, nb, d);
+  const int j = d - i;
+  u64 a[E], b[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    if (a <= b) {
-      v[e] = a;
-      ++i;
-      a = i < na ? A[i] : ENT_MAX;
-    } else {
-      v[e] = b;
-      ++j;
-      b = j < nb ? B[j] : ENT_MAX;
+    a[e] = (i + e < na) ? A[i + e] : ENT_MAX;
+    b[e] = (j + e < nb) ? B[j + e] : ENT_MAX;
+  }
+  // a ascending and b descending form a bitonic sequence; its lower half
+  // (elementwise minima) holds the E smallest, still bitonic
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = umin64(a[e], b[E - 1 - e]);
+#pragma unroll
+  for (int st = E / 2; st >= 1; st >>= 1) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if ((e & st) == 0) {
+        const u64 x = v[e], y = v[e + st];
+        v[e] = umin64(x, y);
+        v[e + st] = umax64(x, y);
+      }
     }
   }
 }

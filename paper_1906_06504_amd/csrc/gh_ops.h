@@ -4,9 +4,10 @@
 //
 // Locking summary (Sec. 3.3.1 lock order, Sec. 3.3.2 states):
 //  * The root is taken with a ticket lock: an operation with ticket t waits
-//    until meta.serving == t and releases it by storing t + 1.  Root order is
-//    the linearization order (Theorem 1).  The partial buffer and the root
-//    metadata (m, s) are guarded by the root.
+//    until the heap's root word shows t and releases it by storing t + 1
+//    together with the new node count m and partial-buffer size s.  Root
+//    order is the linearization order (Theorem 1).  The partial buffer and
+//    (m, s) are guarded by the root.
 //  * Every other node has a lock word.  Locks are taken parent before child
 //    and a child is locked before its parent is released (hand-over-hand).
 //  * An insert that needs a new node reserves it at the root as
@@ -14,13 +15,20 @@
 //    still an in-flight insert's target marks it MARKED; the insert then
 //    leaves its batch in the target slot, sets HANDED and stops, and the
 //    deleteMin proceeds with those entries.
+//  * A deleteMin that took the last node's batch sets its word to REMOVED.
 //  * A deleteMin sifting down treats a child as absent when it does not
-//    exist in the deleteMin's own view of the heap size, when it is the
+//    exist in the deleteMin's own view of the heap size, when it is REMOVED
+//    (a later deleteMin moved its entries to the root), or when it is the
 //    reserved target of a LATER insert (that insert will pass the parent
-//    after this deleteMin), or when its first entry is ENT_MAX (a later
-//    deleteMin already moved its entries to the root).  A target of an
-//    EARLIER insert is waited for: that insert is past the parent and only
-//    has to store its batch.
+//    after this deleteMin).  A target of an EARLIER insert is waited for:
+//    that insert is past the parent and only has to store its batch.
+//
+// The critical section at the root is a chain of dependent memory round
+// trips.  Independent loads and lock atomics are issued together: node
+// payloads go to registers first, the first attempt at each lock is a single
+// compare-and-swap from AVAIL issued next to them, and only a failed attempt
+// falls back to a waiting loop.  No lock is ever waited for while a lock
+// taken later in the parent-to-child order is held.
 #pragma once
 
 #include "gh_device.h"
@@ -31,7 +39,7 @@ struct OpShared {
   u64 m, s;            // root metadata read at root acquire
   u64 t_claim;         // clock when the operation was claimed
   u64 t_root;          // clock at root acquire
-  u32 flag0, flag1;    // broadcast results from thread 0
+  u32 flag0, flag1;    // broadcast results from wave 0
   u32 ok;
   u32 op;
 };
@@ -46,116 +54,142 @@ struct OpResult {
 constexpr u32 F_FULL = 1, F_HANDOFF = 2, F_TOOK = 4, F_ROOT = 8, F_REFILL = 16, F_REJECT = 0x40,
               F_ABORT = 0x80;
 
-// --- thread-0 lock primitives (return false when the wait is abandoned) ---
+// --- lock primitives --------------------------------------------------------
 
-__device__ __forceinline__ bool root_acquire(HeapMeta* meta, u64 ticket, Ctl* ctl) {
+// Thread 0: wait until the root word shows our ticket; returns the word.
+__device__ __forceinline__ bool root_acquire(HeapMeta* meta, u64 ticket, Ctl* ctl, u64& word) {
+  const u64 mine = ticket & RW_TICKET_MASK;
   Waiter w;
   for (;;) {
-    u64 sv = ld_relaxed(&meta->serving);
-    if (sv == ticket) break;
-    u64 ahead = ticket - sv;  // operations still in front of us
+    const u64 v = ld_relaxed(&meta->root);
+    if (rw_ticket(v) == mine) {
+      word = v;
+      break;
+    }
+    const u64 ahead = (mine - rw_ticket(v)) & RW_TICKET_MASK;  // operations in front of us
     if (!w.step(ctl, ahead > 8 ? 16 : (ahead > 2 ? 4 : 1))) return false;
   }
   fence_acquire();
   return true;
 }
 
-// plain lock of a path node for an insert: AVAIL -> INUSE
-__device__ __forceinline__ bool lock_path(u64* lw, u64 ticket, Ctl* ctl) {
+// Thread 0: hand the root to the next ticket, publishing the new (m, s).
+// Node and partial-buffer stores were made visible by publish() before.
+__device__ __forceinline__ void release_root(HeapMeta* meta, u64 ticket, u64 m, u64 s) {
+  st_relaxed(&meta->root, rootword(ticket + 1, m, s));
+}
+
+// How a lane wants to take a lock word.
+enum LockMode : u32 {
+  LM_PATH = 0,    // insert path node: AVAIL -> INUSE
+  LM_CHILD = 2,   // deleteMin child: AVAIL -> INUSE, or absent (see above)
+  LM_PEEK = 3,    // read only: reports MARKED as 1, anything else as 0
+};
+
+// Classify an observed lock word for a deleteMin child: 1 = free (try the
+// swap), 0 = absent, -1 = wait.
+__device__ __forceinline__ int child_view(u64 v, u64 ticket) {
+  const u64 st = lw_state(v);
+  if (st == ST_AVAIL) return 1;
+  if (st == ST_REMOVED) return 0;
+  if (st != ST_INUSE && lw_ticket(v) > ticket) return 0;  // a later insert's target
+  return -1;
+}
+
+// One attempt: 1 = taken (or MARKED seen for LM_PEEK), 0 = absent / not
+// marked, -1 = try again later.
+__device__ __forceinline__ int try_lock(u64* lw, u32 mode, u64 ticket) {
+  const u64 v = ld_relaxed(lw);
+  const u64 st = lw_state(v);
+  if (mode == LM_PEEK) return st == ST_MARKED ? 1 : 0;
+  if (st == ST_AVAIL) return cas_relaxed(lw, v, lockword(ST_INUSE, ticket)) ? 1 : -1;
+  if (mode == LM_CHILD) return child_view(v, ticket) == 0 ? 0 : -1;
+  return -1;
+}
+
+// Executed by every lane of wave 0: each lane with `active` takes its own
+// word; the wave leaves when every active lane has an answer.  Returns false
+// (in every lane) when the wait is abandoned.  Ends with an acquire.
+__device__ __forceinline__ bool lock_lanes(u64* lw, u32 mode, u64 ticket, bool active, int& result,
+                                           Ctl* ctl) {
+  int r = active ? -1 : 0;
   Waiter w;
   for (;;) {
-    u64 v = ld_relaxed(lw);
-    if (lw_state(v) == ST_AVAIL && cas_relaxed(lw, v, lockword(ST_INUSE, ticket))) break;
+    if (r < 0) r = try_lock(lw, mode, ticket);
+    if (__all(r >= 0)) break;
     if (!w.step(ctl)) return false;
   }
   fence_acquire();
+  result = r;
   return true;
 }
 
-// reserve the new target: AVAIL -> TARGET(ticket)
-__device__ __forceinline__ bool lock_target(u64* lw, u64 ticket, Ctl* ctl) {
+// deleteMin taking the last node while holding the root (thread 0), after a
+// failed first swap that saw `v`: 1 = plain lock, 2 = took an in-flight
+// insert's batch (MARKED -> HANDED), -1 = abandoned.
+__device__ __forceinline__ int take_last(u64* lw, u64 v, u64 ticket, Ctl* ctl) {
   Waiter w;
   for (;;) {
-    u64 v = ld_relaxed(lw);
-    if (lw_state(v) == ST_AVAIL && cas_relaxed(lw, v, lockword(ST_TARGET, ticket))) return true;
-    if (!w.step(ctl)) return false;
-  }
-}
-
-// deleteMin locking a child: 1 = locked, 0 = absent, -1 = abandoned
-__device__ __forceinline__ int lock_child(u64* lw, u64 ticket, Ctl* ctl) {
-  Waiter w;
-  for (;;) {
-    u64 v = ld_relaxed(lw);
-    u64 st = lw_state(v);
+    const u64 st = lw_state(v);
     if (st == ST_AVAIL) {
-      if (cas_relaxed(lw, v, lockword(ST_INUSE, ticket))) {
-        fence_acquire();
-        return 1;
-      }
-      continue;
-    }
-    if (st != ST_INUSE && lw_ticket(v) > ticket) return 0;  // a later insert's target
-    if (!w.step(ctl)) return -1;
-  }
-}
-
-// deleteMin taking the last node while holding the root: 1 = plain lock,
-// 2 = took an in-flight insert's batch (MARKED -> HANDED), -1 = abandoned
-__device__ __forceinline__ int take_last(u64* lw, u64 ticket, Ctl* ctl) {
-  Waiter w;
-  for (;;) {
-    u64 v = ld_relaxed(lw);
-    u64 st = lw_state(v);
-    if (st == ST_AVAIL) {
-      if (cas_relaxed(lw, v, lockword(ST_INUSE, ticket))) {
-        fence_acquire();
-        return 1;
-      }
-      continue;
-    }
-    if (st == ST_TARGET) {
-      u64 owner = lw_ticket(v);
+      if (cas_relaxed(lw, v, lockword(ST_INUSE, ticket))) return 1;
+    } else if (st == ST_TARGET) {
+      const u64 owner = lw_ticket(v);
       if (cas_relaxed(lw, v, lockword(ST_MARKED, owner))) {
         Waiter w2;
         for (;;) {
-          u64 x = ld_relaxed(lw);
+          const u64 x = ld_relaxed(lw);
           if (x == lockword(ST_HANDED, owner)) break;
-          if (lw_state(x) == ST_AVAIL) break;  // cannot happen: the insert saw MARKED
           if (!w2.step(ctl)) return -1;
         }
-        st_release(lw, lockword(ST_INUSE, ticket));
-        fence_acquire();
         return 2;
       }
-      continue;
+    } else if (!w.step(ctl)) {
+      return -1;
     }
-    if (!w.step(ctl)) return -1;
+    v = ld_relaxed(lw);
   }
 }
 
-__device__ __forceinline__ void unlock(u64* lw) { st_release(lw, lockword(ST_AVAIL, 0)); }
+// Thread 0, after publish() (or when the holder stored nothing).
+__device__ __forceinline__ void unlock(u64* lw) { st_relaxed(lw, lockword(ST_AVAIL, 0)); }
 
 // An operation that may not change the heap (an insert of 0 entries, or a
 // malformed record) still passes the root in its turn, so the tickets after
 // it keep flowing.
-__device__ __forceinline__ OpResult op_pass_root(const HeapDesc& H, u64 ticket, OpShared& sh, Ctl* ctl) {
+__device__ __forceinline__ OpResult op_pass_root(const HeapDesc& H, u64 ticket, OpShared& sh,
+                                                 Ctl* ctl) {
   OpResult res{0, 0, 0, true};
   if (threadIdx.x == 0) {
-    sh.ok = root_acquire(H.meta, ticket, ctl) ? 1u : 0u;
+    u64 w = 0;
+    sh.ok = root_acquire(H.meta, ticket, ctl, w) ? 1u : 0u;
     sh.t_root = now_ticks();
-    sh.s = 0;
-    if (sh.ok) st_release(&H.meta->serving, ticket + 1);
+    sh.s = rw_s(w);
+    if (sh.ok) release_root(H.meta, ticket, rw_m(w), rw_s(w));
   }
   __syncthreads();
   res.ok = sh.ok != 0;
   return res;
 }
 
+// Thread 0 takes the root; everyone learns (m, s) from the root word.
+__device__ __forceinline__ bool acquire_root(const HeapDesc& H, u64 ticket, OpShared& sh,
+                                             Ctl* ctl) {
+  if (threadIdx.x == 0) {
+    u64 w = 0;
+    sh.ok = root_acquire(H.meta, ticket, ctl, w) ? 1u : 0u;
+    sh.t_root = now_ticks();
+    sh.m = rw_m(w);
+    sh.s = rw_s(w);
+  }
+  __syncthreads();
+  return sh.ok != 0;
+}
+
 // ---------------------------------------------------------------------------
 // INS (Sec. 3.2.2 top-down insert, Sec. 3.3.2 partial batches and
 // cooperation).  `keys` holds n (1..K) entries in global memory.
-// LDS: buf[0..4] of K entries each.
+// LDS: five buffers of K entries.
 // ---------------------------------------------------------------------------
 template <int K, int T>
 __device__ OpResult op_insert(const HeapDesc& H, u64 ticket, const u64* __restrict__ keys, u32 n,
@@ -165,9 +199,9 @@ __device__ OpResult op_insert(const HeapDesc& H, u64 ticket, const u64* __restri
   OpResult res{n, 0, 0, true};
   u64* b0 = lds;
   u64* b1 = lds + K;
-  u64* b2 = lds + 2 * K;
-  u64* b3 = lds + 3 * K;
-  u64* b4 = lds + 4 * K;
+  u64* P = lds + 2 * K;   // partial buffer
+  u64* F = lds + 3 * K;   // full batch / merged head
+  u64* N = lds + 4 * K;   // node being merged (root first)
   HeapMeta* meta = H.meta;
 
   // sort the batch before touching the heap (holds no lock)
@@ -175,87 +209,96 @@ __device__ OpResult op_insert(const HeapDesc& H, u64 ticket, const u64* __restri
   u64* xs = block_sort<K, T>(b0, b1, (int)n);
   u64* xfree = (xs == b0) ? b1 : b0;
 
-  if (tid == 0) {
-    sh.ok = root_acquire(meta, ticket, ctl) ? 1u : 0u;
-    sh.t_root = now_ticks();
-    if (sh.ok) {
-      sh.m = meta->m;
-      sh.s = meta->s;
-    }
-  }
-  __syncthreads();
-  if (!sh.ok) { res.ok = false; return res; }
+  if (!acquire_root(H, ticket, sh, ctl)) { res.ok = false; return res; }
   const u64 m = sh.m;
   const u32 s = (u32)sh.s;
   if (m >= 1) res.flags |= F_ROOT;
-  if (n + s >= (u32)K && m + 1 > H.max_nodes) {
+  const bool full = n + s >= (u32)K;
+  if (full && m + 1 > H.max_nodes) {
     // no room for another node: reject the insert, leave the heap unchanged
     if (tid == 0) {
       note_error(ctl, ERR_NOMEM);
-      st_release(&meta->serving, ticket + 1);
+      release_root(meta, ticket, m, s);
     }
     res.count = 0;
     res.flags |= F_REJECT;
     return res;
   }
-
-  // merged = merge(sorted input, partial buffer): first K -> b3, rest -> xfree
-  if (s > 0) load_n<T>(b2, H.pb, s);
-  __syncthreads();
-  const u32 tot = n + s;
-  merge_split<E, T>(xs, (int)n, b2, (int)s, K, Sink{b3}, Sink{xfree});
-  __syncthreads();
-
-  u64* root = H.nodes;  // position 1
-  if (tot <= (u32)(K - 1)) {
-    // the partial buffer keeps everything; restore Property 3 against the root
-    if (m >= 1) {
-      load_node<K, T>(b4, root);
-      __syncthreads();
-      if (b4[K - 1] <= b3[0]) {
-        store_n<T>(H.pb, b3, tot);
-      } else {
-        merge_split<E, T>(b4, K, b3, (int)tot, K, Sink{root}, Sink{H.pb});
-      }
-    } else {
-      store_n<T>(H.pb, b3, tot);
-    }
-    if (tid == 0) meta->s = tot;
-    publish();
-    if (tid == 0) st_release(&meta->serving, ticket + 1);
-    return res;
-  }
-
-  // a full batch F = b3 goes down from the root; the rest stays in the pb
-  res.flags |= F_FULL;
-  const u32 rest = tot - K;
-  store_n<T>(H.pb, xfree, rest);
   const u64 m2 = m + 1;
-  const u32 t = bitrev_pos((u32)m2);  // target node index
-  const int L = level_of(t);
-  if (tid == 0) {
-    meta->m = m2;
-    meta->s = rest;
-  }
-  if (L == 0) {
-    store_node<K, T>(root, b3);
-    publish();
-    if (tid == 0) st_release(&meta->serving, ticket + 1);
-    return res;
-  }
+  const u32 t = full ? bitrev_pos((u32)m2) : 0u;  // target node index
+  const int L = full ? level_of(t) : 0;
+  const u32 child1 = L >= 2 ? (t >> (L - 1)) : 0u;
   u64* tlock = H.locks + m2;
-  if (tid == 0) sh.ok = lock_target(tlock, ticket, ctl) ? 1u : 0u;
-  // root level: root keeps the K smallest of root + F
-  load_node<K, T>(b4, root);
+
+  // One round trip: partial buffer and root into registers, the target
+  // reserved, and a first try at the root's child on the insert path.  The
+  // target slot can only be AVAIL (never used) or REMOVED here: any in-flight
+  // insert's target lies at or below position m, and only the root holder
+  // reserves new ones.
+  {
+    NodeRegs<K, T> pr, rr;
+    pr.load(H.pb);
+    if (m >= 1) rr.load(H.nodes);
+    u64 old = 0;
+    if (tid == 0 && L >= 1) old = xchg_relaxed(tlock, lockword(ST_TARGET, ticket));
+    if (tid == 1 && L >= 2) old = cas_old(lock_ptr(H, child1), 0, lockword(ST_INUSE, ticket));
+    pr.store(P);
+    if (m >= 1) rr.store(N);
+    if (tid < 64) {
+      const bool bad = tid == 0 && L >= 1 && lw_state(old) != ST_AVAIL &&
+                       lw_state(old) != ST_REMOVED;
+      const bool need = tid == 1 && L >= 2 && old != 0;
+      int r = 0;
+      bool ok = true;
+      if (__any(need)) ok = lock_lanes(lock_ptr(H, child1), LM_PATH, ticket, need, r, ctl);
+      else if (L >= 2) fence_acquire();
+      const bool allok = __all(ok);
+      const bool anybad = __any(bad);
+      if (tid == 0) {
+        if (anybad) raise_error(ctl, ERR_STATE);
+        sh.ok = (allok && !anybad) ? 1u : 0u;
+      }
+    }
+  }
   __syncthreads();
   if (!sh.ok) { res.ok = false; return res; }
 
-  u64* F = b3;        // carry
-  u64* N = b4;        // node being merged
-  u64* spare0 = b0;   // free buffers
+  // merged = merge(sorted input, partial buffer): first K -> F, rest -> xfree
+  const u32 tot = n + s;
+  merge_split<E, T>(xs, (int)n, P, (int)s, K, Sink{F}, Sink{xfree});
+  __syncthreads();
+
+  u64* root = H.nodes;  // position 1
+  if (!full) {
+    // the partial buffer keeps everything; restore Property 3 against the root
+    if (m >= 1 && !(N[K - 1] <= F[0])) {
+      merge_split<E, T>(N, K, F, (int)tot, K, Sink{root}, Sink{H.pb});
+    } else {
+      store_n<T>(H.pb, F, tot);
+    }
+    publish();
+    if (tid == 0) release_root(meta, ticket, m, tot);
+    return res;
+  }
+
+  // a full batch F goes down from the root; the rest stays in the pb
+  res.flags |= F_FULL;
+  const u32 rest = tot - K;
+  store_n<T>(H.pb, xfree, rest);
+  if (L == 0) {
+    store_node<K, T>(root, F);
+    publish();
+    if (tid == 0) release_root(meta, ticket, m2, rest);
+    return res;
+  }
+
+  // LDS buffers in play: N (node), F (carry), spare (free; xfree is read by
+  // the pb store above and stays untouched)
+  u64* spare = xfree == b0 ? b1 : b0;
   u32 cur = 1;
   int level = 0;
   for (;;) {
+    const bool at_root = cur == 1;
     // (node, F) = MergeAndSort(node, F) with the shortcuts of Sec. 4.3
     u64* cur_ptr = node_ptr<K>(H, cur);
     if (N[K - 1] <= F[0]) {
@@ -264,58 +307,64 @@ __device__ OpResult op_insert(const HeapDesc& H, u64 ticket, const u64* __restri
       store_node<K, T>(cur_ptr, F);  // swap
       u64* x = F; F = N; N = x;
     } else {
-      merge_split<E, T>(N, K, F, K, K, Sink{cur_ptr}, Sink{spare0});
-      __syncthreads();
-      u64* x = F; F = spare0; spare0 = x;
+      merge_split<E, T>(N, K, F, K, K, Sink{cur_ptr}, Sink{spare});
+      u64* x = F; F = spare; spare = x;
     }
     ++level;
     const u32 child = t >> (L - level);
-    if (child == t) break;
-    // before moving on: was our target claimed by a deleteMin?  Otherwise
-    // lock the next path node (child before parent release).
-    if (tid == 0) {
-      u64 w = ld_relaxed(tlock);
-      if (lw_state(w) == ST_MARKED) {
-        sh.flag0 = 1;
-        sh.ok = 1;
-      } else {
-        sh.flag0 = 0;
-        sh.ok = lock_path(lock_ptr(H, child), ticket, ctl) ? 1u : 0u;
+    if (!at_root) {
+      // below the root: lane 0 looks whether a deleteMin claimed our target,
+      // lane 1 locks the next path node (child before parent release)
+      if (tid < 64) {
+        const bool next_is_path = child != t;
+        u64* w = (tid == 0) ? tlock : lock_ptr(H, child);
+        const u32 mode = (tid == 0) ? (u32)LM_PEEK : (u32)LM_PATH;
+        const bool active = tid == 0 || (tid == 1 && next_is_path);
+        int r = 0;
+        const bool ok = lock_lanes(w, mode, ticket, active, r, ctl);
+        const bool allok = __all(ok);
+        if (tid == 0) {
+          sh.flag0 = r == 1 ? 1u : 0u;   // MARKED seen
+          sh.ok = allok ? 1u : 0u;
+        }
       }
-    }
-    __syncthreads();
-    if (!sh.ok) { res.ok = false; return res; }
-    if (sh.flag0) {
-      // cooperation: leave the batch in the target slot for the deleteMin
-      store_node<K, T>(node_ptr<K>(H, t), F);
-      publish();
-      if (tid == 0) {
-        if (cur == 1) st_release(&meta->serving, ticket + 1);
-        else unlock(lock_ptr(H, cur));
-        st_release(tlock, lockword(ST_HANDED, ticket));
+      __syncthreads();
+      if (!sh.ok) { res.ok = false; return res; }
+      if (sh.flag0) {
+        // cooperation: leave the batch in the target slot for the deleteMin
+        store_node<K, T>(node_ptr<K>(H, t), F);
+        publish();
+        if (tid == 0) {
+          if (child != t) unlock(lock_ptr(H, child));
+          unlock(lock_ptr(H, cur));
+          st_relaxed(tlock, lockword(ST_HANDED, ticket));
+        }
+        res.levels = level;
+        res.flags |= F_HANDOFF;
+        return res;
       }
-      res.levels = level;
-      res.flags |= F_HANDOFF;
-      return res;
     }
     publish();
     if (tid == 0) {
-      if (cur == 1) st_release(&meta->serving, ticket + 1);
+      if (at_root) release_root(meta, ticket, m2, rest);
       else unlock(lock_ptr(H, cur));
     }
+    if (child == t) break;
     cur = child;
-    load_node<K, T>(N, node_ptr<K>(H, cur));
+    {
+      NodeRegs<K, T> nr;
+      nr.load(node_ptr<K>(H, cur));
+      nr.store(N);
+    }
     __syncthreads();
   }
-  // release the last path node, then fill the target
+  // fill the target
   store_node<K, T>(node_ptr<K>(H, t), F);
   publish();
   if (tid == 0) {
-    if (cur == 1) st_release(&meta->serving, ticket + 1);
-    else unlock(lock_ptr(H, cur));
     if (!cas_relaxed(tlock, lockword(ST_TARGET, ticket), lockword(ST_AVAIL, 0))) {
       // MARKED by a deleteMin: the batch is already in the target slot
-      st_release(tlock, lockword(ST_HANDED, ticket));
+      st_relaxed(tlock, lockword(ST_HANDED, ticket));
       sh.flag1 = 1;
     } else {
       sh.flag1 = 0;
@@ -324,7 +373,6 @@ __device__ OpResult op_insert(const HeapDesc& H, u64 ticket, const u64* __restri
   __syncthreads();
   if (sh.flag1) res.flags |= F_HANDOFF;
   res.levels = L;
-  (void)b2;
   return res;
 }
 
@@ -339,18 +387,10 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
   const int tid = threadIdx.x;
   OpResult res{0, 0, 0, true};
   HeapMeta* meta = H.meta;
-  u64* root = H.nodes;
+  u64* bufs[4] = {lds, lds + K, lds + 2 * K, lds + 3 * K};
+  u64* P = lds + 4 * K;
 
-  if (tid == 0) {
-    sh.ok = root_acquire(meta, ticket, ctl) ? 1u : 0u;
-    sh.t_root = now_ticks();
-    if (sh.ok) {
-      sh.m = meta->m;
-      sh.s = meta->s;
-    }
-  }
-  __syncthreads();
-  if (!sh.ok) { res.ok = false; return res; }
+  if (!acquire_root(H, ticket, sh, ctl)) { res.ok = false; return res; }
   const u64 m = sh.m;
   const u32 s = (u32)sh.s;
   if (m >= 1) res.flags |= F_ROOT;
@@ -358,35 +398,39 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
   if (m == 0) {
     // no node: the partial buffer is the whole heap
     copy_n<T>(out, H.pb, s);
-    if (tid == 0) meta->s = 0;
-    publish();
-    if (tid == 0) st_release(&meta->serving, ticket + 1);
+    __syncthreads();   // every read of the pb is done before the root moves on
+    if (tid == 0) release_root(meta, ticket, 0, 0);
     res.count = s;
     return res;
   }
   res.count = K;
-  for (int i = tid * 2; i < K; i += 2 * T) {
-    ulonglong2 v = *reinterpret_cast<const ulonglong2*>(root + i);
-    out[i] = v.x;
-    out[i + 1] = v.y;
-  }
-  if (m == 1) {
-    if (tid == 0) {
-      meta->m = 0;
-      root[0] = ENT_MAX;
-    }
-    publish();
-    if (tid == 0) st_release(&meta->serving, ticket + 1);
-    return res;
-  }
-
-  // refill the root from the last node (Sec. 3.2.1), MAX-marking that node
-  res.flags |= F_REFILL;
   const u64 m2 = m - 1;
   u64* llock = H.locks + m;
   u64* lastp = H.nodes + (m - 1) * (u64)K;
+
+  // Round trip 1: root and partial buffer into registers, first try at the
+  // last node's lock.
+  u64 old_last = 0;
+  {
+    NodeRegs<K, T> rr, pr;
+    rr.load(H.nodes);
+    if (m >= 2 && s > 0) pr.load(H.pb);
+    if (tid == 0 && m >= 2) old_last = cas_old(llock, 0, lockword(ST_INUSE, ticket));
+    rr.store(bufs[1]);
+    if (m >= 2 && s > 0) pr.store(P);
+  }
+  __syncthreads();
+  store_n<T>(out, bufs[1], K);   // the root batch is the answer
+  if (m == 1) {
+    if (tid == 0) release_root(meta, ticket, 0, s);
+    return res;
+  }
+
+  // refill the root from the last node (Sec. 3.2.1)
+  res.flags |= F_REFILL;
   if (tid == 0) {
-    int r = take_last(llock, ticket, ctl);
+    int r = old_last == 0 ? 1 : take_last(llock, old_last, ticket, ctl);
+    fence_acquire();
     sh.ok = r > 0 ? 1u : 0u;
     sh.flag0 = (r == 2) ? 1u : 0u;
   }
@@ -394,60 +438,104 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
   if (!sh.ok) { res.ok = false; return res; }
   if (sh.flag0) res.flags |= F_TOOK;
 
-  u64* bufs[4] = {lds, lds + K, lds + 2 * K, lds + 3 * K};
-  u64* P = lds + 4 * K;
-  u64* C = bufs[0];
-  load_node<K, T>(C, lastp);
-  if (s > 0) load_n<T>(P, H.pb, s);
-  __syncthreads();
-  // Release the last node before locking any child of the root: an earlier
-  // deleteMin may be waiting for it while holding a node on our way down.
-  if (tid == 0) lastp[0] = ENT_MAX;
-  publish();
-  if (tid == 0) {
-    unlock(llock);
-    meta->m = m2;
+  // Round trip 2: the last node into registers, first tries at the root's
+  // children (a failed try does not wait while the last node is held).
+  const bool el1 = node_exists(2, m2), er1 = node_exists(3, m2);
+  u64 oc = 0;
+  {
+    NodeRegs<K, T> lr;
+    lr.load(lastp);
+    if (tid == 1 && el1) oc = cas_old(lock_ptr(H, 2), 0, lockword(ST_INUSE, ticket));
+    if (tid == 2 && er1) oc = cas_old(lock_ptr(H, 3), 0, lockword(ST_INUSE, ticket));
+    lr.store(bufs[0]);
   }
-  if (s > 0) {
-    // Property 3 again: the refilled root keeps the K smallest of root + pb
-    if (!(C[K - 1] <= P[0])) {
-      merge_split<E, T>(C, K, P, (int)s, K, Sink{bufs[1]}, Sink{H.pb});
+  __syncthreads();
+  // The batch is in LDS: mark the node REMOVED right away (nothing was
+  // stored, so no fence).
+  if (tid == 0)
+    st_relaxed(llock, lockword(ST_REMOVED, ticket));
+  // finish the children's locks if the first tries did not settle them
+  if (tid < 64) {
+    const bool mine = (tid == 1 && el1) || (tid == 2 && er1);
+    int got = 0;
+    bool need = false;
+    if (mine) {
+      if (oc == 0) got = 1;
+      else if (child_view(oc, ticket) == 0) got = 0;
+      else need = true;
+    }
+    bool ok = true;
+    if (__any(need)) {
+      int r2 = 0;
+      u64* w = tid == 1 ? lock_ptr(H, 2) : lock_ptr(H, 3);
+      ok = lock_lanes(w, LM_CHILD, ticket, need, r2, ctl);
+      if (need) got = r2;
+    } else if (__any(got == 1)) {
+      fence_acquire();
+    }
+    const bool allok = __all(ok);
+    if (tid == 0) sh.ok = allok ? 1u : 0u;
+    if (tid == 1) sh.flag0 = got > 0 ? 1u : 0u;
+    if (tid == 2) sh.flag1 = got > 0 ? 1u : 0u;
+  }
+  __syncthreads();
+  if (!sh.ok) { res.ok = false; return res; }
+
+  u64* C = bufs[0];
+  // Round trip 3: the children, loaded while cur merges with the partial
+  // buffer (Property 3 again: the refilled root keeps the K smallest).
+  bool hl = sh.flag0, hr = sh.flag1;
+  {
+    NodeRegs<K, T> lc, rc;
+    if (hl) lc.load(H.nodes + 1 * (u64)K);   // node 2 is position 2
+    if (hr) rc.load(node_ptr<K>(H, 3));
+    if (s > 0 && !(C[K - 1] <= P[0])) {
+      merge_split<E, T>(C, K, P, (int)s, K, Sink{bufs[3]}, Sink{H.pb});
       __syncthreads();
-      u64* x = bufs[0]; bufs[0] = bufs[1]; bufs[1] = x;
+      u64* x = bufs[0]; bufs[0] = bufs[3]; bufs[3] = x;
       C = bufs[0];
     }
+    if (hl) lc.store(bufs[1]);
+    if (hr) rc.store(bufs[2]);
   }
+  __syncthreads();
 
-  // sift down
+  // sift down; the root level's children are already locked and loaded
   u32 c = 1;
+  bool loaded = true;
   for (;;) {
     const u64 l = 2ull * c, r = l + 1;
-    const bool el = node_exists(l, m2), er = node_exists(r, m2);
-    if (tid == 0) {
-      int pl = 0, pr = 0;
-      bool ok = true;
-      if (el) {
-        pl = lock_child(lock_ptr(H, (u32)l), ticket, ctl);
-        ok = pl >= 0;
-      }
-      if (ok && er) {
-        pr = lock_child(lock_ptr(H, (u32)r), ticket, ctl);
-        ok = pr >= 0;
-      }
-      sh.ok = ok ? 1u : 0u;
-      sh.flag0 = pl > 0 ? 1u : 0u;
-      sh.flag1 = pr > 0 ? 1u : 0u;
-    }
-    __syncthreads();
-    if (!sh.ok) { res.ok = false; return res; }
-    const bool pl = sh.flag0, pr = sh.flag1;
     u64* Lb = bufs[1];
     u64* Rb = bufs[2];
-    if (pl) load_node<K, T>(Lb, node_ptr<K>(H, (u32)l));
-    if (pr) load_node<K, T>(Rb, node_ptr<K>(H, (u32)r));
-    __syncthreads();
-    const bool hl = pl && Lb[0] != ENT_MAX;
-    const bool hr = pr && Rb[0] != ENT_MAX;
+    if (!loaded) {
+      const bool el = node_exists(l, m2), er = node_exists(r, m2);
+      if (tid < 64) {
+        u64* w = (tid == 0) ? (el ? lock_ptr(H, (u32)l) : nullptr)
+                            : (er ? lock_ptr(H, (u32)r) : nullptr);
+        const bool active = (tid == 0 && el) || (tid == 1 && er);
+        int got = 0;
+        const bool ok = lock_lanes(w, LM_CHILD, ticket, active, got, ctl);
+        const bool allok = __all(ok);
+        if (tid == 0) {
+          sh.flag0 = got > 0 ? 1u : 0u;
+          sh.ok = allok ? 1u : 0u;
+        }
+        if (tid == 1) sh.flag1 = got > 0 ? 1u : 0u;
+      }
+      __syncthreads();
+      if (!sh.ok) { res.ok = false; return res; }
+      hl = sh.flag0;
+      hr = sh.flag1;
+      {
+        NodeRegs<K, T> lc, rc;
+        if (hl) lc.load(node_ptr<K>(H, (u32)l));
+        if (hr) rc.load(node_ptr<K>(H, (u32)r));
+        if (hl) lc.store(Lb);
+        if (hr) rc.store(Rb);
+      }
+      __syncthreads();
+    }
+    loaded = false;
     const u64 lmin = hl ? Lb[0] : ENT_MAX;
     const u64 rmin = hr ? Rb[0] : ENT_MAX;
     const u64 cmin = lmin < rmin ? lmin : rmin;
@@ -458,9 +546,9 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
       store_node<K, T>(cptr, C);
       publish();
       if (tid == 0) {
-        if (pl) unlock(lock_ptr(H, (u32)l));
-        if (pr) unlock(lock_ptr(H, (u32)r));
-        if (c == 1) st_release(&meta->serving, ticket + 1);
+        if (hl) unlock(lock_ptr(H, (u32)l));
+        if (hr) unlock(lock_ptr(H, (u32)r));
+        if (c == 1) release_root(meta, ticket, m2, s);
         else unlock(lock_ptr(H, c));
       }
       return res;
@@ -470,8 +558,8 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
     u64* newcur;
     if (hl && hr) {
       // (hi, lo) = MergeAndSort(l, r); lo stays in the child whose max was
-      // larger, hi merges with cur; cur's k smallest stay here
-      // (on a tie of the maxima the right child counts as larger)
+      // larger (on a tie the right child counts as larger), hi merges with
+      // cur; cur's k smallest stay here
       const bool big_is_l = Lb[K - 1] > Rb[K - 1];
       const u32 big = big_is_l ? (u32)l : (u32)r;
       const u32 small = big_is_l ? (u32)r : (u32)l;
@@ -499,7 +587,7 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
       publish();
       if (tid == 0) {
         unlock(lock_ptr(H, big));
-        if (c == 1) st_release(&meta->serving, ticket + 1);
+        if (c == 1) release_root(meta, ticket, m2, s);
         else unlock(lock_ptr(H, c));
       }
       next = small;
@@ -518,10 +606,7 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
       }
       publish();
       if (tid == 0) {
-        // a child that was locked but found MAX-marked is released here
-        if (pl && !hl) unlock(lock_ptr(H, (u32)l));
-        if (pr && !hr) unlock(lock_ptr(H, (u32)r));
-        if (c == 1) st_release(&meta->serving, ticket + 1);
+        if (c == 1) release_root(meta, ticket, m2, s);
         else unlock(lock_ptr(H, c));
       }
       next = x;

@@ -30,8 +30,12 @@ __global__ void k_init_ctl(Ctl* ctl, u64 timeout_ticks) {
 // count, the claim counter restarts, and the start clock is taken.
 __global__ void k_prep(const HeapDesc* __restrict__ descs, u32 nheaps, Ctl* ctl) {
   for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < nheaps; i += gridDim.x * blockDim.x) {
+    // the root word keeps the low 24 bits of the next ticket; a submission
+    // runs fewer than 2^24 operations, so the full ticket is recovered from
+    // the previous base
     HeapMeta* m = descs[i].meta;
-    m->base = m->serving;
+    const u64 b = m->base;
+    m->base = b + ((rw_ticket(m->root) - b) & RW_TICKET_MASK);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctl->next_op = 0;

@@ -73,7 +73,7 @@ bool make_layout(u32 k, u32 nheaps, const u64* max_keys, u64 each, Layout& L) {
   for (u32 i = 0; i < nheaps; ++i) {
     u64 mk = max_keys ? max_keys[i] : each;
     u64 mn = max_nodes_for(mk, k);
-    if (mn >= 0x7FFFFFFFull) return false;
+    if (mn >= RW_M_MASK) return false;
     L.max_nodes[i] = mn;
     L.meta_off[i] = off;
     off = align_up(off + sizeof(HeapMeta));
@@ -133,6 +133,7 @@ u64 watchdog_ticks(u32 clock_mhz) {
 int run_ops(gh_heap* h, const gh_op* d_ops, u32 nops, const OpParams& p, const u64* d_in,
             u64* d_out, u32* d_counts, gh_logrec* d_log, const gh_tuning* t) {
   if (nops == 0) return GH_OK;
+  if (nops > RW_TICKET_MASK) return GH_EINVAL;   // tickets of one submission fit 24 bits
   u32 threads = (t && t->threads) ? t->threads : default_threads(h->k);
   if (!heap_supported_shape(h->k, threads)) return GH_EINVAL;
   u32 wg = (t && t->workgroups) ? t->workgroups : 256;
@@ -321,10 +322,11 @@ int heap_size(gh_heap_t h, uint32_t i, uint64_t* out_host) {
   if (!h || !out_host || i >= h->nheaps) return GH_EINVAL;
   int rc = refresh_status(h);
   if (rc == GH_EDEVICE) return rc;
-  u64 ms[2];
+  u64 w = 0;
   const HeapDesc& d = h->host_descs[i];
-  if (hipMemcpy(ms, &d.meta->m, sizeof(ms), hipMemcpyDeviceToHost) != hipSuccess) return GH_EDEVICE;
-  *out_host = ms[0] * h->k + ms[1];
+  if (hipMemcpy(&w, &d.meta->root, sizeof(w), hipMemcpyDeviceToHost) != hipSuccess)
+    return GH_EDEVICE;
+  *out_host = rw_m(w) * h->k + rw_s(w);
   if (i == 0 && rc == GH_OK) {
     h->size0 = *out_host;
     h->size0_known = true;
@@ -339,16 +341,17 @@ int heap_read_state(gh_heap_t h, uint32_t i, uint64_t* meta_host, uint64_t* node
   const HeapDesc& d = h->host_descs[i];
   HeapMeta m;
   if (hipMemcpy(&m, d.meta, sizeof(m), hipMemcpyDeviceToHost) != hipSuccess) return GH_EDEVICE;
-  meta_host[0] = m.m;
-  meta_host[1] = m.s;
-  meta_host[2] = m.serving;
+  const u64 mm = rw_m(m.root), ss = rw_s(m.root);
+  meta_host[0] = mm;
+  meta_host[1] = ss;
+  meta_host[2] = m.base + ((rw_ticket(m.root) - m.base) & RW_TICKET_MASK);
   meta_host[3] = d.max_nodes;
   if (nodes_host &&
       hipMemcpy(nodes_host, d.nodes, (u64)d.max_nodes * h->k * 8, hipMemcpyDeviceToHost) !=
           hipSuccess)
     return GH_EDEVICE;
-  if (pb_host && m.s > 0 &&
-      hipMemcpy(pb_host, d.pb, m.s * 8, hipMemcpyDeviceToHost) != hipSuccess)
+  if (pb_host && ss > 0 &&
+      hipMemcpy(pb_host, d.pb, ss * 8, hipMemcpyDeviceToHost) != hipSuccess)
     return GH_EDEVICE;
   return GH_OK;
 }
