@@ -111,6 +111,30 @@ typedef struct gh_logrec {
     uint32_t t_done;
 } gh_logrec;
 
+/* Per-request record written by heap_serve (32 bytes, device memory).
+ *   first_ticket  root ticket of the request's first operation on its heap
+ *   count         deleteMin: entries returned; insert: entries inserted
+ *                 (0 if rejected)
+ *   nops          operations the request was split into (ceil(n / k) for
+ *                 an insert, 1 for a deleteMin)
+ *   kind          GH_OP_INSERT or GH_OP_DELETE_MIN
+ *   flags         bit 0: admitted; bit 1: an insert waited for heap memory;
+ *                 bit 6: rejected (larger than the heap's capacity, never
+ *                 fitted before the stream ended, or a malformed record)
+ *   t_admit, t_done  device wall clock in ticks after the start of the
+ *                 serving launch: admission, and completion of the last
+ *                 operation (32-bit) */
+typedef struct gh_reqrec {
+    uint64_t first_ticket;
+    uint32_t count;
+    uint16_t nops;
+    uint8_t kind;
+    uint8_t flags;
+    uint32_t t_admit;
+    uint32_t t_done;
+    uint64_t reserved;
+} gh_reqrec;
+
 /* Launch shape of a submission: workgroups = number of operations in flight
  * (0 = library default), threads = workgroup size (0 = library default; must
  * be one of the shapes heap_supported_shape accepts for k). */
@@ -178,6 +202,30 @@ int heap_submit_graph(gh_heap_t h, const gh_op *d_ops, uint32_t nops,
                       gh_logrec *d_log, const gh_tuning *tuning, void **graph_out);
 int heap_graph_launch(gh_heap_t h, void *graph);
 int heap_graph_destroy(void *graph);
+
+/* Bytes of device workspace heap_serve needs for nreq requests that expand
+ * into at most max_ops operations on a set of nheaps heaps. */
+uint64_t heap_serve_workspace_bytes(uint32_t nheaps, uint32_t nreq, uint64_t max_ops);
+
+/* Serve a request stream with a device-resident loop (one persistent
+ * launch).  d_reqs (device, nreq gh_op records, non-decreasing arrival_ns;
+ * `seq` is ignored) are requests: an insert of any n >= 0 entries from
+ * d_in + off, or a deleteMin writing up to k entries to d_out + off.
+ * Workgroup 0 admits requests in arrival order once their arrival time has
+ * passed: a deleteMin always, an insert when the heap's size after all
+ * admitted requests plus n stays within the heap's max_keys; otherwise the
+ * insert waits (per heap, first in first out) until admitted deleteMins make
+ * room.  Each heap's admitted requests take the root in admission order, so
+ * a heap's results do not depend on the other heaps in the stream.  Admitted
+ * requests become operations of at most k entries that the other
+ * workgroups (the slots, tuning->workgroups of them) run as in heap_submit.
+ * d_recs (device, nreq records) receives one gh_reqrec per request.
+ * d_work is a caller-owned device workspace of heap_serve_workspace_bytes.
+ * Errors: GH_EINVAL (bad sizes, max_ops too small is reported as a sticky
+ * GH_ENOMEM and the requests that did not fit are rejected). */
+int heap_serve(gh_heap_t h, const gh_op *d_reqs, uint32_t nreq, const uint64_t *d_in,
+               uint64_t *d_out, gh_reqrec *d_recs, void *d_work, uint64_t work_bytes,
+               uint64_t max_ops, const gh_tuning *tuning);
 
 /* Wait for the set's stream; return the sticky device error (GH_OK if none). */
 int heap_sync(gh_heap_t h);

@@ -50,7 +50,8 @@ struct alignas(64) HeapDesc {
   HeapMeta* meta;
   u32 max_nodes;
   u32 k;
-  u64 pad[2];
+  u64 max_keys;       // capacity in entries (the served form admits by it)
+  u64 pad;
 };
 static_assert(sizeof(HeapDesc) == 64, "desc layout");
 
@@ -265,48 +266,13 @@ __device__ __forceinline__ void copy_n(u64* __restrict__ dst, const u64* __restr
 
 // ---------------------------------------------------------------------------
 // Merge path (Green, McColl and Bader, "GPU merge path", cited in Sec. 4.2):
-// output positions [d, d+E) of the merge of sorted A[0,na) and B[0,nb) are
-// the E smallest entries of A[i, i+E) and B[j, j+E), where (i, j) is where
-// the merge path crosses diagonal d.  The crossing is found with a 4-ary
-// search (three independent LDS probes per round); the two E-entry windows
-// are read at once and merged in registers by a bitonic network.  Positions
-// past na+nb yield ENT_MAX.  Equal entries are indistinguishable, so the
-// result equals the stable merge.
+// output positions [d, d+E) of the stable merge of sorted A[0,na) and
+// B[0,nb) (A first on ties), found by a binary search along the diagonal and
+// a short sequential merge.  Positions past na+nb yield ENT_MAX.  (A 4-ary
+// search with a register-window merge measured slower on gfx950: the merge
+// is bound by dependent LDS latency, and the extra probes cost more than the
+// rounds they save.)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ u64 umin64(u64 a, u64 b) { return a < b ? a : b; }
-__device__ __forceinline__ u64 umax64(u64 a, u64 b) { return a < b ? b : a; }
-
-// number of A entries among the first d outputs
-__device__ __forceinline__ int merge_path_split(const u64* A, int na, const u64* B, int nb, int d) {
-  int lo = d > nb ? d - nb : 0;
-  int hi = d < na ? d : na;
-  // p(x) = A[x] <= B[d-1-x] holds for x < answer and fails from it on
-  while (hi - lo > 3) {
-    const int q = (hi - lo) >> 2;
-    const int m1 = lo + q, m2 = lo + 2 * q, m3 = lo + 3 * q;
-    const bool t1 = A[m1] <= B[d - 1 - m1];
-    const bool t2 = A[m2] <= B[d - 1 - m2];
-    const bool t3 = A[m3] <= B[d - 1 - m3];
-    if (t3) {
-      lo = m3 + 1;
-    } else if (t2) {
-      lo = m2 + 1;
-      hi = m3;
-    } else if (t1) {
-      lo = m1 + 1;
-      hi = m2;
-    } else {
-      hi = m1;
-    }
-  }
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (A[mid] <= B[d - 1 - mid]) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
-}
-
 template <int E>
 __device__ __forceinline__ void merge_path(const u64* A, int na, const u64* B, int nb, int d,
                                            u64 (&v)[E]) {
@@ -316,27 +282,26 @@ __device__ __forceinline__ void merge_path(const u64* A, int na, const u64* B, i
     for (int e = 0; e < E; ++e) v[e] = ENT_MAX;
     return;
   }
-  const int i = merge_path_split(A, na, B, nb, d);
-  const int j = d - i;
-  u64 a[E], b[E];
+  int lo = d > nb ? d - nb : 0;
+  int hi = d < na ? d : na;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (A[mid] <= B[d - 1 - mid]) lo = mid + 1;
+    else hi = mid;
+  }
+  int i = lo, j = d - lo;
+  u64 a = i < na ? A[i] : ENT_MAX;
+  u64 b = j < nb ? B[j] : ENT_MAX;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    a[e] = (i + e < na) ? A[i + e] : ENT_MAX;
-    b[e] = (j + e < nb) ? B[j + e] : ENT_MAX;
-  }
-  // a ascending and b descending form a bitonic sequence; its lower half
-  // (elementwise minima) holds the E smallest, still bitonic
-#pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = umin64(a[e], b[E - 1 - e]);
-#pragma unroll
-  for (int st = E / 2; st >= 1; st >>= 1) {
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      if ((e & st) == 0) {
-        const u64 x = v[e], y = v[e + st];
-        v[e] = umin64(x, y);
-        v[e + st] = umax64(x, y);
-      }
+    if (a <= b) {
+      v[e] = a;
+      ++i;
+      a = i < na ? A[i] : ENT_MAX;
+    } else {
+      v[e] = b;
+      ++j;
+      b = j < nb ? B[j] : ENT_MAX;
     }
   }
 }

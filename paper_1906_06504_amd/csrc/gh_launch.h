@@ -43,4 +43,52 @@ constexpr bool shape_ok(int K, int T) {
 template <int K>
 hipError_t launch_ops_k(const LaunchArgs& a);
 
+// ---------------------------------------------------------------------------
+// Served form: device workspace layout
+// ---------------------------------------------------------------------------
+struct alignas(256) ServeHead {
+  u32 claim;      // next queue slot a worker takes
+  u32 pad0[31];
+  u32 tail;       // queue slots the scheduler has published
+  u32 done;       // the scheduler has admitted or rejected every request
+  u32 pad1[30];
+};
+struct HeapSched {  // scheduler-private, one per heap
+  u64 size;       // entries after every admitted request
+  u32 seq;        // next operation rank on this heap
+  u32 head;       // first deferred insert (request id), or NONE
+  u32 last;       // last deferred insert
+  u32 pad;
+};
+constexpr u32 SCHED_NONE = 0xFFFFFFFFu;
+
+struct ServeWork {
+  ServeHead* head;
+  HeapSched* heaps;
+  u32* next;      // per request: next deferred insert of the same heap
+  u32* left;      // per request: operations not finished yet
+  gh_op* queue;   // admitted operations, in admission order
+  u32* qreq;      // request of each queued operation
+  u64 max_ops;
+};
+
+struct ServeArgs {
+  const HeapDesc* descs;
+  u32 nheaps;
+  const gh_op* reqs;
+  u32 nreq;
+  const u64* in;
+  u64* out;
+  gh_reqrec* recs;
+  ServeWork w;
+  Ctl* ctl;
+  u32 clock_mhz;
+  u32 workgroups;   // worker slots (the scheduler is one more workgroup)
+  u32 threads;
+  hipStream_t stream;
+};
+
+template <int K>
+hipError_t launch_serve_k(const ServeArgs& a);
+
 }  // namespace gh

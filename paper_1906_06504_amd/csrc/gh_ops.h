@@ -35,6 +35,22 @@
 
 namespace gh {
 
+// Phase timestamps for profiling the root critical section: compiled in only
+// when GH_PHASE_TRACE is defined (never in the library build); slot s of
+// operation i goes to gh_phase_trace[i * 8 + s].
+#ifdef GH_PHASE_TRACE
+__device__ uint32_t gh_phase_trace[1 << 22];
+#define GH_TRACE(slot)                                                                 \
+  do {                                                                                 \
+    if (threadIdx.x == 0 && sh.op < (1u << 19))                                        \
+      gh_phase_trace[sh.op * 8 + (slot)] = (uint32_t)wall_clock64();                   \
+  } while (0)
+#else
+#define GH_TRACE(slot) \
+  do {                 \
+  } while (0)
+#endif
+
 struct OpShared {
   u64 m, s;            // root metadata read at root acquire
   u64 t_claim;         // clock when the operation was claimed
@@ -183,6 +199,7 @@ __device__ __forceinline__ bool acquire_root(const HeapDesc& H, u64 ticket, OpSh
     sh.s = rw_s(w);
   }
   __syncthreads();
+  GH_TRACE(0);
   return sh.ok != 0;
 }
 
@@ -261,12 +278,14 @@ __device__ OpResult op_insert(const HeapDesc& H, u64 ticket, const u64* __restri
     }
   }
   __syncthreads();
+  GH_TRACE(1);
   if (!sh.ok) { res.ok = false; return res; }
 
   // merged = merge(sorted input, partial buffer): first K -> F, rest -> xfree
   const u32 tot = n + s;
   merge_split<E, T>(xs, (int)n, P, (int)s, K, Sink{F}, Sink{xfree});
   __syncthreads();
+  GH_TRACE(2);
 
   u64* root = H.nodes;  // position 1
   if (!full) {
@@ -311,6 +330,7 @@ __device__ OpResult op_insert(const HeapDesc& H, u64 ticket, const u64* __restri
       u64* x = F; F = spare; spare = x;
     }
     ++level;
+    if (at_root) GH_TRACE(3);
     const u32 child = t >> (L - level);
     if (!at_root) {
       // below the root: lane 0 looks whether a deleteMin claimed our target,
@@ -345,6 +365,7 @@ __device__ OpResult op_insert(const HeapDesc& H, u64 ticket, const u64* __restri
       }
     }
     publish();
+    if (at_root) GH_TRACE(4);
     if (tid == 0) {
       if (at_root) release_root(meta, ticket, m2, rest);
       else unlock(lock_ptr(H, cur));
@@ -420,6 +441,7 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
     if (m >= 2 && s > 0) pr.store(P);
   }
   __syncthreads();
+  GH_TRACE(1);
   store_n<T>(out, bufs[1], K);   // the root batch is the answer
   if (m == 1) {
     if (tid == 0) release_root(meta, ticket, 0, s);
@@ -435,6 +457,7 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
     sh.flag0 = (r == 2) ? 1u : 0u;
   }
   __syncthreads();
+  GH_TRACE(2);
   if (!sh.ok) { res.ok = false; return res; }
   if (sh.flag0) res.flags |= F_TOOK;
 
@@ -450,6 +473,7 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
     lr.store(bufs[0]);
   }
   __syncthreads();
+  GH_TRACE(3);
   // The batch is in LDS: mark the node REMOVED right away (nothing was
   // stored, so no fence).
   if (tid == 0)
@@ -479,6 +503,7 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
     if (tid == 2) sh.flag1 = got > 0 ? 1u : 0u;
   }
   __syncthreads();
+  GH_TRACE(4);
   if (!sh.ok) { res.ok = false; return res; }
 
   u64* C = bufs[0];
@@ -499,6 +524,7 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
     if (hr) rc.store(bufs[2]);
   }
   __syncthreads();
+  GH_TRACE(5);
 
   // sift down; the root level's children are already locked and loaded
   u32 c = 1;
@@ -584,7 +610,9 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
         __syncthreads();
         newcur = freeb;
       }
+      if (c == 1) GH_TRACE(6);
       publish();
+      if (c == 1) GH_TRACE(7);
       if (tid == 0) {
         unlock(lock_ptr(H, big));
         if (c == 1) release_root(meta, ticket, m2, s);

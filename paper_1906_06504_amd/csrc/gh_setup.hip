@@ -43,6 +43,17 @@ __global__ void k_prep(const HeapDesc* __restrict__ descs, u32 nheaps, Ctl* ctl)
   }
 }
 
+// Before a serving launch: empty queue, no claims, scheduler not done.
+__global__ void k_serve_reset(ServeHead* head) {
+  u32* w = reinterpret_cast<u32*>(head);
+  for (u32 i = threadIdx.x; i < sizeof(ServeHead) / 4; i += blockDim.x) w[i] = 0;
+}
+
+hipError_t launch_serve_reset(ServeHead* head, hipStream_t st) {
+  hipLaunchKernelGGL(k_serve_reset, dim3(1), dim3(64), 0, st, head);
+  return hipGetLastError();
+}
+
 hipError_t launch_init(HeapDesc* descs_dev, const HeapDesc* descs_host, u32 nheaps, Ctl* ctl,
                        u64 timeout_ticks, hipStream_t st) {
   hipError_t e = hipMemcpyAsync(descs_dev, descs_host, sizeof(HeapDesc) * nheaps,

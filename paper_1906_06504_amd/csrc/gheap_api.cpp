@@ -16,6 +16,7 @@ namespace gh {
 hipError_t launch_init(HeapDesc* descs_dev, const HeapDesc* descs_host, u32 nheaps, Ctl* ctl,
                        u64 timeout_ticks, hipStream_t st);
 hipError_t launch_prep(const HeapDesc* descs, u32 nheaps, Ctl* ctl, hipStream_t st);
+hipError_t launch_serve_reset(ServeHead* head, hipStream_t st);
 }  // namespace gh
 
 struct gh_heap {
@@ -96,6 +97,41 @@ int from_status(u32 st) {
     case ERR_TIMEOUT: return GH_ETIMEDOUT;
     default: return GH_ESTATE;
   }
+}
+
+hipError_t launch_serve(const gh_heap* h, const ServeArgs& a) {
+  switch (h->k) {
+    case 32: return launch_serve_k<32>(a);
+    case 64: return launch_serve_k<64>(a);
+    case 128: return launch_serve_k<128>(a);
+    case 256: return launch_serve_k<256>(a);
+    case 512: return launch_serve_k<512>(a);
+    case 1024: return launch_serve_k<1024>(a);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+struct ServeLayout {
+  u64 head, heaps, next, left, queue, qreq, total;
+};
+
+ServeLayout serve_layout(u32 nheaps, u32 nreq, u64 max_ops) {
+  ServeLayout L;
+  u64 off = 0;
+  L.head = off;
+  off = align_up(off + sizeof(ServeHead));
+  L.heaps = off;
+  off = align_up(off + (u64)nheaps * sizeof(HeapSched));
+  L.next = off;
+  off = align_up(off + (u64)nreq * 4);
+  L.left = off;
+  off = align_up(off + (u64)nreq * 4);
+  L.queue = off;
+  off = align_up(off + max_ops * sizeof(gh_op));
+  L.qreq = off;
+  off = align_up(off + max_ops * 4);
+  L.total = off;
+  return L;
 }
 
 hipError_t launch_ops(const gh_heap* h, const LaunchArgs& a) {
@@ -216,6 +252,7 @@ int heap_create_many(gh_heap_t* out, uint32_t k, uint32_t nheaps, const uint64_t
     d.nodes = reinterpret_cast<u64*>(h->arena + L.node_off[i]);
     d.max_nodes = (u32)L.max_nodes[i];
     d.k = k;
+    d.max_keys = max_keys[i];
   }
   if (launch_init(h->descs, h->host_descs.data(), nheaps, h->ctl, watchdog_ticks(h->clock_mhz),
                   h->stream) != hipSuccess) {
@@ -311,6 +348,51 @@ int heap_graph_destroy(void* graph) {
   if (!graph) return GH_EINVAL;
   return hipGraphExecDestroy(reinterpret_cast<hipGraphExec_t>(graph)) == hipSuccess ? GH_OK
                                                                                      : GH_EDEVICE;
+}
+
+uint64_t heap_serve_workspace_bytes(uint32_t nheaps, uint32_t nreq, uint64_t max_ops) {
+  return serve_layout(nheaps, nreq, max_ops).total;
+}
+
+int heap_serve(gh_heap_t h, const gh_op* d_reqs, uint32_t nreq, const uint64_t* d_in,
+               uint64_t* d_out, gh_reqrec* d_recs, void* d_work, uint64_t work_bytes,
+               uint64_t max_ops, const gh_tuning* t) {
+  if (!h) return GH_EINVAL;
+  if (h->sticky != GH_OK) return h->sticky;
+  if (nreq == 0) return GH_OK;
+  if (!d_reqs || !d_recs || !d_work || max_ops == 0 || max_ops > RW_TICKET_MASK) return GH_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(d_work) & (ALIGN - 1)) != 0) return GH_EINVAL;
+  const ServeLayout L = serve_layout(h->nheaps, nreq, max_ops);
+  if (work_bytes < L.total) return GH_ENOMEM;
+  u32 threads = (t && t->threads) ? t->threads : default_threads(h->k);
+  if (!heap_supported_shape(h->k, threads)) return GH_EINVAL;
+  u32 wg = (t && t->workgroups) ? t->workgroups : 512;
+  h->size0_known = false;
+  unsigned char* base = reinterpret_cast<unsigned char*>(d_work);
+  ServeArgs a;
+  a.descs = h->descs;
+  a.nheaps = h->nheaps;
+  a.reqs = d_reqs;
+  a.nreq = nreq;
+  a.in = d_in;
+  a.out = d_out;
+  a.recs = d_recs;
+  a.w.head = reinterpret_cast<ServeHead*>(base + L.head);
+  a.w.heaps = reinterpret_cast<HeapSched*>(base + L.heaps);
+  a.w.next = reinterpret_cast<u32*>(base + L.next);
+  a.w.left = reinterpret_cast<u32*>(base + L.left);
+  a.w.queue = reinterpret_cast<gh_op*>(base + L.queue);
+  a.w.qreq = reinterpret_cast<u32*>(base + L.qreq);
+  a.w.max_ops = max_ops;
+  a.ctl = h->ctl;
+  a.clock_mhz = h->clock_mhz;
+  a.workgroups = wg;
+  a.threads = threads;
+  a.stream = h->stream;
+  if (launch_prep(h->descs, h->nheaps, h->ctl, h->stream) != hipSuccess) return GH_EDEVICE;
+  if (launch_serve_reset(a.w.head, h->stream) != hipSuccess) return GH_EDEVICE;
+  if (launch_serve(h, a) != hipSuccess) return GH_EDEVICE;
+  return GH_OK;
 }
 
 int heap_sync(gh_heap_t h) {

@@ -34,7 +34,13 @@ OP_DTYPE = np.dtype([("heap", "<u4"), ("kind", "<u4"), ("n", "<u4"), ("seq", "<u
 LOG_DTYPE = np.dtype([("ticket", "<u8"), ("count", "<u4"), ("levels", "<u2"), ("kind", "u1"),
                       ("flags", "u1"), ("pb", "<u2"), ("reserved", "<u2"), ("t_claim", "<u4"),
                       ("t_root", "<u4"), ("t_done", "<u4")])
-assert OP_DTYPE.itemsize == 32 and LOG_DTYPE.itemsize == 32
+REQ_DTYPE = np.dtype([("first_ticket", "<u8"), ("count", "<u4"), ("nops", "<u2"), ("kind", "u1"),
+                      ("flags", "u1"), ("t_admit", "<u4"), ("t_done", "<u4"), ("reserved", "<u8")])
+assert OP_DTYPE.itemsize == 32 and LOG_DTYPE.itemsize == 32 and REQ_DTYPE.itemsize == 32
+
+REQ_ADMITTED = 1
+REQ_DEFERRED = 2
+REQ_REJECTED = 0x40
 
 FLAG_FULL = 1
 FLAG_HANDOFF = 2
@@ -47,7 +53,8 @@ FLAG_ABORTED = 0x80
 EXPORTS = ("heap_arena_bytes", "heap_supported_shape", "heap_create", "heap_create_many",
            "heap_insert", "heap_delete_min", "heap_submit", "heap_submit_graph",
            "heap_graph_launch", "heap_graph_destroy", "heap_sync", "heap_size",
-           "heap_read_state", "heap_destroy", "heap_strerror", "heap_clock_hz")
+           "heap_read_state", "heap_destroy", "heap_strerror", "heap_clock_hz",
+           "heap_serve_workspace_bytes", "heap_serve")
 
 
 class GHeapError(RuntimeError):
@@ -90,6 +97,8 @@ def load_library(path: str = LIB_PATH):
         "heap_destroy": (i32, [vp]),
         "heap_strerror": (ctypes.c_char_p, [i32]),
         "heap_clock_hz": (u64, []),
+        "heap_serve_workspace_bytes": (u64, [u32, u32, u64]),
+        "heap_serve": (i32, [vp, vp, u32, vp, vp, vp, vp, u64, u64, ctypes.POINTER(_Tuning)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -205,6 +214,20 @@ class HeapSet:
     def graph_launch(self, g: int) -> None:
         _check(self.lib.heap_graph_launch(self.h, ctypes.c_void_p(g)), "heap_graph_launch")
 
+    def serve(self, reqs: torch.Tensor, nreq: int, d_in: torch.Tensor | None,
+              d_out: torch.Tensor | None, recs: torch.Tensor, max_ops: int,
+              work: torch.Tensor | None = None, workgroups: int = 0, threads: int = 0):
+        """Run a request stream through the device-resident serving loop.
+        Returns the workspace tensor (reusable for the next call)."""
+        need = int(self.lib.heap_serve_workspace_bytes(self.nheaps, nreq, max_ops))
+        if work is None or work.numel() < need:
+            work = torch.empty(need, dtype=torch.uint8, device=self.device)
+        t = _Tuning(workgroups, threads)
+        rc = self.lib.heap_serve(self.h, _ptr(reqs), nreq, _ptr(d_in), _ptr(d_out), _ptr(recs),
+                                 work.data_ptr(), work.numel(), max_ops, ctypes.byref(t))
+        _check(rc, "heap_serve")
+        return work
+
     def sync(self) -> int:
         return int(self.lib.heap_sync(self.h))
 
@@ -274,3 +297,29 @@ def new_log(nops: int, device="cuda") -> torch.Tensor:
 
 def log_to_host(log: torch.Tensor, nops: int) -> np.ndarray:
     return log.cpu().numpy().view(LOG_DTYPE)[:nops].copy()
+
+
+def requests_to_device(oplist, device="cuda"):
+    """Pack a request stream (workloads.OpList with heap ids and arrivals)
+    into gh_op records on the device.  Returns (reqs, nreq, keys, out, recs,
+    max_ops) where max_ops bounds the operations the stream can expand to."""
+    n = len(oplist)
+    rec = np.zeros(n, dtype=OP_DTYPE)
+    rec["heap"] = oplist.heap_ids()
+    rec["kind"] = oplist.kind
+    rec["n"] = oplist.n
+    rec["off"] = oplist.off
+    if oplist.arrival is not None:
+        rec["arrival_ns"] = oplist.arrival
+    k = int(oplist.meta.get("k", 1))
+    ins = oplist.kind == OP_INSERT
+    max_ops = int(np.sum(-(-oplist.n[ins].astype(np.int64) // k))) + int((~ins).sum())
+    reqs = torch.from_numpy(rec.view(np.uint8).copy()).to(device)
+    keys = to_device_u64(oplist.keys if oplist.keys.size else np.zeros(1, np.uint64), device)
+    out = torch.full((max(oplist.out_entries, 1),), -1, dtype=torch.int64, device=device)
+    recs = torch.zeros(max(n, 1) * REQ_DTYPE.itemsize, dtype=torch.uint8, device=device)
+    return reqs, n, keys, out, recs, max(max_ops, 1)
+
+
+def recs_to_host(recs: torch.Tensor, nreq: int) -> np.ndarray:
+    return recs.cpu().numpy().view(REQ_DTYPE)[:nreq].copy()

@@ -216,3 +216,101 @@ def config2(prefill: int = 1 << 22, requested: int = 1 << 24, k: int = 1024):
     pre = prefill_ops(prefill, k, CONFIG_SEED[2])
     mix = mixed_ops(requested, k, CONFIG_SEED[2] + 1, first_id=prefill)
     return pre, mix, k
+
+
+def _interleave(lists, st: Stream):
+    """Random interleave of per-heap op lists (each keeps its order)."""
+    counts = np.array([len(l) for l in lists], dtype=np.int64)
+    owner = np.repeat(np.arange(len(lists)), counts)
+    perm = np.argsort(st.u64(owner.size), kind="stable")
+    owner = owner[perm]
+    # stable per owner: j-th occurrence of heap h takes op j of list h
+    order = np.argsort(owner, kind="stable")
+    rank = np.empty(owner.size, dtype=np.int64)
+    starts = np.r_[0, np.cumsum(counts)[:-1]]
+    rank[order] = np.arange(owner.size) - np.repeat(starts, counts)
+    return owner, rank
+
+
+def multi_heap(lists, k: int, st: Stream) -> OpList:
+    """One op list over several heaps: a random interleave of `lists` (each an
+    OpList for one heap, offsets into its own buffers)."""
+    owner, rank = _interleave(lists, st)
+    key_base = np.r_[0, np.cumsum([l.keys.size for l in lists])[:-1]].astype(np.uint64)
+    out_base = np.r_[0, np.cumsum([l.out_entries for l in lists])[:-1]].astype(np.uint64)
+    kind = np.empty(owner.size, dtype=np.uint8)
+    n = np.empty(owner.size, dtype=np.uint32)
+    off = np.empty(owner.size, dtype=np.uint64)
+    for h, l in enumerate(lists):
+        sel = owner == h
+        r = rank[sel]
+        kind[sel] = l.kind[r]
+        n[sel] = l.n[r]
+        off[sel] = np.where(l.kind[r] == OP_INSERT, l.off[r] + key_base[h], l.off[r] + out_base[h])
+    keys = np.concatenate([l.keys for l in lists]) if lists else np.zeros(0, np.uint64)
+    out = OpList(kind, n, off, keys, int(sum(l.out_entries for l in lists)),
+                 heap=owner.astype(np.uint32))
+    out.meta["k"] = k
+    return out
+
+
+def batched_mixed(nheaps: int, k: int, prefill_each: int, requested_each: int, seed: int):
+    """nheaps independent heaps, each prefilled with `prefill_each` keys and
+    then given a 50/50 insert U[1,k] / deleteMin(k) mix requesting
+    `requested_each` keys; returns (prefill list, mixed list), both over all
+    heaps (ids unique across heaps)."""
+    st = Stream(seed)
+    pres, mixes = [], []
+    next_id = 0
+    for h in range(nheaps):
+        p = prefill_ops(prefill_each, k, seed + 101 * (h + 1), first_id=next_id)
+        next_id += prefill_each
+        m = mixed_ops(requested_each, k, seed + 101 * (h + 1) + 7, first_id=next_id)
+        next_id += int(m.n.sum())
+        pres.append(p)
+        mixes.append(m)
+    return multi_heap(pres, k, st), multi_heap(mixes, k, st), pres, mixes
+
+
+def served_stream(nheaps: int, k: int, nreq: int, seed: int, rate_per_s: float | None = None,
+                  min_log2: int = 10, max_log2: int = 22, ins_frac: float = 0.6,
+                  max_ins_log2: int = 12):
+    """Request stream for the served form.
+
+    Heap h is prefilled with floor(2^(min_log2 + (max_log2-min_log2) u)) keys
+    (log-uniform).  Each request picks a heap uniformly; it is an insert of
+    floor(2^(max_ins_log2 u)) fresh keys (log-uniform on [1, 2^max_ins_log2])
+    with probability ins_frac, else a deleteMin(k).  Arrivals are a Poisson
+    process of rate `rate_per_s` (exponential gaps; None = all at time 0).
+    Returns (prefill list over all heaps, request list, prefill sizes)."""
+    st = Stream(seed)
+    u = st.unit(nheaps)
+    sizes = np.floor(2.0 ** (min_log2 + (max_log2 - min_log2) * u)).astype(np.int64)
+    pre_lists = []
+    next_id = 0
+    for h in range(nheaps):
+        pre_lists.append(prefill_ops(int(sizes[h]), k, seed + 7 * (h + 1), first_id=next_id))
+        next_id += int(sizes[h])
+    pre = multi_heap(pre_lists, k, st)
+    heap = np.minimum((st.unit(nreq) * nheaps).astype(np.int64), nheaps - 1)
+    is_ins = st.unit(nreq) < ins_frac
+    n_ins = np.floor(2.0 ** (max_ins_log2 * st.unit(nreq))).astype(np.int64)
+    kinds = np.where(is_ins, OP_INSERT, OP_DELETE_MIN).astype(np.uint8)
+    sizes_req = np.where(is_ins, n_ins, 0)
+    if rate_per_s is None:
+        arrival = np.zeros(nreq, dtype=np.uint64)
+    else:
+        gaps = -np.log1p(-st.unit(nreq)) / rate_per_s * 1e9
+        arrival = np.floor(np.cumsum(gaps)).astype(np.uint64)
+    key_stream = Stream(seed ^ 0x77777777)
+    reqs = build_oplist(kinds, sizes_req, _keys_with_ids(key_stream, next_id), k,
+                        heap=heap.astype(np.uint32), arrival=arrival)
+    reqs.meta["k"] = k
+    pre.meta["k"] = k
+    return pre, reqs, sizes
+
+
+def served_capacity(prefill_sizes: np.ndarray) -> np.ndarray:
+    """Memory budget (entries) per heap for the served form: the prefill plus
+    a quarter of it plus 4096."""
+    return (np.ceil(1.25 * prefill_sizes) + 4096).astype(np.int64)
