@@ -38,7 +38,15 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain device copy of known size (for counter scaling)")
-    ap.add_argument("--json-extra", action="store_true", help="print extra diagnostics")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-form leg")
+    ap.add_argument("--no-served", action="store_true", help="skip the served-form leg")
+    ap.add_argument("--batched-heaps", type=int, default=64)
+    ap.add_argument("--served-heaps", type=int, default=256)
+    ap.add_argument("--served-requests", type=int, default=1 << 20)
+    ap.add_argument("--served-max-log2", type=int, default=22)
+    ap.add_argument("--served-slots", type=int, default=1024)
+    ap.add_argument("--served-budget", type=int, default=1 << 20,
+                    help="memory budget per heap beyond its prefill (entries)")
     return ap.parse_args()
 
 
@@ -160,6 +168,11 @@ def main():
         "wall_s_timed_steps": wall,
     }
 
+    if not args.no_batched:
+        result["batched"] = run_batched(args, wg_default=wg, th=th, plain_value=value)
+    if not args.no_served:
+        result["served"] = run_served(args)
+
     if args.calib_copy:
         n = 1 << 25  # 256 MiB of int64
         a = torch.empty(n, dtype=torch.int64, device="cuda").fill_(1)
@@ -189,6 +202,219 @@ def main():
         log("cpu baseline: %.3g keys/s" % (omoved / dt))
 
     print(json.dumps(result), flush=True)
+
+
+def _timed_submit(hs, d, workgroups, threads, log=None):
+    import torch
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(hs.stream)
+    hs.submit(d[0], d[1], d[2], d[3], d[4], log, workgroups=workgroups, threads=threads)
+    ev1.record(hs.stream)
+    rc = hs.sync()
+    torch.cuda.synchronize()
+    if rc != 0:
+        raise SystemExit("submission failed: %d" % rc)
+    return ev0.elapsed_time(ev1)
+
+
+def run_batched(args, wg_default, th, plain_value):
+    """The same total work as the plain workload (prefill 2^22, 2^24 keys
+    requested, k = 1024) spread over H independent heaps: one persistent
+    launch for all heaps (batched form, also replayed as a HIP graph) against
+    one launch per heap (plain form)."""
+    import torch
+    from paper_1906_06504_amd import gheap as G
+    from paper_1906_06504_amd import metrics as M
+    from paper_1906_06504_amd import workloads as W
+    k = 1024
+    H = args.batched_heaps
+    pre_each = args.prefill // H
+    req_each = args.requested // H
+    log("batched leg: %d heaps, prefill %d and %d requested each" % (H, pre_each, req_each))
+    pre, mix, pres, mixes = W.batched_mixed(H, k, pre_each, req_each, seed=0x5EED0002)
+    cap = pre_each + int(max(int(m.n.sum()) for m in mixes)) + k
+    hs = G.HeapSet(k, [cap] * H, stream=torch.cuda.Stream())
+    res = {}
+    with torch.cuda.stream(hs.stream):
+        dpre = G.ops_to_device(pre)
+        _timed_submit(hs, dpre, 256, th)
+        snap = hs.arena.clone()
+        dmix = G.ops_to_device(mix)
+        nops = dmix[1]
+        dlog = G.new_log(nops)
+        wgb = min(4 * H, 1024)
+        times = []
+        for i in range(args.warmup + args.steps):
+            hs.arena.copy_(snap)
+            torch.cuda.synchronize()
+            t = _timed_submit(hs, dmix, wgb, th, dlog)
+            if i >= args.warmup:
+                times.append(t)
+        lg = G.log_to_host(dlog, nops)
+        moved = M.keys_moved(lg)
+        ms = float(np.mean(times))
+        alg = int(M.algorithmic_bytes(lg, k).sum())
+        # graph replays of the same launch
+        g = hs.submit_graph(dmix[0], nops, dmix[2], dmix[3], dmix[4], dlog, workgroups=wgb,
+                            threads=th)
+        gt = []
+        for i in range(args.steps):
+            hs.arena.copy_(snap)
+            torch.cuda.synchronize()
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record(hs.stream)
+            hs.graph_launch(g)
+            ev1.record(hs.stream)
+            assert hs.sync() == 0
+            torch.cuda.synchronize()
+            gt.append(ev0.elapsed_time(ev1))
+        # plain form: every heap in its own launch, one after the other
+        hs.arena.copy_(snap)
+        torch.cuda.synchronize()
+        plain_ms = 0.0
+        plain_moved = 0
+        for h in range(H):
+            one = G.HeapSet(k, [cap], stream=hs.stream)
+            dp = G.ops_to_device(pres[h])
+            _timed_submit(one, dp, 64, th)
+            dm = G.ops_to_device(mixes[h])
+            l1 = G.new_log(dm[1])
+            plain_ms += _timed_submit(one, dm, 64, th, l1)
+            plain_moved += M.keys_moved(G.log_to_host(l1, dm[1]))
+            one.close()
+    value = moved / (ms / 1e3)
+    res = {
+        "workload": "%d heaps, k=1024, each prefilled with %d keys then a 50/50 mix of insert "
+                    "U[1,1024] and deleteMin(1024) until %d keys requested" % (H, pre_each, req_each),
+        "ops": nops, "workgroups": wgb, "threads": th,
+        "value": value, "unit": "keys/s", "ms_per_step": ms,
+        "graph_ms_per_step": float(np.mean(gt)),
+        "plain_one_heap_per_launch_keys_per_s": plain_moved / (plain_ms / 1e3),
+        "vs_plain_per_launch": value / (plain_moved / (plain_ms / 1e3)),
+        "vs_plain_single_heap_headline": value / plain_value,
+        "roofline": {"bound": "hbm", "achieved": alg / (ms / 1e3) / 1e9, "peak": M.HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": alg / (ms / 1e3) / 1e9 / M.HBM_PEAK_GBS},
+    }
+    log("batched: %.3g keys/s (%.2f ms), plain per-heap launches %.3g keys/s"
+        % (value, ms, res["plain_one_heap_per_launch_keys_per_s"]))
+    hs.close()
+    return res
+
+
+def run_served(args):
+    """Served form: H heaps (k = 256) prefilled log-uniform on
+    [2^10, 2^max], a stream of requests (60% inserts of log-uniform [1, 4096]
+    keys, 40% deleteMin(256), uniform heap), admitted on the device by heap
+    memory.  Saturated run (all requests present at the start) gives the
+    capacity; Poisson streams at 0.5x and 0.9x of it give latency."""
+    import torch
+    from paper_1906_06504_amd import gheap as G
+    from paper_1906_06504_amd import workloads as W
+    k = 256
+    H = args.served_heaps
+    R = args.served_requests
+    log("served leg: %d heaps, %d requests" % (H, R))
+    pre, reqs, sizes = W.served_stream(H, k, R, seed=0x5EED0005, rate_per_s=None,
+                                       max_log2=args.served_max_log2)
+    caps = W.served_capacity(sizes, extra=args.served_budget)
+    hz = G.clock_hz()
+    hs = G.HeapSet(k, caps, stream=torch.cuda.Stream())
+    out = {"workload": "%d heaps, k=256, prefill log-uniform [2^10, 2^%d] (%d keys), %d requests: "
+                       "60%% insert of log-uniform [1,4096] keys, 40%% deleteMin(256); budget per "
+                       "heap prefill + %d entries" % (H, args.served_max_log2, int(sizes.sum()), R,
+                                                   args.served_budget),
+           "slots": args.served_slots}
+    with torch.cuda.stream(hs.stream):
+        dpre = G.ops_to_device(pre)
+        _timed_submit(hs, dpre, 1024, 0)
+        snap = hs.arena.clone()
+        work = None
+
+        def serve_once(stream_reqs):
+            nonlocal work
+            hs.arena.copy_(snap)
+            torch.cuda.synchronize()
+            r, nreq, keys, outb, recs, max_ops = G.requests_to_device(stream_reqs)
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record(hs.stream)
+            work = hs.serve(r, nreq, keys, outb, recs, max_ops, work=work,
+                            workgroups=args.served_slots)
+            ev1.record(hs.stream)
+            rc = hs.sync()
+            torch.cuda.synchronize()
+            if rc != 0:
+                raise SystemExit("serving failed: %d" % rc)
+            return ev0.elapsed_time(ev1), G.recs_to_host(recs, nreq)
+
+        def summarize(ms, recs, stream_reqs):
+            adm = (recs["flags"] & G.REQ_ADMITTED) != 0
+            keys = int(recs["count"][adm].astype(np.int64).sum())
+            arr_ticks = stream_reqs.arrival.astype(np.float64) * hz / 1e9
+            lat_us = (recs["t_done"][adm].astype(np.float64) - arr_ticks[adm]) * 1e6 / hz
+            return {"ms": ms, "keys_per_s": keys / (ms / 1e3),
+                    "requests_per_s": int(adm.sum()) / (ms / 1e3),
+                    "admitted": int(adm.sum()),
+                    "deferred_for_memory": int(((recs["flags"] & G.REQ_DEFERRED) != 0).sum()),
+                    "rejected": int(((recs["flags"] & G.REQ_REJECTED) != 0).sum()),
+                    "latency_us": {"p50": float(np.percentile(lat_us, 50)),
+                                   "p99": float(np.percentile(lat_us, 99))}}
+
+        serve_once(reqs)  # warmup
+        ms, recs = serve_once(reqs)
+        sat = summarize(ms, recs, reqs)
+        out["saturated"] = sat
+        log("served saturated: %.3g keys/s, %.3g req/s" % (sat["keys_per_s"], sat["requests_per_s"]))
+        lam_sat = sat["requests_per_s"]
+        sat_recs = recs
+        import copy
+        for frac in (0.5, 0.9):
+            rate = frac * lam_sat
+            rq = copy.copy(reqs)
+            rq.arrival = W.poisson_arrivals(R, rate, seed=0x5EED0005 + int(frac * 10))
+            ms, recs = serve_once(rq)
+            res = summarize(ms, recs, rq)
+            res["offered_requests_per_s"] = rate
+            out["poisson_%.1fx" % frac] = res
+            log("served at %.1fx: p50 %.1f us p99 %.1f us" % (frac, res["latency_us"]["p50"],
+                                                             res["latency_us"]["p99"]))
+        # plain comparison: a sample of heaps, each heap's admitted requests
+        # as its own launch (same operations, same order)
+        hs.arena.copy_(snap)
+        torch.cuda.synchronize()
+        sample = list(range(0, H, max(1, H // 16)))
+        plain_ms, plain_keys = 0.0, 0
+        for h in sample:
+            sel = np.flatnonzero((reqs.heap == h) & ((sat_recs["flags"] & G.REQ_ADMITTED) != 0))
+            sel = sel[np.argsort(sat_recs["first_ticket"][sel], kind="stable")]
+            kinds, ns, offs = [], [], []
+            for i in sel:
+                if reqs.kind[i] == W.OP_INSERT:
+                    n = int(reqs.n[i])
+                    for c in range(0, n, k):
+                        kinds.append(0)
+                        ns.append(min(k, n - c))
+                        offs.append(int(reqs.off[i]) + c)
+                else:
+                    kinds.append(1)
+                    ns.append(0)
+                    offs.append(int(reqs.off[i]))
+            if not kinds:
+                continue
+            ol = W.OpList(np.array(kinds, np.uint8), np.array(ns, np.uint32),
+                          np.array(offs, np.uint64), reqs.keys, reqs.out_entries,
+                          heap=np.full(len(kinds), h, np.uint32))
+            d = G.ops_to_device(ol)
+            lg = G.new_log(d[1])
+            plain_ms += _timed_submit(hs, d, 64, 0, lg)
+            from paper_1906_06504_amd import metrics as M
+            plain_keys += M.keys_moved(G.log_to_host(lg, d[1]))
+        out["plain_one_heap_per_launch_keys_per_s"] = plain_keys / (plain_ms / 1e3)
+        out["vs_plain_per_launch"] = sat["keys_per_s"] / out["plain_one_heap_per_launch_keys_per_s"]
+    hs.close()
+    return out
 
 
 if __name__ == "__main__":

@@ -221,6 +221,8 @@ uint64_t heap_serve_workspace_bytes(uint32_t nheaps, uint32_t nreq, uint64_t max
  * workgroups (the slots, tuning->workgroups of them) run as in heap_submit.
  * d_recs (device, nreq records) receives one gh_reqrec per request.
  * d_work is a caller-owned device workspace of heap_serve_workspace_bytes.
+ * The scheduler keeps 32 bytes per heap in LDS: nheaps * 32 + k * 40 must
+ * stay below 64 KiB (1024 heaps at k = 256; 256 heaps at k = 1024).
  * Errors: GH_EINVAL (bad sizes, max_ops too small is reported as a sticky
  * GH_ENOMEM and the requests that did not fit are rejected). */
 int heap_serve(gh_heap_t h, const gh_op *d_reqs, uint32_t nreq, const uint64_t *d_in,

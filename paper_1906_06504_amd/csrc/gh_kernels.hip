@@ -118,26 +118,36 @@ __global__ __launch_bounds__(T) void k_ops(const HeapDesc* __restrict__ descs,
 // order depends only on its own requests, so its results are the same alone
 // and in any mix.
 // ---------------------------------------------------------------------------
+// Scheduler's per-heap state, kept in LDS (dynamic shared memory sized by the
+// number of heaps) so that admitting a request touches no global memory on
+// its critical path.
+struct SchedHot {
+  u64 size;   // entries after every admitted request
+  u64 cap;    // memory budget (the heap's max_keys)
+  u64 base;   // ticket of the first operation of this launch
+  u32 seq;    // next operation rank on this heap
+  u32 head;   // first deferred insert (request id), or SCHED_NONE
+};
+static_assert(sizeof(SchedHot) == 32, "sched layout");
+extern __shared__ __align__(16) unsigned char gh_dyn_lds[];
+
 template <int K>
 struct Scheduler {
-  const HeapDesc* descs;
   u32 nheaps;
   const gh_op* reqs;
   gh_reqrec* recs;
   ServeWork w;
-  Ctl* ctl;
+  SchedHot* hot;
   u64 t0;
   u32 tail;       // queue slots written
   u32 published;  // queue slots published
   bool overflow;
 
   __device__ void put_op(u32 r, u32 heap, u32 kind, u32 n, u32 seq, u64 off) {
-    gh_op* q = w.queue + tail;
-    u64* qw = reinterpret_cast<u64*>(q);
+    u64* qw = reinterpret_cast<u64*>(w.queue + tail);
     st_relaxed(qw + 0, (u64)heap | ((u64)kind << 32));
     st_relaxed(qw + 1, (u64)n | ((u64)seq << 32));
     st_relaxed(qw + 2, off);
-    st_relaxed(qw + 3, 0);
     __hip_atomic_store(w.qreq + tail, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     ++tail;
   }
@@ -149,30 +159,47 @@ struct Scheduler {
     published = tail;
   }
 
+  __device__ void write_rec(u32 r, const gh_reqrec& rec) {
+    const u64* src = reinterpret_cast<const u64*>(&rec);
+    u64* dst = reinterpret_cast<u64*>(recs + r);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) st_relaxed(dst + i, src[i]);
+  }
+
+  __device__ void reject(u32 r, u32 kind) {
+    gh_reqrec rec;
+    rec.first_ticket = 0;
+    rec.count = 0;
+    rec.nops = 0;
+    rec.kind = (uint8_t)kind;
+    rec.flags = 0x40;
+    rec.t_admit = (u32)(now_ticks() - t0);
+    rec.t_done = rec.t_admit;
+    rec.reserved = 0;
+    write_rec(r, rec);
+  }
+
   // Admit request r: its operations get the heap's next tickets.  A request
   // that no longer fits the operation queue is rejected instead (its heap's
   // tickets and size are left as they were).
-  __device__ void admit(u32 r, const gh_op& q, HeapSched& hs, u32 flags) {
-    const u32 need = q.kind == GH_OP_DELETE_MIN ? 1u : (q.n + K - 1) / K;
-    if ((u64)tail + need > w.max_ops) {
+  __device__ void admit(u32 r, const gh_op& q, SchedHot& hs, u32 flags) {
+    const u32 nops = q.kind == GH_OP_DELETE_MIN ? 1u : (q.n + K - 1) / K;
+    if ((u64)tail + nops > w.max_ops) {
       overflow = true;
-      reject(r, q);
+      reject(r, q.kind);
       return;
     }
-    const u64 base = descs[q.heap].meta->base;
     gh_reqrec rec;
-    rec.first_ticket = base + hs.seq;
+    rec.first_ticket = hs.base + hs.seq;
+    rec.count = q.kind == GH_OP_DELETE_MIN ? 0u : q.n;
+    rec.nops = (uint16_t)nops;
     rec.kind = (uint8_t)q.kind;
     rec.flags = (uint8_t)(flags | 1u);
     rec.t_admit = (u32)(now_ticks() - t0);
     rec.t_done = rec.t_admit;
     rec.reserved = 0;
-    u32 nops;
-    nops = q.kind == GH_OP_DELETE_MIN ? 1u : (q.n + K - 1) / K;
-    rec.count = q.kind == GH_OP_DELETE_MIN ? 0u : q.n;
-    rec.nops = (uint16_t)nops;
     // slots write count and t_done of this record: every word goes out
-    // coherently, and is complete before the queue entries are published
+    // coherently and is complete before the queue entries are published
     write_rec(r, rec);
     __hip_atomic_store(w.left + r, nops, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (q.kind == GH_OP_DELETE_MIN) {
@@ -185,26 +212,6 @@ struct Scheduler {
       }
       hs.size += q.n;
     }
-  }
-
-  __device__ void write_rec(u32 r, const gh_reqrec& rec) {
-    const u64* src = reinterpret_cast<const u64*>(&rec);
-    u64* dst = reinterpret_cast<u64*>(recs + r);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) st_relaxed(dst + i, src[i]);
-  }
-
-  __device__ void reject(u32 r, const gh_op& q) {
-    gh_reqrec rec;
-    rec.first_ticket = 0;
-    rec.count = 0;
-    rec.nops = 0;
-    rec.kind = (uint8_t)q.kind;
-    rec.flags = 0x40;
-    rec.t_admit = (u32)(now_ticks() - t0);
-    rec.t_done = rec.t_admit;
-    rec.reserved = 0;
-    write_rec(r, rec);
   }
 };
 
@@ -220,26 +227,27 @@ __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs,
 
   if (blockIdx.x == 0) {
     // ---- scheduler ----
+    SchedHot* hot = reinterpret_cast<SchedHot*>(gh_dyn_lds);
     for (u32 h = tid; h < nheaps; h += T) {
       const u64 rw = ld_relaxed(&descs[h].meta->root);
-      HeapSched hs;
+      SchedHot hs;
       hs.size = rw_m(rw) * (u64)K + rw_s(rw);
+      hs.cap = descs[h].max_keys;
+      hs.base = descs[h].meta->base;
       hs.seq = 0;
       hs.head = SCHED_NONE;
-      hs.last = SCHED_NONE;
-      hs.pad = 0;
-      w.heaps[h] = hs;
+      hot[h] = hs;
+      w.heaps[h].last = SCHED_NONE;
     }
     __syncthreads();
     constexpr u32 CH = (5 * K) / 4;   // request records staged in LDS per chunk
     gh_op* stage = reinterpret_cast<gh_op*>(lds);
     Scheduler<K> S;
-    S.descs = descs;
     S.nheaps = nheaps;
     S.reqs = reqs;
     S.recs = recs;
     S.w = w;
-    S.ctl = ctl;
+    S.hot = hot;
     S.t0 = ctl->t0;
     S.tail = 0;
     S.published = 0;
@@ -263,35 +271,35 @@ __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs,
             }
           }
           if (q.heap >= nheaps || q.kind > GH_OP_DELETE_MIN) {
-            S.reject(r, q);
+            S.reject(r, q.kind);
             note_error(ctl, ERR_INVAL);
             continue;
           }
-          HeapSched hs = w.heaps[q.heap];
-          const u64 cap = descs[q.heap].max_keys;
+          SchedHot hs = hot[q.heap];
           if (q.kind == GH_OP_DELETE_MIN) {
             S.admit(r, q, hs, 0);
             // room freed: admit deferred inserts of this heap in order
             while (hs.head != SCHED_NONE) {
               const gh_op d = reqs[hs.head];
-              if (hs.size + d.n > cap) break;
+              if (hs.size + d.n > hs.cap) break;
               const u32 dr = hs.head;
               hs.head = w.next[dr];
-              if (hs.head == SCHED_NONE) hs.last = SCHED_NONE;
+              if (hs.head == SCHED_NONE) w.heaps[q.heap].last = SCHED_NONE;
               S.admit(dr, d, hs, 2u);
             }
-          } else if ((u64)q.n > cap || q.n > 65535u * (u32)K) {
-            S.reject(r, q);
-          } else if (hs.head == SCHED_NONE && hs.size + q.n <= cap) {
+          } else if ((u64)q.n > hs.cap || q.n > 65535u * (u32)K) {
+            S.reject(r, q.kind);
+          } else if (hs.head == SCHED_NONE && hs.size + q.n <= hs.cap) {
             S.admit(r, q, hs, 0);
           } else {
             // wait for memory behind earlier deferred inserts
             w.next[r] = SCHED_NONE;
-            if (hs.last == SCHED_NONE) hs.head = r;
-            else w.next[hs.last] = r;
-            hs.last = r;
+            const u32 last = hs.head == SCHED_NONE ? SCHED_NONE : w.heaps[q.heap].last;
+            if (last == SCHED_NONE) hs.head = r;
+            else w.next[last] = r;
+            w.heaps[q.heap].last = r;
           }
-          w.heaps[q.heap] = hs;
+          hot[q.heap] = hs;
           if (S.tail - S.published >= 64) S.publish_queue();
         }
       }
@@ -300,9 +308,9 @@ __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs,
     if (tid == 0) {
       // inserts still waiting for memory when the stream ends are rejected
       for (u32 h = 0; h < nheaps; ++h) {
-        u32 r = w.heaps[h].head;
+        u32 r = hot[h].head;
         while (r != SCHED_NONE) {
-          S.reject(r, reqs[r]);
+          S.reject(r, GH_OP_INSERT);
           r = w.next[r];
         }
       }
@@ -368,7 +376,8 @@ __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs,
 
 template <int K, int T>
 static hipError_t launch_serve_t(const ServeArgs& a) {
-  hipLaunchKernelGGL((k_serve<K, T>), dim3(a.workgroups + 1), dim3(T), 0, a.stream, a.descs,
+  hipLaunchKernelGGL((k_serve<K, T>), dim3(a.workgroups + 1), dim3(T),
+                     (size_t)a.nheaps * sizeof(SchedHot), a.stream, a.descs,
                      a.nheaps, a.reqs, a.nreq, a.in, a.out, a.recs, a.w, a.ctl, a.clock_mhz);
   return hipGetLastError();
 }

@@ -310,7 +310,17 @@ def served_stream(nheaps: int, k: int, nreq: int, seed: int, rate_per_s: float |
     return pre, reqs, sizes
 
 
-def served_capacity(prefill_sizes: np.ndarray) -> np.ndarray:
+def poisson_arrivals(n: int, rate_per_s: float, seed: int) -> np.ndarray:
+    """Arrival times (ns) of a Poisson process of the given rate."""
+    st = Stream(seed)
+    gaps = -np.log1p(-st.unit(n)) / rate_per_s * 1e9
+    return np.floor(np.cumsum(gaps)).astype(np.uint64)
+
+
+def served_capacity(prefill_sizes: np.ndarray, extra: int | None = None) -> np.ndarray:
     """Memory budget (entries) per heap for the served form: the prefill plus
-    a quarter of it plus 4096."""
+    `extra` entries, or (extra None) the prefill plus a quarter of it plus
+    4096, a tight budget under which inserts regularly wait for memory."""
+    if extra is not None:
+        return (prefill_sizes + int(extra)).astype(np.int64)
     return (np.ceil(1.25 * prefill_sizes) + 4096).astype(np.int64)
