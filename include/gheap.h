@@ -229,6 +229,42 @@ int heap_serve(gh_heap_t h, const gh_op *d_reqs, uint32_t nreq, const uint64_t *
                uint64_t *d_out, gh_reqrec *d_recs, void *d_work, uint64_t work_bytes,
                uint64_t max_ops, const gh_tuning *tuning);
 
+/* Result of one knapsack instance solved by heap_knapsack (32 bytes).
+ *   best      optimal value found
+ *   explored  nodes taken from the heap and expanded (bound above best)
+ *   created   nodes pushed into the heap
+ *   ops       heap operations (inserts + deleteMins) the instance ran
+ *   flags     bit 0: finished; bit 6: the node pool overflowed (best is
+ *             then only a lower bound) */
+typedef struct gh_knapres {
+    uint64_t best;
+    uint64_t explored;
+    uint64_t created;
+    uint32_t ops;
+    uint32_t flags;
+} gh_knapres;
+
+/* Solve ninst 0/1 knapsack instances by best-first branch and bound, one
+ * heap of the set per instance, all in one persistent launch (the
+ * application of Sec. 5.6.2).  Instance i has d_n[i] <= 255 items starting
+ * at d_item_off[i] in d_w / d_v (uint32, sorted by value/weight
+ * descending), capacity d_cap[i].  Heap entries carry the negated
+ * fractional upper bound in fixed point (scale 2^16) above a 29-bit node id,
+ * so deleteMin returns the k most promising nodes; a node is expanded only if
+ * its bound exceeds the best value found, children are pushed only if their
+ * bound does.  d_pool (device, ninst * pool_per_inst uint64) holds the nodes;
+ * d_scratch (device, ninst * 3 * k uint64) holds per-instance batches;
+ * d_res (device, ninst gh_knapres).  Heap i must hold pool_per_inst entries
+ * (pool_per_inst < 2^29).  The sum of an instance's values must stay below
+ * 2^18 and its capacity below 2^28 (so bounds fit 35 bits).  Instances are
+ * claimed by the workgroups in order; a submission may not overlap another
+ * submission on the same set.  Errors: GH_EINVAL, GH_ENOMEM (a heap smaller
+ * than pool_per_inst). */
+int heap_knapsack(gh_heap_t h, uint32_t ninst, const uint32_t *d_item_off,
+                  const uint32_t *d_n, const uint64_t *d_cap, const uint32_t *d_w,
+                  const uint32_t *d_v, uint64_t *d_pool, uint64_t pool_per_inst,
+                  uint64_t *d_scratch, gh_knapres *d_res, const gh_tuning *tuning);
+
 /* Wait for the set's stream; return the sticky device error (GH_OK if none). */
 int heap_sync(gh_heap_t h);
 

@@ -402,6 +402,243 @@ hipError_t launch_serve_k<GH_K>(const ServeArgs& a) {
   return hipErrorInvalidValue;
 }
 
+// ---------------------------------------------------------------------------
+// 0/1 knapsack by best-first branch and bound on the heap (the application
+// of Sec. 5.6.2).  One heap per instance; a workgroup claims an instance,
+// pushes the root node, and repeats: deleteMin(K) the most promising nodes,
+// expand those whose bound still exceeds the best value found, insert their
+// promising children.  Items are sorted by value/weight descending.
+//   bound(level, V, W): V plus the items from `level` on while they fit plus
+//   the fitting fraction of the next one, in fixed point with scale 2^16
+//   (floored, so never below the true bound);
+//   entry = (2^35 - 1 - bound) << 29 | node id  (deleteMin = largest bound);
+//   node  = level << 56 | V << 28 | W.
+// ---------------------------------------------------------------------------
+constexpr u64 KN_KEYMAX = (1ull << 35) - 1;
+constexpr u32 KN_IDBITS = 29;
+constexpr u64 KN_IDMASK = (1ull << KN_IDBITS) - 1;
+constexpr u32 KN_MAXN = 255;
+
+struct KnapShared {
+  u32 w[KN_MAXN + 1];
+  u32 v[KN_MAXN + 1];
+  u64 pw[KN_MAXN + 2];   // prefix sums of the sorted weights and values
+  u64 pv[KN_MAXN + 2];
+  u64 best;
+  u64 cap;
+  u64 explored;
+  u64 created;
+  u64 pool_next;
+  u32 n;
+  u32 cnt;              // children produced in this round
+  u32 popped;
+  u32 inst;
+  u32 overflow;
+};
+
+__device__ __forceinline__ u64 kn_bound(const KnapShared& ks, u32 level, u64 V, u64 W) {
+  if (W > ks.cap) return 0;
+  const u64 rem = ks.cap - W;
+  u32 lo = level, hi = ks.n;   // largest j with pw[j] - pw[level] <= rem
+  while (lo < hi) {
+    const u32 mid = (lo + hi + 1) >> 1;
+    if (ks.pw[mid] - ks.pw[level] <= rem) lo = mid;
+    else hi = mid - 1;
+  }
+  u64 b = (V + ks.pv[lo] - ks.pv[level]) << 16;
+  if (lo < ks.n) {
+    const u64 r2 = rem - (ks.pw[lo] - ks.pw[level]);
+    b += ((r2 * (u64)ks.v[lo]) << 16) / (u64)ks.w[lo];
+  }
+  return b;
+}
+
+template <int K, int T>
+__global__ __launch_bounds__(T) void k_knap(const HeapDesc* __restrict__ descs, u32 ninst,
+                                            const u32* __restrict__ item_off,
+                                            const u32* __restrict__ nitems,
+                                            const u64* __restrict__ caps,
+                                            const u32* __restrict__ wts,
+                                            const u32* __restrict__ vals, u64* __restrict__ pool,
+                                            u64 pool_per_inst, u64* __restrict__ scratch,
+                                            gh_knapres* __restrict__ res, Ctl* __restrict__ ctl) {
+  __shared__ __align__(16) u64 lds[5 * K];
+  __shared__ OpShared sh;
+  __shared__ KnapShared ks;
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) {
+      u32 i = atomicAdd(&ctl->next_op, 1u);
+      if (ld_relaxed32(&ctl->abort)) i = ninst;
+      ks.inst = i;
+    }
+    __syncthreads();
+    const u32 inst = ks.inst;
+    if (inst >= ninst) break;
+    const HeapDesc H = descs[inst];
+    u64 ticket = H.meta->base;
+    u64* ipool = pool + (u64)inst * pool_per_inst;
+    u64* out = scratch + (u64)inst * 3 * K;   // K popped entries, then 2K children
+    u64* kids = out + K;
+    // stage the instance
+    const u32 n = nitems[inst] < KN_MAXN ? nitems[inst] : KN_MAXN;
+    const u32 base = item_off[inst];
+    for (u32 j = tid; j < n; j += T) {
+      ks.w[j] = wts[base + j];
+      ks.v[j] = vals[base + j];
+    }
+    if (tid == 0) {
+      ks.n = n;
+      ks.cap = caps[inst];
+      ks.explored = 0;
+      ks.created = 0;
+      ks.overflow = 0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      ks.pw[0] = 0;
+      ks.pv[0] = 0;
+      for (u32 j = 0; j < n; ++j) {
+        ks.pw[j + 1] = ks.pw[j] + ks.w[j];
+        ks.pv[j + 1] = ks.pv[j] + ks.v[j];
+      }
+      // greedy incumbent: items in ratio order while they fit
+      u64 W = 0, V = 0;
+      for (u32 j = 0; j < n; ++j)
+        if (W + ks.w[j] <= ks.cap) {
+          W += ks.w[j];
+          V += ks.v[j];
+        }
+      ks.best = V;
+      // the root node
+      const u64 b = kn_bound(ks, 0, 0, 0);
+      ipool[0] = 0;
+      kids[0] = ((KN_KEYMAX - b) << KN_IDBITS) | 0ull;
+      ks.pool_next = 1;
+      ks.cnt = (b > (V << 16)) ? 1u : 0u;
+      ks.created = ks.cnt;
+    }
+    __syncthreads();
+    u32 ops = 0;
+    for (;;) {
+      // push this round's children (at most 2K: two inserts)
+      const u32 c = ks.cnt;
+      for (u32 j = 0; j < c; j += K) {
+        const u32 nn = c - j < (u32)K ? c - j : (u32)K;
+        OpResult r = op_insert<K, T>(H, ticket++, kids + j, nn, lds, sh, ctl);
+        ++ops;
+        if (!r.ok) break;
+        __syncthreads();
+      }
+      // take the most promising nodes
+      OpResult r = op_delete<K, T>(H, ticket++, out, lds, sh, ctl);
+      ++ops;
+      __syncthreads();
+      if (!r.ok || r.count == 0) break;
+      if (tid == 0) {
+        ks.cnt = 0;
+        ks.popped = r.count;
+      }
+      __syncthreads();
+      // expand
+      const u32 popped = r.count;
+      for (u32 e = tid; e < popped; e += T) {
+        const u64 ent = out[e];
+        const u64 id = ent & KN_IDMASK;
+        const u64 b = KN_KEYMAX - (ent >> KN_IDBITS);
+        if (b <= (__hip_atomic_load(&ks.best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) << 16))
+          continue;   // cannot beat the incumbent any more
+        const u64 node = ipool[id];
+        const u32 level = (u32)(node >> 56);
+        const u64 V = (node >> 28) & ((1ull << 28) - 1);
+        const u64 W = node & ((1ull << 28) - 1);
+        atomicAdd(reinterpret_cast<unsigned long long*>(&ks.explored), 1ull);
+        if (level >= ks.n) {
+          atomicMax(reinterpret_cast<unsigned long long*>(&ks.best), (unsigned long long)V);
+          continue;
+        }
+        const u64 wl = ks.w[level], vl = ks.v[level];
+        u64 cand[2];
+        u64 cb[2];
+        int nc = 0;
+        if (W + wl <= ks.cap) {
+          const u64 V1 = V + vl, W1 = W + wl;
+          atomicMax(reinterpret_cast<unsigned long long*>(&ks.best), (unsigned long long)V1);
+          cb[nc] = kn_bound(ks, level + 1, V1, W1);
+          cand[nc++] = ((u64)(level + 1) << 56) | (V1 << 28) | W1;
+        }
+        cb[nc] = kn_bound(ks, level + 1, V, W);
+        cand[nc++] = ((u64)(level + 1) << 56) | (V << 28) | W;
+        const u64 bestnow =
+            __hip_atomic_load(&ks.best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) << 16;
+        for (int q = 0; q < nc; ++q) {
+          if (cb[q] <= bestnow) continue;
+          const u32 slot = atomicAdd(&ks.cnt, 1u);
+          const u64 nid = ks.pool_next + slot;
+          if (nid >= pool_per_inst || nid > KN_IDMASK) {
+            atomicOr(&ks.overflow, 1u);
+            continue;
+          }
+          ipool[nid] = cand[q];
+          kids[slot] = ((KN_KEYMAX - cb[q]) << KN_IDBITS) | nid;
+        }
+      }
+      __syncthreads();
+      if (tid == 0) {
+        u32 c2 = ks.cnt;
+        if (ks.overflow) {
+          // children beyond the pool were dropped; keep the ones written
+          const u64 room = pool_per_inst > ks.pool_next ? pool_per_inst - ks.pool_next : 0;
+          if ((u64)c2 > room) c2 = (u32)room;
+          ks.cnt = c2;
+        }
+        ks.pool_next += c2;
+        ks.created += c2;
+      }
+      // pool writes are read back by other threads after later barriers
+      __syncthreads();
+    }
+    if (tid == 0) {
+      gh_knapres o;
+      o.best = ks.best;
+      o.explored = ks.explored;
+      o.created = ks.created;
+      o.ops = ops;
+      o.flags = 1u | (ks.overflow ? 0x40u : 0u);
+      res[inst] = o;
+    }
+    __syncthreads();
+  }
+}
+
+template <int K, int T>
+static hipError_t launch_knap_t(const KnapArgs& a) {
+  hipLaunchKernelGGL((k_knap<K, T>), dim3(a.workgroups), dim3(T), 0, a.stream, a.descs, a.ninst,
+                     a.item_off, a.n, a.cap, a.w, a.v, a.pool, a.pool_per_inst, a.scratch, a.res,
+                     a.ctl);
+  return hipGetLastError();
+}
+
+template <>
+hipError_t launch_knap_k<GH_K>(const KnapArgs& a) {
+  constexpr int K = GH_K;
+  switch (a.threads) {
+#define GH_CASE(TT)                                                \
+  case TT:                                                         \
+    if constexpr (shape_ok(K, TT)) return launch_knap_t<K, TT>(a); \
+    break;
+    GH_CASE(64)
+    GH_CASE(128)
+    GH_CASE(256)
+    GH_CASE(512)
+    GH_CASE(1024)
+#undef GH_CASE
+    default:
+      break;
+  }
+  return hipErrorInvalidValue;
+}
+
 template <int K, int T>
 static hipError_t launch_t(const LaunchArgs& a) {
   hipLaunchKernelGGL((k_ops<K, T>), dim3(a.workgroups), dim3(T), 0, a.stream, a.descs, a.ops,

@@ -91,4 +91,26 @@ struct ServeArgs {
 template <int K>
 hipError_t launch_serve_k(const ServeArgs& a);
 
+// Knapsack branch and bound driver (one heap per instance).
+struct KnapArgs {
+  const HeapDesc* descs;
+  u32 ninst;
+  const u32* item_off;
+  const u32* n;
+  const u64* cap;
+  const u32* w;
+  const u32* v;
+  u64* pool;
+  u64 pool_per_inst;
+  u64* scratch;
+  gh_knapres* res;
+  Ctl* ctl;
+  u32 workgroups;
+  u32 threads;
+  hipStream_t stream;
+};
+
+template <int K>
+hipError_t launch_knap_k(const KnapArgs& a);
+
 }  // namespace gh

@@ -111,6 +111,18 @@ hipError_t launch_serve(const gh_heap* h, const ServeArgs& a) {
   }
 }
 
+hipError_t launch_knap(const gh_heap* h, const KnapArgs& a) {
+  switch (h->k) {
+    case 32: return launch_knap_k<32>(a);
+    case 64: return launch_knap_k<64>(a);
+    case 128: return launch_knap_k<128>(a);
+    case 256: return launch_knap_k<256>(a);
+    case 512: return launch_knap_k<512>(a);
+    case 1024: return launch_knap_k<1024>(a);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 struct ServeLayout {
   u64 head, heaps, next, left, queue, qreq, total;
 };
@@ -394,6 +406,43 @@ int heap_serve(gh_heap_t h, const gh_op* d_reqs, uint32_t nreq, const uint64_t* 
   if (launch_prep(h->descs, h->nheaps, h->ctl, h->stream) != hipSuccess) return GH_EDEVICE;
   if (launch_serve_reset(a.w.head, h->stream) != hipSuccess) return GH_EDEVICE;
   if (launch_serve(h, a) != hipSuccess) return GH_EDEVICE;
+  return GH_OK;
+}
+
+int heap_knapsack(gh_heap_t h, uint32_t ninst, const uint32_t* d_item_off, const uint32_t* d_n,
+                  const uint64_t* d_cap, const uint32_t* d_w, const uint32_t* d_v,
+                  uint64_t* d_pool, uint64_t pool_per_inst, uint64_t* d_scratch,
+                  gh_knapres* d_res, const gh_tuning* t) {
+  if (!h) return GH_EINVAL;
+  if (h->sticky != GH_OK) return h->sticky;
+  if (ninst == 0) return GH_OK;
+  if (ninst > h->nheaps || !d_item_off || !d_n || !d_cap || !d_w || !d_v || !d_pool ||
+      !d_scratch || !d_res || pool_per_inst == 0 || pool_per_inst >= (1ull << 29))
+    return GH_EINVAL;
+  for (u32 i = 0; i < ninst; ++i)
+    if (h->max_keys[i] < pool_per_inst) return GH_ENOMEM;
+  u32 threads = (t && t->threads) ? t->threads : default_threads(h->k);
+  if (!heap_supported_shape(h->k, threads)) return GH_EINVAL;
+  u32 wg = (t && t->workgroups) ? t->workgroups : (ninst < 1024 ? ninst : 1024);
+  h->size0_known = false;
+  KnapArgs a;
+  a.descs = h->descs;
+  a.ninst = ninst;
+  a.item_off = d_item_off;
+  a.n = d_n;
+  a.cap = d_cap;
+  a.w = d_w;
+  a.v = d_v;
+  a.pool = d_pool;
+  a.pool_per_inst = pool_per_inst;
+  a.scratch = d_scratch;
+  a.res = d_res;
+  a.ctl = h->ctl;
+  a.workgroups = wg;
+  a.threads = threads;
+  a.stream = h->stream;
+  if (launch_prep(h->descs, h->nheaps, h->ctl, h->stream) != hipSuccess) return GH_EDEVICE;
+  if (launch_knap(h, a) != hipSuccess) return GH_EDEVICE;
   return GH_OK;
 }
 

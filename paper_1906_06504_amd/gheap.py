@@ -36,7 +36,10 @@ LOG_DTYPE = np.dtype([("ticket", "<u8"), ("count", "<u4"), ("levels", "<u2"), ("
                       ("t_root", "<u4"), ("t_done", "<u4")])
 REQ_DTYPE = np.dtype([("first_ticket", "<u8"), ("count", "<u4"), ("nops", "<u2"), ("kind", "u1"),
                       ("flags", "u1"), ("t_admit", "<u4"), ("t_done", "<u4"), ("reserved", "<u8")])
+KNAP_DTYPE = np.dtype([("best", "<u8"), ("explored", "<u8"), ("created", "<u8"), ("ops", "<u4"),
+                       ("flags", "<u4")])
 assert OP_DTYPE.itemsize == 32 and LOG_DTYPE.itemsize == 32 and REQ_DTYPE.itemsize == 32
+assert KNAP_DTYPE.itemsize == 32
 
 REQ_ADMITTED = 1
 REQ_DEFERRED = 2
@@ -54,7 +57,7 @@ EXPORTS = ("heap_arena_bytes", "heap_supported_shape", "heap_create", "heap_crea
            "heap_insert", "heap_delete_min", "heap_submit", "heap_submit_graph",
            "heap_graph_launch", "heap_graph_destroy", "heap_sync", "heap_size",
            "heap_read_state", "heap_destroy", "heap_strerror", "heap_clock_hz",
-           "heap_serve_workspace_bytes", "heap_serve")
+           "heap_serve_workspace_bytes", "heap_serve", "heap_knapsack")
 
 
 class GHeapError(RuntimeError):
@@ -99,6 +102,8 @@ def load_library(path: str = LIB_PATH):
         "heap_clock_hz": (u64, []),
         "heap_serve_workspace_bytes": (u64, [u32, u32, u64]),
         "heap_serve": (i32, [vp, vp, u32, vp, vp, vp, vp, u64, u64, ctypes.POINTER(_Tuning)]),
+        "heap_knapsack": (i32, [vp, u32, vp, vp, vp, vp, vp, vp, u64, vp, vp,
+                                ctypes.POINTER(_Tuning)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

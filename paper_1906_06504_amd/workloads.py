@@ -324,3 +324,19 @@ def served_capacity(prefill_sizes: np.ndarray, extra: int | None = None) -> np.n
     if extra is not None:
         return (prefill_sizes + int(extra)).astype(np.int64)
     return (np.ceil(1.25 * prefill_sizes) + 4096).astype(np.int64)
+
+
+def knapsack_instances(ninst: int, seed: int, n_lo: int = 40, n_hi: int = 200,
+                       w_hi: int = 1000, extra_hi: int = 100):
+    """0/1 knapsack instances: n ~ U[n_lo, n_hi] items, weights U[1, w_hi],
+    value = weight + U[0, extra_hi], capacity = floor(sum of weights / 2).
+    Returns a list of (weights, values, capacity)."""
+    st = Stream(seed)
+    ns = st.uniform_int(n_lo, n_hi, ninst)
+    out = []
+    for i in range(ninst):
+        n = int(ns[i])
+        w = st.uniform_int(1, w_hi, n).astype(np.uint32)
+        v = (w.astype(np.int64) + st.uniform_int(0, extra_hi, n)).astype(np.uint32)
+        out.append((w, v, int(w.astype(np.int64).sum() // 2)))
+    return out

@@ -1,0 +1,50 @@
+"""Knapsack branch and bound on the device heaps: every instance's optimum
+equals the CPU dynamic program exactly, for several node capacities k (the
+search order changes with k, the optimum does not)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1906_06504_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def K():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1906_06504_amd import knapsack
+    oracle.build(force=False)
+    return knapsack
+
+
+@pytest.mark.parametrize("k", [32, 256, 1024])
+def test_small_instances_match_dp(K, k):
+    inst = W.knapsack_instances(48, seed=7, n_lo=10, n_hi=60)
+    ref = [oracle.knapsack_dp(w, v, c) for (w, v, c) in inst]
+    s = K.Solver(len(inst), k, pool_per_inst=1 << 16)
+    res = s.run(K.Instances(inst), workgroups=24)
+    assert np.all(res["flags"] & 1)
+    assert not np.any(res["flags"] & 0x40), "node pool overflow"
+    assert [int(b) for b in res["best"]] == ref
+    s.close()
+
+
+def test_full_size_sample_matches_dp(K):
+    """Instances of the batched configuration's shape (n in [40, 200])."""
+    inst = W.knapsack_instances(24, seed=0x5EED0004)
+    ref = [oracle.knapsack_dp(w, v, c) for (w, v, c) in inst]
+    s = K.Solver(len(inst), 256, pool_per_inst=1 << 20)
+    res = s.run(K.Instances(inst), workgroups=24)
+    assert not np.any(res["flags"] & 0x40), "node pool overflow"
+    assert [int(b) for b in res["best"]] == ref
+    print("explored", res["explored"].tolist(), flush=True)
+    s.close()
+
+
+def test_ratio_order_is_exact(K):
+    w = np.array([3, 6, 2, 4], np.uint32)
+    v = np.array([6, 12, 5, 4], np.uint32)   # ratios 2, 2, 2.5, 1
+    assert list(K.ratio_order(w, v)) == [2, 0, 1, 3]
