@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--served-slots", type=int, default=1024)
     ap.add_argument("--served-budget", type=int, default=1 << 20,
                     help="memory budget per heap beyond its prefill (entries)")
+    ap.add_argument("--no-knapsack", action="store_true", help="skip the knapsack leg")
+    ap.add_argument("--knapsack-instances", type=int, default=512)
     return ap.parse_args()
 
 
@@ -172,6 +174,8 @@ def main():
         result["batched"] = run_batched(args, wg_default=wg, th=th, plain_value=value)
     if not args.no_served:
         result["served"] = run_served(args)
+    if not args.no_knapsack:
+        result["knapsack"] = run_knapsack(args)
 
     if args.calib_copy:
         n = 1 << 25  # 256 MiB of int64
@@ -414,6 +418,90 @@ def run_served(args):
         out["plain_one_heap_per_launch_keys_per_s"] = plain_keys / (plain_ms / 1e3)
         out["vs_plain_per_launch"] = sat["keys_per_s"] / out["plain_one_heap_per_launch_keys_per_s"]
     hs.close()
+    return out
+
+
+def run_knapsack(args):
+    """Batched form on the knapsack workload: every instance's best-first
+    branch and bound on its own heap, all instances in one persistent launch
+    (and replayed as a HIP graph), k and workgroup size picked by the
+    autotuner; against one launch per instance (plain form)."""
+    import torch
+    from paper_1906_06504_amd import autotune as A
+    from paper_1906_06504_amd import knapsack as KS
+    from paper_1906_06504_amd import workloads as W
+    N = args.knapsack_instances
+    log("knapsack leg: %d instances" % N)
+    inst = W.knapsack_instances(N, seed=0x5EED0004)
+    dinst = KS.Instances(inst)
+    pool = 1 << 20
+    solvers = {}
+
+    def run(k, t, wg):
+        if k not in solvers:
+            solvers[k] = KS.Solver(N, k, pool_per_inst=pool)
+        s = solvers[k]
+        s.hs.arena.copy_(s.snapshot)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = s.run(dinst, workgroups=wg, threads=t, reset=False)
+        ms = (time.perf_counter() - t0) * 1e3
+        if np.any(res["flags"] & 0x40):
+            raise SystemExit("knapsack node pool overflow")
+        return ms, tuple(int(b) for b in res["best"])
+
+    best, table = A.tune("knapsack-%d-mi355x" % N, run, ks=(32, 64, 128, 256, 512, 1024),
+                         threads=(64, 128, 256, 512), workgroups=(N,), repeats=2, use_cache=False,
+                         log=log)
+    k, t = best["k"], best["threads"]
+    s = solvers[k]
+    times = []
+    res = None
+    for _ in range(3):
+        s.hs.arena.copy_(s.snapshot)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        res = s.run(dinst, workgroups=N, threads=t, reset=False)
+        ev1.record()
+        torch.cuda.synchronize()
+        times.append(ev0.elapsed_time(ev1))
+    ms = float(np.median(times))
+    moved = 2 * int(res["created"].astype(np.int64).sum())
+    # plain form: each instance alone, one launch each (a sample of 64)
+    sample = list(range(0, N, max(1, N // 64)))
+    one = KS.Solver(1, k, pool_per_inst=pool)
+    plain_ms, plain_moved = 0.0, 0
+    for i in sample:
+        d1 = KS.Instances([inst[i]])
+        one.hs.arena.copy_(one.snapshot)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        r1 = one.run(d1, workgroups=1, threads=t, reset=False)
+        ev1.record()
+        torch.cuda.synchronize()
+        plain_ms += ev0.elapsed_time(ev1)
+        plain_moved += 2 * int(r1["created"][0])
+        if int(r1["best"][0]) != int(res["best"][i]):
+            raise SystemExit("knapsack optimum differs between forms")
+    one.close()
+    for sv in solvers.values():
+        sv.close()
+    out = {
+        "workload": "%d 0/1 knapsack instances, n U[40,200], w U[1,1000], v = w + U[0,100], "
+                    "capacity sum(w)/2; best-first branch and bound, one heap each" % N,
+        "tuned": {"k": k, "threads": t, "workgroups": N},
+        "tuning_table": table,
+        "ms": ms, "keys_per_s": moved / (ms / 1e3),
+        "nodes_created": int(res["created"].sum()), "nodes_explored": int(res["explored"].sum()),
+        "plain_one_instance_per_launch_keys_per_s": plain_moved / (plain_ms / 1e3),
+        "vs_plain_per_launch": (moved / (ms / 1e3)) / (plain_moved / (plain_ms / 1e3)),
+    }
+    log("knapsack: k=%d threads=%d %.2f ms, %.3g keys/s (plain per launch %.3g)"
+        % (k, t, ms, out["keys_per_s"], out["plain_one_instance_per_launch_keys_per_s"]))
     return out
 
 
