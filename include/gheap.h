@@ -265,6 +265,46 @@ int heap_knapsack(gh_heap_t h, uint32_t ninst, const uint32_t *d_item_off,
                   const uint32_t *d_v, uint64_t *d_pool, uint64_t pool_per_inst,
                   uint64_t *d_scratch, gh_knapres *d_res, const gh_tuning *tuning);
 
+/* Counters of a heap_sssp run (64 bytes, device memory).
+ *   popped      entries taken from the heap
+ *   stale       popped entries whose distance had already improved (skipped)
+ *   pushed      entries inserted (each a strict improvement of a distance)
+ *   heap_ops    heap operations (inserts + deleteMins)
+ *   heap_ticks, relax_ticks  device wall-clock ticks summed over workgroups
+ *               spent in heap operations and in edge relaxation
+ *   rounds      deleteMins that returned entries */
+typedef struct gh_ssspstats {
+    uint64_t popped;
+    uint64_t stale;
+    uint64_t pushed;
+    uint64_t heap_ops;
+    uint64_t heap_ticks;
+    uint64_t relax_ticks;
+    uint64_t rounds;
+    uint64_t reserved;
+} gh_ssspstats;
+
+/* Single-source shortest paths (the application of Sec. 5.6.1) with heap 0
+ * of the set as a shared priority queue: entries are dist << 32 | vertex;
+ * every workgroup repeatedly takes the k nearest entries, skips those whose
+ * vertex has since been reached by a shorter path, relaxes the out-edges of
+ * the rest with an atomic minimum on the distance, and inserts an entry for
+ * every strict improvement.  Many workgroups use the heap at once.  The run
+ * ends when the heap is empty and no workgroup holds entries.  Graph in CSR
+ * (device): d_rowptr[V + 1], d_col / d_w[E] (uint32 weights); distances
+ * must stay below 2^32 - 1; d_dist[V] receives the distances (UINT32_MAX =
+ * unreachable).  d_push (device) holds workgroups * (push_per_wg + k)
+ * entries (workgroups = tuning->workgroups, 256 when 0 or tuning is NULL);
+ * push_per_wg >= k * (largest out-degree) guarantees room for one round of
+ * improvements, else the run stops with GH_ENOMEM.  Heap 0 must be empty;
+ * the run stops with GH_ENOMEM if the live entries outgrow its capacity
+ * (E + 1 entries is ample: live entries are far fewer than pushes).
+ * d_stats: one gh_ssspstats (device).  Asynchronous on the set's stream;
+ * errors surface at heap_sync.  The heap is empty again afterwards. */
+int heap_sssp(gh_heap_t h, uint32_t V, const uint32_t *d_rowptr, const uint32_t *d_col,
+              const uint32_t *d_w, uint32_t src, uint32_t *d_dist, uint64_t *d_push,
+              uint64_t push_per_wg, gh_ssspstats *d_stats, const gh_tuning *tuning);
+
 /* Wait for the set's stream; return the sticky device error (GH_OK if none). */
 int heap_sync(gh_heap_t h);
 

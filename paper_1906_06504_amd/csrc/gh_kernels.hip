@@ -639,6 +639,181 @@ hipError_t launch_knap_k<GH_K>(const KnapArgs& a) {
   return hipErrorInvalidValue;
 }
 
+// ---------------------------------------------------------------------------
+// Single-source shortest paths with the heap as a shared priority queue (the
+// application of Sec. 5.6.1), lazy deletion: entries are dist << 32 | vertex;
+// every workgroup takes the K nearest, skips entries whose vertex was since
+// reached by a shorter path, relaxes out-edges with an atomic minimum, and
+// inserts one entry per strict improvement.  Tickets are taken dynamically.
+// Termination: `outstanding` counts entries pushed and not yet processed; a
+// workgroup adds its pushes (after inserting them) before it subtracts the
+// entries it popped, so the count reaches zero only when the heap is empty
+// and no workgroup holds entries, and it stays zero from then on.
+// ---------------------------------------------------------------------------
+template <int K, int T>
+__global__ __launch_bounds__(T) void k_sssp(const HeapDesc* __restrict__ descs, u32 V,
+                                            const u32* __restrict__ rowptr,
+                                            const u32* __restrict__ col,
+                                            const u32* __restrict__ wt, u32* __restrict__ dist,
+                                            u64* __restrict__ push, u64 push_per_wg,
+                                            gh_ssspstats* __restrict__ stats,
+                                            SsspState* __restrict__ st, Ctl* __restrict__ ctl) {
+  __shared__ __align__(16) u64 lds[5 * K];
+  __shared__ OpShared sh;
+  __shared__ u64 s_ticket;
+  __shared__ u32 s_exit, s_cnt, s_stale;
+  const int tid = threadIdx.x;
+  const HeapDesc H = descs[0];
+  u64* out = push + (u64)blockIdx.x * (push_per_wg + K);   // K popped entries
+  u64* mine = out + K;                                      // this workgroup's pushes
+  u64 popped = 0, stale = 0, pushed = 0, ops = 0, heap_t = 0, relax_t = 0, rounds = 0;
+  u32 idle = 0;
+  u64 idle_since = 0;
+  for (;;) {
+    if (tid == 0) {
+      s_exit = (__hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+                ld_relaxed32(&ctl->abort)) ? 1u : 0u;
+      if (!s_exit)
+        s_ticket = atomicAdd(reinterpret_cast<unsigned long long*>(&st->next_ticket), 1ull);
+    }
+    __syncthreads();
+    if (s_exit) break;
+    u64 t0 = now_ticks();
+    const OpResult r = op_delete<K, T>(H, s_ticket, out, lds, sh, ctl);
+    ++ops;
+    __syncthreads();
+    heap_t += now_ticks() - t0;
+    if (!r.ok) break;
+    if (r.count == 0) {
+      if (tid == 0) {
+        const u64 now = now_ticks();
+        if (ld_relaxed(&st->outstanding) == 0) {
+          __hip_atomic_store(&st->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (idle != 0 && now - idle_since > ctl->timeout_ticks) {
+          // entries outstanding yet the heap stayed empty for the whole
+          // watchdog period: give up instead of spinning forever
+          raise_error(ctl, ERR_TIMEOUT);
+        } else {
+          if (idle == 0) idle_since = now;
+          // back off (growing to ~7 us) so idle workgroups leave the root to
+          // those carrying entries (s_sleep 32 is 2048 clocks, ~0.9 us)
+          const u32 n = idle < 3 ? (1u << idle) : 8u;
+          for (u32 j = 0; j < n; ++j) __builtin_amdgcn_s_sleep(32);
+        }
+      }
+      ++idle;
+      __syncthreads();
+      continue;
+    }
+    idle = 0;
+    ++rounds;
+    popped += r.count;
+    // relax the out-edges of the popped vertices
+    t0 = now_ticks();
+    if (tid == 0) {
+      s_cnt = 0;
+      s_stale = 0;
+    }
+    __syncthreads();
+    for (u32 e = tid; e < r.count; e += T) {
+      const u64 ent = out[e];
+      const u32 d = (u32)(ent >> 32);
+      const u32 u = (u32)ent;
+      const u32 du = __hip_atomic_load(dist + u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (d > du) {
+        atomicAdd(&s_stale, 1u);
+        continue;
+      }
+      const u32 j1 = rowptr[u + 1];
+      for (u32 j = rowptr[u]; j < j1; ++j) {
+        const u32 v = col[j];
+        const u64 nd64 = (u64)d + wt[j];
+        if (nd64 >= 0xFFFFFFFFull) continue;
+        const u32 nd = (u32)nd64;
+        if (nd < __hip_atomic_load(dist + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          const u32 old = atomicMin(dist + v, nd);
+          if (old > nd) {
+            const u32 slot = atomicAdd(&s_cnt, 1u);
+            if (slot < push_per_wg) mine[slot] = ((u64)nd << 32) | v;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    relax_t += now_ticks() - t0;
+    const u32 c = s_cnt < push_per_wg ? s_cnt : (u32)push_per_wg;
+    if (tid == 0) {
+      stale += s_stale;
+      if (s_cnt > push_per_wg) raise_error(ctl, ERR_NOMEM);
+    }
+    // insert the improvements, K at a time
+    t0 = now_ticks();
+    bool ok = true;
+    for (u32 j = 0; j < c && ok; j += K) {
+      if (tid == 0)
+        s_ticket = atomicAdd(reinterpret_cast<unsigned long long*>(&st->next_ticket), 1ull);
+      __syncthreads();
+      const u32 nn = c - j < (u32)K ? c - j : (u32)K;
+      const OpResult ri = op_insert<K, T>(H, s_ticket, mine + j, nn, lds, sh, ctl);
+      ++ops;
+      ok = ri.ok && !(ri.flags & F_REJECT);
+      if (ri.flags & F_REJECT) {
+        // the heap is full: a dropped entry would lose a vertex, stop the run
+        if (tid == 0) raise_error(ctl, ERR_NOMEM);
+      }
+      __syncthreads();
+    }
+    heap_t += now_ticks() - t0;
+    pushed += c;
+    if (tid == 0) {
+      // pushes are counted before the popped entries are retired
+      if (c) atomicAdd(reinterpret_cast<unsigned long long*>(&st->outstanding),
+                       (unsigned long long)c);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      atomicAdd(reinterpret_cast<unsigned long long*>(&st->outstanding),
+                (unsigned long long)(0ull - (u64)r.count));
+    }
+    if (!ok) break;
+  }
+  if (tid == 0) {
+    atomicAdd(reinterpret_cast<unsigned long long*>(&stats->popped), (unsigned long long)popped);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&stats->stale), (unsigned long long)stale);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&stats->pushed), (unsigned long long)pushed);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&stats->heap_ops), (unsigned long long)ops);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&stats->heap_ticks), (unsigned long long)heap_t);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&stats->relax_ticks),
+              (unsigned long long)relax_t);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&stats->rounds), (unsigned long long)rounds);
+  }
+}
+
+template <int K, int T>
+static hipError_t launch_sssp_t(const SsspArgs& a) {
+  hipLaunchKernelGGL((k_sssp<K, T>), dim3(a.workgroups), dim3(T), 0, a.stream, a.descs, a.V,
+                     a.rowptr, a.col, a.w, a.dist, a.push, a.push_per_wg, a.stats, a.st, a.ctl);
+  return hipGetLastError();
+}
+
+template <>
+hipError_t launch_sssp_k<GH_K>(const SsspArgs& a) {
+  constexpr int K = GH_K;
+  switch (a.threads) {
+#define GH_CASE(TT)                                                \
+  case TT:                                                         \
+    if constexpr (shape_ok(K, TT)) return launch_sssp_t<K, TT>(a); \
+    break;
+    GH_CASE(64)
+    GH_CASE(128)
+    GH_CASE(256)
+    GH_CASE(512)
+    GH_CASE(1024)
+#undef GH_CASE
+    default:
+      break;
+  }
+  return hipErrorInvalidValue;
+}
+
 template <int K, int T>
 static hipError_t launch_t(const LaunchArgs& a) {
   hipLaunchKernelGGL((k_ops<K, T>), dim3(a.workgroups), dim3(T), 0, a.stream, a.descs, a.ops,

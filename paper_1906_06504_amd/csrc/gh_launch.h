@@ -113,4 +113,32 @@ struct KnapArgs {
 template <int K>
 hipError_t launch_knap_k(const KnapArgs& a);
 
+// SSSP driver (one shared heap, dynamic tickets).
+struct alignas(256) SsspState {
+  u64 next_ticket;   // dynamic root tickets of heap 0
+  u64 outstanding;   // entries pushed and not yet fully processed
+  u32 done;
+  u32 pad[59];
+};
+struct SsspArgs {
+  const HeapDesc* descs;
+  u32 V;
+  const u32* rowptr;
+  const u32* col;
+  const u32* w;
+  u32 src;
+  u32* dist;
+  u64* push;
+  u64 push_per_wg;
+  gh_ssspstats* stats;
+  SsspState* st;
+  Ctl* ctl;
+  u32 workgroups;
+  u32 threads;
+  hipStream_t stream;
+};
+
+template <int K>
+hipError_t launch_sssp_k(const SsspArgs& a);
+
 }  // namespace gh

@@ -54,6 +54,44 @@ hipError_t launch_serve_reset(ServeHead* head, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Before an SSSP run: distances unreached, the source at 0, its entry ready
+// in the first push slot, counters cleared, dynamic tickets after the one
+// the source's insert takes.
+__global__ void k_sssp_init(const HeapDesc* __restrict__ descs, SsspState* st, u32* dist, u32 V,
+                            u32 src, u64* push, gh_ssspstats* stats) {
+  const u64 i0 = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+  for (u64 i = i0; i < V; i += (u64)gridDim.x * blockDim.x) dist[i] = i == src ? 0u : 0xFFFFFFFFu;
+  if (i0 == 0) {
+    st->next_ticket = descs[0].meta->base + 1;
+    st->outstanding = 1;   // the source's entry
+    st->done = 0;
+    push[0] = (u64)src;   // entry (0 << 32 | src)
+    u64* sw = reinterpret_cast<u64*>(stats);
+    for (int j = 0; j < 8; ++j) sw[j] = 0;
+  }
+}
+
+hipError_t launch_sssp_init(const HeapDesc* descs, SsspState* st, u32* dist, u32 V, u32 src,
+                            u64* push, gh_ssspstats* stats, hipStream_t stream) {
+  u32 blocks = (V + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(k_sssp_init, dim3(blocks), dim3(256), 0, stream, descs, st, dist, V, src, push,
+                     stats);
+  return hipGetLastError();
+}
+
+// After an SSSP run: the ticket base becomes the next dynamic ticket, so the
+// next submission's base is exact however many tickets the run took.
+__global__ void k_sssp_fini(const HeapDesc* __restrict__ descs, const SsspState* st) {
+  if (threadIdx.x == 0) descs[0].meta->base = st->next_ticket;
+}
+
+hipError_t launch_sssp_fini(const HeapDesc* descs, const SsspState* st, hipStream_t stream) {
+  hipLaunchKernelGGL(k_sssp_fini, dim3(1), dim3(64), 0, stream, descs, st);
+  return hipGetLastError();
+}
+
 hipError_t launch_init(HeapDesc* descs_dev, const HeapDesc* descs_host, u32 nheaps, Ctl* ctl,
                        u64 timeout_ticks, hipStream_t st) {
   hipError_t e = hipMemcpyAsync(descs_dev, descs_host, sizeof(HeapDesc) * nheaps,

@@ -17,6 +17,9 @@ hipError_t launch_init(HeapDesc* descs_dev, const HeapDesc* descs_host, u32 nhea
                        u64 timeout_ticks, hipStream_t st);
 hipError_t launch_prep(const HeapDesc* descs, u32 nheaps, Ctl* ctl, hipStream_t st);
 hipError_t launch_serve_reset(ServeHead* head, hipStream_t st);
+hipError_t launch_sssp_init(const HeapDesc* descs, SsspState* st, u32* dist, u32 V, u32 src,
+                            u64* push, gh_ssspstats* stats, hipStream_t stream);
+hipError_t launch_sssp_fini(const HeapDesc* descs, const SsspState* st, hipStream_t stream);
 }  // namespace gh
 
 struct gh_heap {
@@ -26,6 +29,7 @@ struct gh_heap {
   unsigned char* arena;
   u64 arena_bytes;
   Ctl* ctl;                        // device
+  SsspState* sssp;                 // device
   HeapDesc* descs;                 // device
   std::vector<HeapDesc> host_descs;
   std::vector<u64> max_keys;
@@ -58,13 +62,14 @@ u32 default_threads(u32 k) {
 u64 max_nodes_for(u64 max_keys, u32 k) { return max_keys / k + 1; }
 
 struct Layout {
-  u64 ctl_off, desc_off, total;
+  u64 ctl_off, sssp_off, desc_off, total;
   std::vector<u64> meta_off, pb_off, lock_off, node_off, max_nodes;
 };
 
 bool make_layout(u32 k, u32 nheaps, const u64* max_keys, u64 each, Layout& L) {
   L.ctl_off = 0;
-  L.desc_off = align_up(sizeof(Ctl));
+  L.sssp_off = align_up(sizeof(Ctl));
+  L.desc_off = align_up(L.sssp_off + sizeof(SsspState));
   u64 off = align_up(L.desc_off + (u64)nheaps * sizeof(HeapDesc));
   L.meta_off.resize(nheaps);
   L.pb_off.resize(nheaps);
@@ -107,6 +112,18 @@ hipError_t launch_serve(const gh_heap* h, const ServeArgs& a) {
     case 256: return launch_serve_k<256>(a);
     case 512: return launch_serve_k<512>(a);
     case 1024: return launch_serve_k<1024>(a);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_sssp(const gh_heap* h, const SsspArgs& a) {
+  switch (h->k) {
+    case 32: return launch_sssp_k<32>(a);
+    case 64: return launch_sssp_k<64>(a);
+    case 128: return launch_sssp_k<128>(a);
+    case 256: return launch_sssp_k<256>(a);
+    case 512: return launch_sssp_k<512>(a);
+    case 1024: return launch_sssp_k<1024>(a);
     default: return hipErrorInvalidValue;
   }
 }
@@ -248,6 +265,7 @@ int heap_create_many(gh_heap_t* out, uint32_t k, uint32_t nheaps, const uint64_t
   h->arena = reinterpret_cast<unsigned char*>(d_arena);
   h->arena_bytes = arena_bytes;
   h->ctl = reinterpret_cast<Ctl*>(h->arena + L.ctl_off);
+  h->sssp = reinterpret_cast<SsspState*>(h->arena + L.sssp_off);
   h->descs = reinterpret_cast<HeapDesc*>(h->arena + L.desc_off);
   h->max_keys.assign(max_keys, max_keys + nheaps);
   h->size0 = 0;
@@ -443,6 +461,58 @@ int heap_knapsack(gh_heap_t h, uint32_t ninst, const uint32_t* d_item_off, const
   a.stream = h->stream;
   if (launch_prep(h->descs, h->nheaps, h->ctl, h->stream) != hipSuccess) return GH_EDEVICE;
   if (launch_knap(h, a) != hipSuccess) return GH_EDEVICE;
+  return GH_OK;
+}
+
+int heap_sssp(gh_heap_t h, uint32_t V, const uint32_t* d_rowptr, const uint32_t* d_col,
+              const uint32_t* d_w, uint32_t src, uint32_t* d_dist, uint64_t* d_push,
+              uint64_t push_per_wg, gh_ssspstats* d_stats, const gh_tuning* t) {
+  if (!h) return GH_EINVAL;
+  if (h->sticky != GH_OK) return h->sticky;
+  if (V == 0 || src >= V || !d_rowptr || !d_col || !d_w || !d_dist || !d_push || !d_stats ||
+      push_per_wg == 0)
+    return GH_EINVAL;
+  u32 threads = (t && t->threads) ? t->threads : default_threads(h->k);
+  if (!heap_supported_shape(h->k, threads)) return GH_EINVAL;
+  u32 wg = (t && t->workgroups) ? t->workgroups : 256;
+  h->size0_known = false;
+  // prep (ticket base), init, the source's insert (ticket base), the run
+  if (launch_prep(h->descs, h->nheaps, h->ctl, h->stream) != hipSuccess) return GH_EDEVICE;
+  if (launch_sssp_init(h->descs, h->sssp, d_dist, V, src, d_push, d_stats, h->stream) !=
+      hipSuccess)
+    return GH_EDEVICE;
+  LaunchArgs la;
+  la.descs = h->descs;
+  la.ops = nullptr;
+  la.nops = 1;
+  la.direct = OpParams{GH_OP_INSERT, h->clock_mhz, 1, h->nheaps, 0};
+  la.in = d_push;
+  la.out = nullptr;
+  la.counts = nullptr;
+  la.log = nullptr;
+  la.ctl = h->ctl;
+  la.workgroups = 1;
+  la.threads = threads;
+  la.stream = h->stream;
+  if (launch_ops(h, la) != hipSuccess) return GH_EDEVICE;
+  SsspArgs a;
+  a.descs = h->descs;
+  a.V = V;
+  a.rowptr = d_rowptr;
+  a.col = d_col;
+  a.w = d_w;
+  a.src = src;
+  a.dist = d_dist;
+  a.push = d_push;
+  a.push_per_wg = push_per_wg;
+  a.stats = d_stats;
+  a.st = h->sssp;
+  a.ctl = h->ctl;
+  a.workgroups = wg;
+  a.threads = threads;
+  a.stream = h->stream;
+  if (launch_sssp(h, a) != hipSuccess) return GH_EDEVICE;
+  if (launch_sssp_fini(h->descs, h->sssp, h->stream) != hipSuccess) return GH_EDEVICE;
   return GH_OK;
 }
 

@@ -40,6 +40,10 @@ KNAP_DTYPE = np.dtype([("best", "<u8"), ("explored", "<u8"), ("created", "<u8"),
                        ("flags", "<u4")])
 assert OP_DTYPE.itemsize == 32 and LOG_DTYPE.itemsize == 32 and REQ_DTYPE.itemsize == 32
 assert KNAP_DTYPE.itemsize == 32
+SSSP_DTYPE = np.dtype([("popped", "<u8"), ("stale", "<u8"), ("pushed", "<u8"), ("heap_ops", "<u8"),
+                       ("heap_ticks", "<u8"), ("relax_ticks", "<u8"), ("rounds", "<u8"),
+                       ("reserved", "<u8")])
+assert SSSP_DTYPE.itemsize == 64
 
 REQ_ADMITTED = 1
 REQ_DEFERRED = 2
@@ -57,7 +61,7 @@ EXPORTS = ("heap_arena_bytes", "heap_supported_shape", "heap_create", "heap_crea
            "heap_insert", "heap_delete_min", "heap_submit", "heap_submit_graph",
            "heap_graph_launch", "heap_graph_destroy", "heap_sync", "heap_size",
            "heap_read_state", "heap_destroy", "heap_strerror", "heap_clock_hz",
-           "heap_serve_workspace_bytes", "heap_serve", "heap_knapsack")
+           "heap_serve_workspace_bytes", "heap_serve", "heap_knapsack", "heap_sssp")
 
 
 class GHeapError(RuntimeError):
@@ -104,6 +108,8 @@ def load_library(path: str = LIB_PATH):
         "heap_serve": (i32, [vp, vp, u32, vp, vp, vp, vp, u64, u64, ctypes.POINTER(_Tuning)]),
         "heap_knapsack": (i32, [vp, u32, vp, vp, vp, vp, vp, vp, u64, vp, vp,
                                 ctypes.POINTER(_Tuning)]),
+        "heap_sssp": (i32, [vp, u32, vp, vp, vp, u32, vp, vp, u64, vp,
+                            ctypes.POINTER(_Tuning)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

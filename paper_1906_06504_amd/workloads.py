@@ -340,3 +340,47 @@ def knapsack_instances(ninst: int, seed: int, n_lo: int = 40, n_hi: int = 200,
         v = (w.astype(np.int64) + st.uniform_int(0, extra_hi, n)).astype(np.uint32)
         out.append((w, v, int(w.astype(np.int64).sum() // 2)))
     return out
+
+
+def poisson_cdf(lam: float, dmax: int) -> np.ndarray:
+    """P(X <= d) for d = 0..dmax of a Poisson(lam) variable."""
+    pmf = np.empty(dmax + 1)
+    pmf[0] = np.exp(-lam)
+    for d in range(1, dmax + 1):
+        pmf[d] = pmf[d - 1] * lam / d
+    return np.cumsum(pmf)
+
+
+def sssp_graph(V: int, seed: int, mean_degree: float = 8.0, w_lo: int = 1, w_hi: int = 1000):
+    """Random directed graph in CSR: out-degrees Poisson(mean_degree) by
+    inverse CDF, targets uniform on [0, V) with self-loops redrawn (multi-edges
+    kept), weights uniform on [w_lo, w_hi].  Returns (rowptr[V+1], col[E],
+    w[E]) as uint32 arrays."""
+    st = Stream(seed)
+    cdf = poisson_cdf(mean_degree, 200)
+    deg = np.searchsorted(cdf, st.unit(V), side="right").astype(np.int64)
+    deg = np.minimum(deg, 200)
+    rowptr = np.zeros(V + 1, dtype=np.int64)
+    np.cumsum(deg, out=rowptr[1:])
+    E = int(rowptr[-1])
+    if V > 1:
+        src = np.repeat(np.arange(V, dtype=np.int64), deg)
+        col = st.uniform_int(0, V - 1, E)
+        bad = np.flatnonzero(col == src)
+        while bad.size:
+            col[bad] = st.uniform_int(0, V - 1, bad.size)
+            bad = bad[col[bad] == src[bad]]
+    else:
+        # a single vertex can only have self-loops: it gets no edges
+        rowptr[:] = 0
+        E = 0
+        col = np.zeros(0, dtype=np.int64)
+    w = st.uniform_int(w_lo, w_hi, E)
+    return rowptr.astype(np.uint32), col.astype(np.uint32), w.astype(np.uint32)
+
+
+def config3(V: int = 1 << 20):
+    """SSSP workload: V vertices, out-degree Poisson(8), weights U[1, 1000],
+    source vertex 0, k = 512."""
+    rowptr, col, w = sssp_graph(V, CONFIG_SEED[3])
+    return rowptr, col, w, 0, 512

@@ -42,9 +42,3 @@ def test_full_size_sample_matches_dp(K):
     assert [int(b) for b in res["best"]] == ref
     print("explored", res["explored"].tolist(), flush=True)
     s.close()
-
-
-def test_ratio_order_is_exact(K):
-    w = np.array([3, 6, 2, 4], np.uint32)
-    v = np.array([6, 12, 5, 4], np.uint32)   # ratios 2, 2, 2.5, 1
-    assert list(K.ratio_order(w, v)) == [2, 0, 1, 3]

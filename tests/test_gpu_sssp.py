@@ -1,0 +1,90 @@
+"""GPU parity tests of the SSSP driver: many workgroups share one device heap
+as the priority queue; the distances must equal CPU Dijkstra's exactly."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1906_06504_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1906_06504_amd import gheap, sssp
+    gheap.load_library()
+    oracle.build(force=False)
+    return sssp
+
+
+def _p(*a):
+    print(*a, flush=True)
+
+
+def _check(S, rowptr, col, w, src, k, workgroups, threads=0):
+    V = rowptr.size - 1
+    _p("sssp V=%d E=%d k=%d workgroups=%d threads=%d src=%d" % (V, col.size, k, workgroups,
+                                                                threads, src))
+    g = S.Graph(rowptr, col, w)
+    sol = S.Solver(g, k, workgroups=workgroups, threads=threads)
+    d, st = sol.run(src)
+    want = oracle.dijkstra(V, rowptr, col, w, src)
+    assert np.array_equal(d, want), "%d distances differ" % int(np.sum(d != want))
+    reached = int(np.sum(want != 0xFFFFFFFF))
+    # every reached vertex is expanded at least once (more than once only
+    # when a concurrent workgroup improved it after it was popped); every
+    # pushed entry is popped, so the heap ends empty
+    assert int(st["popped"]) - int(st["stale"]) >= reached
+    assert int(st["pushed"]) + 1 == int(st["popped"])
+    _p("  popped=%d stale=%d reexpanded=%d heap_ops=%d" % (
+        int(st["popped"]), int(st["stale"]), int(st["popped"]) - int(st["stale"]) - reached,
+        int(st["heap_ops"])))
+    assert sol.hs.size(0) == 0
+    return sol, st
+
+
+@pytest.mark.parametrize("V,k,wg", [(1, 32, 4), (2, 32, 4), (100, 32, 8), (3000, 64, 32),
+                                    (20000, 256, 64), (50000, 512, 128)])
+def test_sssp_matches_dijkstra(S, V, k, wg):
+    rowptr, col, w = W.sssp_graph(V, seed=1000 + V)
+    sol, st = _check(S, rowptr, col, w, 0, k, wg)
+    sol.close()
+
+
+def test_sssp_other_source_and_reuse(S):
+    """Two runs on one solver (different sources): the heap is empty and its
+    ticket base exact between runs."""
+    rowptr, col, w = W.sssp_graph(5000, seed=77)
+    V = 5000
+    g = S.Graph(rowptr, col, w)
+    sol = S.Solver(g, 64, workgroups=48)
+    for src in (17, 4999):
+        d, st = sol.run(src)
+        assert np.array_equal(d, oracle.dijkstra(V, rowptr, col, w, src))
+    sol.close()
+
+
+def test_sssp_unreachable_and_heavy_ties(S):
+    """A graph with an unreachable half and all weights equal (many equal
+    distances, ties broken by vertex id)."""
+    V = 4000
+    rowptr, col, w = W.sssp_graph(V // 2, seed=5, w_lo=7, w_hi=7)
+    # second half: isolated vertices
+    rowptr = np.concatenate([rowptr, np.full(V // 2, rowptr[-1], np.uint32)])
+    _check(S, rowptr, col, w, 0, 32, 64)[0].close()
+
+
+@pytest.mark.parametrize("threads", [64, 256, 1024])
+def test_sssp_workgroup_shapes(S, threads):
+    rowptr, col, w = W.sssp_graph(8000, seed=99)
+    _check(S, rowptr, col, w, 3, 512, 96, threads)[0].close()
+
+
+def test_sssp_full_size(S):
+    """The full workload (2^20 vertices, Poisson(8) out-degree, k = 512) at
+    the benchmark's launch shape: all distances equal CPU Dijkstra's."""
+    rowptr, col, w, src, k = W.config3()
+    _check(S, rowptr, col, w, src, k, 256, 512)[0].close()
