@@ -49,6 +49,8 @@ def parse():
                     help="memory budget per heap beyond its prefill (entries)")
     ap.add_argument("--no-knapsack", action="store_true", help="skip the knapsack leg")
     ap.add_argument("--knapsack-instances", type=int, default=512)
+    ap.add_argument("--no-sssp", action="store_true", help="skip the SSSP leg")
+    ap.add_argument("--sssp-log2v", type=int, default=20)
     return ap.parse_args()
 
 
@@ -176,6 +178,9 @@ def main():
         result["served"] = run_served(args)
     if not args.no_knapsack:
         result["knapsack"] = run_knapsack(args)
+    sssp_graph = None
+    if not args.no_sssp:
+        result["sssp"], sssp_graph = run_sssp(args)
 
     if args.calib_copy:
         n = 1 << 25  # 256 MiB of int64
@@ -204,6 +209,18 @@ def main():
                       "order after an untimed prefill; %.2f s" % (nops, omoved, dt),
         }
         log("cpu baseline: %.3g keys/s" % (omoved / dt))
+        if sssp_graph is not None:
+            rowptr, col, w, src, dist = sssp_graph
+            t0 = time.perf_counter()
+            want = oracle.dijkstra(rowptr.size - 1, rowptr, col, w, src)
+            dt = time.perf_counter() - t0
+            result["sssp"]["cpu_baseline"] = {
+                "value": dt * 1e3, "unit": "ms", "cores": 1, "kind": "oracle",
+                "sample": "CPU Dijkstra (binary heap) on the whole graph, once",
+                "distances_equal": bool(np.array_equal(dist, want)),
+            }
+            log("cpu baseline sssp: %.1f ms, distances equal: %s"
+                % (dt * 1e3, np.array_equal(dist, want)))
 
     print(json.dumps(result), flush=True)
 
@@ -503,6 +520,71 @@ def run_knapsack(args):
     log("knapsack: k=%d threads=%d %.2f ms, %.3g keys/s (plain per launch %.3g)"
         % (k, t, ms, out["keys_per_s"], out["plain_one_instance_per_launch_keys_per_s"]))
     return out
+
+
+def run_sssp(args):
+    """SSSP on one shared heap (lazy Dijkstra, many workgroups popping k = 512
+    entries at a time): run time, edges per second, and the split of device
+    time between heap operations and edge relaxation."""
+    import torch
+    from paper_1906_06504_amd import gheap as GH
+    from paper_1906_06504_amd import sssp as SP
+    from paper_1906_06504_amd import workloads as W
+    V = 1 << args.sssp_log2v
+    log("sssp leg: generating graph with %d vertices" % V)
+    rowptr, col, w, src, k = W.config3(V)
+    g = SP.Graph(rowptr, col, w)
+    table = []
+    best = None
+    dist = None
+    for t in (256, 512):
+        for wg in (16, 32, 64, 128, 256):
+            sol = SP.Solver(g, k, workgroups=wg, threads=t, stream=torch.cuda.Stream())
+            sol.run(src)   # warm
+            times, stats = [], None
+            for _ in range(3):
+                ev0 = torch.cuda.Event(enable_timing=True)
+                ev1 = torch.cuda.Event(enable_timing=True)
+                ev0.record(sol.hs.stream)
+                sol.launch(src)
+                ev1.record(sol.hs.stream)
+                rc = sol.hs.sync()
+                if rc != 0:
+                    raise SystemExit("sssp failed: %d" % rc)
+                torch.cuda.synchronize()
+                times.append(ev0.elapsed_time(ev1))
+            d = sol.dist.cpu().numpy().view(np.uint32)[:V].copy()
+            stats = sol.stats.cpu().numpy().view(GH.SSSP_DTYPE)[0]
+            if dist is None:
+                dist = d
+            elif not np.array_equal(d, dist):
+                raise SystemExit("sssp distances differ between launch shapes")
+            ms = float(np.median(times))
+            row = {"threads": t, "workgroups": wg, "ms": ms}
+            table.append(row)
+            log("sssp threads=%d workgroups=%d: %.2f ms" % (t, wg, ms))
+            if best is None or ms < best[0]["ms"]:
+                best = (row, stats)
+            sol.close()
+    row, st = best
+    ht, rt = int(st["heap_ticks"]), int(st["relax_ticks"])
+    moved = int(st["pushed"]) + 1 + int(st["popped"])
+    reached = int(np.sum(dist != 0xFFFFFFFF))
+    out = {
+        "workload": "SSSP from vertex 0, V=2^%d, out-degree Poisson(8), w U[1,1000], E=%d, k=%d; "
+                    "lazy deletion on one shared heap" % (args.sssp_log2v, g.E, k),
+        "best": row, "table": table,
+        "ms": row["ms"],
+        "edges_per_s": g.E / (row["ms"] / 1e3),
+        "heap_keys_per_s": moved / (row["ms"] / 1e3),
+        "heap_time_share": ht / max(1, ht + rt),
+        "popped": int(st["popped"]), "stale": int(st["stale"]), "pushed": int(st["pushed"]),
+        "reexpanded": int(st["popped"]) - int(st["stale"]) - reached,
+        "heap_ops": int(st["heap_ops"]), "reached": reached,
+    }
+    log("sssp: %.2f ms, %.3g edges/s, heap share %.2f" % (row["ms"], out["edges_per_s"],
+                                                         out["heap_time_share"]))
+    return out, (rowptr, col, w, src, dist)
 
 
 if __name__ == "__main__":

@@ -661,7 +661,7 @@ __global__ __launch_bounds__(T) void k_sssp(const HeapDesc* __restrict__ descs, 
   __shared__ __align__(16) u64 lds[5 * K];
   __shared__ OpShared sh;
   __shared__ u64 s_ticket;
-  __shared__ u32 s_exit, s_cnt, s_stale;
+  __shared__ u32 s_exit, s_idle, s_cnt, s_stale;
   const int tid = threadIdx.x;
   const HeapDesc H = descs[0];
   u64* out = push + (u64)blockIdx.x * (push_per_wg + K);   // K popped entries
@@ -673,16 +673,27 @@ __global__ __launch_bounds__(T) void k_sssp(const HeapDesc* __restrict__ descs, 
     if (tid == 0) {
       s_exit = (__hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
                 ld_relaxed32(&ctl->abort)) ? 1u : 0u;
-      if (!s_exit)
-        s_ticket = atomicAdd(reinterpret_cast<unsigned long long*>(&st->next_ticket), 1ull);
+      // a heap that looks empty (no node, empty partial buffer, as of the
+      // last root release) is not worth a ticket: idle without one
+      s_idle = 0;
+      if (!s_exit) {
+        const u64 w = ld_relaxed(&H.meta->root);
+        if (rw_m(w) == 0 && rw_s(w) == 0)
+          s_idle = 1;
+        else
+          s_ticket = atomicAdd(reinterpret_cast<unsigned long long*>(&st->next_ticket), 1ull);
+      }
     }
     __syncthreads();
     if (s_exit) break;
-    u64 t0 = now_ticks();
-    const OpResult r = op_delete<K, T>(H, s_ticket, out, lds, sh, ctl);
-    ++ops;
-    __syncthreads();
-    heap_t += now_ticks() - t0;
+    OpResult r{0, 0, 0, true};
+    if (!s_idle) {
+      const u64 t0 = now_ticks();
+      r = op_delete<K, T>(H, s_ticket, out, lds, sh, ctl);
+      ++ops;
+      __syncthreads();
+      heap_t += now_ticks() - t0;
+    }
     if (!r.ok) break;
     if (r.count == 0) {
       if (tid == 0) {
@@ -709,7 +720,7 @@ __global__ __launch_bounds__(T) void k_sssp(const HeapDesc* __restrict__ descs, 
     ++rounds;
     popped += r.count;
     // relax the out-edges of the popped vertices
-    t0 = now_ticks();
+    u64 t0 = now_ticks();
     if (tid == 0) {
       s_cnt = 0;
       s_stale = 0;
