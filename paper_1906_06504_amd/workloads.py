@@ -24,15 +24,28 @@ OP_DELETE_MIN = 1
 ENTRY_MAX = np.uint64(0xFFFFFFFFFFFFFFFF)
 
 
+def _splitmix64_block(z: np.ndarray, base: np.uint64, first: int):
+    """z[i] = draw (first + i) of the stream with seed `base`, in place."""
+    z[:] = np.arange(first + 1, first + 1 + z.size, dtype=np.uint64)
+    z *= GOLDEN_GAMMA
+    z += base
+    z ^= z >> np.uint64(30)
+    z *= _M1
+    z ^= z >> np.uint64(27)
+    z *= _M2
+    z ^= z >> np.uint64(31)
+
+
+_BLOCK = 1 << 16   # cache-sized pieces
+
+
 def splitmix64(seed: int, start: int, count: int) -> np.ndarray:
     """Draws start .. start+count-1 of the SplitMix64 stream `seed`."""
-    with np.errstate(over="ignore"):
-        i = np.arange(start + 1, start + count + 1, dtype=np.uint64)
-        z = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + i * GOLDEN_GAMMA
-        z = (z ^ (z >> np.uint64(30))) * _M1
-        z = (z ^ (z >> np.uint64(27))) * _M2
-        z = z ^ (z >> np.uint64(31))
-    return z
+    out = np.empty(count, dtype=np.uint64)
+    base = np.uint64(seed & 0xFFFFFFFFFFFFFFFF)
+    for a in range(0, count, _BLOCK):
+        _splitmix64_block(out[a:a + _BLOCK], base, start + a)
+    return out
 
 
 class Stream:
@@ -126,12 +139,21 @@ def _keys_with_ids(stream: Stream, first_id: int):
     state = {"next": first_id}
 
     def src(count: int) -> np.ndarray:
-        keys = stream.u32(count)
-        ids = np.arange(state["next"], state["next"] + count, dtype=np.uint64)
-        state["next"] += count
-        if ids.size and int(ids[-1]) >= 0xFFFFFFFF:
+        if count and state["next"] + count - 1 >= 0xFFFFFFFF:
             raise ValueError("id space exhausted")
-        return pack(keys, ids)
+        # key = top 32 bits of the draw (as Stream.u32), already in place;
+        # built block by block so that every pass stays in cache
+        out = np.empty(count, dtype=np.uint64)
+        base = np.uint64(stream.seed & 0xFFFFFFFFFFFFFFFF)
+        hi = np.uint64(0xFFFFFFFF00000000)
+        for a in range(0, count, _BLOCK):
+            z = out[a:a + _BLOCK]
+            _splitmix64_block(z, base, stream.pos + a)
+            z &= hi
+            z |= np.arange(state["next"] + a, state["next"] + a + z.size, dtype=np.uint64)
+        stream.pos += count
+        state["next"] += count
+        return out
 
     return src
 

@@ -68,6 +68,24 @@ def test_batched_many_heaps_replay_and_alone(G):
     hs1.close()
 
 
+def test_batched_full_size(G):
+    """The benchmark's batched workload and launch shape: 64 heaps, k = 1024,
+    2^16 prefill and 2^18 keys requested each, 256 workgroups of 512
+    threads; every heap's log replayed on its own oracle."""
+    k, nh = 1024, 64
+    pre, mix, pres, mixes = W.batched_mixed(nh, k, 1 << 16, 1 << 18, seed=0x5EED0002)
+    _p("batched-full heaps=%d prefill ops=%d mixed ops=%d" % (nh, len(pre), len(mix)))
+    cap = (1 << 16) + (1 << 18) + k
+    hs, _, _, _ = run_gpu(pre, k, max_keys=cap, workgroups=256, threads=512, nheaps=nh)
+    hs, out, counts, log = run_gpu(mix, k, max_keys=cap, workgroups=256, threads=512, heapset=hs)
+    for h in range(nh):
+        oh = oracle.OracleHeap(k)
+        pl = pres[h]
+        oh.replay(pl.kind, pl.n, pl.off, pl.keys, 1)
+        replay_and_compare(mix, k, out, counts, log, heap=h, base_ticket=len(pl), oracle_heap=oh)
+    hs.close()
+
+
 def test_batched_graph_replays(G):
     """The batched launch captured once as a HIP graph and replayed three
     times (arena restored between replays, eager work in between): every
@@ -179,3 +197,32 @@ def test_served_alone_equals_mix(G):
         assert np.array_equal(out[o:o + c], out1[o:o + c]), "request %d differs alone" % i
     hs.close()
     hs1.close()
+
+
+def test_served_full_size_sampled(G):
+    """The benchmark's served workload and launch shape (256 heaps, k = 256,
+    prefill log-uniform up to 2^22, 2^20 requests, 1024 slots, budget prefill
+    + 2^20): every request is admitted or rejected, and a sample of heaps
+    (the largest, the smallest and six more) replays bit for bit."""
+    k, nh, nreq = 256, 256, 1 << 20
+    pre, reqs, sizes = W.served_stream(nh, k, nreq, seed=0x5EED0005, rate_per_s=None,
+                                       max_log2=22)
+    caps = W.served_capacity(sizes, extra=1 << 20)
+    _p("served-full heaps=%d requests=%d prefill=%d" % (nh, nreq, int(sizes.sum())))
+    hs = G.HeapSet(k, caps)
+    d = G.ops_to_device(pre)
+    hs.submit(*d[:5], workgroups=1024)
+    assert hs.sync() == 0
+    del d
+    r, n, keys, out, recs, max_ops = G.requests_to_device(reqs)
+    hs.serve(r, n, keys, out, recs, max_ops, workgroups=1024)
+    rc = hs.sync()
+    assert rc == G.GH_OK, G.strerror(rc)
+    torch.cuda.synchronize()
+    out = G.to_host_u64(out)
+    recs = G.recs_to_host(recs, n)
+    assert np.all((recs["flags"] & (G.REQ_ADMITTED | G.REQ_REJECTED)) != 0)
+    sample = [int(np.argmax(sizes)), int(np.argmin(sizes))] + list(range(3, nh, nh // 6))[:6]
+    for h in sample:
+        _replay_served(G, pre, reqs, recs, out, k, h, caps)
+    hs.close()

@@ -132,6 +132,23 @@ def test_config2_reduced(G):
     hs.close()
 
 
+def test_config2_full_size(G):
+    """The benchmark's workload and launch shape (k = 1024, prefill 2^22, 2^24
+    keys requested, 64 workgroups of 512 threads): every deleteMin of the
+    timed launch equals the oracle's replay of the ticket log, and the final
+    state satisfies Properties 1-3 with the oracle's live multiset."""
+    pre, mix, k = W.config2()
+    _print("config2-full prefill ops=%d mixed ops=%d" % (len(pre), len(mix)))
+    cap = (1 << 22) + int(mix.n.astype(np.int64).sum()) + k
+    hs, _, _, prelog = run_gpu(pre, k, max_keys=cap, workgroups=64, threads=512)
+    hs, out, counts, log = run_gpu(mix, k, max_keys=cap, workgroups=64, threads=512, heapset=hs)
+    oh = oracle.OracleHeap(k)
+    oh.replay(pre.kind, pre.n, pre.off, pre.keys, 1)
+    replay_and_compare(mix, k, out, counts, log, base_ticket=len(pre), oracle_heap=oh)
+    check_gpu_state(hs, 0, k)
+    hs.close()
+
+
 def test_edge_cases(G):
     k = 64
     h = G.Heap(k, 200)

@@ -42,3 +42,17 @@ def test_full_size_sample_matches_dp(K):
     assert [int(b) for b in res["best"]] == ref
     print("explored", res["explored"].tolist(), flush=True)
     s.close()
+
+
+def test_full_batch_sampled_matches_dp(K):
+    """All 512 instances of the benchmark's batch in one launch (k = 256,
+    256 threads, one workgroup per instance); a sample of 64 optima equals
+    the DP."""
+    inst = W.knapsack_instances(512, seed=0x5EED0004)
+    s = K.Solver(len(inst), 256, pool_per_inst=1 << 20)
+    res = s.run(K.Instances(inst), workgroups=512, threads=256)
+    assert not np.any(res["flags"] & 0x40), "node pool overflow"
+    for i in range(0, 512, 8):
+        w, v, c = inst[i]
+        assert int(res["best"][i]) == oracle.knapsack_dp(w, v, c), "instance %d" % i
+    s.close()
