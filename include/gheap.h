@@ -272,7 +272,9 @@ int heap_knapsack(gh_heap_t h, uint32_t ninst, const uint32_t *d_item_off,
  *   heap_ops    heap operations (inserts + deleteMins)
  *   heap_ticks, relax_ticks  device wall-clock ticks summed over workgroups
  *               spent in heap operations and in edge relaxation
- *   rounds      deleteMins that returned entries */
+ *   rounds      deleteMins that returned entries
+ *   traced      heap operations the trace asked to record (0 without a
+ *               trace; more than trace->op_cap means the trace is cut) */
 typedef struct gh_ssspstats {
     uint64_t popped;
     uint64_t stale;
@@ -281,8 +283,35 @@ typedef struct gh_ssspstats {
     uint64_t heap_ticks;
     uint64_t relax_ticks;
     uint64_t rounds;
-    uint64_t reserved;
+    uint64_t traced;
 } gh_ssspstats;
+
+/* One heap operation of a traced SSSP run (32 bytes): its root ticket, its
+ * kind (GH_OP_INSERT / GH_OP_DELETE_MIN), the entry count (inserted, or
+ * returned), and where its entries start in the trace's key buffer
+ * (inserts: the batch as given, unsorted; deleteMins: the output).
+ * `reserved` = m << 32 | s << 16 | flags << 8 | levels: the node count and
+ * partial-buffer size seen at the root, and the gh_logrec flags and levels. */
+typedef struct gh_ssspop {
+    uint64_t ticket;
+    uint64_t off;
+    uint32_t count;
+    uint32_t kind;
+    uint64_t reserved;
+} gh_ssspop;
+
+/* Optional trace of an SSSP run (host struct naming device buffers): room
+ * for op_cap records and key_cap entries.  Records come in completion
+ * order; sorted by ticket they replay the run on a sequential heap
+ * (Theorem 1).  An operation that does not fit is not recorded (the stats'
+ * `traced` count tells); the source's insert (the run's first ticket) is
+ * not recorded. */
+typedef struct gh_sssptrace {
+    gh_ssspop *d_ops;
+    uint64_t op_cap;
+    uint64_t *d_keys;
+    uint64_t key_cap;
+} gh_sssptrace;
 
 /* Single-source shortest paths (the application of Sec. 5.6.1) with heap 0
  * of the set as a shared priority queue: entries are dist << 32 | vertex;
@@ -299,11 +328,14 @@ typedef struct gh_ssspstats {
  * improvements, else the run stops with GH_ENOMEM.  Heap 0 must be empty;
  * the run stops with GH_ENOMEM if the live entries outgrow its capacity
  * (E + 1 entries is ample: live entries are far fewer than pushes).
- * d_stats: one gh_ssspstats (device).  Asynchronous on the set's stream;
- * errors surface at heap_sync.  The heap is empty again afterwards. */
+ * d_stats: one gh_ssspstats (device).  trace (host struct, may be NULL):
+ * record every heap operation (slower; for verification).  Asynchronous on
+ * the set's stream; errors surface at heap_sync.  The heap is empty again
+ * afterwards. */
 int heap_sssp(gh_heap_t h, uint32_t V, const uint32_t *d_rowptr, const uint32_t *d_col,
               const uint32_t *d_w, uint32_t src, uint32_t *d_dist, uint64_t *d_push,
-              uint64_t push_per_wg, gh_ssspstats *d_stats, const gh_tuning *tuning);
+              uint64_t push_per_wg, gh_ssspstats *d_stats, const gh_tuning *tuning,
+              const gh_sssptrace *trace);
 
 /* Wait for the set's stream; return the sticky device error (GH_OK if none). */
 int heap_sync(gh_heap_t h);

@@ -650,6 +650,37 @@ hipError_t launch_knap_k<GH_K>(const KnapArgs& a) {
 // entries it popped, so the count reaches zero only when the heap is empty
 // and no workgroup holds entries, and it stays zero from then on.
 // ---------------------------------------------------------------------------
+// Traced runs: record one heap operation.  Thread 0 claims a record and room
+// for `count` entries; the workgroup copies the entries.
+template <int T>
+__device__ void sssp_trace(const gh_sssptrace& tr, SsspState* st, u64 ticket, u32 kind,
+                           const u64* src, u32 count, const OpResult& r, const OpShared& sh,
+                           u64& s_off) {
+  if (threadIdx.x == 0) {
+    const u64 i = atomicAdd(reinterpret_cast<unsigned long long*>(&st->trace_ops), 1ull);
+    const u64 off = atomicAdd(reinterpret_cast<unsigned long long*>(&st->trace_keys),
+                              (unsigned long long)count);
+    const bool fits = i < tr.op_cap && off + count <= tr.key_cap;
+    if (fits) {
+      gh_ssspop rec{};
+      rec.ticket = ticket;
+      rec.off = off;
+      rec.count = count;
+      rec.kind = kind;
+      // what the operation saw and did: m and s at the root, flags, levels
+      rec.reserved = (sh.m & 0xFFFFFFFFull) << 32 | (sh.s & 0xFFFFull) << 16 |
+                     (u64)(r.flags & 0xFF) << 8 | (u64)(r.levels & 0xFF);
+      tr.d_ops[i] = rec;
+    }
+    s_off = fits ? off : ~0ull;
+  }
+  __syncthreads();
+  const u64 off = s_off;
+  if (off != ~0ull)
+    for (u32 j = threadIdx.x; j < count; j += T) tr.d_keys[off + j] = src[j];
+  __syncthreads();
+}
+
 template <int K, int T>
 __global__ __launch_bounds__(T) void k_sssp(const HeapDesc* __restrict__ descs, u32 V,
                                             const u32* __restrict__ rowptr,
@@ -657,10 +688,11 @@ __global__ __launch_bounds__(T) void k_sssp(const HeapDesc* __restrict__ descs, 
                                             const u32* __restrict__ wt, u32* __restrict__ dist,
                                             u64* __restrict__ push, u64 push_per_wg,
                                             gh_ssspstats* __restrict__ stats,
-                                            SsspState* __restrict__ st, Ctl* __restrict__ ctl) {
+                                            SsspState* __restrict__ st, gh_sssptrace tr,
+                                            Ctl* __restrict__ ctl) {
   __shared__ __align__(16) u64 lds[5 * K];
   __shared__ OpShared sh;
-  __shared__ u64 s_ticket;
+  __shared__ u64 s_ticket, s_toff;
   __shared__ u32 s_exit, s_idle, s_cnt, s_stale;
   const int tid = threadIdx.x;
   const HeapDesc H = descs[0];
@@ -693,6 +725,8 @@ __global__ __launch_bounds__(T) void k_sssp(const HeapDesc* __restrict__ descs, 
       ++ops;
       __syncthreads();
       heap_t += now_ticks() - t0;
+      if (tr.d_ops && r.ok)
+        sssp_trace<T>(tr, st, s_ticket, GH_OP_DELETE_MIN, out, r.count, r, sh, s_toff);
     }
     if (!r.ok) break;
     if (r.count == 0) {
@@ -767,6 +801,9 @@ __global__ __launch_bounds__(T) void k_sssp(const HeapDesc* __restrict__ descs, 
       const u32 nn = c - j < (u32)K ? c - j : (u32)K;
       const OpResult ri = op_insert<K, T>(H, s_ticket, mine + j, nn, lds, sh, ctl);
       ++ops;
+      // (the batch in `mine` is unchanged by the insert)
+      if (tr.d_ops && ri.ok)
+        sssp_trace<T>(tr, st, s_ticket, GH_OP_INSERT, mine + j, nn, ri, sh, s_toff);
       ok = ri.ok && !(ri.flags & F_REJECT);
       if (ri.flags & F_REJECT) {
         // the heap is full: a dropped entry would lose a vertex, stop the run
@@ -801,7 +838,8 @@ __global__ __launch_bounds__(T) void k_sssp(const HeapDesc* __restrict__ descs, 
 template <int K, int T>
 static hipError_t launch_sssp_t(const SsspArgs& a) {
   hipLaunchKernelGGL((k_sssp<K, T>), dim3(a.workgroups), dim3(T), 0, a.stream, a.descs, a.V,
-                     a.rowptr, a.col, a.w, a.dist, a.push, a.push_per_wg, a.stats, a.st, a.ctl);
+                     a.rowptr, a.col, a.w, a.dist, a.push, a.push_per_wg, a.stats, a.st, a.trace,
+                     a.ctl);
   return hipGetLastError();
 }
 

@@ -117,8 +117,10 @@ hipError_t launch_knap_k(const KnapArgs& a);
 struct alignas(256) SsspState {
   u64 next_ticket;   // dynamic root tickets of heap 0
   u64 outstanding;   // entries pushed and not yet fully processed
+  u64 trace_ops;     // trace cursors: records and entries claimed
+  u64 trace_keys;
   u32 done;
-  u32 pad[59];
+  u32 pad[55];
 };
 struct SsspArgs {
   const HeapDesc* descs;
@@ -132,6 +134,7 @@ struct SsspArgs {
   u64 push_per_wg;
   gh_ssspstats* stats;
   SsspState* st;
+  gh_sssptrace trace;   // d_ops == nullptr: no trace
   Ctl* ctl;
   u32 workgroups;
   u32 threads;

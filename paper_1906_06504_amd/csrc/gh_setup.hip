@@ -64,6 +64,8 @@ __global__ void k_sssp_init(const HeapDesc* __restrict__ descs, SsspState* st, u
   if (i0 == 0) {
     st->next_ticket = descs[0].meta->base + 1;
     st->outstanding = 1;   // the source's entry
+    st->trace_ops = 0;
+    st->trace_keys = 0;
     st->done = 0;
     push[0] = (u64)src;   // entry (0 << 32 | src)
     u64* sw = reinterpret_cast<u64*>(stats);
@@ -83,12 +85,17 @@ hipError_t launch_sssp_init(const HeapDesc* descs, SsspState* st, u32* dist, u32
 
 // After an SSSP run: the ticket base becomes the next dynamic ticket, so the
 // next submission's base is exact however many tickets the run took.
-__global__ void k_sssp_fini(const HeapDesc* __restrict__ descs, const SsspState* st) {
-  if (threadIdx.x == 0) descs[0].meta->base = st->next_ticket;
+__global__ void k_sssp_fini(const HeapDesc* __restrict__ descs, const SsspState* st,
+                            gh_ssspstats* stats) {
+  if (threadIdx.x == 0) {
+    descs[0].meta->base = st->next_ticket;
+    stats->traced = st->trace_ops;
+  }
 }
 
-hipError_t launch_sssp_fini(const HeapDesc* descs, const SsspState* st, hipStream_t stream) {
-  hipLaunchKernelGGL(k_sssp_fini, dim3(1), dim3(64), 0, stream, descs, st);
+hipError_t launch_sssp_fini(const HeapDesc* descs, const SsspState* st, gh_ssspstats* stats,
+                            hipStream_t stream) {
+  hipLaunchKernelGGL(k_sssp_fini, dim3(1), dim3(64), 0, stream, descs, st, stats);
   return hipGetLastError();
 }
 

@@ -19,7 +19,8 @@ hipError_t launch_prep(const HeapDesc* descs, u32 nheaps, Ctl* ctl, hipStream_t 
 hipError_t launch_serve_reset(ServeHead* head, hipStream_t st);
 hipError_t launch_sssp_init(const HeapDesc* descs, SsspState* st, u32* dist, u32 V, u32 src,
                             u64* push, gh_ssspstats* stats, hipStream_t stream);
-hipError_t launch_sssp_fini(const HeapDesc* descs, const SsspState* st, hipStream_t stream);
+hipError_t launch_sssp_fini(const HeapDesc* descs, const SsspState* st, gh_ssspstats* stats,
+                            hipStream_t stream);
 }  // namespace gh
 
 struct gh_heap {
@@ -466,12 +467,14 @@ int heap_knapsack(gh_heap_t h, uint32_t ninst, const uint32_t* d_item_off, const
 
 int heap_sssp(gh_heap_t h, uint32_t V, const uint32_t* d_rowptr, const uint32_t* d_col,
               const uint32_t* d_w, uint32_t src, uint32_t* d_dist, uint64_t* d_push,
-              uint64_t push_per_wg, gh_ssspstats* d_stats, const gh_tuning* t) {
+              uint64_t push_per_wg, gh_ssspstats* d_stats, const gh_tuning* t,
+              const gh_sssptrace* trace) {
   if (!h) return GH_EINVAL;
   if (h->sticky != GH_OK) return h->sticky;
   if (V == 0 || src >= V || !d_rowptr || !d_col || !d_w || !d_dist || !d_push || !d_stats ||
       push_per_wg == 0)
     return GH_EINVAL;
+  if (trace && (!trace->d_ops || !trace->d_keys)) return GH_EINVAL;
   u32 threads = (t && t->threads) ? t->threads : default_threads(h->k);
   if (!heap_supported_shape(h->k, threads)) return GH_EINVAL;
   u32 wg = (t && t->workgroups) ? t->workgroups : 256;
@@ -507,12 +510,13 @@ int heap_sssp(gh_heap_t h, uint32_t V, const uint32_t* d_rowptr, const uint32_t*
   a.push_per_wg = push_per_wg;
   a.stats = d_stats;
   a.st = h->sssp;
+  a.trace = trace ? *trace : gh_sssptrace{nullptr, 0, nullptr, 0};
   a.ctl = h->ctl;
   a.workgroups = wg;
   a.threads = threads;
   a.stream = h->stream;
   if (launch_sssp(h, a) != hipSuccess) return GH_EDEVICE;
-  if (launch_sssp_fini(h->descs, h->sssp, h->stream) != hipSuccess) return GH_EDEVICE;
+  if (launch_sssp_fini(h->descs, h->sssp, d_stats, h->stream) != hipSuccess) return GH_EDEVICE;
   return GH_OK;
 }
 

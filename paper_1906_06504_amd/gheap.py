@@ -42,8 +42,10 @@ assert OP_DTYPE.itemsize == 32 and LOG_DTYPE.itemsize == 32 and REQ_DTYPE.itemsi
 assert KNAP_DTYPE.itemsize == 32
 SSSP_DTYPE = np.dtype([("popped", "<u8"), ("stale", "<u8"), ("pushed", "<u8"), ("heap_ops", "<u8"),
                        ("heap_ticks", "<u8"), ("relax_ticks", "<u8"), ("rounds", "<u8"),
-                       ("reserved", "<u8")])
-assert SSSP_DTYPE.itemsize == 64
+                       ("traced", "<u8")])
+SSSPOP_DTYPE = np.dtype([("ticket", "<u8"), ("off", "<u8"), ("count", "<u4"), ("kind", "<u4"),
+                         ("reserved", "<u8")])
+assert SSSP_DTYPE.itemsize == 64 and SSSPOP_DTYPE.itemsize == 32
 
 REQ_ADMITTED = 1
 REQ_DEFERRED = 2
@@ -75,6 +77,12 @@ _lib = None
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("workgroups", ctypes.c_uint32), ("threads", ctypes.c_uint32)]
+
+
+class SsspTrace(ctypes.Structure):
+    """struct gh_sssptrace (device pointers and capacities)."""
+    _fields_ = [("d_ops", ctypes.c_void_p), ("op_cap", ctypes.c_uint64),
+                ("d_keys", ctypes.c_void_p), ("key_cap", ctypes.c_uint64)]
 
 
 def load_library(path: str = LIB_PATH):
@@ -109,7 +117,7 @@ def load_library(path: str = LIB_PATH):
         "heap_knapsack": (i32, [vp, u32, vp, vp, vp, vp, vp, vp, u64, vp, vp,
                                 ctypes.POINTER(_Tuning)]),
         "heap_sssp": (i32, [vp, u32, vp, vp, vp, u32, vp, vp, u64, vp,
-                            ctypes.POINTER(_Tuning)]),
+                            ctypes.POINTER(_Tuning), ctypes.POINTER(SsspTrace)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -50,18 +50,25 @@ class Solver:
         self.dist = torch.empty(max(1, graph.V), dtype=torch.int32, device=device)
         self.stats = torch.zeros(G.SSSP_DTYPE.itemsize, dtype=torch.uint8, device=device)
 
-    def launch(self, src: int = 0):
-        """Enqueue a run on the heap set's stream (no synchronization)."""
+    def launch(self, src: int = 0, trace=None):
+        """Enqueue a run on the heap set's stream (no synchronization).
+        `trace`: (ops uint8 tensor, keys int64 tensor) to record every heap
+        operation, or None."""
         t = G._Tuning(self.workgroups, self.threads)
+        tr = None
+        if trace is not None:
+            ops, keys = trace
+            tr = ctypes.byref(G.SsspTrace(ops.data_ptr(), ops.numel() // G.SSSPOP_DTYPE.itemsize,
+                                          keys.data_ptr(), keys.numel()))
         rc = self.hs.lib.heap_sssp(self.hs.h, self.g.V, self.g.rowptr.data_ptr(),
                                    self.g.col.data_ptr(), self.g.w.data_ptr(), src,
                                    self.dist.data_ptr(), self.push.data_ptr(), self.push_per_wg,
-                                   self.stats.data_ptr(), ctypes.byref(t))
+                                   self.stats.data_ptr(), ctypes.byref(t), tr)
         G._check(rc, "heap_sssp")
 
-    def run(self, src: int = 0):
+    def run(self, src: int = 0, trace=None):
         """Solve; returns (distances as uint32 numpy, counters record)."""
-        self.launch(src)
+        self.launch(src, trace)
         rc = self.hs.sync()
         if rc != G.GH_OK:
             raise G.GHeapError(rc, "heap_sssp (device)")
@@ -69,5 +76,25 @@ class Solver:
         s = self.stats.cpu().numpy().view(G.SSSP_DTYPE)[0].copy()
         return d, s
 
+    def new_trace(self, op_cap: int, key_cap: int):
+        """Device buffers for a trace of up to op_cap operations and key_cap
+        entries."""
+        ops = torch.zeros(op_cap * G.SSSPOP_DTYPE.itemsize, dtype=torch.uint8,
+                          device=self.dist.device)
+        keys = torch.zeros(key_cap, dtype=torch.int64, device=self.dist.device)
+        return ops, keys
+
     def close(self):
         self.hs.close()
+
+
+def trace_to_host(trace, stats):
+    """(records sorted by ticket, keys) of a finished traced run."""
+    ops, keys = trace
+    n = int(stats["traced"])
+    cap = ops.numel() // G.SSSPOP_DTYPE.itemsize
+    if n > cap:
+        raise ValueError("trace cut: %d operations, room for %d" % (n, cap))
+    recs = ops.cpu().numpy().view(G.SSSPOP_DTYPE)[:n].copy()
+    recs = recs[np.argsort(recs["ticket"], kind="stable")]
+    return recs, keys.cpu().numpy().view(np.uint64)

@@ -92,6 +92,22 @@ def test_concurrent_replay(G, k, wg):
     hs.close()
 
 
+@pytest.mark.parametrize("k,threads,wg", [(32, 64, 128), (64, 128, 128), (256, 256, 96),
+                                           (512, 256, 96), (512, 512, 96), (1024, 256, 64),
+                                           (1024, 1024, 64)])
+def test_concurrent_near_empty(G, k, threads, wg):
+    """A heap that keeps draining: inserts of U[1,k] entries and
+    deleteMin(k) with equal odds from an empty start, so most operations
+    meet an empty heap, a partial buffer only, or one or two nodes, with
+    many in flight.  Replay is exact."""
+    ops = W.mixed_ops(300 * k, k, seed=500 + k + threads, first_id=0)
+    _print("near-empty k=%d threads=%d wg=%d ops=%d" % (k, threads, wg, len(ops)))
+    hs, out, counts, log = run_gpu(ops, k, max_keys=len(ops) * k, workgroups=wg, threads=threads)
+    replay_and_compare(ops, k, out, counts, log)
+    check_gpu_state(hs, 0, k)
+    hs.close()
+
+
 def test_concurrent_small_k_heavy_contention(G):
     """k = 32, 512 workgroups on a small heap: many cooperations and absent
     children; the replay must still be exact."""

@@ -32,6 +32,8 @@ def _check(S, rowptr, col, w, src, k, workgroups, threads=0):
     sol = S.Solver(g, k, workgroups=workgroups, threads=threads)
     d, st = sol.run(src)
     want = oracle.dijkstra(V, rowptr, col, w, src)
+    _p("  popped=%d stale=%d pushed=%d heap_ops=%d" % (int(st["popped"]), int(st["stale"]),
+                                                       int(st["pushed"]), int(st["heap_ops"])))
     assert np.array_equal(d, want), "%d distances differ" % int(np.sum(d != want))
     reached = int(np.sum(want != 0xFFFFFFFF))
     # every reached vertex is expanded at least once (more than once only
@@ -39,9 +41,7 @@ def _check(S, rowptr, col, w, src, k, workgroups, threads=0):
     # pushed entry is popped, so the heap ends empty
     assert int(st["popped"]) - int(st["stale"]) >= reached
     assert int(st["pushed"]) + 1 == int(st["popped"])
-    _p("  popped=%d stale=%d reexpanded=%d heap_ops=%d" % (
-        int(st["popped"]), int(st["stale"]), int(st["popped"]) - int(st["stale"]) - reached,
-        int(st["heap_ops"])))
+    _p("  reexpanded=%d" % (int(st["popped"]) - int(st["stale"]) - reached))
     assert sol.hs.size(0) == 0
     return sol, st
 
@@ -88,3 +88,51 @@ def test_sssp_full_size(S):
     the benchmark's launch shape: all distances equal CPU Dijkstra's."""
     rowptr, col, w, src, k = W.config3()
     _check(S, rowptr, col, w, src, k, 256, 512)[0].close()
+
+
+TRACE_CASES = [(3000, 64, 32, 0, 1), (8000, 512, 96, 256, 2), (8000, 512, 96, 512, 3),
+               (20000, 128, 128, 0, 4), (8000, 512, 96, 256, 5), (8000, 512, 96, 256, 6),
+               (8000, 512, 96, 64, 7), (8000, 512, 96, 1024, 8), (6000, 256, 128, 128, 9),
+               (6000, 256, 256, 256, 10), (12000, 32, 256, 64, 11), (12000, 1024, 64, 256, 12)]
+
+
+@pytest.mark.parametrize("V,k,wg,threads,seed", TRACE_CASES)
+def test_sssp_heap_trace_replays(S, V, k, wg, threads, seed):
+    """Every heap operation of an SSSP run, replayed on the oracle in ticket
+    order (Theorem 1), gives the same deleteMin outputs; tickets are
+    consecutive; then the distances equal Dijkstra's."""
+    from paper_1906_06504_amd import sssp as SP
+    rowptr, col, w = W.sssp_graph(V, seed=4242 + seed)
+    _p("sssp-trace V=%d k=%d workgroups=%d threads=%d seed=%d" % (V, k, wg, threads, seed))
+    g = S.Graph(rowptr, col, w)
+    sol = S.Solver(g, k, workgroups=wg, threads=threads)
+    tr = sol.new_trace(1 << 18, 1 << 24)
+    d, st = sol.run(0, trace=tr)
+    recs, keys = SP.trace_to_host(tr, st)
+    _p("  traced ops=%d" % recs.size)
+    t = recs["ticket"].astype(np.int64)
+    assert np.array_equal(t, np.arange(t[0], t[0] + t.size)), "tickets not consecutive"
+    oh = oracle.OracleHeap(k)
+    oh.insert(np.array([0], np.uint64))   # the source's entry, the first ticket
+    for i, r in enumerate(recs):
+        o, c = int(r["off"]), int(r["count"])
+        x = int(r["reserved"])
+        assert (x >> 32, (x >> 16) & 0xFFFF) == (oh.m, oh.s), \
+            "op %d (ticket %d): root saw m=%d s=%d, oracle has m=%d s=%d" % (
+                i, int(r["ticket"]), x >> 32, (x >> 16) & 0xFFFF, oh.m, oh.s)
+        if r["kind"] == W.OP_INSERT:
+            oh.insert(keys[o:o + c])
+        else:
+            want = oh.delete_min()
+            if not (c == want.size and np.array_equal(keys[o:o + c], want)):
+                for j in range(max(0, i - 6), min(recs.size, i + 3)):
+                    q = recs[j]
+                    x = int(q["reserved"])
+                    _p("  op %d ticket %d kind %d count %d m %d s %d flags %#x levels %d" % (
+                        j, int(q["ticket"]), int(q["kind"]), int(q["count"]), x >> 32,
+                        (x >> 16) & 0xFFFF, (x >> 8) & 0xFF, x & 0xFF))
+                pytest.fail("op %d (ticket %d) differs: count %d vs %d" % (
+                    i, int(r["ticket"]), c, want.size))
+    assert oh.size == 0
+    assert np.array_equal(d, oracle.dijkstra(V, rowptr, col, w, 0))
+    sol.close()
