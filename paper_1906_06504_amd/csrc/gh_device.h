@@ -91,17 +91,14 @@ __device__ __forceinline__ u64 lw_ticket(u64 w) { return w >> 3; }
 // ---------------------------------------------------------------------------
 // Memory ordering across the XCDs (each has its own L2).
 //
-// Node payloads move with ordinary loads and stores; lock words and the root
-// word are agent-scope atomics.  A holder publishes with publish(): every
-// wave waits for its stores, the workgroup meets at a barrier, and thread 0
-// writes the XCD's L2 back to memory and waits for that write-back before it
-// issues any releasing store.  An acquirer invalidates its XCD's L2 after
-// taking the lock and before reading the protected data.
-//
-// The two cache operations are written out with their waits: the compiler's
-// own release sequence can omit the wait after the L2 write-back when it
-// sees no other outstanding memory operation, which lets the releasing store
-// overtake the write-back.
+// Lock words and the root word are agent-scope atomics.  Heap payload (nodes
+// and the partial buffer) also moves with device-scope accesses: buffer
+// loads and stores carrying the device-scope cache bit, which read from and
+// write through to the point of coherence of all XCDs.  So no whole-cache
+// write-back or invalidate is needed: a holder publishes with publish()
+// (every wave waits until its stores are complete, then the workgroup meets
+// at a barrier) and thread 0 then releases with a relaxed store; an acquirer
+// waits for the lock atomic to return before any payload load is issued.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ u64 ld_relaxed(const u64* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -126,22 +123,60 @@ __device__ __forceinline__ u64 xchg_relaxed(u64* p, u64 v) {
   return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// write the XCD's L2 back to memory and wait until it is done
-__device__ __forceinline__ void l2_writeback() {
-  asm volatile("s_waitcnt vmcnt(0)\n\tbuffer_wbl2 sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
-}
-// acquire side: after the lock atomic returned, drop stale L2 and L1 lines
+// Acquire side: the lock atomic has returned before any later load issues.
 __device__ __forceinline__ void fence_acquire() {
-  asm volatile("s_waitcnt vmcnt(0)\n\tbuffer_inv sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
-// All threads: make this workgroup's global stores visible at agent scope.
-// Afterwards thread 0 may release locks with relaxed atomic stores.
+// All threads: this workgroup's heap stores are complete at the point of
+// coherence.  Afterwards thread 0 may release locks with relaxed stores.
 __device__ __forceinline__ void publish() {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
-  if (threadIdx.x == 0) l2_writeback();
 }
+
+// Device-scope transfers of heap memory.  A buffer resource describes one
+// region (a node or the partial buffer) whose base is the same in every
+// lane; offsets are per lane, in bytes.
+constexpr int CP_DEVICE = 16;   // cache-policy operand: device scope (sc1)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+struct HeapRegion {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ HeapRegion(const u64* base, u32 bytes) {
+    const u64 a = reinterpret_cast<u64>(base);
+    const u32 lo = __builtin_amdgcn_readfirstlane((u32)a);
+    const u32 hi = __builtin_amdgcn_readfirstlane((u32)(a >> 32));
+    r = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(((u64)hi << 32) | lo), 0,
+                                          bytes, 0x00020000);
+  }
+  __device__ __forceinline__ ulonglong2 load16(u32 off) const {
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, CP_DEVICE);
+    ulonglong2 o;
+    o.x = (u64)v.x | ((u64)v.y << 32);
+    o.y = (u64)v.z | ((u64)v.w << 32);
+    return o;
+  }
+  __device__ __forceinline__ u64 load8(u32 off) const {
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, CP_DEVICE);
+    return (u64)v.x | ((u64)v.y << 32);
+  }
+  __device__ __forceinline__ void store16(u32 off, u64 a, u64 b) const {
+    u32x4 v;
+    v.x = (u32)a;
+    v.y = (u32)(a >> 32);
+    v.z = (u32)b;
+    v.w = (u32)(b >> 32);
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, CP_DEVICE);
+  }
+  __device__ __forceinline__ void store8(u32 off, u64 a) const {
+    u32x2 v;
+    v.x = (u32)a;
+    v.y = (u32)(a >> 32);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, CP_DEVICE);
+  }
+};
 
 __device__ __forceinline__ u64 now_ticks() { return wall_clock64(); }
 
@@ -212,21 +247,12 @@ __device__ __forceinline__ u64* lock_ptr(const HeapDesc& H, u32 c) {
 }
 
 // ---------------------------------------------------------------------------
-// Coalesced node transfers between global memory and LDS (16 bytes a lane).
+// Coalesced node transfers between heap memory and LDS (16 bytes a lane).
 // ---------------------------------------------------------------------------
 template <int K, int T>
-__device__ __forceinline__ void load_node(u64* __restrict__ lds, const u64* __restrict__ g) {
-  for (int i = threadIdx.x * 2; i < K; i += 2 * T) {
-    ulonglong2 v = *reinterpret_cast<const ulonglong2*>(g + i);
-    *reinterpret_cast<ulonglong2*>(lds + i) = v;
-  }
-}
-template <int K, int T>
-__device__ __forceinline__ void store_node(u64* __restrict__ g, const u64* __restrict__ lds) {
-  for (int i = threadIdx.x * 2; i < K; i += 2 * T) {
-    ulonglong2 v = *reinterpret_cast<const ulonglong2*>(lds + i);
-    *reinterpret_cast<ulonglong2*>(g + i) = v;
-  }
+__device__ __forceinline__ void store_node(u64* g, const u64* __restrict__ lds) {
+  const HeapRegion R(g, K * 8);
+  for (int i = threadIdx.x * 2; i < K; i += 2 * T) R.store16(i * 8, lds[i], lds[i + 1]);
 }
 // A node's share per thread held in registers, so that several node loads
 // (and lock atomics) can be in flight before anything is written to LDS.
@@ -234,11 +260,12 @@ template <int K, int T>
 struct NodeRegs {
   static constexpr int C = (K / 2 + T - 1) / T;  // 16-byte chunks per thread
   ulonglong2 v[C];
-  __device__ __forceinline__ void load(const u64* __restrict__ g) {
+  __device__ __forceinline__ void load(const u64* g) {
+    const HeapRegion R(g, K * 8);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int i = (threadIdx.x + c * T) * 2;
-      if (i < K) v[c] = *reinterpret_cast<const ulonglong2*>(g + i);
+      if (i < K) v[c] = R.load16(i * 8);
     }
   }
   __device__ __forceinline__ void store(u64* __restrict__ lds) const {
@@ -250,7 +277,7 @@ struct NodeRegs {
   }
 };
 
-// n entries, any n, 8 bytes a lane
+// n entries, any n, 8 bytes a lane: caller memory to LDS and back
 template <int T>
 __device__ __forceinline__ void load_n(u64* __restrict__ lds, const u64* __restrict__ g, u32 n) {
   for (u32 i = threadIdx.x; i < n; i += T) lds[i] = g[i];
@@ -259,9 +286,17 @@ template <int T>
 __device__ __forceinline__ void store_n(u64* __restrict__ g, const u64* __restrict__ lds, u32 n) {
   for (u32 i = threadIdx.x; i < n; i += T) g[i] = lds[i];
 }
-template <int T>
-__device__ __forceinline__ void copy_n(u64* __restrict__ dst, const u64* __restrict__ src, u32 n) {
-  for (u32 i = threadIdx.x; i < n; i += T) dst[i] = src[i];
+// n entries from LDS to heap memory (the partial buffer)
+template <int K, int T>
+__device__ __forceinline__ void store_heap_n(u64* g, const u64* __restrict__ lds, u32 n) {
+  const HeapRegion R(g, K * 8);
+  for (u32 i = threadIdx.x; i < n; i += T) R.store8(i * 8, lds[i]);
+}
+// n entries from heap memory (the partial buffer) to caller memory
+template <int K, int T>
+__device__ __forceinline__ void copy_heap_n(u64* __restrict__ dst, const u64* src, u32 n) {
+  const HeapRegion R(src, K * 8);
+  for (u32 i = threadIdx.x; i < n; i += T) dst[i] = R.load8(i * 8);
 }
 
 // ---------------------------------------------------------------------------
@@ -306,7 +341,8 @@ __device__ __forceinline__ void merge_path(const u64* A, int na, const u64* B, i
   }
 }
 
-// Destinations for merge output: LDS or global, written E entries a thread.
+// Destinations for merge output, written E entries a thread: LDS or caller
+// memory (Sink), or a region of heap memory (HeapSink, device scope).
 struct Sink {
   u64* p;
   __device__ __forceinline__ void put1(int off, u64 x) const { p[off] = x; }
@@ -329,23 +365,40 @@ struct Sink {
     for (int e = 0; e < E; ++e) q[e] = v[e];
   }
 };
+struct HeapSink {
+  HeapRegion R;
+  __device__ __forceinline__ HeapSink(u64* p, u32 bytes) : R(p, bytes) {}
+  __device__ __forceinline__ void put1(int off, u64 x) const { R.store8(off * 8, x); }
+  template <int E>
+  __device__ __forceinline__ void put_range(int off, const u64 (&v)[E]) const {
+    if constexpr (E % 2 == 0) {
+      if ((off & 1) == 0) {
+#pragma unroll
+        for (int e = 0; e < E; e += 2) R.store16((off + e) * 8, v[e], v[e + 1]);
+        return;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) R.store8((off + e) * 8, v[e]);
+  }
+};
 
 // Workgroup-wide MergeAndSort (Sec. 3.2.1 display equation, generalized to
 // unequal sizes): the stable merge of A[0,na) and B[0,nb) is split at
 // `split`; positions < split go to lo[p], the rest to hi[p - split].  Inputs
 // must be in LDS and must not overlap the outputs.  No barrier inside: the
 // caller synchronizes before reusing inputs or reading outputs.
-template <int E, int T>
+template <int E, int T, class SinkLo, class SinkHi>
 __device__ __forceinline__ void merge_split(const u64* A, int na, const u64* B, int nb, int split,
-                                            Sink lo, Sink hi) {
+                                            const SinkLo& lo, const SinkHi& hi) {
   const int total = na + nb;
   for (int d = threadIdx.x * E; d < total; d += T * E) {
     u64 v[E];
     merge_path<E>(A, na, B, nb, d, v);
     if (d + E <= total && d + E <= split) {
-      lo.put_range<E>(d, v);
+      lo.template put_range<E>(d, v);
     } else if (d + E <= total && d >= split) {
-      hi.put_range<E>(d - split, v);
+      hi.template put_range<E>(d - split, v);
     } else {
 #pragma unroll
       for (int e = 0; e < E; ++e) {

@@ -645,10 +645,12 @@ hipError_t launch_knap_k<GH_K>(const KnapArgs& a) {
 // every workgroup takes the K nearest, skips entries whose vertex was since
 // reached by a shorter path, relaxes out-edges with an atomic minimum, and
 // inserts one entry per strict improvement.  Tickets are taken dynamically.
-// Termination: `outstanding` counts entries pushed and not yet processed; a
-// workgroup adds its pushes (after inserting them) before it subtracts the
-// entries it popped, so the count reaches zero only when the heap is empty
-// and no workgroup holds entries, and it stays zero from then on.
+// Termination: `outstanding` counts entries pushed and not yet processed.  A
+// workgroup adds its pushes before it inserts them (an inserted entry can be
+// popped and retired by another workgroup at once) and subtracts the entries
+// it popped only after its inserts, so the count bounds the entries in the
+// heap plus those held by workgroups; it reaches zero only when both are
+// none, and stays zero from then on.
 // ---------------------------------------------------------------------------
 // Traced runs: record one heap operation.  Thread 0 claims a record and room
 // for `count` entries; the workgroup copies the entries.
@@ -790,6 +792,12 @@ __global__ __launch_bounds__(T) void k_sssp(const HeapDesc* __restrict__ descs, 
     if (tid == 0) {
       stale += s_stale;
       if (s_cnt > push_per_wg) raise_error(ctl, ERR_NOMEM);
+      // count the pushes before any of them can be popped: once inserted,
+      // another workgroup may pop and retire them at once
+      if (c) {
+        atomicAdd(reinterpret_cast<unsigned long long*>(&st->outstanding), (unsigned long long)c);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      }
     }
     // insert the improvements, K at a time
     t0 = now_ticks();
@@ -814,10 +822,7 @@ __global__ __launch_bounds__(T) void k_sssp(const HeapDesc* __restrict__ descs, 
     heap_t += now_ticks() - t0;
     pushed += c;
     if (tid == 0) {
-      // pushes are counted before the popped entries are retired
-      if (c) atomicAdd(reinterpret_cast<unsigned long long*>(&st->outstanding),
-                       (unsigned long long)c);
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      // the popped entries are retired after their pushes are in the heap
       atomicAdd(reinterpret_cast<unsigned long long*>(&st->outstanding),
                 (unsigned long long)(0ull - (u64)r.count));
     }

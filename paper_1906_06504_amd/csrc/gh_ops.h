@@ -291,9 +291,9 @@ __device__ OpResult op_insert(const HeapDesc& H, u64 ticket, const u64* __restri
   if (!full) {
     // the partial buffer keeps everything; restore Property 3 against the root
     if (m >= 1 && !(N[K - 1] <= F[0])) {
-      merge_split<E, T>(N, K, F, (int)tot, K, Sink{root}, Sink{H.pb});
+      merge_split<E, T>(N, K, F, (int)tot, K, HeapSink(root, K * 8), HeapSink(H.pb, K * 8));
     } else {
-      store_n<T>(H.pb, F, tot);
+      store_heap_n<K, T>(H.pb, F, tot);
     }
     publish();
     if (tid == 0) release_root(meta, ticket, m, tot);
@@ -303,7 +303,7 @@ __device__ OpResult op_insert(const HeapDesc& H, u64 ticket, const u64* __restri
   // a full batch F goes down from the root; the rest stays in the pb
   res.flags |= F_FULL;
   const u32 rest = tot - K;
-  store_n<T>(H.pb, xfree, rest);
+  store_heap_n<K, T>(H.pb, xfree, rest);
   if (L == 0) {
     store_node<K, T>(root, F);
     publish();
@@ -326,7 +326,7 @@ __device__ OpResult op_insert(const HeapDesc& H, u64 ticket, const u64* __restri
       store_node<K, T>(cur_ptr, F);  // swap
       u64* x = F; F = N; N = x;
     } else {
-      merge_split<E, T>(N, K, F, K, K, Sink{cur_ptr}, Sink{spare});
+      merge_split<E, T>(N, K, F, K, K, HeapSink(cur_ptr, K * 8), Sink{spare});
       u64* x = F; F = spare; spare = x;
     }
     ++level;
@@ -418,7 +418,7 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
 
   if (m == 0) {
     // no node: the partial buffer is the whole heap
-    copy_n<T>(out, H.pb, s);
+    copy_heap_n<K, T>(out, H.pb, s);
     __syncthreads();   // every read of the pb is done before the root moves on
     if (tid == 0) release_root(meta, ticket, 0, 0);
     res.count = s;
@@ -515,7 +515,7 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
     if (hl) lc.load(H.nodes + 1 * (u64)K);   // node 2 is position 2
     if (hr) rc.load(node_ptr<K>(H, 3));
     if (s > 0 && !(C[K - 1] <= P[0])) {
-      merge_split<E, T>(C, K, P, (int)s, K, Sink{bufs[3]}, Sink{H.pb});
+      merge_split<E, T>(C, K, P, (int)s, K, Sink{bufs[3]}, HeapSink(H.pb, K * 8));
       __syncthreads();
       u64* x = bufs[0]; bufs[0] = bufs[3]; bufs[3] = x;
       C = bufs[0];
@@ -597,7 +597,7 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
         hi = Sm;             // lo is the big child's batch, already in place
         freeb = bufs[3];
       } else {
-        merge_split<E, T>(Lb, K, Rb, K, K, Sink{bufs[3]}, Sink{node_ptr<K>(H, big)});
+        merge_split<E, T>(Lb, K, Rb, K, K, Sink{bufs[3]}, HeapSink(node_ptr<K>(H, big), K * 8));
         __syncthreads();
         hi = bufs[3];
         freeb = Lb;
@@ -606,7 +606,7 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
         store_node<K, T>(cptr, hi);
         newcur = C;
       } else {
-        merge_split<E, T>(C, K, hi, K, K, Sink{cptr}, Sink{freeb});
+        merge_split<E, T>(C, K, hi, K, K, HeapSink(cptr, K * 8), Sink{freeb});
         __syncthreads();
         newcur = freeb;
       }
@@ -628,7 +628,7 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
         store_node<K, T>(cptr, X);
         newcur = C;
       } else {
-        merge_split<E, T>(C, K, X, K, K, Sink{cptr}, Sink{freeb});
+        merge_split<E, T>(C, K, X, K, K, HeapSink(cptr, K * 8), Sink{freeb});
         __syncthreads();
         newcur = freeb;
       }
