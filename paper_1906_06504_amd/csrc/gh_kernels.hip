@@ -108,15 +108,22 @@ __global__ __launch_bounds__(T) void k_ops(const HeapDesc* __restrict__ descs,
 
 // ---------------------------------------------------------------------------
 // Served form: one persistent launch.  Workgroup 0 is the scheduler: it
-// walks the requests in arrival order, waits for each arrival time, admits
-// the request if its heap's memory allows (deleteMins always; an insert when
-// the heap's size after everything admitted plus n fits max_keys, otherwise
-// it waits in the heap's FIFO of deferred inserts until admitted deleteMins
-// make room), and appends the admitted request's operations to a queue with
-// the heap's next tickets.  Every other workgroup is a slot that claims queue
-// entries in order and runs them exactly like k_ops.  A heap's admission
-// order depends only on its own requests, so its results are the same alone
-// and in any mix.
+// walks the requests in arrival order and admits every request once it is
+// due: deleteMins always; an insert when the heap's size after everything
+// admitted plus n fits max_keys, otherwise it waits in the heap's FIFO of
+// deferred inserts until admitted deleteMins make room.  An admitted
+// request's operations take the heap's next tickets and are appended to a
+// queue.  Every other workgroup is a slot that claims queue entries in order
+// and runs them exactly like k_ops.
+//
+// The scheduler works lane-parallel: heap h belongs to scheduler thread
+// h mod T.  It takes the requests in windows (the due prefix of a staged
+// chunk), sorts each window's requests stably by owner, and every thread
+// admits its own requests in stream order; queue slots come from a shared
+// counter, so one heap's operations stay in ticket order in the queue.  The
+// queue tail is published at the end of each window.  A heap's admissions
+// depend only on its own requests, so its results are the same alone and in
+// any mix.
 // ---------------------------------------------------------------------------
 // Scheduler's per-heap state, kept in LDS (dynamic shared memory sized by the
 // number of heaps) so that admitting a request touches no global memory on
@@ -131,6 +138,17 @@ struct SchedHot {
 static_assert(sizeof(SchedHot) == 32, "sched layout");
 extern __shared__ __align__(16) unsigned char gh_dyn_lds[];
 
+// Scheduler values shared by its threads.
+struct SchedShared {
+  u64 now;        // clock of the current window
+  u32 qtail;      // queue slots handed out
+  u32 wend;       // end of the current window (index in the chunk)
+  u32 overflow;   // the queue ran out of room
+};
+
+// Queue entries of a request rejected after its slots were handed out.
+constexpr u32 QUEUE_SKIP = 0xFFFFFFFFu;
+
 template <int K>
 struct Scheduler {
   u32 nheaps;
@@ -138,54 +156,48 @@ struct Scheduler {
   gh_reqrec* recs;
   ServeWork w;
   SchedHot* hot;
+  SchedShared* ss;
   u64 t0;
-  u32 tail;       // queue slots written
-  u32 published;  // queue slots published
-  bool overflow;
 
-  __device__ void put_op(u32 r, u32 heap, u32 kind, u32 n, u32 seq, u64 off) {
-    u64* qw = reinterpret_cast<u64*>(w.queue + tail);
+  __device__ void put_op(u32 slot, u32 r, u32 heap, u32 kind, u32 n, u32 seq, u64 off) const {
+    u64* qw = reinterpret_cast<u64*>(w.queue + slot);
     st_relaxed(qw + 0, (u64)heap | ((u64)kind << 32));
     st_relaxed(qw + 1, (u64)n | ((u64)seq << 32));
     st_relaxed(qw + 2, off);
-    __hip_atomic_store(w.qreq + tail, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    ++tail;
+    __hip_atomic_store(w.qreq + slot, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 
-  __device__ void publish_queue() {
-    if (published == tail) return;
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // queue entries are complete
-    __hip_atomic_store(&w.head->tail, tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    published = tail;
-  }
-
-  __device__ void write_rec(u32 r, const gh_reqrec& rec) {
+  __device__ void write_rec(u32 r, const gh_reqrec& rec) const {
     const u64* src = reinterpret_cast<const u64*>(&rec);
     u64* dst = reinterpret_cast<u64*>(recs + r);
 #pragma unroll
     for (int i = 0; i < 4; ++i) st_relaxed(dst + i, src[i]);
   }
 
-  __device__ void reject(u32 r, u32 kind) {
+  __device__ void reject(u32 r, u32 kind) const {
     gh_reqrec rec;
     rec.first_ticket = 0;
     rec.count = 0;
     rec.nops = 0;
     rec.kind = (uint8_t)kind;
     rec.flags = 0x40;
-    rec.t_admit = (u32)(now_ticks() - t0);
+    rec.t_admit = (u32)(ss->now - t0);
     rec.t_done = rec.t_admit;
     rec.reserved = 0;
     write_rec(r, rec);
   }
 
-  // Admit request r: its operations get the heap's next tickets.  A request
-  // that no longer fits the operation queue is rejected instead (its heap's
-  // tickets and size are left as they were).
-  __device__ void admit(u32 r, const gh_op& q, SchedHot& hs, u32 flags) {
+  // Admit request r: its operations get the heap's next tickets and queue
+  // slots.  A request that no longer fits the operation queue is rejected
+  // instead (its heap's tickets and size are left as they were; slots it was
+  // handed are marked to be skipped).
+  __device__ void admit(u32 r, const gh_op& q, SchedHot& hs, u32 flags) const {
     const u32 nops = q.kind == GH_OP_DELETE_MIN ? 1u : (q.n + K - 1) / K;
-    if ((u64)tail + nops > w.max_ops) {
-      overflow = true;
+    const u32 slot = atomicAdd(&ss->qtail, nops);
+    if ((u64)slot + nops > w.max_ops) {
+      for (u64 x = slot; x < w.max_ops && x < (u64)slot + nops; ++x)
+        put_op((u32)x, QUEUE_SKIP, QUEUE_SKIP, 0, 0, 0, 0);
+      ss->overflow = 1;
       reject(r, q.kind);
       return;
     }
@@ -195,7 +207,7 @@ struct Scheduler {
     rec.nops = (uint16_t)nops;
     rec.kind = (uint8_t)q.kind;
     rec.flags = (uint8_t)(flags | 1u);
-    rec.t_admit = (u32)(now_ticks() - t0);
+    rec.t_admit = (u32)(ss->now - t0);
     rec.t_done = rec.t_admit;
     rec.reserved = 0;
     // slots write count and t_done of this record: every word goes out
@@ -203,17 +215,61 @@ struct Scheduler {
     write_rec(r, rec);
     __hip_atomic_store(w.left + r, nops, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (q.kind == GH_OP_DELETE_MIN) {
-      put_op(r, q.heap, GH_OP_DELETE_MIN, 0, hs.seq++, q.off);
+      put_op(slot, r, q.heap, GH_OP_DELETE_MIN, 0, hs.seq++, q.off);
       hs.size -= hs.size < (u64)K ? hs.size : (u64)K;
     } else {
       for (u32 c = 0; c < nops; ++c) {
         const u32 nc = (q.n - c * K) < (u32)K ? (q.n - c * K) : (u32)K;
-        put_op(r, q.heap, GH_OP_INSERT, nc, hs.seq++, q.off + (u64)c * K);
+        put_op(slot + c, r, q.heap, GH_OP_INSERT, nc, hs.seq++, q.off + (u64)c * K);
       }
       hs.size += q.n;
     }
   }
+
+  // Request r (q) by its heap's owner thread, in stream order.
+  __device__ void process(u32 r, const gh_op& q, Ctl* ctl) const {
+    if (q.heap >= nheaps || q.kind > GH_OP_DELETE_MIN) {
+      reject(r, q.kind);
+      note_error(ctl, ERR_INVAL);
+      return;
+    }
+    SchedHot hs = hot[q.heap];
+    if (q.kind == GH_OP_DELETE_MIN) {
+      admit(r, q, hs, 0);
+      // room freed: admit deferred inserts of this heap in order
+      while (hs.head != SCHED_NONE) {
+        const gh_op d = reqs[hs.head];
+        if (hs.size + d.n > hs.cap) break;
+        const u32 dr = hs.head;
+        hs.head = w.next[dr];
+        if (hs.head == SCHED_NONE) w.heaps[q.heap].last = SCHED_NONE;
+        admit(dr, d, hs, 2u);
+      }
+    } else if ((u64)q.n > hs.cap || q.n > 65535u * (u32)K) {
+      reject(r, q.kind);
+    } else if (hs.head == SCHED_NONE && hs.size + q.n <= hs.cap) {
+      admit(r, q, hs, 0);
+    } else {
+      // wait for memory behind earlier deferred inserts
+      w.next[r] = SCHED_NONE;
+      const u32 last = hs.head == SCHED_NONE ? SCHED_NONE : w.heaps[q.heap].last;
+      if (last == SCHED_NONE) hs.head = r;
+      else w.next[last] = r;
+      w.heaps[q.heap].last = r;
+    }
+    hot[q.heap] = hs;
+  }
 };
+
+// 16 consecutive u32 from LDS (16-byte aligned) with four 16-byte loads.
+__device__ __forceinline__ void load_ids16(const u32* p, u32 (&ids)[16]) {
+  const uint4* q = reinterpret_cast<const uint4*>(p);
+  const uint4 a = q[0], b = q[1], c = q[2], d = q[3];
+  ids[0] = a.x; ids[1] = a.y; ids[2] = a.z; ids[3] = a.w;
+  ids[4] = b.x; ids[5] = b.y; ids[6] = b.z; ids[7] = b.w;
+  ids[8] = c.x; ids[9] = c.y; ids[10] = c.z; ids[11] = c.w;
+  ids[12] = d.x; ids[13] = d.y; ids[14] = d.z; ids[15] = d.w;
+}
 
 template <int K, int T>
 __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs, u32 nheaps,
@@ -227,7 +283,9 @@ __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs,
 
   if (blockIdx.x == 0) {
     // ---- scheduler ----
+    __shared__ SchedShared ss;
     SchedHot* hot = reinterpret_cast<SchedHot*>(gh_dyn_lds);
+    u32* cnt = reinterpret_cast<u32*>(gh_dyn_lds + (size_t)nheaps * sizeof(SchedHot));
     for (u32 h = tid; h < nheaps; h += T) {
       const u64 rw = ld_relaxed(&descs[h].meta->root);
       SchedHot hs;
@@ -239,84 +297,121 @@ __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs,
       hot[h] = hs;
       w.heaps[h].last = SCHED_NONE;
     }
-    __syncthreads();
-    constexpr u32 CH = (5 * K) / 4;   // request records staged in LDS per chunk
+    if (tid == 0) {
+      ss.now = now_ticks();
+      ss.qtail = 0;
+      ss.overflow = 0;
+    }
+    // a chunk of K requests staged in LDS: records, heap ids, window order
+    constexpr u32 CH = K;
     gh_op* stage = reinterpret_cast<gh_op*>(lds);
+    u32* hid = reinterpret_cast<u32*>(lds + 4 * K);
+    uint16_t* list = reinterpret_cast<uint16_t*>(lds + 4 * K + K / 2);
     Scheduler<K> S;
     S.nheaps = nheaps;
     S.reqs = reqs;
     S.recs = recs;
     S.w = w;
     S.hot = hot;
+    S.ss = &ss;
     S.t0 = ctl->t0;
-    S.tail = 0;
-    S.published = 0;
-    S.overflow = false;
+    const u32 mine = (u32)tid;
+    auto due_of = [&](const gh_op& q) -> u64 {
+      // arrival, bounded to one minute after the start
+      const u64 ns = q.arrival_ns < 60000000000ull ? q.arrival_ns : 60000000000ull;
+      return S.t0 + (ns * clock_mhz) / 1000ull;
+    };
+    __syncthreads();
     for (u32 c0 = 0; c0 < nreq; c0 += CH) {
       const u32 cn = nreq - c0 < CH ? nreq - c0 : CH;
-      for (u32 j = tid; j < cn; j += T) stage[j] = reqs[c0 + j];
+      for (u32 j = tid; j < cn; j += T) {
+        const gh_op q = reqs[c0 + j];
+        stage[j] = q;
+        hid[j] = q.heap;
+      }
       __syncthreads();
-      if (tid == 0) {
-        for (u32 j = 0; j < cn; ++j) {
-          const u32 r = c0 + j;
-          const gh_op q = stage[j];
-          // arrival (bounded to one minute after the start)
-          const u64 ns = q.arrival_ns < 60000000000ull ? q.arrival_ns : 60000000000ull;
-          const u64 due = S.t0 + (ns * clock_mhz) / 1000ull;
-          if (now_ticks() < due) {
-            S.publish_queue();   // nothing else to do until then
-            while (now_ticks() < due) {
-              if (ld_relaxed32(&ctl->abort)) break;
-              __builtin_amdgcn_s_sleep(4);
-            }
+      u32 w0 = 0;
+      while (w0 < cn) {
+        // the window: from w0 up to the first request not due yet (w0 itself
+        // is waited for)
+        if (tid == 0) {
+          const u64 due0 = due_of(stage[w0]);
+          u64 now = now_ticks();
+          while (now < due0) {
+            if (ld_relaxed32(&ctl->abort)) break;
+            __builtin_amdgcn_s_sleep(4);
+            now = now_ticks();
           }
-          if (q.heap >= nheaps || q.kind > GH_OP_DELETE_MIN) {
-            S.reject(r, q.kind);
-            note_error(ctl, ERR_INVAL);
-            continue;
-          }
-          SchedHot hs = hot[q.heap];
-          if (q.kind == GH_OP_DELETE_MIN) {
-            S.admit(r, q, hs, 0);
-            // room freed: admit deferred inserts of this heap in order
-            while (hs.head != SCHED_NONE) {
-              const gh_op d = reqs[hs.head];
-              if (hs.size + d.n > hs.cap) break;
-              const u32 dr = hs.head;
-              hs.head = w.next[dr];
-              if (hs.head == SCHED_NONE) w.heaps[q.heap].last = SCHED_NONE;
-              S.admit(dr, d, hs, 2u);
-            }
-          } else if ((u64)q.n > hs.cap || q.n > 65535u * (u32)K) {
-            S.reject(r, q.kind);
-          } else if (hs.head == SCHED_NONE && hs.size + q.n <= hs.cap) {
-            S.admit(r, q, hs, 0);
-          } else {
-            // wait for memory behind earlier deferred inserts
-            w.next[r] = SCHED_NONE;
-            const u32 last = hs.head == SCHED_NONE ? SCHED_NONE : w.heaps[q.heap].last;
-            if (last == SCHED_NONE) hs.head = r;
-            else w.next[last] = r;
-            w.heaps[q.heap].last = r;
-          }
-          hot[q.heap] = hs;
-          if (S.tail - S.published >= 64) S.publish_queue();
+          ss.now = now;
+          ss.wend = cn;
         }
+        __syncthreads();
+        for (u32 j = w0 + 1 + tid; j < cn; j += T)
+          if (due_of(stage[j]) > ss.now) atomicMin(&ss.wend, j);
+        __syncthreads();
+        const u32 we = ss.wend;
+        // stable order of the window's requests by owner thread; the heap
+        // ids are read 16 at a time (K is a multiple of 16, so a block that
+        // starts below `we` lies inside the staging array)
+        u32 c = 0;
+        for (u32 b = w0 & ~15u; b < we; b += 16) {
+          u32 ids[16];
+          load_ids16(hid + b, ids);
+#pragma unroll
+          for (int e = 0; e < 16; ++e) {
+            const u32 j = b + e;
+            c += (j >= w0 && j < we && (ids[e] & (T - 1)) == mine) ? 1u : 0u;
+          }
+        }
+        u32 v = c;   // inclusive scan of the counts over the threads
+        for (u32 off = 1; off < (u32)T; off <<= 1) {
+          cnt[tid] = v;
+          __syncthreads();
+          if ((u32)tid >= off) v += cnt[tid - off];
+          __syncthreads();
+        }
+        const u32 first = v - c;
+        if (c) {
+          u32 x = first;
+          for (u32 b = w0 & ~15u; b < we; b += 16) {
+            u32 ids[16];
+            load_ids16(hid + b, ids);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+              const u32 j = b + e;
+              if (j >= w0 && j < we && (ids[e] & (T - 1)) == mine) list[x++] = (uint16_t)j;
+            }
+          }
+        }
+        // every thread admits its own requests in stream order
+        for (u32 x = first; x < first + c; ++x) {
+          const u32 j = list[x];
+          S.process(c0 + j, stage[j], ctl);
+        }
+        // publish the window's queue entries
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (tid == 0) {
+          const u32 qt = ss.qtail;
+          const u32 tl = (u64)qt < w.max_ops ? qt : (u32)w.max_ops;
+          __hip_atomic_store(&w.head->tail, tl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        w0 = we;
       }
       __syncthreads();
     }
-    if (tid == 0) {
-      // inserts still waiting for memory when the stream ends are rejected
-      for (u32 h = 0; h < nheaps; ++h) {
-        u32 r = hot[h].head;
-        while (r != SCHED_NONE) {
-          S.reject(r, GH_OP_INSERT);
-          r = w.next[r];
-        }
+    // inserts still waiting for memory when the stream ends are rejected
+    for (u32 h = tid; h < nheaps; h += T) {
+      u32 r = hot[h].head;
+      while (r != SCHED_NONE) {
+        S.reject(r, GH_OP_INSERT);
+        r = w.next[r];
       }
-      if (S.overflow) note_error(ctl, ERR_NOMEM);
-      S.publish_queue();
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (tid == 0) {
+      if (ss.overflow) note_error(ctl, ERR_NOMEM);
       __hip_atomic_store(&w.head->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     return;
@@ -326,18 +421,25 @@ __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs,
   for (;;) {
     if (tid == 0) {
       u32 i = atomicAdd(&w.head->claim, 1u);
-      for (;;) {
+      // wait for queue entry i; an idle slot polls ever more gently (up to
+      // ~1 us apart) so that a thousand of them do not crowd the line the
+      // scheduler publishes to
+      for (u32 spins = 0;; ++spins) {
         const u32 tl = ld_relaxed32(&w.head->tail);
         if (i < tl) break;
-        if (ld_relaxed32(&w.head->done)) {
-          if (i >= ld_relaxed32(&w.head->tail)) i = 0xFFFFFFFFu;
-          break;
+        if ((spins & 7) == 7) {
+          if (ld_relaxed32(&w.head->done)) {
+            if (i >= ld_relaxed32(&w.head->tail)) i = 0xFFFFFFFFu;
+            break;
+          }
+          if (ld_relaxed32(&ctl->abort)) {
+            i = 0xFFFFFFFFu;
+            break;
+          }
         }
-        if (ld_relaxed32(&ctl->abort)) {
-          i = 0xFFFFFFFFu;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(2);
+        if (spins < 4) __builtin_amdgcn_s_sleep(2);
+        else if (spins < 16) __builtin_amdgcn_s_sleep(8);
+        else __builtin_amdgcn_s_sleep(32);
       }
       sh.op = i;
       sh.t_claim = now_ticks();
@@ -348,6 +450,10 @@ __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs,
     const u64* qw = reinterpret_cast<const u64*>(w.queue + i);
     const u64 q0 = ld_relaxed(qw + 0), q1 = ld_relaxed(qw + 1), q2 = ld_relaxed(qw + 2);
     const u32 r = __hip_atomic_load(w.qreq + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((u32)q0 == QUEUE_SKIP) {
+      __syncthreads();   // every thread has read the entry before sh is reused
+      continue;
+    }
     gh_op op;
     op.heap = (u32)q0;
     op.kind = (u32)(q0 >> 32);
@@ -377,7 +483,7 @@ __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs,
 template <int K, int T>
 static hipError_t launch_serve_t(const ServeArgs& a) {
   hipLaunchKernelGGL((k_serve<K, T>), dim3(a.workgroups + 1), dim3(T),
-                     (size_t)a.nheaps * sizeof(SchedHot), a.stream, a.descs,
+                     (size_t)a.nheaps * sizeof(SchedHot) + T * sizeof(u32), a.stream, a.descs,
                      a.nheaps, a.reqs, a.nreq, a.in, a.out, a.recs, a.w, a.ctl, a.clock_mhz);
   return hipGetLastError();
 }
