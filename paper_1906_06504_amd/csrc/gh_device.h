@@ -11,6 +11,14 @@ namespace gh {
 typedef uint64_t u64;
 typedef uint32_t u32;
 
+// LDS (workgroup-local) entries.  Buffers in LDS are always reached through
+// pointers of this type, so that every access is an LDS instruction: a
+// generic pointer would make the compiler emit flat accesses, each of which
+// also waits for every outstanding global memory operation.
+typedef __attribute__((address_space(3))) u64 lu64;
+typedef u64 u64x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) u64x2 lu64x2;
+
 constexpr u64 ENT_MAX = ~0ull;  // reserved filler; never a live entry
 
 // ---------------------------------------------------------------------------
@@ -100,27 +108,37 @@ __device__ __forceinline__ u64 lw_ticket(u64 w) { return w >> 3; }
 // at a barrier) and thread 0 then releases with a relaxed store; an acquirer
 // waits for the lock atomic to return before any payload load is issued.
 // ---------------------------------------------------------------------------
+// Global memory through global-address-space pointers: global instructions
+// count only against the vector memory counter, while flat ones (generic
+// pointers) also hold up every later LDS wait.
+typedef __attribute__((address_space(1))) u64 gu64;
+typedef __attribute__((address_space(1))) u32 gu32;
+__device__ __forceinline__ gu64* gptr(u64* p) { return (gu64*)p; }
+__device__ __forceinline__ const gu64* gptr(const u64* p) { return (const gu64*)p; }
+__device__ __forceinline__ gu32* gptr(u32* p) { return (gu32*)p; }
+__device__ __forceinline__ const gu32* gptr(const u32* p) { return (const gu32*)p; }
+
 __device__ __forceinline__ u64 ld_relaxed(const u64* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(gptr(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ u32 ld_relaxed32(const u32* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(gptr(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_relaxed(u64* p, u64 v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(gptr(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ bool cas_relaxed(u64* p, u64 expect, u64 desired) {
-  return __hip_atomic_compare_exchange_strong(p, &expect, desired, __ATOMIC_RELAXED,
+  return __hip_atomic_compare_exchange_strong(gptr(p), &expect, desired, __ATOMIC_RELAXED,
                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // compare-and-swap returning the previous value (== expect on success)
 __device__ __forceinline__ u64 cas_old(u64* p, u64 expect, u64 desired) {
-  __hip_atomic_compare_exchange_strong(p, &expect, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_compare_exchange_strong(gptr(p), &expect, desired, __ATOMIC_RELAXED,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return expect;
 }
 __device__ __forceinline__ u64 xchg_relaxed(u64* p, u64 v) {
-  return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_exchange(gptr(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Acquire side: the lock atomic has returned before any later load issues.
@@ -250,9 +268,12 @@ __device__ __forceinline__ u64* lock_ptr(const HeapDesc& H, u32 c) {
 // Coalesced node transfers between heap memory and LDS (16 bytes a lane).
 // ---------------------------------------------------------------------------
 template <int K, int T>
-__device__ __forceinline__ void store_node(u64* g, const u64* __restrict__ lds) {
+__device__ __forceinline__ void store_node(u64* g, const lu64* __restrict__ lds) {
   const HeapRegion R(g, K * 8);
-  for (int i = threadIdx.x * 2; i < K; i += 2 * T) R.store16(i * 8, lds[i], lds[i + 1]);
+  for (int i = threadIdx.x * 2; i < K; i += 2 * T) {
+    const u64x2 v = *reinterpret_cast<const lu64x2*>(lds + i);
+    R.store16(i * 8, v.x, v.y);
+  }
 }
 // A node's share per thread held in registers, so that several node loads
 // (and lock atomics) can be in flight before anything is written to LDS.
@@ -268,27 +289,34 @@ struct NodeRegs {
       if (i < K) v[c] = R.load16(i * 8);
     }
   }
-  __device__ __forceinline__ void store(u64* __restrict__ lds) const {
+  __device__ __forceinline__ void store(lu64* __restrict__ lds) const {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int i = (threadIdx.x + c * T) * 2;
-      if (i < K) *reinterpret_cast<ulonglong2*>(lds + i) = v[c];
+      if (i < K) {
+        u64x2 t;
+        t.x = v[c].x;
+        t.y = v[c].y;
+        *reinterpret_cast<lu64x2*>(lds + i) = t;
+      }
     }
   }
 };
 
 // n entries, any n, 8 bytes a lane: caller memory to LDS and back
 template <int T>
-__device__ __forceinline__ void load_n(u64* __restrict__ lds, const u64* __restrict__ g, u32 n) {
-  for (u32 i = threadIdx.x; i < n; i += T) lds[i] = g[i];
+__device__ __forceinline__ void load_n(lu64* __restrict__ lds, const u64* __restrict__ g, u32 n) {
+  const gu64* gg = gptr(g);
+  for (u32 i = threadIdx.x; i < n; i += T) lds[i] = gg[i];
 }
 template <int T>
-__device__ __forceinline__ void store_n(u64* __restrict__ g, const u64* __restrict__ lds, u32 n) {
-  for (u32 i = threadIdx.x; i < n; i += T) g[i] = lds[i];
+__device__ __forceinline__ void store_n(u64* __restrict__ g, const lu64* __restrict__ lds, u32 n) {
+  gu64* gg = gptr(g);
+  for (u32 i = threadIdx.x; i < n; i += T) gg[i] = lds[i];
 }
 // n entries from LDS to heap memory (the partial buffer)
 template <int K, int T>
-__device__ __forceinline__ void store_heap_n(u64* g, const u64* __restrict__ lds, u32 n) {
+__device__ __forceinline__ void store_heap_n(u64* g, const lu64* __restrict__ lds, u32 n) {
   const HeapRegion R(g, K * 8);
   for (u32 i = threadIdx.x; i < n; i += T) R.store8(i * 8, lds[i]);
 }
@@ -296,7 +324,8 @@ __device__ __forceinline__ void store_heap_n(u64* g, const u64* __restrict__ lds
 template <int K, int T>
 __device__ __forceinline__ void copy_heap_n(u64* __restrict__ dst, const u64* src, u32 n) {
   const HeapRegion R(src, K * 8);
-  for (u32 i = threadIdx.x; i < n; i += T) dst[i] = R.load8(i * 8);
+  gu64* gd = gptr(dst);
+  for (u32 i = threadIdx.x; i < n; i += T) gd[i] = R.load8(i * 8);
 }
 
 // ---------------------------------------------------------------------------
@@ -309,7 +338,7 @@ __device__ __forceinline__ void copy_heap_n(u64* __restrict__ dst, const u64* sr
 // rounds they save.)
 // ---------------------------------------------------------------------------
 template <int E>
-__device__ __forceinline__ void merge_path(const u64* A, int na, const u64* B, int nb, int d,
+__device__ __forceinline__ void merge_path(const lu64* A, int na, const lu64* B, int nb, int d,
                                            u64 (&v)[E]) {
   const int total = na + nb;
   if (d >= total) {
@@ -344,19 +373,19 @@ __device__ __forceinline__ void merge_path(const u64* A, int na, const u64* B, i
 // Destinations for merge output, written E entries a thread: LDS or caller
 // memory (Sink), or a region of heap memory (HeapSink, device scope).
 struct Sink {
-  u64* p;
+  lu64* p;
   __device__ __forceinline__ void put1(int off, u64 x) const { p[off] = x; }
   template <int E>
   __device__ __forceinline__ void put_range(int off, const u64 (&v)[E]) const {
-    u64* q = p + off;
+    lu64* q = p + off;
     if constexpr (E % 2 == 0) {
-      if ((reinterpret_cast<uintptr_t>(q) & 15) == 0) {
+      if ((off & 1) == 0) {   // LDS buffers are 16-byte aligned
 #pragma unroll
         for (int e = 0; e < E; e += 2) {
-          ulonglong2 w;
+          u64x2 w;
           w.x = v[e];
           w.y = v[e + 1];
-          *reinterpret_cast<ulonglong2*>(q + e) = w;
+          *reinterpret_cast<lu64x2*>(q + e) = w;
         }
         return;
       }
@@ -389,7 +418,7 @@ struct HeapSink {
 // must be in LDS and must not overlap the outputs.  No barrier inside: the
 // caller synchronizes before reusing inputs or reading outputs.
 template <int E, int T, class SinkLo, class SinkHi>
-__device__ __forceinline__ void merge_split(const u64* A, int na, const u64* B, int nb, int split,
+__device__ __forceinline__ void merge_split(const lu64* A, int na, const lu64* B, int nb, int split,
                                             const SinkLo& lo, const SinkHi& hi) {
   const int total = na + nb;
   for (int d = threadIdx.x * E; d < total; d += T * E) {
@@ -420,7 +449,7 @@ __device__ __forceinline__ void merge_split(const u64* A, int na, const u64* B, 
 // holds the sorted result.
 // ---------------------------------------------------------------------------
 template <int K, int T>
-__device__ u64* block_sort(u64* A, u64* B, int n) {
+__device__ lu64* block_sort(lu64* A, lu64* B, int n) {
   constexpr int EPT = (K >= T) ? (K / T) : 1;
   int np = EPT;
   while (np < n) np <<= 1;
@@ -446,8 +475,8 @@ __device__ u64* block_sort(u64* A, u64* B, int n) {
     for (int e = 0; e < EPT; ++e) A[tid * EPT + e] = v[e];
   }
   __syncthreads();
-  u64* src = A;
-  u64* dst = B;
+  lu64* src = A;
+  lu64* dst = B;
   for (int w = EPT; w < np; w <<= 1) {
     if (tid < active) {
       int d0 = tid * EPT;
@@ -458,7 +487,7 @@ __device__ u64* block_sort(u64* A, u64* B, int n) {
       for (int e = 0; e < EPT; ++e) dst[d0 + e] = v[e];
     }
     __syncthreads();
-    u64* t = src;
+    lu64* t = src;
     src = dst;
     dst = t;
   }

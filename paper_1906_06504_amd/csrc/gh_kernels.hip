@@ -21,6 +21,7 @@ __global__ __launch_bounds__(T) void k_ops(const HeapDesc* __restrict__ descs,
                                            u64* __restrict__ out, u32* __restrict__ counts,
                                            gh_logrec* __restrict__ log, Ctl* __restrict__ ctl) {
   __shared__ __align__(16) u64 lds[5 * K];
+  lu64* const L = (lu64*)lds;
   __shared__ OpShared sh;
   const int tid = threadIdx.x;
   for (;;) {
@@ -61,7 +62,7 @@ __global__ __launch_bounds__(T) void k_ops(const HeapDesc* __restrict__ descs,
       continue;
     }
     const HeapDesc H = descs[op.heap];
-    const u64 ticket = H.meta->base + op.seq;
+    const u64 ticket = *gptr(&H.meta->base) + op.seq;
     if (op.arrival_ns != 0 && tid == 0) {
       // admission: the request may not start before its arrival time
       // (bounded to one minute after the submission started)
@@ -80,9 +81,9 @@ __global__ __launch_bounds__(T) void k_ops(const HeapDesc* __restrict__ descs,
       r = op_pass_root(H, ticket, sh, ctl);
       if (malformed) r.flags |= F_REJECT;
     } else if (op.kind == GH_OP_INSERT) {
-      r = op_insert<K, T>(H, ticket, in + op.off, op.n, lds, sh, ctl);
+      r = op_insert<K, T>(H, ticket, in + op.off, op.n, L, sh, ctl);
     } else {
-      r = op_delete<K, T>(H, ticket, out + op.off, lds, sh, ctl);
+      r = op_delete<K, T>(H, ticket, out + op.off, L, sh, ctl);
     }
     if (tid == 0) {
       if (counts) counts[i] = op.kind == GH_OP_INSERT ? 0u : r.count;
@@ -136,6 +137,23 @@ struct SchedHot {
   u32 head;   // first deferred insert (request id), or SCHED_NONE
 };
 static_assert(sizeof(SchedHot) == 32, "sched layout");
+typedef __attribute__((address_space(3))) SchedHot lSchedHot;
+__device__ __forceinline__ SchedHot hot_get(const lSchedHot* p) {
+  SchedHot v;
+  v.size = p->size;
+  v.cap = p->cap;
+  v.base = p->base;
+  v.seq = p->seq;
+  v.head = p->head;
+  return v;
+}
+__device__ __forceinline__ void hot_put(lSchedHot* p, const SchedHot& v) {
+  p->size = v.size;
+  p->cap = v.cap;
+  p->base = v.base;
+  p->seq = v.seq;
+  p->head = v.head;
+}
 extern __shared__ __align__(16) unsigned char gh_dyn_lds[];
 
 // Scheduler values shared by its threads.
@@ -145,6 +163,28 @@ struct SchedShared {
   u32 wend;       // end of the current window (index in the chunk)
   u32 overflow;   // the queue ran out of room
 };
+typedef __attribute__((address_space(3))) SchedShared lSchedShared;
+typedef __attribute__((address_space(3))) gh_op lgh_op;
+typedef __attribute__((address_space(3))) u32 lu32;
+typedef __attribute__((address_space(3))) uint16_t lu16;
+__device__ __forceinline__ gh_op stage_get(const lgh_op* p) {
+  gh_op q;
+  q.heap = p->heap;
+  q.kind = p->kind;
+  q.n = p->n;
+  q.seq = p->seq;
+  q.off = p->off;
+  q.arrival_ns = p->arrival_ns;
+  return q;
+}
+__device__ __forceinline__ void stage_put(lgh_op* p, const gh_op& q) {
+  p->heap = q.heap;
+  p->kind = q.kind;
+  p->n = q.n;
+  p->seq = q.seq;
+  p->off = q.off;
+  p->arrival_ns = q.arrival_ns;
+}
 
 // Queue entries of a request rejected after its slots were handed out.
 constexpr u32 QUEUE_SKIP = 0xFFFFFFFFu;
@@ -155,8 +195,8 @@ struct Scheduler {
   const gh_op* reqs;
   gh_reqrec* recs;
   ServeWork w;
-  SchedHot* hot;
-  SchedShared* ss;
+  lSchedHot* hot;
+  lSchedShared* ss;
   u64 t0;
 
   __device__ void put_op(u32 slot, u32 r, u32 heap, u32 kind, u32 n, u32 seq, u64 off) const {
@@ -193,7 +233,8 @@ struct Scheduler {
   // handed are marked to be skipped).
   __device__ void admit(u32 r, const gh_op& q, SchedHot& hs, u32 flags) const {
     const u32 nops = q.kind == GH_OP_DELETE_MIN ? 1u : (q.n + K - 1) / K;
-    const u32 slot = atomicAdd(&ss->qtail, nops);
+    const u32 slot =
+        __hip_atomic_fetch_add(&ss->qtail, nops, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if ((u64)slot + nops > w.max_ops) {
       for (u64 x = slot; x < w.max_ops && x < (u64)slot + nops; ++x)
         put_op((u32)x, QUEUE_SKIP, QUEUE_SKIP, 0, 0, 0, 0);
@@ -233,7 +274,7 @@ struct Scheduler {
       note_error(ctl, ERR_INVAL);
       return;
     }
-    SchedHot hs = hot[q.heap];
+    SchedHot hs = hot_get(hot + q.heap);
     if (q.kind == GH_OP_DELETE_MIN) {
       admit(r, q, hs, 0);
       // room freed: admit deferred inserts of this heap in order
@@ -257,14 +298,23 @@ struct Scheduler {
       else w.next[last] = r;
       w.heaps[q.heap].last = r;
     }
-    hot[q.heap] = hs;
+    hot_put(hot + q.heap, hs);
   }
 };
 
+// Which compute unit this wave runs on: the XCD number and the shader
+// engine, array and unit fields of the hardware id register.
+__device__ __forceinline__ u32 compute_unit_id() {
+  const u32 hw = __builtin_amdgcn_s_getreg((31 << 11) | 4);     // HW_ID
+  const u32 xcc = __builtin_amdgcn_s_getreg((31 << 11) | 20);   // XCC_ID
+  return ((xcc & 0xF) << 8) | ((hw >> 8) & 0xFF);
+}
+
 // 16 consecutive u32 from LDS (16-byte aligned) with four 16-byte loads.
-__device__ __forceinline__ void load_ids16(const u32* p, u32 (&ids)[16]) {
-  const uint4* q = reinterpret_cast<const uint4*>(p);
-  const uint4 a = q[0], b = q[1], c = q[2], d = q[3];
+__device__ __forceinline__ void load_ids16(const lu32* p, u32 (&ids)[16]) {
+  typedef const __attribute__((address_space(3))) u32x4 lu32x4;
+  lu32x4* q = reinterpret_cast<lu32x4*>(p);
+  const u32x4 a = q[0], b = q[1], c = q[2], d = q[3];
   ids[0] = a.x; ids[1] = a.y; ids[2] = a.z; ids[3] = a.w;
   ids[4] = b.x; ids[5] = b.y; ids[6] = b.z; ids[7] = b.w;
   ids[8] = c.x; ids[9] = c.y; ids[10] = c.z; ids[11] = c.w;
@@ -278,14 +328,15 @@ __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs,
                                              gh_reqrec* __restrict__ recs, ServeWork w,
                                              Ctl* __restrict__ ctl, u32 clock_mhz) {
   __shared__ __align__(16) u64 lds[5 * K];
+  lu64* const L = (lu64*)lds;
   __shared__ OpShared sh;
   const int tid = threadIdx.x;
 
   if (blockIdx.x == 0) {
     // ---- scheduler ----
     __shared__ SchedShared ss;
-    SchedHot* hot = reinterpret_cast<SchedHot*>(gh_dyn_lds);
-    u32* cnt = reinterpret_cast<u32*>(gh_dyn_lds + (size_t)nheaps * sizeof(SchedHot));
+    lSchedHot* hot = (lSchedHot*)gh_dyn_lds;
+    lu32* cnt = (lu32*)(gh_dyn_lds + (size_t)nheaps * sizeof(SchedHot));
     for (u32 h = tid; h < nheaps; h += T) {
       const u64 rw = ld_relaxed(&descs[h].meta->root);
       SchedHot hs;
@@ -294,26 +345,31 @@ __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs,
       hs.base = descs[h].meta->base;
       hs.seq = 0;
       hs.head = SCHED_NONE;
-      hot[h] = hs;
+      hot_put(hot + h, hs);
       w.heaps[h].last = SCHED_NONE;
     }
     if (tid == 0) {
       ss.now = now_ticks();
       ss.qtail = 0;
       ss.overflow = 0;
+      // let slots that landed on this compute unit step aside
+      __hip_atomic_store(&w.head->sched_cu, compute_unit_id(), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __hip_atomic_store(&w.head->cu_ready, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     // a chunk of K requests staged in LDS: records, heap ids, window order
     constexpr u32 CH = K;
-    gh_op* stage = reinterpret_cast<gh_op*>(lds);
-    u32* hid = reinterpret_cast<u32*>(lds + 4 * K);
-    uint16_t* list = reinterpret_cast<uint16_t*>(lds + 4 * K + K / 2);
+    lgh_op* stage = (lgh_op*)lds;
+    lu32* hid = (lu32*)(lds + 4 * K);
+    lu16* list = (lu16*)(lds + 4 * K + K / 2);
     Scheduler<K> S;
     S.nheaps = nheaps;
     S.reqs = reqs;
     S.recs = recs;
     S.w = w;
     S.hot = hot;
-    S.ss = &ss;
+    S.ss = (lSchedShared*)&ss;
     S.t0 = ctl->t0;
     const u32 mine = (u32)tid;
     auto due_of = [&](const gh_op& q) -> u64 {
@@ -326,7 +382,7 @@ __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs,
       const u32 cn = nreq - c0 < CH ? nreq - c0 : CH;
       for (u32 j = tid; j < cn; j += T) {
         const gh_op q = reqs[c0 + j];
-        stage[j] = q;
+        stage_put(stage + j, q);
         hid[j] = q.heap;
       }
       __syncthreads();
@@ -335,7 +391,7 @@ __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs,
         // the window: from w0 up to the first request not due yet (w0 itself
         // is waited for)
         if (tid == 0) {
-          const u64 due0 = due_of(stage[w0]);
+          const u64 due0 = due_of(stage_get(stage + w0));
           u64 now = now_ticks();
           while (now < due0) {
             if (ld_relaxed32(&ctl->abort)) break;
@@ -347,7 +403,7 @@ __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs,
         }
         __syncthreads();
         for (u32 j = w0 + 1 + tid; j < cn; j += T)
-          if (due_of(stage[j]) > ss.now) atomicMin(&ss.wend, j);
+          if (due_of(stage_get(stage + j)) > ss.now) atomicMin(&ss.wend, j);
         __syncthreads();
         const u32 we = ss.wend;
         // stable order of the window's requests by owner thread; the heap
@@ -386,7 +442,8 @@ __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs,
         // every thread admits its own requests in stream order
         for (u32 x = first; x < first + c; ++x) {
           const u32 j = list[x];
-          S.process(c0 + j, stage[j], ctl);
+          const gh_op q = stage_get(stage + j);
+          S.process(c0 + j, q, ctl);
         }
         // publish the window's queue entries
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -418,6 +475,21 @@ __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs,
   }
 
   // ---- slots ----
+  // The scheduler admits every request; a slot sharing its compute unit
+  // would slow it down for every other slot, so up to 8 such slots leave.
+  if (tid == 0) {
+    sh.ok = 1;
+    // (bounded: after ~0.2 s without the scheduler's mark, just go on)
+    for (u32 spins = 0; spins < (1u << 20) && !ld_relaxed32(&w.head->cu_ready); ++spins) {
+      if (ld_relaxed32(&ctl->abort)) break;
+      __builtin_amdgcn_s_sleep(8);
+    }
+    if (ld_relaxed32(&w.head->cu_ready) && compute_unit_id() == ld_relaxed32(&w.head->sched_cu) &&
+        atomicAdd(&w.head->cu_left, 1u) < 8u)
+      sh.ok = 0;
+  }
+  __syncthreads();
+  if (!sh.ok) return;
   for (;;) {
     if (tid == 0) {
       u32 i = atomicAdd(&w.head->claim, 1u);
@@ -462,12 +534,12 @@ __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs,
     op.off = q2;
     op.arrival_ns = 0;
     const HeapDesc H = descs[op.heap];
-    const u64 ticket = H.meta->base + op.seq;
+    const u64 ticket = *gptr(&H.meta->base) + op.seq;
     OpResult res;
     if (op.kind == GH_OP_INSERT) {
-      res = op_insert<K, T>(H, ticket, in + op.off, op.n, lds, sh, ctl);
+      res = op_insert<K, T>(H, ticket, in + op.off, op.n, L, sh, ctl);
     } else {
-      res = op_delete<K, T>(H, ticket, out + op.off, lds, sh, ctl);
+      res = op_delete<K, T>(H, ticket, out + op.off, L, sh, ctl);
     }
     if (tid == 0) {
       if (op.kind == GH_OP_DELETE_MIN)
@@ -569,6 +641,7 @@ __global__ __launch_bounds__(T) void k_knap(const HeapDesc* __restrict__ descs, 
                                             u64 pool_per_inst, u64* __restrict__ scratch,
                                             gh_knapres* __restrict__ res, Ctl* __restrict__ ctl) {
   __shared__ __align__(16) u64 lds[5 * K];
+  lu64* const L = (lu64*)lds;
   __shared__ OpShared sh;
   __shared__ KnapShared ks;
   const int tid = threadIdx.x;
@@ -582,7 +655,7 @@ __global__ __launch_bounds__(T) void k_knap(const HeapDesc* __restrict__ descs, 
     const u32 inst = ks.inst;
     if (inst >= ninst) break;
     const HeapDesc H = descs[inst];
-    u64 ticket = H.meta->base;
+    u64 ticket = *gptr(&H.meta->base);
     u64* ipool = pool + (u64)inst * pool_per_inst;
     u64* out = scratch + (u64)inst * 3 * K;   // K popped entries, then 2K children
     u64* kids = out + K;
@@ -631,13 +704,13 @@ __global__ __launch_bounds__(T) void k_knap(const HeapDesc* __restrict__ descs, 
       const u32 c = ks.cnt;
       for (u32 j = 0; j < c; j += K) {
         const u32 nn = c - j < (u32)K ? c - j : (u32)K;
-        OpResult r = op_insert<K, T>(H, ticket++, kids + j, nn, lds, sh, ctl);
+        OpResult r = op_insert<K, T>(H, ticket++, kids + j, nn, L, sh, ctl);
         ++ops;
         if (!r.ok) break;
         __syncthreads();
       }
       // take the most promising nodes
-      OpResult r = op_delete<K, T>(H, ticket++, out, lds, sh, ctl);
+      OpResult r = op_delete<K, T>(H, ticket++, out, L, sh, ctl);
       ++ops;
       __syncthreads();
       if (!r.ok || r.count == 0) break;
@@ -799,6 +872,7 @@ __global__ __launch_bounds__(T) void k_sssp(const HeapDesc* __restrict__ descs, 
                                             SsspState* __restrict__ st, gh_sssptrace tr,
                                             Ctl* __restrict__ ctl) {
   __shared__ __align__(16) u64 lds[5 * K];
+  lu64* const L = (lu64*)lds;
   __shared__ OpShared sh;
   __shared__ u64 s_ticket, s_toff;
   __shared__ u32 s_exit, s_idle, s_cnt, s_stale;
@@ -829,7 +903,7 @@ __global__ __launch_bounds__(T) void k_sssp(const HeapDesc* __restrict__ descs, 
     OpResult r{0, 0, 0, true};
     if (!s_idle) {
       const u64 t0 = now_ticks();
-      r = op_delete<K, T>(H, s_ticket, out, lds, sh, ctl);
+      r = op_delete<K, T>(H, s_ticket, out, L, sh, ctl);
       ++ops;
       __syncthreads();
       heap_t += now_ticks() - t0;
@@ -913,7 +987,7 @@ __global__ __launch_bounds__(T) void k_sssp(const HeapDesc* __restrict__ descs, 
         s_ticket = atomicAdd(reinterpret_cast<unsigned long long*>(&st->next_ticket), 1ull);
       __syncthreads();
       const u32 nn = c - j < (u32)K ? c - j : (u32)K;
-      const OpResult ri = op_insert<K, T>(H, s_ticket, mine + j, nn, lds, sh, ctl);
+      const OpResult ri = op_insert<K, T>(H, s_ticket, mine + j, nn, L, sh, ctl);
       ++ops;
       // (the batch in `mine` is unchanged by the insert)
       if (tr.d_ops && ri.ok)

@@ -52,6 +52,10 @@ struct alignas(256) ServeHead {
   u32 tail;       // queue slots the scheduler has published
   u32 done;       // the scheduler has admitted or rejected every request
   u32 pad1[30];
+  u32 sched_cu;   // compute unit the scheduler runs on (valid once cu_ready)
+  u32 cu_ready;
+  u32 cu_left;    // slots that stepped aside from the scheduler's unit
+  u32 pad2[29];
 };
 struct HeapSched {  // scheduler-private, one per heap
   u64 size;       // entries after every admitted request

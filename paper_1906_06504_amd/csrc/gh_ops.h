@@ -210,21 +210,21 @@ __device__ __forceinline__ bool acquire_root(const HeapDesc& H, u64 ticket, OpSh
 // ---------------------------------------------------------------------------
 template <int K, int T>
 __device__ OpResult op_insert(const HeapDesc& H, u64 ticket, const u64* __restrict__ keys, u32 n,
-                              u64* lds, OpShared& sh, Ctl* ctl) {
+                              lu64* lds, OpShared& sh, Ctl* ctl) {
   constexpr int E = (2 * K) / T >= 1 ? (2 * K) / T : 1;
   const int tid = threadIdx.x;
   OpResult res{n, 0, 0, true};
-  u64* b0 = lds;
-  u64* b1 = lds + K;
-  u64* P = lds + 2 * K;   // partial buffer
-  u64* F = lds + 3 * K;   // full batch / merged head
-  u64* N = lds + 4 * K;   // node being merged (root first)
+  lu64* b0 = lds;
+  lu64* b1 = lds + K;
+  lu64* P = lds + 2 * K;   // partial buffer
+  lu64* F = lds + 3 * K;   // full batch / merged head
+  lu64* N = lds + 4 * K;   // node being merged (root first)
   HeapMeta* meta = H.meta;
 
   // sort the batch before touching the heap (holds no lock)
   load_n<T>(b0, keys, n);
-  u64* xs = block_sort<K, T>(b0, b1, (int)n);
-  u64* xfree = (xs == b0) ? b1 : b0;
+  lu64* xs = block_sort<K, T>(b0, b1, (int)n);
+  lu64* xfree = (xs == b0) ? b1 : b0;
 
   if (!acquire_root(H, ticket, sh, ctl)) { res.ok = false; return res; }
   const u64 m = sh.m;
@@ -313,7 +313,7 @@ __device__ OpResult op_insert(const HeapDesc& H, u64 ticket, const u64* __restri
 
   // LDS buffers in play: N (node), F (carry), spare (free; xfree is read by
   // the pb store above and stays untouched)
-  u64* spare = xfree == b0 ? b1 : b0;
+  lu64* spare = xfree == b0 ? b1 : b0;
   u32 cur = 1;
   int level = 0;
   for (;;) {
@@ -324,10 +324,10 @@ __device__ OpResult op_insert(const HeapDesc& H, u64 ticket, const u64* __restri
       // node already holds the smallest: nothing moves
     } else if (F[K - 1] <= N[0]) {
       store_node<K, T>(cur_ptr, F);  // swap
-      u64* x = F; F = N; N = x;
+      lu64* x = F; F = N; N = x;
     } else {
       merge_split<E, T>(N, K, F, K, K, HeapSink(cur_ptr, K * 8), Sink{spare});
-      u64* x = F; F = spare; spare = x;
+      lu64* x = F; F = spare; spare = x;
     }
     ++level;
     if (at_root) GH_TRACE(3);
@@ -402,14 +402,14 @@ __device__ OpResult op_insert(const HeapDesc& H, u64 ticket, const u64* __restri
 // Writes min(K, size) entries to out.
 // ---------------------------------------------------------------------------
 template <int K, int T>
-__device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ out, u64* lds,
+__device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ out, lu64* lds,
                               OpShared& sh, Ctl* ctl) {
   constexpr int E = (2 * K) / T >= 1 ? (2 * K) / T : 1;
   const int tid = threadIdx.x;
   OpResult res{0, 0, 0, true};
   HeapMeta* meta = H.meta;
-  u64* bufs[4] = {lds, lds + K, lds + 2 * K, lds + 3 * K};
-  u64* P = lds + 4 * K;
+  lu64* bufs[4] = {lds, lds + K, lds + 2 * K, lds + 3 * K};
+  lu64* P = lds + 4 * K;
 
   if (!acquire_root(H, ticket, sh, ctl)) { res.ok = false; return res; }
   const u64 m = sh.m;
@@ -506,7 +506,7 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
   GH_TRACE(4);
   if (!sh.ok) { res.ok = false; return res; }
 
-  u64* C = bufs[0];
+  lu64* C = bufs[0];
   // Round trip 3: the children, loaded while cur merges with the partial
   // buffer (Property 3 again: the refilled root keeps the K smallest).
   bool hl = sh.flag0, hr = sh.flag1;
@@ -517,7 +517,7 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
     if (s > 0 && !(C[K - 1] <= P[0])) {
       merge_split<E, T>(C, K, P, (int)s, K, Sink{bufs[3]}, HeapSink(H.pb, K * 8));
       __syncthreads();
-      u64* x = bufs[0]; bufs[0] = bufs[3]; bufs[3] = x;
+      lu64* x = bufs[0]; bufs[0] = bufs[3]; bufs[3] = x;
       C = bufs[0];
     }
     if (hl) lc.store(bufs[1]);
@@ -531,8 +531,8 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
   bool loaded = true;
   for (;;) {
     const u64 l = 2ull * c, r = l + 1;
-    u64* Lb = bufs[1];
-    u64* Rb = bufs[2];
+    lu64* Lb = bufs[1];
+    lu64* Rb = bufs[2];
     if (!loaded) {
       const bool el = node_exists(l, m2), er = node_exists(r, m2);
       if (tid < 64) {
@@ -581,7 +581,7 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
     }
 
     u32 next;
-    u64* newcur;
+    lu64* newcur;
     if (hl && hr) {
       // (hi, lo) = MergeAndSort(l, r); lo stays in the child whose max was
       // larger (on a tie the right child counts as larger), hi merges with
@@ -589,10 +589,10 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
       const bool big_is_l = Lb[K - 1] > Rb[K - 1];
       const u32 big = big_is_l ? (u32)l : (u32)r;
       const u32 small = big_is_l ? (u32)r : (u32)l;
-      u64* Bg = big_is_l ? Lb : Rb;
-      u64* Sm = big_is_l ? Rb : Lb;
-      u64* hi;
-      u64* freeb;
+      lu64* Bg = big_is_l ? Lb : Rb;
+      lu64* Sm = big_is_l ? Rb : Lb;
+      lu64* hi;
+      lu64* freeb;
       if (Sm[K - 1] <= Bg[0]) {
         hi = Sm;             // lo is the big child's batch, already in place
         freeb = bufs[3];
@@ -622,8 +622,8 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
     } else {
       // one live child x
       const u32 x = hl ? (u32)l : (u32)r;
-      u64* X = hl ? Lb : Rb;
-      u64* freeb = bufs[3];
+      lu64* X = hl ? Lb : Rb;
+      lu64* freeb = bufs[3];
       if (X[K - 1] <= C[0]) {
         store_node<K, T>(cptr, X);
         newcur = C;
@@ -640,13 +640,18 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
       next = x;
     }
     ++res.levels;
-    // rotate buffers: newcur becomes C, the other three are free
+    // rotate buffers: newcur becomes C, the other three are free (in
+    // their old order; newcur is one of the four)
     {
-      u64* all[4] = {bufs[0], bufs[1], bufs[2], bufs[3]};
-      int j = 1;
+      lu64* const a0 = bufs[0];
+      lu64* const a1 = bufs[1];
+      lu64* const a2 = bufs[2];
+      lu64* const a3 = bufs[3];
+      const bool n0 = newcur == a0, n1 = newcur == a1, n2 = newcur == a2;
       bufs[0] = newcur;
-      for (int q = 0; q < 4; ++q)
-        if (all[q] != newcur) bufs[j++] = all[q];
+      bufs[1] = n0 ? a1 : a0;
+      bufs[2] = (n0 || n1) ? a2 : a1;
+      bufs[3] = (n0 || n1 || n2) ? a3 : a2;
       C = bufs[0];
     }
     c = next;
