@@ -337,6 +337,7 @@ __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs,
     __shared__ SchedShared ss;
     lSchedHot* hot = (lSchedHot*)gh_dyn_lds;
     lu32* cnt = (lu32*)(gh_dyn_lds + (size_t)nheaps * sizeof(SchedHot));
+    lu32* cur = cnt + T;
     for (u32 h = tid; h < nheaps; h += T) {
       const u64 rw = ld_relaxed(&descs[h].meta->root);
       SchedHot hs;
@@ -406,39 +407,47 @@ __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs,
           if (due_of(stage_get(stage + j)) > ss.now) atomicMin(&ss.wend, j);
         __syncthreads();
         const u32 we = ss.wend;
-        // stable order of the window's requests by owner thread; the heap
-        // ids are read 16 at a time (K is a multiple of 16, so a block that
-        // starts below `we` lies inside the staging array)
-        u32 c = 0;
-        for (u32 b = w0 & ~15u; b < we; b += 16) {
-          u32 ids[16];
-          load_ids16(hid + b, ids);
-#pragma unroll
-          for (int e = 0; e < 16; ++e) {
-            const u32 j = b + e;
-            c += (j >= w0 && j < we && (ids[e] & (T - 1)) == mine) ? 1u : 0u;
-          }
-        }
+        // stable order of the window's requests by owner thread: counts by
+        // LDS atomics, an exclusive scan over the threads, then wave 0 places
+        // the requests 64 at a time in stream order, ranking lanes of equal
+        // owner with ballots
+        cnt[tid] = 0;
+        __syncthreads();
+        for (u32 j = w0 + tid; j < we; j += T)
+          __hip_atomic_fetch_add(cnt + (hid[j] & (T - 1)), 1u, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+        __syncthreads();
+        const u32 c = cnt[tid];
         u32 v = c;   // inclusive scan of the counts over the threads
         for (u32 off = 1; off < (u32)T; off <<= 1) {
+          __syncthreads();
           cnt[tid] = v;
           __syncthreads();
           if ((u32)tid >= off) v += cnt[tid - off];
-          __syncthreads();
         }
         const u32 first = v - c;
-        if (c) {
-          u32 x = first;
-          for (u32 b = w0 & ~15u; b < we; b += 16) {
-            u32 ids[16];
-            load_ids16(hid + b, ids);
+        cur[tid] = first;
+        __syncthreads();
+        if (tid < 64) {
+          const u64 below = (1ull << tid) - 1ull;
+          for (u32 b0 = w0; b0 < we; b0 += 64) {
+            const u32 j = b0 + tid;
+            const bool valid = j < we;
+            const u32 own = valid ? (hid[j] & (T - 1)) : 0u;
+            u64 same = __ballot(valid);
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-              const u32 j = b + e;
-              if (j >= w0 && j < we && (ids[e] & (T - 1)) == mine) list[x++] = (uint16_t)j;
+            for (u32 bit = 1; bit < (u32)T; bit <<= 1) {
+              const u64 m = __ballot((own & bit) != 0);
+              same &= (own & bit) ? m : ~m;
+            }
+            if (valid) {
+              const u32 pos = cur[own] + (u32)__popcll(same & below);
+              list[pos] = (uint16_t)j;
+              if ((same >> tid) >> 1 == 0) cur[own] = pos + 1;   // last of its owner
             }
           }
         }
+        __syncthreads();
         // every thread admits its own requests in stream order
         for (u32 x = first; x < first + c; ++x) {
           const u32 j = list[x];
@@ -555,7 +564,7 @@ __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs,
 template <int K, int T>
 static hipError_t launch_serve_t(const ServeArgs& a) {
   hipLaunchKernelGGL((k_serve<K, T>), dim3(a.workgroups + 1), dim3(T),
-                     (size_t)a.nheaps * sizeof(SchedHot) + T * sizeof(u32), a.stream, a.descs,
+                     (size_t)a.nheaps * sizeof(SchedHot) + 2 * T * sizeof(u32), a.stream, a.descs,
                      a.nheaps, a.reqs, a.nreq, a.in, a.out, a.recs, a.w, a.ctl, a.clock_mhz);
   return hipGetLastError();
 }

@@ -398,9 +398,9 @@ int heap_serve(gh_heap_t h, const gh_op* d_reqs, uint32_t nreq, const uint64_t* 
   u32 threads = (t && t->threads) ? t->threads : default_threads(h->k);
   if (!heap_supported_shape(h->k, threads)) return GH_EINVAL;
   u32 wg = (t && t->workgroups) ? t->workgroups : 512;
-  // the scheduler keeps 32 bytes per heap and 4 per thread in LDS next to
+  // the scheduler keeps 32 bytes per heap and 8 per thread in LDS next to
   // the k-entry buffers
-  if ((u64)h->nheaps * 32 + (u64)threads * 4 + (u64)h->k * 40 + 1024 > 65536) return GH_EINVAL;
+  if ((u64)h->nheaps * 32 + (u64)threads * 8 + (u64)h->k * 40 + 1024 > 65536) return GH_EINVAL;
   h->size0_known = false;
   unsigned char* base = reinterpret_cast<unsigned char*>(d_work);
   ServeArgs a;
