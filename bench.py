@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--served-heaps", type=int, default=256)
     ap.add_argument("--served-requests", type=int, default=1 << 20)
     ap.add_argument("--served-max-log2", type=int, default=22)
-    ap.add_argument("--served-slots", type=int, default=1024)
+    ap.add_argument("--served-slots", type=int, default=2048)
     ap.add_argument("--served-budget", type=int, default=1 << 20,
                     help="memory budget per heap beyond its prefill (entries)")
     ap.add_argument("--no-knapsack", action="store_true", help="skip the knapsack leg")
