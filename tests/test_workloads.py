@@ -47,3 +47,16 @@ def test_sssp_graph_tiny():
     r, c, w = W.sssp_graph(2, seed=2)
     src = np.repeat(np.arange(2), np.diff(r.astype(np.int64)))
     assert np.all(c == 1 - src)
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py runs on one GPU only and says so for any other count."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr or "one gpu" in p.stderr.lower()
+    assert p.stdout.strip() == ""
