@@ -226,3 +226,57 @@ def test_served_full_size_sampled(G):
     for h in sample:
         _replay_served(G, pre, reqs, recs, out, k, h, caps)
     hs.close()
+
+
+def test_served_queue_overflow_rejects_and_replays(G):
+    """An operation queue too small for the stream: requests that no longer
+    fit are rejected (their queue slots skipped by the slots), the launch
+    ends with GH_ENOMEM, and every admitted request still replays."""
+    k, nh, nreq = 64, 8, 2000
+    pre, reqs, sizes = W.served_stream(nh, k, nreq, seed=47, rate_per_s=None, min_log2=6,
+                                       max_log2=11, max_ins_log2=9)
+    caps = W.served_capacity(sizes, extra=1 << 14)
+    hs = G.HeapSet(k, caps)
+    d = G.ops_to_device(pre)
+    hs.submit(*d[:5], workgroups=64)
+    assert hs.sync() == 0
+    r, n, keys, out, recs, max_ops = G.requests_to_device(reqs)
+    _p("served overflow: queue %d of %d operations" % (max_ops // 2, max_ops))
+    hs.serve(r, n, keys, out, recs, max_ops // 2, workgroups=48)
+    assert hs.sync() == G.GH_ENOMEM
+    torch.cuda.synchronize()
+    out = G.to_host_u64(out)
+    recs = G.recs_to_host(recs, n)
+    flags = recs["flags"]
+    assert np.all((flags & (G.REQ_ADMITTED | G.REQ_REJECTED)) != 0)
+    assert np.any((flags & G.REQ_REJECTED) != 0) and np.any((flags & G.REQ_ADMITTED) != 0)
+    assert int(recs["nops"][(flags & G.REQ_ADMITTED) != 0].astype(np.int64).sum()) <= max_ops // 2
+    for h in range(nh):
+        _replay_served(G, pre, reqs, recs, out, k, h, caps)
+    hs.close()
+
+
+def test_served_invalid_heap_rejected(G):
+    """Requests naming a heap outside the set are rejected (GH_EINVAL at the
+    end); the other heaps' requests replay."""
+    k, nh, nreq = 64, 6, 1200
+    pre, reqs, sizes = W.served_stream(nh, k, nreq, seed=53, rate_per_s=None, min_log2=6,
+                                       max_log2=10, max_ins_log2=8)
+    bad = np.arange(7, nreq, 97)
+    reqs.heap = reqs.heap.copy()
+    reqs.heap[bad] = nh + 5
+    caps = W.served_capacity(sizes, extra=1 << 14)
+    hs = G.HeapSet(k, caps)
+    d = G.ops_to_device(pre)
+    hs.submit(*d[:5], workgroups=64)
+    assert hs.sync() == 0
+    r, n, keys, out, recs, max_ops = G.requests_to_device(reqs)
+    hs.serve(r, n, keys, out, recs, max_ops, workgroups=32)
+    assert hs.sync() == G.GH_EINVAL
+    torch.cuda.synchronize()
+    out = G.to_host_u64(out)
+    recs = G.recs_to_host(recs, n)
+    assert np.all((recs["flags"][bad] & G.REQ_REJECTED) != 0)
+    for h in range(nh):
+        _replay_served(G, pre, reqs, recs, out, k, h, caps)
+    hs.close()
