@@ -322,7 +322,9 @@ typedef struct gh_sssptrace {
  * ends when the heap is empty and no workgroup holds entries.  Graph in CSR
  * (device): d_rowptr[V + 1], d_col / d_w[E] (uint32 weights); distances
  * must stay below 2^32 - 1; d_dist[V] receives the distances (UINT32_MAX =
- * unreachable).  d_push (device) holds workgroups * (push_per_wg + k)
+ * unreachable).  An edge whose target is not below V is skipped and the run
+ * reports GH_EINVAL; rowptr must be non-decreasing with rowptr[V] = E (not
+ * checked on the device).  d_push (device) holds workgroups * (push_per_wg + k)
  * entries (workgroups = tuning->workgroups, 256 when 0 or tuning is NULL);
  * push_per_wg >= k * (largest out-degree) guarantees room for one round of
  * improvements, else the run stops with GH_ENOMEM.  Heap 0 must be empty;

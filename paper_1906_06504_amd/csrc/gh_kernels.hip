@@ -372,7 +372,6 @@ __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs,
     S.hot = hot;
     S.ss = (lSchedShared*)&ss;
     S.t0 = ctl->t0;
-    const u32 mine = (u32)tid;
     auto due_of = [&](const gh_op& q) -> u64 {
       // arrival, bounded to one minute after the start
       const u64 ns = q.arrival_ns < 60000000000ull ? q.arrival_ns : 60000000000ull;
@@ -963,6 +962,10 @@ __global__ __launch_bounds__(T) void k_sssp(const HeapDesc* __restrict__ descs, 
       const u32 j1 = rowptr[u + 1];
       for (u32 j = rowptr[u]; j < j1; ++j) {
         const u32 v = col[j];
+        if (v >= V) {   // not a vertex: skip the edge, report the graph
+          note_error(ctl, ERR_INVAL);
+          continue;
+        }
         const u64 nd64 = (u64)d + wt[j];
         if (nd64 >= 0xFFFFFFFFull) continue;
         const u32 nd = (u32)nd64;

@@ -26,8 +26,12 @@ class Graph:
         self.E = int(rowptr[-1])
         if self.V <= 0 or self.V >= (1 << 32) - 1:
             raise ValueError("vertex count out of range")
-        if col.size != self.E or w.size != self.E:
+        if col.size != self.E or w.size != self.E or int(rowptr[0]) != 0:
             raise ValueError("CSR arrays disagree")
+        if np.any(np.diff(rowptr.astype(np.int64)) < 0):
+            raise ValueError("rowptr must be non-decreasing")
+        if self.E and int(np.max(col)) >= self.V:
+            raise ValueError("edge target out of range")
         self.max_degree = int(np.max(np.diff(rowptr.astype(np.int64)))) if self.V else 0
         self.rowptr = _dev_u32(rowptr, device)
         self.col = _dev_u32(col, device)

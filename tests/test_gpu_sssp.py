@@ -136,3 +136,32 @@ def test_sssp_heap_trace_replays(S, V, k, wg, threads, seed):
     assert oh.size == 0
     assert np.array_equal(d, oracle.dijkstra(V, rowptr, col, w, 0))
     sol.close()
+
+
+def test_sssp_edge_out_of_range_reported(S):
+    """An edge whose target is not a vertex is skipped on the device and the
+    run reports GH_EINVAL (the host-side graph class refuses such input, so
+    the device copy is altered after the check)."""
+    from paper_1906_06504_amd import gheap as G
+    rowptr, col, w = W.sssp_graph(500, seed=61)
+    g = S.Graph(rowptr, col, w)
+    bad = g.col.cpu()
+    bad[3] = 500 + 7
+    g.col.copy_(bad)
+    sol = S.Solver(g, 32, workgroups=8)
+    with pytest.raises(G.GHeapError) as e:
+        sol.run(0)
+    assert e.value.code == G.GH_EINVAL
+    sol.close()
+
+
+def test_sssp_graph_checks_on_host(S):
+    rowptr, col, w = W.sssp_graph(50, seed=62)
+    col2 = col.copy()
+    col2[0] = 50
+    with pytest.raises(ValueError):
+        S.Graph(rowptr, col2, w)
+    r2 = rowptr.copy()
+    r2[3], r2[4] = r2[4], r2[3] - 1
+    with pytest.raises(ValueError):
+        S.Graph(r2, col, w)
