@@ -50,6 +50,10 @@ def parse():
     ap.add_argument("--no-knapsack", action="store_true", help="skip the knapsack leg")
     ap.add_argument("--knapsack-instances", type=int, default=512)
     ap.add_argument("--no-sssp", action="store_true", help="skip the SSSP leg")
+    ap.add_argument("--no-paper-table", action="store_true",
+                    help="skip the insert-all-then-drain leg in the paper's key orders")
+    ap.add_argument("--paper-log2n", type=int, default=26,
+                    help="keys of that leg (the paper's table uses 2^29)")
     ap.add_argument("--sssp-log2v", type=int, default=20)
     return ap.parse_args()
 
@@ -178,6 +182,8 @@ def main():
         result["served"] = run_served(args)
     if not args.no_knapsack:
         result["knapsack"] = run_knapsack(args)
+    if not args.no_paper_table:
+        result["paper_table"] = run_paper_table(args)
     sssp_graph = None
     if not args.no_sssp:
         result["sssp"], sssp_graph = run_sssp(args)
@@ -522,6 +528,60 @@ def run_knapsack(args):
     }
     log("knapsack: k=%d threads=%d %.2f ms, %.3g keys/s (plain per launch %.3g)"
         % (k, t, ms, out["keys_per_s"], out["plain_one_instance_per_launch_keys_per_s"]))
+    return out
+
+
+# The paper's Table vscpu: TD-INS/TD-DEL heap, 2^29 keys inserted then all
+# deleted, k = 1024, on its GPU (ms); context for the scaled run here.
+PAPER_TD_MS_2E29 = {"random": 112090.0, "descending": 100163.0, "ascending": 99082.0}
+
+
+def run_paper_table(args):
+    """The comparison workload of the paper's Table vscpu at 2^paper_log2n
+    keys: insert all keys in batches of 1024, then deleteMin(1024) until
+    empty, for random, descending and ascending keys, in one launch each;
+    the deleteMin outputs in ticket order must be the sorted keys."""
+    import torch
+    from paper_1906_06504_amd import gheap as G
+    from paper_1906_06504_amd import workloads as W
+    k = 1024
+    N = 1 << args.paper_log2n
+    out = {"workload": "insert 2^%d keys in batches of %d, then deleteMin(%d) until empty "
+                       "(the paper's Table vscpu uses 2^29)" % (args.paper_log2n, k, k)}
+    for order in ("random", "descending", "ascending"):
+        log("paper table: %s keys, 2^%d" % (order, args.paper_log2n))
+        ops = W.ordered_insert_then_drain(N, k, order, seed=0x5EED0009)
+        rows = {}
+        for wg in (128, 64):
+            hs = G.HeapSet(k, [N + k], stream=torch.cuda.Stream())
+            with torch.cuda.stream(hs.stream):
+                d = G.ops_to_device(ops)
+                lg = G.new_log(d[1])
+                ms = _timed_submit(hs, d, wg, 512, lg)
+                if wg == 128:
+                    # deleteMin outputs in ticket order = all keys sorted
+                    res = G.to_host_u64(d[3])
+                    cnt = d[4].cpu().numpy()[:d[1]].astype(np.int64)
+                    tk = G.log_to_host(lg, d[1])["ticket"]
+                    dels = np.flatnonzero(ops.kind == W.OP_DELETE_MIN)
+                    dels = dels[np.argsort(tk[dels], kind="stable")]
+                    got = np.concatenate([res[int(ops.off[i]):int(ops.off[i]) + int(cnt[i])]
+                                          for i in dels])
+                    want = {"random": lambda: np.sort(ops.keys),
+                            "ascending": lambda: ops.keys,
+                            "descending": lambda: ops.keys[::-1]}[order]()
+                    if not np.array_equal(got, want):
+                        raise SystemExit("paper table: drained keys are not the sorted input")
+                del d
+            hs.close()
+            rows["workgroups_%d" % wg] = {"ms": ms, "keys_per_s": 2 * N / (ms / 1e3)}
+        best = min(r["ms"] for r in rows.values())
+        rows["paper_ms_2e29_titan_x"] = PAPER_TD_MS_2E29[order]
+        rows["paper_ms_scaled_to_this_n"] = PAPER_TD_MS_2E29[order] * N / (1 << 29)
+        rows["speedup_vs_paper_scaled"] = rows["paper_ms_scaled_to_this_n"] / best
+        out[order] = rows
+        log("paper table %s: %.1f ms (paper, scaled: %.1f ms)"
+            % (order, best, rows["paper_ms_scaled_to_this_n"]))
     return out
 
 

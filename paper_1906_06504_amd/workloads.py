@@ -174,6 +174,31 @@ def insert_then_drain(total: int, k: int, batch: int, seed: int) -> OpList:
     return build_oplist(kinds, sizes, _keys_with_ids(st, 0), k)
 
 
+def ordered_insert_then_drain(total: int, k: int, order: str, seed: int) -> OpList:
+    """The workload of the paper's comparison with CPU heaps (Table vscpu):
+    insert `total` keys in batches of k, then deleteMin until empty (one
+    extra deleteMin returns 0).  Keys are uniform u32 ("random"), or
+    0, 1, 2, ... ("ascending") or total-1, ..., 0 ("descending"), each
+    with its insertion rank as id."""
+    if total > (1 << 32) - 1:
+        raise ValueError("at most 2^32 - 1 keys")
+    n_ins = -(-total // k)
+    sizes = [k] * (total // k) + ([total % k] if total % k else [])
+    n_del = -(-total // k) + 1
+    kinds = [OP_INSERT] * n_ins + [OP_DELETE_MIN] * n_del
+    sizes = sizes + [0] * n_del
+    if order == "random":
+        src = _keys_with_ids(Stream(seed), 0)
+    elif order in ("ascending", "descending"):
+        def src(count: int) -> np.ndarray:
+            ids = np.arange(count, dtype=np.uint64)
+            keys = ids if order == "ascending" else np.uint64(count - 1) - ids
+            return (keys << np.uint64(32)) | ids
+    else:
+        raise ValueError("order must be random, ascending or descending")
+    return build_oplist(kinds, sizes, src, k)
+
+
 def prefill_ops(nkeys: int, k: int, seed: int, first_id: int = 0) -> OpList:
     """`nkeys` uniform u32 keys inserted as full batches of k."""
     st = Stream(seed)
