@@ -60,3 +60,21 @@ def test_bench_refuses_several_gpus():
     assert p.returncode == 2
     assert "one GPU" in p.stderr or "one gpu" in p.stderr.lower()
     assert p.stdout.strip() == ""
+
+
+def test_ordered_insert_then_drain():
+    k = 64
+    for order in ("random", "ascending", "descending"):
+        ops = W.ordered_insert_then_drain(1000, k, order, seed=5)
+        ins = ops.kind == W.OP_INSERT
+        assert int(ops.n[ins].sum()) == 1000 and ins.sum() == 16 and (~ins).sum() == 17
+        assert np.all(ops.n[ins][:-1] == k) and ops.n[ins][-1] == 1000 - 15 * k
+        ids = ops.keys & np.uint64(0xFFFFFFFF)
+        assert np.array_equal(ids, np.arange(1000, dtype=np.uint64))
+        keys = ops.keys >> np.uint64(32)
+        if order == "ascending":
+            assert np.array_equal(keys, np.arange(1000, dtype=np.uint64))
+        elif order == "descending":
+            assert np.array_equal(keys, np.arange(999, -1, -1).astype(np.uint64))
+        else:
+            assert np.unique(keys).size > 990
