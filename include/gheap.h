@@ -174,6 +174,17 @@ int heap_create_many(gh_heap_t *out, uint32_t k, uint32_t nheaps,
  * heap would exceed max_keys; nothing is inserted). */
 int heap_insert(gh_heap_t h, const uint64_t *d_keys, uint64_t n);
 
+/* Bulk build (Sec. 3.1: a sorted array already satisfies Properties 1-3):
+ * heap i of the set, which must be empty, takes the n entries of d_sorted
+ * (device, ascending) without any heap operation.  The first floor(n / k) * k
+ * entries become the nodes in the order they would have been added (node
+ * slot p - 1 holds entries [(p - 1) k, p k); every parent precedes its
+ * children in that order), the rest the partial buffer.  n = 0 is a no-op.
+ * Errors: GH_EINVAL (null, i out of range; from the device: d_sorted not
+ * ascending), GH_ENOMEM (n > max_keys of heap i), GH_ESTATE (from the
+ * device: heap i not empty).  Device errors are sticky. */
+int heap_build(gh_heap_t h, uint32_t i, const uint64_t *d_sorted, uint64_t n);
+
 /* deleteMin on heap 0 of the set (Sec. 3.2.1, Sec. 3.3.2): writes the
  * min(k, size) smallest entries in ascending order to d_out (device, room for
  * k entries) and that number to *d_count (device).  An empty heap gives

@@ -71,7 +71,8 @@ struct alignas(256) Ctl {
   u64 timeout_ticks;  // watchdog limit for one lock wait
   u32 status;         // sticky error code (0 = ok), first error wins
   u32 abort;          // nonzero: every workgroup leaves as soon as it can
-  u32 pad1[26];
+  u32 build_ok;       // a bulk build found its heap empty
+  u32 pad1[25];
 };
 static_assert(sizeof(Ctl) == 256, "ctl layout");
 

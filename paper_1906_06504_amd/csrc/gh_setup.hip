@@ -99,6 +99,60 @@ hipError_t launch_sssp_fini(const HeapDesc* descs, const SsspState* st, gh_sssps
   return hipGetLastError();
 }
 
+// Bulk build of one empty heap from an ascending array: entries go to the
+// node slots in storage order (slot p - 1 is the p-th node added; its parent
+// was added earlier) and the remainder to the partial buffer.  Three
+// launches: the emptiness check, the copy, and the new root word.
+__global__ void k_build_check(const HeapDesc* __restrict__ d, Ctl* ctl) {
+  if (threadIdx.x == 0) {
+    const u64 w = ld_relaxed(&d->meta->root);
+    const bool empty = rw_m(w) == 0 && rw_s(w) == 0;
+    ctl->build_ok = empty ? 1u : 0u;
+    if (!empty) note_error(ctl, ERR_STATE);
+  }
+}
+
+__global__ void k_build_copy(const HeapDesc* __restrict__ d, const u64* __restrict__ keys, u64 n,
+                             Ctl* ctl) {
+  if (!ctl->build_ok) return;
+  const HeapDesc H = *d;
+  const u64 m = n / H.k, body = m * H.k;
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  const u64 i0 = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+  bool sorted = true;
+  for (u64 i = i0; i < n; i += stride) {
+    const u64 x = keys[i];
+    if (i + 1 < n && x > keys[i + 1]) sorted = false;
+    if (i < body) H.nodes[i] = x;
+    else H.pb[i - body] = x;
+  }
+  if (!sorted) note_error(ctl, ERR_INVAL);
+  for (u64 p = i0 + 1; p <= m; p += stride) H.locks[p] = 0;
+}
+
+__global__ void k_build_root(const HeapDesc* __restrict__ d, u64 n, Ctl* ctl) {
+  if (threadIdx.x == 0 && ctl->build_ok) {
+    const HeapDesc H = *d;
+    const u64 m = n / H.k;
+    const u64 w = ld_relaxed(&H.meta->root);
+    st_relaxed(&H.meta->root, rootword(rw_ticket(w), m, n - m * H.k));
+  }
+}
+
+hipError_t launch_build(const HeapDesc* d, const u64* keys, u64 n, Ctl* ctl, hipStream_t st) {
+  u64 blocks = (n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(k_build_check, dim3(1), dim3(64), 0, st, d, ctl);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_build_copy, dim3((u32)blocks), dim3(256), 0, st, d, keys, n, ctl);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_build_root, dim3(1), dim3(64), 0, st, d, n, ctl);
+  return hipGetLastError();
+}
+
 hipError_t launch_init(HeapDesc* descs_dev, const HeapDesc* descs_host, u32 nheaps, Ctl* ctl,
                        u64 timeout_ticks, hipStream_t st) {
   hipError_t e = hipMemcpyAsync(descs_dev, descs_host, sizeof(HeapDesc) * nheaps,

@@ -17,6 +17,7 @@ hipError_t launch_init(HeapDesc* descs_dev, const HeapDesc* descs_host, u32 nhea
                        u64 timeout_ticks, hipStream_t st);
 hipError_t launch_prep(const HeapDesc* descs, u32 nheaps, Ctl* ctl, hipStream_t st);
 hipError_t launch_serve_reset(ServeHead* head, hipStream_t st);
+hipError_t launch_build(const HeapDesc* d, const u64* keys, u64 n, Ctl* ctl, hipStream_t st);
 hipError_t launch_sssp_init(const HeapDesc* descs, SsspState* st, u32* dist, u32 V, u32 src,
                             u64* push, gh_ssspstats* stats, hipStream_t stream);
 hipError_t launch_sssp_fini(const HeapDesc* descs, const SsspState* st, gh_ssspstats* stats,
@@ -317,6 +318,18 @@ int heap_insert(gh_heap_t h, const uint64_t* d_keys, uint64_t n) {
   int rc = run_ops(h, nullptr, (u32)nops, p, d_keys, nullptr, nullptr, nullptr, &t);
   if (rc == GH_OK) h->size0 += n;
   return rc;
+}
+
+int heap_build(gh_heap_t h, uint32_t i, const uint64_t* d_sorted, uint64_t n) {
+  if (!h) return GH_EINVAL;
+  if (h->sticky != GH_OK) return h->sticky;
+  if (i >= h->nheaps) return GH_EINVAL;
+  if (n == 0) return GH_OK;
+  if (!d_sorted) return GH_EINVAL;
+  if (n > h->max_keys[i]) return GH_ENOMEM;
+  if (i == 0) h->size0_known = false;
+  if (launch_build(h->descs + i, d_sorted, n, h->ctl, h->stream) != hipSuccess) return GH_EDEVICE;
+  return GH_OK;
 }
 
 int heap_delete_min(gh_heap_t h, uint64_t* d_out, uint32_t k, uint32_t* d_count) {

@@ -63,7 +63,8 @@ EXPORTS = ("heap_arena_bytes", "heap_supported_shape", "heap_create", "heap_crea
            "heap_insert", "heap_delete_min", "heap_submit", "heap_submit_graph",
            "heap_graph_launch", "heap_graph_destroy", "heap_sync", "heap_size",
            "heap_read_state", "heap_destroy", "heap_strerror", "heap_clock_hz",
-           "heap_serve_workspace_bytes", "heap_serve", "heap_knapsack", "heap_sssp")
+           "heap_serve_workspace_bytes", "heap_serve", "heap_knapsack", "heap_sssp",
+           "heap_build")
 
 
 class GHeapError(RuntimeError):
@@ -118,6 +119,7 @@ def load_library(path: str = LIB_PATH):
                                 ctypes.POINTER(_Tuning)]),
         "heap_sssp": (i32, [vp, u32, vp, vp, vp, u32, vp, vp, u64, vp,
                             ctypes.POINTER(_Tuning), ctypes.POINTER(SsspTrace)]),
+        "heap_build": (i32, [vp, u32, vp, u64]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -246,6 +248,11 @@ class HeapSet:
                                  work.data_ptr(), work.numel(), max_ops, ctypes.byref(t))
         _check(rc, "heap_serve")
         return work
+
+    def build(self, i: int, sorted_keys: torch.Tensor):
+        """Bulk-build empty heap i from an ascending int64 tensor of entries."""
+        _check(self.lib.heap_build(self.h, i, _ptr(sorted_keys), sorted_keys.numel()),
+               "heap_build")
 
     def sync(self) -> int:
         return int(self.lib.heap_sync(self.h))

@@ -253,3 +253,29 @@ def test_planted_mistake_is_caught(name):
     with tempfile.TemporaryDirectory() as d:
         lib = _build_mutant(name, d)
         assert _mutant_caught(lib), "planted mistake %s was not detected" % name
+
+
+def test_sorted_array_in_addition_order_is_a_heap():
+    """Sec. 3.1: a sorted array satisfies the properties.  Laid out in the
+    order nodes are added (the p-th chunk of k at position p, node index
+    idx(p)), every parent's chunk precedes its children's, so Properties 1-3
+    hold for any n and k (checked directly, for k = 1..9 and many n)."""
+    import random
+    rnd = random.Random(3)
+    for k in range(1, 10):
+        for n in [0, 1, k - 1, k, k + 1, 5 * k + 3, 37 * k, rnd.randint(1, 400)]:
+            keys = sorted(rnd.randint(0, 50) for _ in range(n))
+            m, s = n // k, n % k
+            node = {}
+            for p in range(1, m + 1):
+                node[oracle.idx(p)] = keys[(p - 1) * k:p * k]
+            pb = keys[m * k:]
+            assert sorted(node) == sorted(oracle.idx(p) for p in range(1, m + 1))
+            for c, batch in node.items():
+                assert batch == sorted(batch)                       # Property 1
+                if c > 1:
+                    assert c // 2 in node                            # complete shape
+                    assert node[c // 2][-1] <= batch[0]              # Property 2
+            if m and pb:
+                assert node[1][-1] <= pb[0]                          # Property 3
+            assert len(pb) < k
