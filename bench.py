@@ -54,6 +54,9 @@ def parse():
                     help="skip the insert-all-then-drain leg in the paper's key orders")
     ap.add_argument("--paper-log2n", type=int, default=26,
                     help="keys of that leg (the paper's table uses 2^29)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="also run the parameter sweeps of the paper's experiments (node "
+                         "capacity, operations in flight, partial batches); not in the default run")
     ap.add_argument("--sssp-log2v", type=int, default=20)
     return ap.parse_args()
 
@@ -184,6 +187,8 @@ def main():
         result["knapsack"] = run_knapsack(args)
     if not args.no_paper_table:
         result["paper_table"] = run_paper_table(args)
+    if args.sweep:
+        result["sweep"] = run_sweep(args)
     sssp_graph = None
     if not args.no_sssp:
         result["sssp"], sssp_graph = run_sssp(args)
@@ -582,6 +587,60 @@ def run_paper_table(args):
         out[order] = rows
         log("paper table %s: %.1f ms (paper, scaled: %.1f ms)"
             % (order, best, rows["paper_ms_scaled_to_this_n"]))
+    return out
+
+
+def run_sweep(args):
+    """The shapes of the paper's parameter studies on this GPU, on the
+    insert-all-then-drain workload with random keys (2^24 keys): node
+    capacity k (default workgroup size for each k, 64 operations in flight),
+    the number of operations in flight at k = 1024, and full against partial
+    insert batches (batches of k, or sizes uniform on [1, k])."""
+    import torch
+    from paper_1906_06504_amd import gheap as G
+    from paper_1906_06504_amd import workloads as W
+    N = 1 << 24
+
+    def timed(ops, k, wg, th):
+        hs = G.HeapSet(k, [N + k], stream=torch.cuda.Stream())
+        with torch.cuda.stream(hs.stream):
+            d = G.ops_to_device(ops)
+            ms = _timed_submit(hs, d, wg, th)
+            del d
+        hs.close()
+        return ms
+
+    out = {"workload": "insert 2^24 random keys, then deleteMin(k) until empty"}
+    rows = []
+    for k in (64, 128, 256, 512, 1024):
+        ops = W.ordered_insert_then_drain(N, k, "random", seed=0x5EED000A)
+        ms = timed(ops, k, 64, 0)
+        rows.append({"k": k, "workgroups": 64, "ms": ms, "keys_per_s": 2 * N / (ms / 1e3)})
+        log("sweep k=%d: %.1f ms" % (k, ms))
+    out["node_capacity"] = rows
+    rows = []
+    ops = W.ordered_insert_then_drain(N, 1024, "random", seed=0x5EED000A)
+    for wg in (1, 4, 16, 32, 64, 128, 256):
+        ms = timed(ops, 1024, wg, 512)
+        rows.append({"k": 1024, "workgroups": wg, "ms": ms, "keys_per_s": 2 * N / (ms / 1e3)})
+        log("sweep workgroups=%d: %.1f ms" % (wg, ms))
+    out["operations_in_flight"] = rows
+    # partial batches: the same keys inserted in batches of uniform size
+    st = W.Stream(0x5EED000B)
+    sizes, acc = [], 0
+    while acc < N:
+        b = int(min(st.uniform_int(1, 1024, 1)[0], N - acc))
+        sizes.append(b)
+        acc += b
+    n_del = N // 1024 + 1
+    kinds = [W.OP_INSERT] * len(sizes) + [W.OP_DELETE_MIN] * n_del
+    part = W.build_oplist(kinds, sizes + [0] * n_del, W._keys_with_ids(W.Stream(0x5EED000A), 0),
+                          1024)
+    ms_full = out["operations_in_flight"][4]["ms"]
+    ms_part = timed(part, 1024, 64, 512)
+    out["partial_batches"] = {"full_batches_ms": ms_full, "uniform_1_to_k_batches_ms": ms_part,
+                              "insert_ops_full": N // 1024, "insert_ops_partial": len(sizes)}
+    log("sweep partial batches: %.1f ms vs full %.1f ms" % (ms_part, ms_full))
     return out
 
 

@@ -136,8 +136,9 @@ typedef struct gh_reqrec {
 } gh_reqrec;
 
 /* Launch shape of a submission: workgroups = number of operations in flight
- * (0 = library default), threads = workgroup size (0 = library default; must
- * be one of the shapes heap_supported_shape accepts for k). */
+ * (0 = library default), threads = workgroup size (0 = library default: 64
+ * for k = 32, 128 for k = 64..256, 512 for k = 512 and 1024; must be one of
+ * the shapes heap_supported_shape accepts for k). */
 typedef struct gh_tuning {
     uint32_t workgroups;
     uint32_t threads;
