@@ -65,6 +65,8 @@ def _declare(lib):
     lib.gho_insert.argtypes = [ctypes.c_void_p, U64P, ctypes.c_uint64]
     lib.gho_delete_min.restype = ctypes.c_uint64
     lib.gho_delete_min.argtypes = [ctypes.c_void_p, U64P]
+    lib.gho_delete_min_n.restype = ctypes.c_uint64
+    lib.gho_delete_min_n.argtypes = [ctypes.c_void_p, U64P, ctypes.c_uint64]
     lib.gho_check.restype = ctypes.c_int
     lib.gho_check.argtypes = [ctypes.c_void_p]
     lib.gho_export.restype = None
@@ -137,10 +139,17 @@ class OracleHeap:
         if self.lib.gho_insert(self.h, _p64(a), a.size) != 0:
             raise MemoryError("gho_insert failed")
 
-    def delete_min(self) -> np.ndarray:
+    def delete_min(self, c: int | None = None) -> np.ndarray:
+        """Remove and return the min(c, size) smallest entries (c = k when
+        None; 1 <= c <= k)."""
         out = np.empty(self.k, dtype=np.uint64)
-        c = self.lib.gho_delete_min(self.h, _p64(out))
-        return out[:c].copy()
+        if c is None:
+            got = self.lib.gho_delete_min(self.h, _p64(out))
+        else:
+            got = self.lib.gho_delete_min_n(self.h, _p64(out), int(c))
+            if got == 0xFFFFFFFFFFFFFFFF:
+                raise ValueError("deleteMin count must be in [1, k]")
+        return out[:got].copy()
 
     def check(self) -> int:
         return int(self.lib.gho_check(self.h))
@@ -173,7 +182,8 @@ class OracleHeap:
 
     def replay(self, types, n, off, in_keys, out_capacity: int, check: bool = False):
         """Apply ops in order (type 0 = INS n[i] keys from in_keys[off[i]:],
-        type 1 = DEL writing to out[off[i]:]).  Returns (out_keys, counts)."""
+        type 1 = DEL of n[i] entries (0 = k) writing to out[off[i]:]).
+        Returns (out_keys, counts)."""
         types = np.ascontiguousarray(types, dtype=np.uint8)
         n = np.ascontiguousarray(n, dtype=np.uint32)
         off = np.ascontiguousarray(off, dtype=np.uint64)

@@ -26,6 +26,9 @@
  *     Sec. 3.3.4 states, the partial buffer is handled whenever an operation
  *     holds the root, so a DEL re-establishes Property 3 after refilling the
  *     root;
+ *   - DEL of c < k entries (variable count; a reading, see gho_delete_min_n):
+ *     the root's c smallest, then the root's rest and the partial buffer
+ *     refill the top, taking the last node only when they are fewer than k;
  *   - target order by bit-reversal permutation (Sec. 4.3, "Bit-Reversal
  *     Permutation"), DEL taking the last node in the reverse order.
  *
@@ -223,6 +226,8 @@ int gho_insert(gho_heap *h, const gho_ent *x, uint64_t n) {
 
 /* ---- DEL (Sec. 3.2.1, partial buffer per Sec. 3.3.2/3.3.4) ------------- */
 
+static void sift_down(gho_heap *h);
+
 /* Removes and returns the min(k, size) smallest entries, ascending. */
 uint64_t gho_delete_min(gho_heap *h, gho_ent *out) {
     const uint64_t k = h->k;
@@ -247,7 +252,69 @@ uint64_t gho_delete_min(gho_heap *h, gho_ent *out) {
     h->m -= 1;
     if (h->s > 0)
         merge_and_sort(h, node_at(h, 1), k, h->pb, h->s, node_at(h, 1), h->pb);
-    /* sift down */
+    sift_down(h);
+    return k;
+}
+
+/* ---- DEL of c < k entries (variable-count deleteMin) -------------------
+ * The plain definition fixes the result: the min(c, size) smallest live
+ * entries, ascending.  The steps are a reading of Sec. 3.2.1 and Sec. 3.3.2
+ * (the paper only defines deleteMin of a whole root): the root's c smallest
+ * are the answer; its k - c others and the partial buffer, merged, are what
+ * must stay above every node.  If they are at least k entries, the k smallest
+ * form the new root and the rest the partial buffer (no node goes away);
+ * otherwise the last node is taken as for a full DEL, and the new root is the
+ * k smallest of it and the merged rest, the remainder (< k entries) the
+ * partial buffer.  Either way the root sifts down as in DEL.  With no node
+ * the partial buffer gives its c smallest; with one node and fewer than k
+ * entries left at the top, they all become the partial buffer.  For c = k
+ * this is exactly gho_delete_min. */
+uint64_t gho_delete_min_n(gho_heap *h, gho_ent *out, uint64_t c) {
+    const uint64_t k = h->k;
+    if (c == 0 || c > k) return UINT64_MAX;
+    if (c == k) return gho_delete_min(h, out);
+    h->del_ops++;
+    if (h->m == 0) {
+        uint64_t cnt = h->s < c ? h->s : c;
+        memcpy(out, h->pb, cnt * sizeof(gho_ent));
+        memmove(h->pb, h->pb + cnt, (h->s - cnt) * sizeof(gho_ent));
+        h->s -= cnt;
+        return cnt;
+    }
+    gho_ent *root = node_at(h, 1);
+    memcpy(out, root, c * sizeof(gho_ent));
+    /* what stays at the top: the root's other k - c entries and the pb */
+    uint64_t nrest = k - c + h->s;
+    gho_ent *rest = h->tmp2;
+    merge_into(root + c, k - c, h->pb, h->s, rest);
+    if (nrest >= k) {
+        memcpy(root, rest, k * sizeof(gho_ent));
+        memcpy(h->pb, rest + k, (nrest - k) * sizeof(gho_ent));
+        h->s = nrest - k;
+    } else if (h->m == 1) {
+        memcpy(h->pb, rest, nrest * sizeof(gho_ent));
+        h->s = nrest;
+        h->m = 0;
+        for (uint64_t i = 0; i < k; i++) root[i] = GHO_MAX;
+        return c;
+    } else {
+        uint64_t last = gho_idx(h->m);
+        merge_and_sort(h, node_at(h, last), k, rest, nrest, root, h->pb);
+        for (uint64_t i = 0; i < k; i++) node_at(h, last)[i] = GHO_MAX;
+        h->m -= 1;
+        h->s = nrest;
+    }
+    sift_down(h);
+    return c;
+}
+
+/* Sift the root down (Sec. 3.2.1): at each node, stop once its largest
+ * entry is <= every existing child's smallest; with two children, their
+ * MergeAndSort leaves lo in the child whose maximum was larger and hi merges
+ * with the node, whose k smallest stay; with one child, the node merges with
+ * it. */
+static void sift_down(gho_heap *h) {
+    const uint64_t k = h->k;
     uint64_t c = 1;
     for (;;) {
         uint64_t l = 2 * c, r = 2 * c + 1;
@@ -276,7 +343,6 @@ uint64_t gho_delete_min(gho_heap *h, gho_ent *out) {
             c = x;
         }
     }
-    return k;
 }
 
 /* ---- invariant checker (Sec. 3.1, Properties 1-3) ---------------------- */
@@ -328,8 +394,9 @@ void gho_counters(const gho_heap *h, uint64_t out[5]) {
 
 /* ---- log replay --------------------------------------------------------
  * Apply ops in the given order: type 0 = INS of n[i] entries read from
- * in_keys + off[i]; type 1 = DEL whose output goes to out_keys + off[i] and
- * whose count goes to out_count[i].  With check != 0 the invariants are
+ * in_keys + off[i]; type 1 = DEL of n[i] entries (0 = k; more than k fails)
+ * whose output goes to out_keys + off[i] and whose count goes to
+ * out_count[i].  With check != 0 the invariants are
  * verified after every op.  Returns 0, or -(1 + index) of the first op that
  * failed (allocation or invariant), or -(1<<40) on a bad type. */
 int64_t gho_replay(gho_heap *h, uint64_t nops, const uint8_t *type,
@@ -341,7 +408,10 @@ int64_t gho_replay(gho_heap *h, uint64_t nops, const uint8_t *type,
             if (gho_insert(h, in_keys + off[i], n[i])) return -(int64_t)(i + 1);
             if (out_count) out_count[i] = 0;
         } else if (type[i] == 1) {
-            uint64_t c = gho_delete_min(h, out_keys + off[i]);
+            /* n[i] = entries requested, 0 meaning k */
+            uint64_t want = n[i] ? n[i] : h->k;
+            uint64_t c = gho_delete_min_n(h, out_keys + off[i], want);
+            if (c == UINT64_MAX) return -(int64_t)(i + 1);
             if (out_count) out_count[i] = (uint32_t)c;
         } else {
             return -((int64_t)1 << 40);

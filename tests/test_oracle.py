@@ -4,6 +4,7 @@
   entries in ascending order (the root holds the k smallest by Properties 1
   and 3, Sec. 3.1; the partial buffer is read only when no node exists,
   Sec. 3.3.2), checked against a sorted Python list on small random traces;
+  likewise deleteMin(c) returns the min(c, size) smallest;
 * Properties 1-3 and the closed form m = size // k, s = size % k after every
   operation (the partial buffer never reaches k entries, Sec. 3.1);
 * k = 1 reduces to the conventional heap (Sec. 3.1, note after Property 3):
@@ -34,14 +35,17 @@ def _built():
     oracle.build(force=False)
 
 
-def random_trace(rng, k, nops, key_range, max_ins=None):
-    """Random op sequence: ('ins', array) or ('del',)."""
+def random_trace(rng, k, nops, key_range, max_ins=None, var_del=False):
+    """Random op sequence: ('ins', array), ('del',) or, with var_del, also
+    ('del', c) with c uniform on [1, k]."""
     max_ins = max_ins or 3 * k
     ops = []
     for _ in range(nops):
         if rng.random() < 0.55:
             n = int(rng.integers(0, max_ins + 1))
             ops.append(("ins", rng.integers(0, key_range, n).astype(np.uint64)))
+        elif var_del and rng.random() < 0.7:
+            ops.append(("del", int(rng.integers(1, k + 1))))
         else:
             ops.append(("del",))
     return ops
@@ -57,8 +61,9 @@ def run_against_brute_force(k, ops, lib=None):
             h.insert(op[1])
             live = sorted(live + [int(v) for v in op[1]])
         else:
-            got = h.delete_min()
-            c = min(k, len(live))
+            want_n = op[1] if len(op) > 1 else k
+            got = h.delete_min(op[1] if len(op) > 1 else None)
+            c = min(want_n, len(live))
             want = live[:c]
             live = live[c:]
             if [int(v) for v in got] != want:
@@ -79,6 +84,55 @@ def test_brute_force_random_traces(k):
         ops = random_trace(rng, k, int(rng.integers(5, 80)), key_range)
         msg = run_against_brute_force(k, ops)
         assert msg is None, "k=%d trial=%d %s" % (k, trial, msg)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 8, 16])
+def test_brute_force_variable_count_deletes(k):
+    """deleteMin(c), 1 <= c <= k: the min(c, size) smallest live entries,
+    ascending, with Properties 1-3 and m = size // k, s = size % k after
+    every operation."""
+    rng = np.random.default_rng(3000 + k)
+    for trial in range(60):
+        key_range = 50 if trial % 3 == 0 else 1 << 40
+        ops = random_trace(rng, k, int(rng.integers(5, 120)), key_range, var_del=True)
+        msg = run_against_brute_force(k, ops)
+        assert msg is None, "k=%d trial=%d %s" % (k, trial, msg)
+
+
+def test_variable_count_delete_bounds_and_full_count():
+    """c = k is the ordinary deleteMin (same output and same internal
+    state); c = 0 and c > k are refused."""
+    rng = np.random.default_rng(5)
+    k = 8
+    a, b = oracle.OracleHeap(k), oracle.OracleHeap(k)
+    for _ in range(200):
+        if rng.random() < 0.6:
+            x = rng.integers(0, 1 << 40, int(rng.integers(1, 3 * k))).astype(np.uint64)
+            a.insert(x)
+            b.insert(x)
+        else:
+            assert np.array_equal(a.delete_min(), b.delete_min(k))
+        na, pa = a.export()
+        nb, pb = b.export()
+        assert np.array_equal(na, nb) and np.array_equal(pa, pb)
+    for bad in (0, k + 1):
+        with pytest.raises(ValueError):
+            a.delete_min(bad)
+
+
+def test_replay_variable_count_deletes():
+    """Replay reads a deleteMin's count from n (0 = k) and refuses n > k."""
+    k = 4
+    keys = np.arange(100, 130, dtype=np.uint64)
+    types = np.array([0, 0, 1, 1, 1, 1], dtype=np.uint8)
+    n = np.array([4, 4, 3, 0, 1, 0], dtype=np.uint32)
+    off = np.array([0, 4, 0, 3, 7, 8], dtype=np.uint64)
+    out, counts = oracle.OracleHeap(k).replay(types, n, off, keys, 16, check=True)
+    assert list(counts) == [0, 0, 3, 4, 1, 0]
+    assert list(out[:8]) == list(range(100, 108))
+    with pytest.raises(RuntimeError):
+        oracle.OracleHeap(k).replay(np.array([1], np.uint8), np.array([5], np.uint32),
+                                    np.array([0], np.uint64), keys, 16)
 
 
 def test_k1_matches_heapq_order():
@@ -193,8 +247,20 @@ SRC = os.path.join(os.path.dirname(oracle.__file__), "gheap_oracle.c")
 
 MUTANTS = {
     "no_pb_merge_on_delete": (
-        "    if (h->s > 0)\n        merge_and_sort(h, node_at(h, 1), k, h->pb, h->s, node_at(h, 1), h->pb);\n    /* sift down */",
-        "    /* sift down */"),
+        "    if (h->s > 0)\n        merge_and_sort(h, node_at(h, 1), k, h->pb, h->s, node_at(h, 1), h->pb);\n    sift_down(h);\n    return k;",
+        "    sift_down(h);\n    return k;"),
+    "partial_delete_no_sift": (
+        "    sift_down(h);\n    return c;",
+        "    return c;"),
+    "partial_delete_always_takes_last": (
+        "    if (nrest >= k) {",
+        "    if (0) {"),
+    "partial_delete_pb_not_shifted": (
+        "        memmove(h->pb, h->pb + cnt, (h->s - cnt) * sizeof(gho_ent));\n",
+        ""),
+    "partial_delete_drops_root_rest": (
+        "    merge_into(root + c, k - c, h->pb, h->s, rest);",
+        "    merge_into(root + k, 0, h->pb, h->s, rest);"),
     "lo_to_smaller_max_child": (
         "uint64_t big = (L[k - 1] > R[k - 1]) ? l : r;",
         "uint64_t big = (L[k - 1] > R[k - 1]) ? r : l;"),
@@ -239,7 +305,7 @@ def _mutant_caught(lib):
     rng = np.random.default_rng(99)
     for k in (1, 2, 3, 4, 8):
         for trial in range(40):
-            ops = random_trace(rng, k, 60, 1 << 40 if trial % 2 else 40)
+            ops = random_trace(rng, k, 60, 1 << 40 if trial % 2 else 40, var_del=trial % 4 >= 2)
             try:
                 if run_against_brute_force(k, ops, lib=lib) is not None:
                     return True
