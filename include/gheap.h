@@ -64,11 +64,14 @@ typedef struct gh_heap *gh_heap_t;
 /* One operation of a multi-operation submission (32 bytes, device memory).
  *   heap   index of the heap within the set, < nheaps
  *   kind   GH_OP_INSERT or GH_OP_DELETE_MIN
- *   n      insert: number of entries, 1..k; deleteMin: ignored
+ *   n      insert: number of entries, 1..k; deleteMin: number of entries to
+ *          take, 1..k, 0 meaning k (a deleteMin of c < k entries returns
+ *          the min(c, size) smallest; heap_submit runs those only with
+ *          GH_TUNE_VARIABLE_DELETE); larger n is rejected (GH_EINVAL)
  *   seq    rank of this operation among the submission's operations on the
  *          same heap: 0, 1, 2, ... in the order they must take the root
  *   off    insert: entry offset of its keys in d_in; deleteMin: entry offset
- *          of its k-entry output slot in d_out
+ *          of its output slot in d_out (room for its count of entries)
  *   arrival_ns  earliest start, in nanoseconds after the submission starts
  *          on the device (0 = immediately); operations must appear in
  *          non-decreasing arrival order */
@@ -83,7 +86,8 @@ typedef struct gh_op {
 
 /* Per-operation record written by a submission (32 bytes, device memory).
  *   ticket   root ticket of the operation on its heap (linearization order)
- *   count    insert: n; deleteMin: entries returned (min(k, heap size))
+ *   count    insert: n; deleteMin: entries returned (min(c, heap size) for a
+ *            deleteMin of c entries)
  *   levels   insert: depth of the target node reached (0 if the keys stayed
  *            in the partial buffer); deleteMin: sift-down levels that merged
  *   kind     GH_OP_INSERT or GH_OP_DELETE_MIN
@@ -138,10 +142,16 @@ typedef struct gh_reqrec {
 /* Launch shape of a submission: workgroups = number of operations in flight
  * (0 = library default), threads = workgroup size (0 = library default: 64
  * for k = 32, 128 for k = 64..256, 512 for k = 512 and 1024; must be one of
- * the shapes heap_supported_shape accepts for k). */
+ * the shapes heap_supported_shape accepts for k).  flags: 0, or
+ * GH_TUNE_VARIABLE_DELETE when the submission holds deleteMins of fewer than
+ * k entries; they run in a kernel of their own, so that submissions of
+ * whole-root deleteMins keep a kernel compiled without that code path.
+ * Without the flag such a record is rejected (GH_EINVAL). */
+#define GH_TUNE_VARIABLE_DELETE 1u
 typedef struct gh_tuning {
     uint32_t workgroups;
     uint32_t threads;
+    uint32_t flags;
 } gh_tuning;
 
 /* Bytes of arena needed for nheaps heaps of node capacity k, heap i holding
@@ -186,12 +196,16 @@ int heap_insert(gh_heap_t h, const uint64_t *d_keys, uint64_t n);
  * device: heap i not empty).  Device errors are sticky. */
 int heap_build(gh_heap_t h, uint32_t i, const uint64_t *d_sorted, uint64_t n);
 
-/* deleteMin on heap 0 of the set (Sec. 3.2.1, Sec. 3.3.2): writes the
- * min(k, size) smallest entries in ascending order to d_out (device, room for
- * k entries) and that number to *d_count (device).  An empty heap gives
- * *d_count = 0, not an error.  k must equal the heap's node capacity.
- * Errors: GH_EINVAL. */
-int heap_delete_min(gh_heap_t h, uint64_t *d_out, uint32_t k, uint32_t *d_count);
+/* deleteMin on heap 0 of the set (Sec. 3.2.1, Sec. 3.3.2) of c entries,
+ * 1 <= c <= k (the node capacity): writes the min(c, size) smallest entries in
+ * ascending order to d_out (device, room for c entries) and that number to
+ * *d_count (device).  An empty heap gives *d_count = 0, not an error.  c = k
+ * is the paper's deleteMin; for c < k the root's other entries and the
+ * partial buffer refill the root, and the last node is taken only when they
+ * are fewer than k (the variable-count deleteMin that a heap sharded over
+ * several devices needs to remove a globally selected share).
+ * Errors: GH_EINVAL (null pointer, c = 0 or c > k). */
+int heap_delete_min(gh_heap_t h, uint64_t *d_out, uint32_t c, uint32_t *d_count);
 
 /* Run nops operations (d_ops, device) on the set's heaps in one persistent
  * launch with many operations in flight (Sec. 3.3): each workgroup claims the
@@ -222,7 +236,8 @@ uint64_t heap_serve_workspace_bytes(uint32_t nheaps, uint32_t nreq, uint64_t max
 /* Serve a request stream with a device-resident loop (one persistent
  * launch).  d_reqs (device, nreq gh_op records, non-decreasing arrival_ns;
  * `seq` is ignored) are requests: an insert of any n >= 0 entries from
- * d_in + off, or a deleteMin writing up to k entries to d_out + off.
+ * d_in + off, or a deleteMin of n entries (1..k, 0 meaning k; a larger n
+ * is rejected with GH_EINVAL) writing up to that many to d_out + off.
  * Workgroup 0 admits requests in arrival order once their arrival time has
  * passed: a deleteMin always, an insert when the heap's size after all
  * admitted requests plus n stays within the heap's max_keys; otherwise the

@@ -41,9 +41,10 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     jobs = jobs or min(8, os.cpu_count() or 4)
     tasks = []
     for k in KS:
-        obj = os.path.join(BUILD, "gh_kernels_k%d.o" % k)
-        tasks.append([HIPCC] + COMMON + ["-DGH_K=%d" % k, "-c",
-                                         os.path.join(CSRC, "gh_kernels.hip"), "-o", obj])
+        for name in ("gh_kernels", "gh_serve"):
+            obj = os.path.join(BUILD, "%s_k%d.o" % (name, k))
+            tasks.append([HIPCC] + COMMON + ["-DGH_K=%d" % k, "-c",
+                                             os.path.join(CSRC, name + ".hip"), "-o", obj])
     tasks.append([HIPCC] + COMMON + ["-c", os.path.join(CSRC, "gh_setup.hip"),
                                      "-o", os.path.join(BUILD, "gh_setup.o")])
     tasks.append([HIPCC] + COMMON + ["-x", "hip", "-c", os.path.join(CSRC, "gheap_api.cpp"),

@@ -31,6 +31,7 @@ struct LaunchArgs {
   Ctl* ctl;
   u32 workgroups;
   u32 threads;
+  u32 var_delete;   // the operations may hold deleteMins of fewer than K entries
   hipStream_t stream;
 };
 
@@ -40,8 +41,12 @@ constexpr bool shape_ok(int K, int T) {
   return T >= 64 && T <= 1024 && (T & (T - 1)) == 0 && 2 * K >= T && 2 * K <= 16 * T;
 }
 
+// the persistent operation loop: whole-root deleteMins only (gh_kernels.hip),
+// or also deleteMins of fewer than K entries (gh_serve.hip)
 template <int K>
 hipError_t launch_ops_k(const LaunchArgs& a);
+template <int K>
+hipError_t launch_ops_var_k(const LaunchArgs& a);
 
 // ---------------------------------------------------------------------------
 // Served form: device workspace layout

@@ -209,7 +209,7 @@ __device__ __forceinline__ bool acquire_root(const HeapDesc& H, u64 ticket, OpSh
 // LDS: five buffers of K entries.
 // ---------------------------------------------------------------------------
 template <int K, int T>
-__device__ OpResult op_insert(const HeapDesc& H, u64 ticket, const u64* __restrict__ keys, u32 n,
+__device__ __forceinline__ OpResult op_insert(const HeapDesc& H, u64 ticket, const u64* __restrict__ keys, u32 n,
                               lu64* lds, OpShared& sh, Ctl* ctl) {
   constexpr int E = (2 * K) / T >= 1 ? (2 * K) / T : 1;
   const int tid = threadIdx.x;
@@ -398,13 +398,20 @@ __device__ OpResult op_insert(const HeapDesc& H, u64 ticket, const u64* __restri
 }
 
 // ---------------------------------------------------------------------------
-// DEL (Sec. 3.2.1 with the partial-buffer rules of Sec. 3.3.2/3.3.4).
-// Writes min(K, size) entries to out.
+// DEL (Sec. 3.2.1 with the partial-buffer rules of Sec. 3.3.2/3.3.4) of
+// `want` entries, 1 <= want <= K: writes min(want, size) entries to out.
+// want < K (variable count): the root's other K - want entries and the
+// partial buffer, merged, refill the top; only when they are fewer than K is
+// the last node taken as well (its K entries and the merged rest give the new
+// root and the partial buffer).  With a single node and fewer than K left,
+// everything left becomes the partial buffer.  Var = false compiles the
+// whole-root deleteMin only (want is K); callers pick Var = true for want < K.
 // ---------------------------------------------------------------------------
-template <int K, int T>
-__device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ out, lu64* lds,
-                              OpShared& sh, Ctl* ctl) {
+template <int K, int T, bool Var = false>
+__device__ __forceinline__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ out, u32 want_n,
+                              lu64* lds, OpShared& sh, Ctl* ctl) {
   constexpr int E = (2 * K) / T >= 1 ? (2 * K) / T : 1;
+  const u32 want = Var ? want_n : (u32)K;
   const int tid = threadIdx.x;
   OpResult res{0, 0, 0, true};
   HeapMeta* meta = H.meta;
@@ -418,14 +425,33 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
 
   if (m == 0) {
     // no node: the partial buffer is the whole heap
-    copy_heap_n<K, T>(out, H.pb, s);
-    __syncthreads();   // every read of the pb is done before the root moves on
-    if (tid == 0) release_root(meta, ticket, 0, 0);
-    res.count = s;
+    const u32 cnt = Var && want < s ? want : s;   // the pb holds < K entries
+    copy_heap_n<K, T>(out, H.pb, cnt);
+    if (cnt < s) {
+      // what is left of the partial buffer moves to its front
+      const HeapRegion R(H.pb, K * 8);
+      for (u32 i = tid; i < s - cnt; i += T) P[i] = R.load8((cnt + i) * 8);
+      __syncthreads();   // every read of the pb is done before it is rewritten
+      store_heap_n<K, T>(H.pb, P, s - cnt);
+      publish();
+    } else {
+      __syncthreads();   // every read of the pb is done before the root moves on
+    }
+    if (tid == 0) release_root(meta, ticket, 0, s - cnt);
+    res.count = cnt;
     return res;
   }
-  res.count = K;
-  const u64 m2 = m - 1;
+  res.count = want;
+  const bool part = Var && want < (u32)K;
+  const u32 nrest = K - want + s;   // what stays at the top (want = K: the pb)
+  // the last node refills the root (a whole-root deleteMin: whenever there
+  // are two or more nodes, and m == 1 returns before that matters)
+  const bool refill = Var ? (m >= 2 && nrest < (u32)K) : true;
+  // node count and pb size after the operation
+  const u64 m2 = refill ? m - 1 : (nrest >= (u32)K ? m : 0);
+  const u32 s2 = !part ? s : (nrest >= (u32)K ? nrest - K : nrest);
+  const bool need_pb = s > 0 && (part || m >= 2);
+  lu64* const PB0 = part ? bufs[3] : P;   // the pb's copy in LDS
   u64* llock = H.locks + m;
   u64* lastp = H.nodes + (m - 1) * (u64)K;
 
@@ -435,100 +461,131 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
   {
     NodeRegs<K, T> rr, pr;
     rr.load(H.nodes);
-    if (m >= 2 && s > 0) pr.load(H.pb);
-    if (tid == 0 && m >= 2) old_last = cas_old(llock, 0, lockword(ST_INUSE, ticket));
+    if (need_pb) pr.load(H.pb);
+    if (tid == 0 && refill && m >= 2) old_last = cas_old(llock, 0, lockword(ST_INUSE, ticket));
     rr.store(bufs[1]);
-    if (m >= 2 && s > 0) pr.store(P);
+    if (need_pb) pr.store(PB0);
   }
   __syncthreads();
   GH_TRACE(1);
-  store_n<T>(out, bufs[1], K);   // the root batch is the answer
-  if (m == 1) {
+  store_n<T>(out, bufs[1], want);   // the root's smallest are the answer
+  if (m == 1 && !part) {
     if (tid == 0) release_root(meta, ticket, 0, s);
     return res;
   }
-
-  // refill the root from the last node (Sec. 3.2.1)
-  res.flags |= F_REFILL;
-  if (tid == 0) {
-    int r = old_last == 0 ? 1 : take_last(llock, old_last, ticket, ctl);
-    fence_acquire();
-    sh.ok = r > 0 ? 1u : 0u;
-    sh.flag0 = (r == 2) ? 1u : 0u;
-  }
-  __syncthreads();
-  GH_TRACE(2);
-  if (!sh.ok) { res.ok = false; return res; }
-  if (sh.flag0) res.flags |= F_TOOK;
-
-  // Round trip 2: the last node into registers, first tries at the root's
-  // children (a failed try does not wait while the last node is held).
-  const bool el1 = node_exists(2, m2), er1 = node_exists(3, m2);
-  u64 oc = 0;
-  {
-    NodeRegs<K, T> lr;
-    lr.load(lastp);
-    if (tid == 1 && el1) oc = cas_old(lock_ptr(H, 2), 0, lockword(ST_INUSE, ticket));
-    if (tid == 2 && er1) oc = cas_old(lock_ptr(H, 3), 0, lockword(ST_INUSE, ticket));
-    lr.store(bufs[0]);
-  }
-  __syncthreads();
-  GH_TRACE(3);
-  // The batch is in LDS: mark the node REMOVED right away (nothing was
-  // stored, so no fence).
-  if (tid == 0)
-    st_relaxed(llock, lockword(ST_REMOVED, ticket));
-  // finish the children's locks if the first tries did not settle them
-  if (tid < 64) {
-    const bool mine = (tid == 1 && el1) || (tid == 2 && er1);
-    int got = 0;
-    bool need = false;
-    if (mine) {
-      if (oc == 0) got = 1;
-      else if (child_view(oc, ticket) == 0) got = 0;
-      else need = true;
+  if (part) {
+    // the root's other entries merged with the pb
+    if (nrest >= (u32)K) {
+      // the K smallest are the new root, the rest the pb; no node goes away
+      merge_split<E, T>(bufs[1] + want, K - want, PB0, (int)s, K, Sink{bufs[0]},
+                        HeapSink(H.pb, K * 8));
+      __syncthreads();
+    } else if (!refill) {
+      // a single node: everything left becomes the pb
+      merge_split<E, T>(bufs[1] + want, K - want, PB0, (int)s, (int)nrest,
+                        HeapSink(H.pb, K * 8), Sink{bufs[0]});
+      publish();
+      if (tid == 0) release_root(meta, ticket, 0, nrest);
+      return res;
+    } else {
+      // waits in P for the last node
+      merge_split<E, T>(bufs[1] + want, K - want, PB0, (int)s, (int)nrest, Sink{P},
+                        Sink{bufs[0]});
+      __syncthreads();
     }
-    bool ok = true;
-    if (__any(need)) {
-      int r2 = 0;
-      u64* w = tid == 1 ? lock_ptr(H, 2) : lock_ptr(H, 3);
-      ok = lock_lanes(w, LM_CHILD, ticket, need, r2, ctl);
-      if (need) got = r2;
-    } else if (__any(got == 1)) {
-      fence_acquire();
-    }
-    const bool allok = __all(ok);
-    if (tid == 0) sh.ok = allok ? 1u : 0u;
-    if (tid == 1) sh.flag0 = got > 0 ? 1u : 0u;
-    if (tid == 2) sh.flag1 = got > 0 ? 1u : 0u;
   }
-  __syncthreads();
-  GH_TRACE(4);
-  if (!sh.ok) { res.ok = false; return res; }
 
   lu64* C = bufs[0];
-  // Round trip 3: the children, loaded while cur merges with the partial
-  // buffer (Property 3 again: the refilled root keeps the K smallest).
-  bool hl = sh.flag0, hr = sh.flag1;
-  {
-    NodeRegs<K, T> lc, rc;
-    if (hl) lc.load(H.nodes + 1 * (u64)K);   // node 2 is position 2
-    if (hr) rc.load(node_ptr<K>(H, 3));
-    if (s > 0 && !(C[K - 1] <= P[0])) {
-      merge_split<E, T>(C, K, P, (int)s, K, Sink{bufs[3]}, HeapSink(H.pb, K * 8));
-      __syncthreads();
-      lu64* x = bufs[0]; bufs[0] = bufs[3]; bufs[3] = x;
-      C = bufs[0];
+  bool hl = false, hr = false;
+  bool loaded = false;
+  if (refill) {
+    // refill the root from the last node (Sec. 3.2.1)
+    res.flags |= F_REFILL;
+    if (tid == 0) {
+      int r = old_last == 0 ? 1 : take_last(llock, old_last, ticket, ctl);
+      fence_acquire();
+      sh.ok = r > 0 ? 1u : 0u;
+      sh.flag0 = (r == 2) ? 1u : 0u;
     }
-    if (hl) lc.store(bufs[1]);
-    if (hr) rc.store(bufs[2]);
-  }
-  __syncthreads();
-  GH_TRACE(5);
+    __syncthreads();
+    GH_TRACE(2);
+    if (!sh.ok) { res.ok = false; return res; }
+    if (sh.flag0) res.flags |= F_TOOK;
 
-  // sift down; the root level's children are already locked and loaded
+    // Round trip 2: the last node into registers, first tries at the root's
+    // children (a failed try does not wait while the last node is held).
+    const bool el1 = node_exists(2, m2), er1 = node_exists(3, m2);
+    u64 oc = 0;
+    {
+      NodeRegs<K, T> lr;
+      lr.load(lastp);
+      // lanes 1 and 2 try children 2 and 3 with one vector atomic
+      if ((tid == 1 && el1) || (tid == 2 && er1))
+        oc = cas_old(lock_ptr(H, (u32)tid + 1), 0, lockword(ST_INUSE, ticket));
+      lr.store(bufs[0]);
+    }
+    __syncthreads();
+    GH_TRACE(3);
+    // The batch is in LDS: mark the node REMOVED right away (nothing was
+    // stored, so no fence).
+    if (tid == 0)
+      st_relaxed(llock, lockword(ST_REMOVED, ticket));
+    // finish the children's locks if the first tries did not settle them
+    if (tid < 64) {
+      const bool mine = (tid == 1 && el1) || (tid == 2 && er1);
+      int got = 0;
+      bool need = false;
+      if (mine) {
+        if (oc == 0) got = 1;
+        else if (child_view(oc, ticket) == 0) got = 0;
+        else need = true;
+      }
+      bool ok = true;
+      if (__any(need)) {
+        int r2 = 0;
+        u64* w = tid == 1 ? lock_ptr(H, 2) : lock_ptr(H, 3);
+        ok = lock_lanes(w, LM_CHILD, ticket, need, r2, ctl);
+        if (need) got = r2;
+      } else if (__any(got == 1)) {
+        fence_acquire();
+      }
+      const bool allok = __all(ok);
+      if (tid == 0) sh.ok = allok ? 1u : 0u;
+      if (tid == 1) sh.flag0 = got > 0 ? 1u : 0u;
+      if (tid == 2) sh.flag1 = got > 0 ? 1u : 0u;
+    }
+    __syncthreads();
+    GH_TRACE(4);
+    if (!sh.ok) { res.ok = false; return res; }
+
+    // Round trip 3: the children, loaded while cur merges with the partial
+    // buffer (Property 3 again: the refilled root keeps the K smallest).
+    // With want < K the merged rest takes the pb's place and always merges:
+    // what does not stay in the root is the new pb.
+    hl = sh.flag0;
+    hr = sh.flag1;
+    {
+      NodeRegs<K, T> lc, rc;
+      if (hl) lc.load(H.nodes + 1 * (u64)K);   // node 2 is position 2
+      if (hr) rc.load(node_ptr<K>(H, 3));
+      const u32 np = part ? nrest : s;
+      if (np > 0 && (part || !(C[K - 1] <= P[0]))) {
+        merge_split<E, T>(C, K, P, (int)np, K, Sink{bufs[3]}, HeapSink(H.pb, K * 8));
+        __syncthreads();
+        lu64* x = bufs[0]; bufs[0] = bufs[3]; bufs[3] = x;
+        C = bufs[0];
+      }
+      if (hl) lc.store(bufs[1]);
+      if (hr) rc.store(bufs[2]);
+    }
+    __syncthreads();
+    GH_TRACE(5);
+    loaded = true;
+  }
+
+  // sift down; after a refill the root level's children are already locked
+  // and loaded
   u32 c = 1;
-  bool loaded = true;
   for (;;) {
     const u64 l = 2ull * c, r = l + 1;
     lu64* Lb = bufs[1];
@@ -574,7 +631,7 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
       if (tid == 0) {
         if (hl) unlock(lock_ptr(H, (u32)l));
         if (hr) unlock(lock_ptr(H, (u32)r));
-        if (c == 1) release_root(meta, ticket, m2, s);
+        if (c == 1) release_root(meta, ticket, m2, s2);
         else unlock(lock_ptr(H, c));
       }
       return res;
@@ -615,7 +672,7 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
       if (c == 1) GH_TRACE(7);
       if (tid == 0) {
         unlock(lock_ptr(H, big));
-        if (c == 1) release_root(meta, ticket, m2, s);
+        if (c == 1) release_root(meta, ticket, m2, s2);
         else unlock(lock_ptr(H, c));
       }
       next = small;
@@ -634,7 +691,7 @@ __device__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ o
       }
       publish();
       if (tid == 0) {
-        if (c == 1) release_root(meta, ticket, m2, s);
+        if (c == 1) release_root(meta, ticket, m2, s2);
         else unlock(lock_ptr(H, c));
       }
       next = x;

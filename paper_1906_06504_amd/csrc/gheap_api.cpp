@@ -169,6 +169,17 @@ ServeLayout serve_layout(u32 nheaps, u32 nreq, u64 max_ops) {
 }
 
 hipError_t launch_ops(const gh_heap* h, const LaunchArgs& a) {
+  if (a.var_delete) {
+    switch (h->k) {
+      case 32: return launch_ops_var_k<32>(a);
+      case 64: return launch_ops_var_k<64>(a);
+      case 128: return launch_ops_var_k<128>(a);
+      case 256: return launch_ops_var_k<256>(a);
+      case 512: return launch_ops_var_k<512>(a);
+      case 1024: return launch_ops_var_k<1024>(a);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (h->k) {
     case 32: return launch_ops_k<32>(a);
     case 64: return launch_ops_k<64>(a);
@@ -224,6 +235,7 @@ int run_ops(gh_heap* h, const gh_op* d_ops, u32 nops, const OpParams& p, const u
   a.ctl = h->ctl;
   a.workgroups = wg;
   a.threads = threads;
+  a.var_delete = (t && (t->flags & GH_TUNE_VARIABLE_DELETE)) ? 1u : 0u;
   a.stream = h->stream;
   if (launch_ops(h, a) != hipSuccess) return GH_EDEVICE;
   return GH_OK;
@@ -317,7 +329,7 @@ int heap_insert(gh_heap_t h, const uint64_t* d_keys, uint64_t n) {
   u64 nops = (n + h->k - 1) / h->k;
   if (nops > 0xFFFFFFFFull) return GH_EINVAL;
   OpParams p{GH_OP_INSERT, 0, n, 0, 0};
-  gh_tuning t{(u32)(nops < 64 ? nops : 64), 0};
+  gh_tuning t{(u32)(nops < 64 ? nops : 64), 0, 0};
   int rc = run_ops(h, nullptr, (u32)nops, p, d_keys, nullptr, nullptr, nullptr, &t);
   if (rc == GH_OK) h->size0 += n;
   return rc;
@@ -335,13 +347,13 @@ int heap_build(gh_heap_t h, uint32_t i, const uint64_t* d_sorted, uint64_t n) {
   return GH_OK;
 }
 
-int heap_delete_min(gh_heap_t h, uint64_t* d_out, uint32_t k, uint32_t* d_count) {
-  if (!h || !d_out || !d_count || k != h->k) return GH_EINVAL;
+int heap_delete_min(gh_heap_t h, uint64_t* d_out, uint32_t c, uint32_t* d_count) {
+  if (!h || !d_out || !d_count || c == 0 || c > h->k) return GH_EINVAL;
   if (h->sticky != GH_OK) return h->sticky;
-  OpParams p{GH_OP_DELETE_MIN, 0, 0, 0, 0};
-  gh_tuning t{1, 0};
+  OpParams p{GH_OP_DELETE_MIN, 0, c, 0, 0};
+  gh_tuning t{1, 0, c < h->k ? GH_TUNE_VARIABLE_DELETE : 0u};
   int rc = run_ops(h, nullptr, 1, p, nullptr, d_out, d_count, nullptr, &t);
-  if (rc == GH_OK && h->size0_known) h->size0 -= (h->size0 < h->k ? h->size0 : h->k);
+  if (rc == GH_OK && h->size0_known) h->size0 -= (h->size0 < c ? h->size0 : c);
   return rc;
 }
 

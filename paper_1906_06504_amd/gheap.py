@@ -76,8 +76,12 @@ class GHeapError(RuntimeError):
 _lib = None
 
 
+GH_TUNE_VARIABLE_DELETE = 1
+
+
 class _Tuning(ctypes.Structure):
-    _fields_ = [("workgroups", ctypes.c_uint32), ("threads", ctypes.c_uint32)]
+    _fields_ = [("workgroups", ctypes.c_uint32), ("threads", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32)]
 
 
 class SsspTrace(ctypes.Structure):
@@ -202,28 +206,34 @@ class HeapSet:
         """Insert a 1-D int64/uint64 device tensor of entries into heap 0."""
         _check(self.lib.heap_insert(self.h, _ptr(keys), keys.numel()), "heap_insert")
 
-    def delete_min(self, out: torch.Tensor | None = None, count: torch.Tensor | None = None):
-        """deleteMin on heap 0; returns (out[k] int64 tensor, count int32 tensor)."""
+    def delete_min(self, out: torch.Tensor | None = None, count: torch.Tensor | None = None,
+                   c: int | None = None):
+        """deleteMin of c entries (default k) on heap 0; returns (out int64
+        tensor with room for c, count int32 tensor)."""
+        c = self.k if c is None else int(c)
         if out is None:
-            out = torch.empty(self.k, dtype=torch.int64, device=self.device)
+            out = torch.empty(max(c, 1), dtype=torch.int64, device=self.device)
         if count is None:
             count = torch.zeros(1, dtype=torch.int32, device=self.device)
-        _check(self.lib.heap_delete_min(self.h, _ptr(out), self.k, _ptr(count)),
+        _check(self.lib.heap_delete_min(self.h, _ptr(out), c, _ptr(count)),
                "heap_delete_min")
         return out, count
 
     # -- submissions -------------------------------------------------------
     def submit(self, ops: torch.Tensor, nops: int, d_in: torch.Tensor | None,
                d_out: torch.Tensor | None, counts: torch.Tensor | None = None,
-               log: torch.Tensor | None = None, workgroups: int = 0, threads: int = 0):
-        t = _Tuning(workgroups, threads)
+               log: torch.Tensor | None = None, workgroups: int = 0, threads: int = 0,
+               var_delete: bool = False):
+        """Run the op records on the set's stream.  var_delete: the records
+        may hold deleteMins of fewer than k entries (n in 1..k-1)."""
+        t = _Tuning(workgroups, threads, GH_TUNE_VARIABLE_DELETE if var_delete else 0)
         rc = self.lib.heap_submit(self.h, _ptr(ops), nops, _ptr(d_in), _ptr(d_out),
                                   _ptr(counts), _ptr(log), ctypes.byref(t))
         _check(rc, "heap_submit")
 
     def submit_graph(self, ops, nops, d_in, d_out, counts=None, log=None, workgroups=0,
-                     threads=0) -> int:
-        t = _Tuning(workgroups, threads)
+                     threads=0, var_delete: bool = False) -> int:
+        t = _Tuning(workgroups, threads, GH_TUNE_VARIABLE_DELETE if var_delete else 0)
         g = ctypes.c_void_p()
         rc = self.lib.heap_submit_graph(self.h, _ptr(ops), nops, _ptr(d_in), _ptr(d_out),
                                         _ptr(counts), _ptr(log), ctypes.byref(t),

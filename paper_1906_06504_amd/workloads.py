@@ -84,7 +84,7 @@ class OpList:
     """A list of heap operations in submission order.
 
     kind[i]  0 = insert, 1 = deleteMin
-    n[i]     insert: number of entries; deleteMin: 0
+    n[i]     insert: number of entries; deleteMin: entries requested, 0 = k
     off[i]   insert: offset into `keys`; deleteMin: offset of its k-entry slot
              in the output buffer
     heap[i]  heap index (0 for single-heap lists)
@@ -120,14 +120,16 @@ class OpList:
 
 def build_oplist(kinds, sizes, key_source, k: int, heap=None, arrival=None) -> OpList:
     """Lay out an op list; inserts take their keys from `key_source(count)` in
-    op order, deleteMin ops each get a k-entry output slot."""
+    op order, deleteMin ops each get a k-entry output slot.  `sizes` holds an
+    insert's entry count and a deleteMin's requested count (0 = k)."""
     kinds = np.asarray(kinds, dtype=np.uint8)
     sizes = np.asarray(sizes, dtype=np.int64)
-    n = np.where(kinds == OP_INSERT, sizes, 0).astype(np.uint32)
-    ins_off = np.cumsum(n.astype(np.uint64)) - n.astype(np.uint64)
+    n = sizes.astype(np.uint32)
+    n_in = np.where(kinds == OP_INSERT, n, 0).astype(np.uint64)
+    ins_off = np.cumsum(n_in) - n_in
     del_rank = np.cumsum(kinds == OP_DELETE_MIN) - (kinds == OP_DELETE_MIN)
     off = np.where(kinds == OP_INSERT, ins_off, del_rank.astype(np.uint64) * np.uint64(k)).astype(np.uint64)
-    total_in = int(n.astype(np.uint64).sum())
+    total_in = int(n_in.sum())
     keys = key_source(total_in)
     out_entries = int((kinds == OP_DELETE_MIN).sum()) * k
     return OpList(kinds, n, off, keys, out_entries,
@@ -208,19 +210,23 @@ def prefill_ops(nkeys: int, k: int, seed: int, first_id: int = 0) -> OpList:
 
 
 def mixed_ops(total_requested: int, k: int, seed: int, first_id: int,
-              max_insert: int | None = None, p_insert: float = 0.5) -> OpList:
+              max_insert: int | None = None, p_insert: float = 0.5,
+              var_delete: bool = False) -> OpList:
     """Random interleave: each op is an insert of U[1, max_insert] fresh keys
-    (probability p_insert) or a deleteMin(k), drawn until the requested keys
-    (insert sizes plus k per deleteMin) reach `total_requested`."""
+    (probability p_insert) or a deleteMin(k) -- with var_delete a
+    deleteMin(c), c uniform on [1, k] -- drawn until the requested keys
+    (insert sizes plus each deleteMin's count) reach `total_requested`."""
     max_insert = k if max_insert is None else max_insert
     st = Stream(seed)
+    cst = Stream(seed ^ 0x0C0C0C0C0C0C0C0C)
     kinds, sizes = [], []
     acc = 0
     chunk = 4096
     while acc < total_requested:
         coin = st.unit(chunk)
         sz = st.uniform_int(1, max_insert, chunk)
-        for c, s in zip(coin, sz):
+        dc = cst.uniform_int(1, k, chunk) if var_delete else None
+        for j, (c, s) in enumerate(zip(coin, sz)):
             if acc >= total_requested:
                 break
             if c < p_insert:
@@ -229,8 +235,9 @@ def mixed_ops(total_requested: int, k: int, seed: int, first_id: int,
                 acc += int(s)
             else:
                 kinds.append(OP_DELETE_MIN)
-                sizes.append(0)
-                acc += k
+                want = int(dc[j]) if var_delete else 0
+                sizes.append(want)
+                acc += want or k
     key_stream = Stream(seed ^ 0x5A5A5A5A5A5A5A5A)
     return build_oplist(kinds, sizes, _keys_with_ids(key_stream, first_id), k)
 

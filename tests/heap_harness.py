@@ -12,13 +12,17 @@ MAXE = np.uint64(0xFFFFFFFFFFFFFFFF)
 
 def run_gpu(oplist, k, max_keys, workgroups=0, threads=0, heapset=None, nheaps=1):
     """Submit `oplist` on a fresh heap set (or `heapset`); returns
-    (heapset, out[uint64], counts[uint32], log records)."""
+    (heapset, out[uint64], counts[uint32], log records).  Lists holding
+    deleteMins of fewer than k entries go to the variable-count kernel."""
     import torch
     from paper_1906_06504_amd import gheap as G
     hs = heapset if heapset is not None else G.HeapSet(k, [max_keys] * nheaps)
     ops, n, keys, out, counts = G.ops_to_device(oplist)
     log = G.new_log(n)
-    hs.submit(ops, n, keys, out, counts, log, workgroups=workgroups, threads=threads)
+    dels = oplist.kind == W.OP_DELETE_MIN
+    var = bool(np.any(dels & (oplist.n != 0) & (oplist.n != k)))
+    hs.submit(ops, n, keys, out, counts, log, workgroups=workgroups, threads=threads,
+              var_delete=var)
     rc = hs.sync()
     assert rc == G.GH_OK, G.strerror(rc)
     torch.cuda.synchronize()

@@ -146,7 +146,7 @@ def _replay_served(G, pre, reqs, recs, out, k, heap, caps):
             assert int(recs["count"][i]) == int(reqs.n[i])
             assert oh.size <= caps[heap], "heap %d over its budget" % heap
         else:
-            want = oh.delete_min()
+            want = oh.delete_min(int(reqs.n[i]) or None)   # n = 0 means k
             c = int(recs["count"][i])
             assert c == want.size, "heap %d request %d count" % (heap, i)
             assert np.array_equal(out[o:o + c], want), "heap %d request %d output" % (heap, i)
@@ -277,6 +277,39 @@ def test_served_invalid_heap_rejected(G):
     out = G.to_host_u64(out)
     recs = G.recs_to_host(recs, n)
     assert np.all((recs["flags"][bad] & G.REQ_REJECTED) != 0)
+    for h in range(nh):
+        _replay_served(G, pre, reqs, recs, out, k, h, caps)
+    hs.close()
+
+
+def test_served_variable_count_deletes(G):
+    """deleteMin requests of c = U[1, k] entries (and a few asking for more
+    than k, which are rejected with GH_EINVAL) through the serving loop;
+    every heap replays on the oracle."""
+    k, nh, nreq = 64, 6, 2500
+    pre, reqs, sizes = W.served_stream(nh, k, nreq, seed=57, rate_per_s=None, min_log2=6,
+                                       max_log2=11, max_ins_log2=8)
+    dels = np.flatnonzero(reqs.kind == W.OP_DELETE_MIN)
+    rng = np.random.default_rng(5)
+    reqs.n = reqs.n.copy()
+    reqs.n[dels] = rng.integers(1, k + 1, dels.size)
+    bad = dels[::50]
+    reqs.n[bad] = k + 3
+    caps = W.served_capacity(sizes)
+    _p("served variable count heaps=%d requests=%d" % (nh, nreq))
+    hs = G.HeapSet(k, caps)
+    d = G.ops_to_device(pre)
+    hs.submit(*d[:5], workgroups=64)
+    assert hs.sync() == 0
+    r, n, keys, out, recs, max_ops = G.requests_to_device(reqs)
+    hs.serve(r, n, keys, out, recs, max_ops, workgroups=32)
+    assert hs.sync() == G.GH_EINVAL
+    torch.cuda.synchronize()
+    out = G.to_host_u64(out)
+    recs = G.recs_to_host(recs, n)
+    assert np.all((recs["flags"][bad] & G.REQ_REJECTED) != 0)
+    good = np.setdiff1d(dels, bad)
+    assert np.all((recs["flags"][good] & G.REQ_ADMITTED) != 0)
     for h in range(nh):
         _replay_served(G, pre, reqs, recs, out, k, h, caps)
     hs.close()
