@@ -279,7 +279,8 @@ typedef struct gh_knapres {
  * fractional upper bound in fixed point (scale 2^16) above a 29-bit node id,
  * so deleteMin returns the k most promising nodes; a node is expanded only if
  * its bound exceeds the best value found, children are pushed only if their
- * bound does.  d_pool (device, ninst * pool_per_inst uint64) holds the nodes;
+ * bound does, and an instance stops (its heap emptied without reading the
+ * rest) once the best bound left cannot beat the best value found.  d_pool (device, ninst * pool_per_inst uint64) holds the nodes;
  * d_scratch (device, ninst * 3 * k uint64) holds per-instance batches;
  * d_res (device, ninst gh_knapres).  Heap i must hold pool_per_inst entries
  * (pool_per_inst < 2^29).  The sum of an instance's values must stay below

@@ -145,6 +145,14 @@ __global__ __launch_bounds__(T) void k_knap(const HeapDesc* __restrict__ descs, 
       ++ops;
       __syncthreads();
       if (!r.ok || r.count == 0) break;
+      // best-first stopping rule: the batch's first entry has the largest
+      // bound left in the heap; if it cannot beat the incumbent, nothing
+      // left can, and the rest of the heap is dropped unread
+      if (KN_KEYMAX - (out[0] >> KN_IDBITS) <= (ks.best << 16)) {
+        op_discard(H, ticket++, sh, ctl);
+        ++ops;
+        break;
+      }
       if (tid == 0) {
         ks.cnt = 0;
         ks.popped = r.count;

@@ -188,6 +188,23 @@ __device__ __forceinline__ OpResult op_pass_root(const HeapDesc& H, u64 ticket, 
   return res;
 }
 
+// Take the root in turn and leave the heap empty (m = s = 0): every entry is
+// discarded.  Only for a heap with no other operation in flight (all node
+// locks AVAIL), such as a branch-and-bound instance's own heap once nothing
+// left in it can matter.
+__device__ __forceinline__ OpResult op_discard(const HeapDesc& H, u64 ticket, OpShared& sh,
+                                               Ctl* ctl) {
+  OpResult res{0, 0, 0, true};
+  if (threadIdx.x == 0) {
+    u64 w = 0;
+    sh.ok = root_acquire(H.meta, ticket, ctl, w) ? 1u : 0u;
+    if (sh.ok) release_root(H.meta, ticket, 0, 0);
+  }
+  __syncthreads();
+  res.ok = sh.ok != 0;
+  return res;
+}
+
 // Thread 0 takes the root; everyone learns (m, s) from the root word.
 __device__ __forceinline__ bool acquire_root(const HeapDesc& H, u64 ticket, OpShared& sh,
                                              Ctl* ctl) {
