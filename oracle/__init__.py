@@ -67,6 +67,10 @@ def _declare(lib):
     lib.gho_delete_min.argtypes = [ctypes.c_void_p, U64P]
     lib.gho_delete_min_n.restype = ctypes.c_uint64
     lib.gho_delete_min_n.argtypes = [ctypes.c_void_p, U64P, ctypes.c_uint64]
+    lib.gho_build.restype = ctypes.c_int
+    lib.gho_build.argtypes = [ctypes.c_void_p, U64P, ctypes.c_uint64]
+    lib.gho_filter.restype = ctypes.c_uint64
+    lib.gho_filter.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
     lib.gho_check.restype = ctypes.c_int
     lib.gho_check.argtypes = [ctypes.c_void_p]
     lib.gho_export.restype = None
@@ -150,6 +154,22 @@ class OracleHeap:
             if got == 0xFFFFFFFFFFFFFFFF:
                 raise ValueError("deleteMin count must be in [1, k]")
         return out[:got].copy()
+
+    def build(self, sorted_keys) -> None:
+        """Bulk build of an empty heap from ascending entries (Sec. 3.1)."""
+        a = np.ascontiguousarray(np.asarray(sorted_keys, dtype=np.uint64))
+        rc = self.lib.gho_build(self.h, _p64(a) if a.size else None, a.size)
+        if rc == -2:
+            raise ValueError("entries must be ascending and not the reserved value")
+        if rc != 0:
+            raise RuntimeError("gho_build failed (heap not empty or no memory)")
+
+    def filter(self, bound: int) -> int:
+        """Remove every entry >= bound; returns the number kept."""
+        kept = self.lib.gho_filter(self.h, int(bound))
+        if kept == 0xFFFFFFFFFFFFFFFF:
+            raise MemoryError("gho_filter failed")
+        return int(kept)
 
     def check(self) -> int:
         return int(self.lib.gho_check(self.h))

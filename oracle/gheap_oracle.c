@@ -29,6 +29,8 @@
  *   - DEL of c < k entries (variable count; a reading, see gho_delete_min_n):
  *     the root's c smallest, then the root's rest and the partial buffer
  *     refill the top, taking the last node only when they are fewer than k;
+ *   - bulk build from an ascending array (Sec. 3.1) and a filter that keeps
+ *     the entries below a bound (garbage collection, Sec. 5.6.2);
  *   - target order by bit-reversal permutation (Sec. 4.3, "Bit-Reversal
  *     Permutation"), DEL taking the last node in the reverse order.
  *
@@ -343,6 +345,56 @@ static void sift_down(gho_heap *h) {
             c = x;
         }
     }
+}
+
+/* ---- bulk build and filter (Sec. 3.1: a sorted array is a heap) -------- */
+
+/* Build an empty heap from n ascending entries: the p-th chunk of k becomes
+ * the node added p-th (node index idx(p)), the rest the partial buffer.
+ * Returns 0, -1 when the heap is not empty or memory runs out, -2 when the
+ * input is not ascending or holds the reserved entry. */
+int gho_build(gho_heap *h, const gho_ent *sorted, uint64_t n) {
+    const uint64_t k = h->k;
+    if (h->m != 0 || h->s != 0) return -1;
+    for (uint64_t i = 0; i < n; i++) {
+        if (sorted[i] == GHO_MAX) return -2;
+        if (i > 0 && sorted[i - 1] > sorted[i]) return -2;
+    }
+    uint64_t m = n / k;
+    for (uint64_t p = 1; p <= m; p++) {
+        uint64_t c = gho_idx(p);
+        if (ensure_cap(h, c)) return -1;
+        memcpy(node_at(h, c), sorted + (p - 1) * k, k * sizeof(gho_ent));
+    }
+    h->m = m;
+    h->s = n - m * k;
+    memcpy(h->pb, sorted + m * k, h->s * sizeof(gho_ent));
+    return 0;
+}
+
+/* Filter: remove every entry >= bound (the garbage collection of a
+ * branch-and-bound search, Sec. 5.6.2, with the bound as the cut).  The
+ * entries kept are gathered, sorted and built again as above.  Returns the
+ * number kept, or UINT64_MAX when memory runs out. */
+uint64_t gho_filter(gho_heap *h, gho_ent bound) {
+    const uint64_t k = h->k;
+    uint64_t size = gho_size(h), kept = 0;
+    gho_ent *buf = (gho_ent *)malloc(size * sizeof(gho_ent) + 8);
+    if (!buf) return UINT64_MAX;
+    for (uint64_t p = 1; p <= h->m; p++) {
+        gho_ent *N = node_at(h, gho_idx(p));
+        for (uint64_t i = 0; i < k; i++)
+            if (N[i] < bound) buf[kept++] = N[i];
+        for (uint64_t i = 0; i < k; i++) N[i] = GHO_MAX;
+    }
+    for (uint64_t i = 0; i < h->s; i++)
+        if (h->pb[i] < bound) buf[kept++] = h->pb[i];
+    h->m = 0;
+    h->s = 0;
+    qsort(buf, kept, sizeof(gho_ent), cmp_ent);
+    int rc = gho_build(h, buf, kept);
+    free(buf);
+    return rc == 0 ? kept : UINT64_MAX;
 }
 
 /* ---- invariant checker (Sec. 3.1, Properties 1-3) ---------------------- */

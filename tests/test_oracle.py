@@ -4,7 +4,10 @@
   entries in ascending order (the root holds the k smallest by Properties 1
   and 3, Sec. 3.1; the partial buffer is read only when no node exists,
   Sec. 3.3.2), checked against a sorted Python list on small random traces;
-  likewise deleteMin(c) returns the min(c, size) smallest;
+  likewise deleteMin(c) returns the min(c, size) smallest, and a filter
+  keeps exactly the entries below its bound;
+* bulk build (Sec. 3.1): a built heap satisfies the properties and drains
+  to its input;
 * Properties 1-3 and the closed form m = size // k, s = size % k after every
   operation (the partial buffer never reaches k entries, Sec. 3.1);
 * k = 1 reduces to the conventional heap (Sec. 3.1, note after Property 3):
@@ -35,13 +38,15 @@ def _built():
     oracle.build(force=False)
 
 
-def random_trace(rng, k, nops, key_range, max_ins=None, var_del=False):
-    """Random op sequence: ('ins', array), ('del',) or, with var_del, also
-    ('del', c) with c uniform on [1, k]."""
+def random_trace(rng, k, nops, key_range, max_ins=None, var_del=False, filt=False):
+    """Random op sequence: ('ins', array), ('del',), with var_del also
+    ('del', c) with c uniform on [1, k], with filt also ('filter', bound)."""
     max_ins = max_ins or 3 * k
     ops = []
     for _ in range(nops):
-        if rng.random() < 0.55:
+        if filt and rng.random() < 0.12:
+            ops.append(("filter", int(rng.integers(0, key_range + 1))))
+        elif rng.random() < 0.55:
             n = int(rng.integers(0, max_ins + 1))
             ops.append(("ins", rng.integers(0, key_range, n).astype(np.uint64)))
         elif var_del and rng.random() < 0.7:
@@ -60,6 +65,10 @@ def run_against_brute_force(k, ops, lib=None):
         if op[0] == "ins":
             h.insert(op[1])
             live = sorted(live + [int(v) for v in op[1]])
+        elif op[0] == "filter":
+            live = [v for v in live if v < op[1]]
+            if h.filter(op[1]) != len(live):
+                return "op %d: filter kept the wrong number" % i
         else:
             want_n = op[1] if len(op) > 1 else k
             got = h.delete_min(op[1] if len(op) > 1 else None)
@@ -97,6 +106,45 @@ def test_brute_force_variable_count_deletes(k):
         ops = random_trace(rng, k, int(rng.integers(5, 120)), key_range, var_del=True)
         msg = run_against_brute_force(k, ops)
         assert msg is None, "k=%d trial=%d %s" % (k, trial, msg)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 8, 16])
+def test_brute_force_with_filters(k):
+    """Filter(bound) removes exactly the entries >= bound; afterwards the
+    heap satisfies Properties 1-3 and the m/s closed form, and every later
+    deleteMin returns the smallest survivors."""
+    rng = np.random.default_rng(4000 + k)
+    for trial in range(60):
+        key_range = 50 if trial % 2 == 0 else 1 << 40
+        ops = random_trace(rng, k, int(rng.integers(5, 120)), key_range, var_del=True, filt=True)
+        msg = run_against_brute_force(k, ops)
+        assert msg is None, "k=%d trial=%d %s" % (k, trial, msg)
+
+
+def test_build_then_drain_is_sorted():
+    """Bulk build (Sec. 3.1): Properties 1-3 hold right after the build and
+    draining returns the input; a non-empty heap or unsorted input is
+    refused."""
+    rng = np.random.default_rng(9)
+    for k in (1, 3, 8, 64):
+        for n in (0, 1, k - 1, k, k + 1, 7 * k + 3, 100 * k):
+            keys = np.sort(rng.integers(0, 1 << 40, n).astype(np.uint64))
+            h = oracle.OracleHeap(k)
+            h.build(keys)
+            assert h.check() == 0 and h.size == n
+            got = []
+            while True:
+                b = h.delete_min()
+                if b.size == 0:
+                    break
+                got.extend(int(x) for x in b)
+            assert got == [int(x) for x in keys]
+    h = oracle.OracleHeap(4)
+    h.insert([5])
+    with pytest.raises(RuntimeError):
+        h.build(np.array([1, 2], dtype=np.uint64))
+    with pytest.raises(ValueError):
+        oracle.OracleHeap(4).build(np.array([3, 2], dtype=np.uint64))
 
 
 def test_variable_count_delete_bounds_and_full_count():
@@ -249,6 +297,15 @@ MUTANTS = {
     "no_pb_merge_on_delete": (
         "    if (h->s > 0)\n        merge_and_sort(h, node_at(h, 1), k, h->pb, h->s, node_at(h, 1), h->pb);\n    sift_down(h);\n    return k;",
         "    sift_down(h);\n    return k;"),
+    "filter_keeps_the_bound": (
+        "            if (N[i] < bound) buf[kept++] = N[i];",
+        "            if (N[i] <= bound) buf[kept++] = N[i];"),
+    "filter_drops_pb": (
+        "        if (h->pb[i] < bound) buf[kept++] = h->pb[i];",
+        "        if (0) buf[kept++] = h->pb[i];"),
+    "build_at_tree_index_p": (
+        "        uint64_t c = gho_idx(p);\n        if (ensure_cap(h, c)) return -1;",
+        "        uint64_t c = p;\n        if (ensure_cap(h, c)) return -1;"),
     "partial_delete_no_sift": (
         "    sift_down(h);\n    return c;",
         "    return c;"),
@@ -305,7 +362,8 @@ def _mutant_caught(lib):
     rng = np.random.default_rng(99)
     for k in (1, 2, 3, 4, 8):
         for trial in range(40):
-            ops = random_trace(rng, k, 60, 1 << 40 if trial % 2 else 40, var_del=trial % 4 >= 2)
+            ops = random_trace(rng, k, 60, 1 << 40 if trial % 2 else 40, var_del=trial % 4 >= 2,
+                               filt=trial % 8 >= 4)
             try:
                 if run_against_brute_force(k, ops, lib=lib) is not None:
                     return True
