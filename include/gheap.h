@@ -196,6 +196,23 @@ int heap_insert(gh_heap_t h, const uint64_t *d_keys, uint64_t n);
  * device: heap i not empty).  Device errors are sticky. */
 int heap_build(gh_heap_t h, uint32_t i, const uint64_t *d_sorted, uint64_t n);
 
+/* Bytes of device workspace heap_filter needs for heap i of the set (0 for
+ * a bad handle or index). */
+uint64_t heap_filter_workspace_bytes(gh_heap_t h, uint32_t i);
+
+/* Filter heap i of the set: every entry >= bound is removed (the garbage
+ * collection of a branch-and-bound search, Sec. 5.6.2, which drops nodes
+ * whose bound can no longer beat the incumbent).  The entries kept are
+ * gathered, sorted and laid out again as by heap_build (Sec. 3.1), all on
+ * the set's stream; the number kept goes to *d_kept (device, may be NULL).
+ * No submission may be in flight on the set (calls on its stream are
+ * ordered).  d_work: caller-owned device workspace, 256-byte aligned, at
+ * least heap_filter_workspace_bytes(h, i) bytes.  Errors: GH_EINVAL (null
+ * handle or workspace, i out of range, workspace too small or misaligned),
+ * GH_EDEVICE. */
+int heap_filter(gh_heap_t h, uint32_t i, uint64_t bound, void *d_work, uint64_t work_bytes,
+                uint64_t *d_kept);
+
 /* deleteMin on heap 0 of the set (Sec. 3.2.1, Sec. 3.3.2) of c entries,
  * 1 <= c <= k (the node capacity): writes the min(c, size) smallest entries in
  * ascending order to d_out (device, room for c entries) and that number to

@@ -45,8 +45,9 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
             obj = os.path.join(BUILD, "%s_k%d.o" % (name, k))
             tasks.append([HIPCC] + COMMON + ["-DGH_K=%d" % k, "-c",
                                              os.path.join(CSRC, name + ".hip"), "-o", obj])
-    tasks.append([HIPCC] + COMMON + ["-c", os.path.join(CSRC, "gh_setup.hip"),
-                                     "-o", os.path.join(BUILD, "gh_setup.o")])
+    for name in ("gh_setup", "gh_filter"):
+        tasks.append([HIPCC] + COMMON + ["-c", os.path.join(CSRC, name + ".hip"),
+                                         "-o", os.path.join(BUILD, name + ".o")])
     tasks.append([HIPCC] + COMMON + ["-x", "hip", "-c", os.path.join(CSRC, "gheap_api.cpp"),
                                      "-o", os.path.join(BUILD, "gheap_api.o")])
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:

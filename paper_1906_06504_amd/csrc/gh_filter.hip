@@ -1,0 +1,234 @@
+// gh_filter.hip -- filter of one quiescent heap: every entry >= a bound is
+// removed (the garbage collection of a branch-and-bound search, Sec. 5.6.2:
+// nodes whose bound can no longer beat the incumbent are dropped while the
+// search runs).  The entries kept are the heap's smallest; in a generalized
+// heap they are the whole of a top subtree of nodes plus a prefix of each
+// node below it and of the partial buffer, which do not occupy the first
+// positions of the addition order.  So they are gathered, sorted (tiles in
+// LDS, then merge-path passes in global memory) and laid out again as a bulk
+// build (Sec. 3.1: a sorted array is a generalized heap).  Node capacity
+// comes from the heap descriptor, so this object is compiled once.
+#include "gh_launch.h"
+
+namespace gh {
+
+constexpr int FT = 256;      // threads of the filter kernels
+constexpr int TILE = 2048;   // entries sorted in LDS, and merged, per workgroup
+
+// The workspace starts with this header; then the per-node counts (one u64
+// per node position and one for the pb), then two sort buffers.
+struct alignas(256) FilterHead {
+  u64 m;      // node count when the filter started
+  u64 s;      // partial-buffer size then
+  u64 kept;   // entries below the bound
+  u64 pad[29];
+};
+static_assert(sizeof(FilterHead) == 256, "filter head layout");
+
+// Entries below the bound in every node (a binary search: nodes are sorted)
+// and in the partial buffer; slot m of cnt is the pb.
+__global__ void k_filter_count(const HeapDesc* __restrict__ d, u64 bound, FilterHead* fh,
+                               u64* __restrict__ cnt) {
+  const HeapDesc H = *d;
+  const u64 w = ld_relaxed(&H.meta->root);
+  const u64 m = rw_m(w), s = rw_s(w);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    fh->m = m;
+    fh->s = s;
+  }
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  for (u64 p = (u64)blockIdx.x * blockDim.x + threadIdx.x; p <= m; p += stride) {
+    const u64* e = p < m ? H.nodes + p * H.k : H.pb;
+    u32 lo = 0, hi = p < m ? H.k : (u32)s;
+    while (lo < hi) {
+      const u32 mid = (lo + hi) >> 1;
+      if (e[mid] < bound) lo = mid + 1;
+      else hi = mid;
+    }
+    cnt[p] = lo;
+  }
+}
+
+// Exclusive scan of cnt[0..m] in place (one workgroup); the total is the
+// number of entries kept.
+__global__ __launch_bounds__(FT) void k_filter_scan(FilterHead* fh, u64* __restrict__ cnt) {
+  __shared__ u64 part[FT];
+  const u64 n = fh->m + 1;
+  const int tid = threadIdx.x;
+  u64 carry = 0;
+  for (u64 base = 0; base < n; base += FT) {
+    const u64 i = base + tid;
+    const u64 v = i < n ? cnt[i] : 0;
+    part[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < FT; off <<= 1) {
+      const u64 t = tid >= off ? part[tid - off] : 0;
+      __syncthreads();
+      part[tid] += t;
+      __syncthreads();
+    }
+    if (i < n) cnt[i] = carry + part[tid] - v;
+    carry += part[FT - 1];
+    __syncthreads();
+  }
+  if (tid == 0) fh->kept = carry;
+}
+
+// Each node's (and the pb's) kept prefix to its offset in out.
+__global__ __launch_bounds__(FT) void k_filter_gather(const HeapDesc* __restrict__ d,
+                                                      const FilterHead* fh,
+                                                      const u64* __restrict__ off,
+                                                      u64* __restrict__ out) {
+  const HeapDesc H = *d;
+  const u64 m = fh->m;
+  for (u64 p = blockIdx.x; p <= m; p += gridDim.x) {
+    const u64* e = p < m ? H.nodes + p * H.k : H.pb;
+    const u64 o = off[p];
+    const u64 n = (p < m ? off[p + 1] : fh->kept) - o;
+    for (u64 i = threadIdx.x; i < n; i += FT) out[o + i] = e[i];
+  }
+}
+
+// Sort every TILE-entry tile of buf in place.
+__global__ __launch_bounds__(FT) void k_filter_tiles(const FilterHead* fh, u64* __restrict__ buf) {
+  __shared__ __align__(16) u64 lds[2 * TILE];
+  lu64* const A = (lu64*)lds;
+  lu64* const B = A + TILE;
+  const u64 n = fh->kept;
+  for (u64 t0 = (u64)blockIdx.x * TILE; t0 < n; t0 += (u64)gridDim.x * TILE) {
+    const int c = n - t0 < (u64)TILE ? (int)(n - t0) : TILE;
+    load_n<FT>(A, buf + t0, (u32)c);
+    __syncthreads();
+    const lu64* r = block_sort<TILE, FT>(A, B, c);
+    store_n<FT>(buf + t0, r, (u32)c);
+    __syncthreads();
+  }
+}
+
+// One merge pass: adjacent sorted runs of w entries (w a multiple of TILE)
+// are merged pairwise from src to dst.  Each workgroup writes TILE outputs:
+// its two merge-path splits are found by binary search in global memory,
+// the input ranges between them are staged in LDS and merged there.
+__global__ __launch_bounds__(FT) void k_filter_merge(const FilterHead* fh,
+                                                     const u64* __restrict__ src,
+                                                     u64* __restrict__ dst, u64 w) {
+  __shared__ __align__(16) u64 lds[2 * TILE];
+  __shared__ u64 split[4];
+  const u64 n = fh->kept;
+  for (u64 o = (u64)blockIdx.x * TILE; o < n; o += (u64)gridDim.x * TILE) {
+    const u64 ps = o / (2 * w) * (2 * w);
+    const u64 na = n - ps < w ? n - ps : w;
+    const u64 nb = n - ps > w ? (n - ps - w < w ? n - ps - w : w) : 0;
+    const u64* A = src + ps;
+    const u64* B = src + ps + na;
+    const u64 d0 = o - ps;
+    const u64 d1 = d0 + TILE < na + nb ? d0 + TILE : na + nb;
+    if (threadIdx.x < 2) {
+      const u64 dd = threadIdx.x == 0 ? d0 : d1;
+      // entries of A among the first dd outputs (A first on ties)
+      u64 lo = dd > nb ? dd - nb : 0;
+      u64 hi = dd < na ? dd : na;
+      while (lo < hi) {
+        const u64 mid = (lo + hi) >> 1;
+        if (A[mid] <= B[dd - 1 - mid]) lo = mid + 1;
+        else hi = mid;
+      }
+      split[threadIdx.x * 2] = lo;
+      split[threadIdx.x * 2 + 1] = dd - lo;
+    }
+    __syncthreads();
+    const u64 a0 = split[0], b0 = split[1], a1 = split[2], b1 = split[3];
+    const int la = (int)(a1 - a0), lb = (int)(b1 - b0);
+    lu64* const LA = (lu64*)lds;
+    lu64* const LB = LA + la;
+    lu64* const LO = (lu64*)lds + TILE;
+    load_n<FT>(LA, A + a0, (u32)la);
+    load_n<FT>(LB, B + b0, (u32)lb);
+    __syncthreads();
+    merge_split<TILE / FT, FT>(LA, la, LB, lb, la + lb, Sink{LO}, Sink{LO});
+    __syncthreads();
+    store_n<FT>(dst + o, LO, (u32)(la + lb));
+    __syncthreads();
+  }
+}
+
+// The kept entries, ascending, become the heap again: nodes in addition
+// order, the rest the partial buffer; the lock words of every position that
+// held a node are cleared.
+__global__ void k_filter_build(const HeapDesc* __restrict__ d, const FilterHead* fh,
+                               const u64* __restrict__ sorted) {
+  const HeapDesc H = *d;
+  const u64 n = fh->kept;
+  const u64 body = n / H.k * H.k;
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  const u64 i0 = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+  for (u64 i = i0; i < n; i += stride) {
+    if (i < body) H.nodes[i] = sorted[i];
+    else H.pb[i - body] = sorted[i];
+  }
+  for (u64 p = i0 + 1; p <= fh->m; p += stride) H.locks[p] = 0;
+}
+
+__global__ void k_filter_root(const HeapDesc* __restrict__ d, const FilterHead* fh) {
+  if (threadIdx.x == 0) {
+    const HeapDesc H = *d;
+    const u64 n = fh->kept;
+    const u64 m = n / H.k;
+    const u64 w = ld_relaxed(&H.meta->root);
+    st_relaxed(&H.meta->root, rootword(rw_ticket(w), m, n - m * H.k));
+  }
+}
+
+u64 filter_workspace_bytes(u64 max_nodes, u32 k) {
+  const u64 cnt = (max_nodes + 1) * 8;
+  const u64 cap = (max_nodes * k + k + TILE - 1) / TILE * TILE;
+  return sizeof(FilterHead) + (cnt + 255) / 256 * 256 + 2 * cap * 8;
+}
+
+hipError_t launch_filter(const HeapDesc* d, u64 max_nodes, u32 k, u64 bound, void* work,
+                         u64* kept_out, hipStream_t st) {
+  unsigned char* base = static_cast<unsigned char*>(work);
+  FilterHead* fh = reinterpret_cast<FilterHead*>(base);
+  u64* cnt = reinterpret_cast<u64*>(base + sizeof(FilterHead));
+  const u64 cap = (max_nodes * k + k + TILE - 1) / TILE * TILE;
+  u64* bufA = reinterpret_cast<u64*>(base + sizeof(FilterHead) +
+                                     ((max_nodes + 1) * 8 + 255) / 256 * 256);
+  u64* bufB = bufA + cap;
+  auto grid = [](u64 items, u64 per, u64 most) {
+    u64 g = (items + per - 1) / per;
+    if (g > most) g = most;
+    return (u32)(g == 0 ? 1 : g);
+  };
+  hipLaunchKernelGGL(k_filter_count, dim3(grid(max_nodes + 1, FT, 1024)), dim3(FT), 0, st, d,
+                     bound, fh, cnt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_filter_scan, dim3(1), dim3(FT), 0, st, fh, cnt);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_filter_gather, dim3(grid(max_nodes + 1, 1, 4096)), dim3(FT), 0, st, d, fh,
+                     cnt, bufA);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_filter_tiles, dim3(grid(cap, TILE, 4096)), dim3(FT), 0, st, fh, bufA);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  u64* src = bufA;
+  u64* dst = bufB;
+  for (u64 w = TILE; w < cap; w *= 2) {
+    hipLaunchKernelGGL(k_filter_merge, dim3(grid(cap, TILE, 4096)), dim3(FT), 0, st, fh, src, dst,
+                       w);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    u64* t = src;
+    src = dst;
+    dst = t;
+  }
+  hipLaunchKernelGGL(k_filter_build, dim3(grid(cap, FT, 2048)), dim3(FT), 0, st, d, fh, src);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_filter_root, dim3(1), dim3(64), 0, st, d, fh);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (kept_out) {
+    e = hipMemcpyAsync(kept_out, &fh->kept, sizeof(u64), hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace gh

@@ -45,6 +45,11 @@ constexpr bool shape_ok(int K, int T) {
 // or also deleteMins of fewer than K entries (gh_serve.hip)
 template <int K>
 hipError_t launch_ops_k(const LaunchArgs& a);
+
+// heap filter (gh_filter.hip): workspace size and the launch sequence
+u64 filter_workspace_bytes(u64 max_nodes, u32 k);
+hipError_t launch_filter(const HeapDesc* d, u64 max_nodes, u32 k, u64 bound, void* work,
+                         u64* kept_out, hipStream_t st);
 template <int K>
 hipError_t launch_ops_var_k(const LaunchArgs& a);
 

@@ -347,6 +347,24 @@ int heap_build(gh_heap_t h, uint32_t i, const uint64_t* d_sorted, uint64_t n) {
   return GH_OK;
 }
 
+uint64_t heap_filter_workspace_bytes(gh_heap_t h, uint32_t i) {
+  if (!h || i >= h->nheaps) return 0;
+  return filter_workspace_bytes(h->host_descs[i].max_nodes, h->k);
+}
+
+int heap_filter(gh_heap_t h, uint32_t i, uint64_t bound, void* d_work, uint64_t work_bytes,
+                uint64_t* d_kept) {
+  if (!h || i >= h->nheaps || !d_work) return GH_EINVAL;
+  if (h->sticky != GH_OK) return h->sticky;
+  if ((reinterpret_cast<uintptr_t>(d_work) & (ALIGN - 1)) != 0) return GH_EINVAL;
+  if (work_bytes < filter_workspace_bytes(h->host_descs[i].max_nodes, h->k)) return GH_EINVAL;
+  if (i == 0) h->size0_known = false;
+  if (launch_filter(h->descs + i, h->host_descs[i].max_nodes, h->k, bound, d_work, d_kept,
+                    h->stream) != hipSuccess)
+    return GH_EDEVICE;
+  return GH_OK;
+}
+
 int heap_delete_min(gh_heap_t h, uint64_t* d_out, uint32_t c, uint32_t* d_count) {
   if (!h || !d_out || !d_count || c == 0 || c > h->k) return GH_EINVAL;
   if (h->sticky != GH_OK) return h->sticky;

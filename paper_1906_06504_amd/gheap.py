@@ -64,7 +64,7 @@ EXPORTS = ("heap_arena_bytes", "heap_supported_shape", "heap_create", "heap_crea
            "heap_graph_launch", "heap_graph_destroy", "heap_sync", "heap_size",
            "heap_read_state", "heap_destroy", "heap_strerror", "heap_clock_hz",
            "heap_serve_workspace_bytes", "heap_serve", "heap_knapsack", "heap_sssp",
-           "heap_build")
+           "heap_build", "heap_filter_workspace_bytes", "heap_filter")
 
 
 class GHeapError(RuntimeError):
@@ -124,6 +124,8 @@ def load_library(path: str = LIB_PATH):
         "heap_sssp": (i32, [vp, u32, vp, vp, vp, u32, vp, vp, u64, vp,
                             ctypes.POINTER(_Tuning), ctypes.POINTER(SsspTrace)]),
         "heap_build": (i32, [vp, u32, vp, u64]),
+        "heap_filter_workspace_bytes": (u64, [vp, u32]),
+        "heap_filter": (i32, [vp, u32, u64, vp, u64, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -263,6 +265,19 @@ class HeapSet:
         """Bulk-build empty heap i from an ascending int64 tensor of entries."""
         _check(self.lib.heap_build(self.h, i, _ptr(sorted_keys), sorted_keys.numel()),
                "heap_build")
+
+    def filter(self, i: int, bound: int, work: torch.Tensor | None = None):
+        """Remove every entry >= bound from heap i (stream-ordered).  Returns
+        (kept: int64 device tensor of one element, workspace for reuse)."""
+        need = int(self.lib.heap_filter_workspace_bytes(self.h, i))
+        if need == 0:
+            raise GHeapError(GH_EINVAL, "heap_filter_workspace_bytes")
+        if work is None or work.numel() < need:
+            work = torch.empty(need, dtype=torch.uint8, device=self.device)
+        kept = torch.zeros(1, dtype=torch.int64, device=self.device)
+        _check(self.lib.heap_filter(self.h, i, int(bound), work.data_ptr(), work.numel(),
+                                    _ptr(kept)), "heap_filter")
+        return kept, work
 
     def sync(self) -> int:
         return int(self.lib.heap_sync(self.h))
