@@ -58,6 +58,9 @@ def parse():
                     help="also run the parameter sweeps of the paper's experiments (node "
                          "capacity, operations in flight, partial batches); not in the default run")
     ap.add_argument("--sssp-log2v", type=int, default=20)
+    ap.add_argument("--filter", action="store_true",
+                    help="also time heap_filter on a 2^22-entry heap (k = 1024) at several "
+                         "cut points; not in the default run")
     return ap.parse_args()
 
 
@@ -189,6 +192,8 @@ def main():
         result["paper_table"] = run_paper_table(args)
     if args.sweep:
         result["sweep"] = run_sweep(args)
+    if args.filter:
+        result["filter"] = run_filter(args)
     sssp_graph = None
     if not args.no_sssp:
         result["sssp"], sssp_graph = run_sssp(args)
@@ -587,6 +592,57 @@ def run_paper_table(args):
         out[order] = rows
         log("paper table %s: %.1f ms (paper, scaled: %.1f ms)"
             % (order, best, rows["paper_ms_scaled_to_this_n"]))
+    return out
+
+
+def run_filter(args):
+    """heap_filter (the garbage collection of branch and bound) on a heap of
+    2^22 entries, k = 1024, built from a sorted array and then shuffled by a
+    concurrent mix of 2^20 requested keys; cut at the 10th, 50th and 90th
+    percentile of its entries.  Each cut starts from the same state (an
+    arena snapshot) and is timed with HIP events on the heap's stream."""
+    import torch
+    from paper_1906_06504_amd import gheap as G
+    from paper_1906_06504_amd import workloads as W
+    k, n = 1024, 1 << 22
+    keys = np.sort(W.prefill_ops(n, k, 0x5EED0002).keys)
+    hs = G.HeapSet(k, [n + (1 << 20)], stream=torch.cuda.Stream())
+    with torch.cuda.stream(hs.stream):
+        hs.build(0, G.to_device_u64(keys))
+        mix = W.mixed_ops(1 << 20, k, seed=77, first_id=n)
+        d = G.ops_to_device(mix)
+        hs.submit(*d[:5], workgroups=64)
+    if hs.sync() != 0:
+        raise SystemExit("filter leg: setup failed")
+    torch.cuda.synchronize()
+    m, s, _, _, nodes, pb = hs.read_state(0)
+    live = np.sort(np.concatenate([nodes[:m].reshape(-1), pb]))
+    snap = hs.arena.clone()
+    out = {"workload": "filter of a %d-entry heap, k = %d" % (live.size, k)}
+    work = None
+    for q in (0.1, 0.5, 0.9):
+        bound = int(live[int(q * (live.size - 1))])
+        times = []
+        for rep in range(4):
+            hs.arena.copy_(snap)
+            torch.cuda.synchronize()
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record(hs.stream)
+            kept, work = hs.filter(0, bound, work)
+            ev1.record(hs.stream)
+            if hs.sync() != 0:
+                raise SystemExit("filter leg: filter failed")
+            torch.cuda.synchronize()
+            times.append(ev0.elapsed_time(ev1))
+            if int(kept.item()) != int(np.sum(live < np.uint64(bound))):
+                raise SystemExit("filter leg: wrong number kept")
+        ms = float(np.median(times[1:]))
+        out["q%02d" % int(q * 100)] = {"kept": int(kept.item()), "ms": ms,
+                                       "entries_per_s": live.size / (ms / 1e3)}
+        log("filter at the %d%% point: kept %d of %d in %.3f ms"
+            % (int(q * 100), int(kept.item()), live.size, ms))
+    hs.close()
     return out
 
 
