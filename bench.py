@@ -269,11 +269,12 @@ def run_batched(args, wg_default, th, plain_value):
     from paper_1906_06504_amd import workloads as W
     k = 1024
     H = args.batched_heaps
-    pre_each = args.prefill // H
+    sizes = W.uneven_sizes(H, args.prefill, 6, seed=0x5EED0012)
     req_each = args.requested // H
-    log("batched leg: %d heaps, prefill %d and %d requested each" % (H, pre_each, req_each))
-    pre, mix, pres, mixes = W.batched_mixed(H, k, pre_each, req_each, seed=0x5EED0002)
-    cap = pre_each + int(max(int(m.n.sum()) for m in mixes)) + k
+    log("batched leg: %d heaps, prefill %d..%d (total %d), %d requested each"
+        % (H, min(sizes), max(sizes), sum(sizes), req_each))
+    pre, mix, pres, mixes = W.batched_mixed(H, k, sizes, req_each, seed=0x5EED0002)
+    cap = max(sizes) + int(max(int(m.n.sum()) for m in mixes)) + k
     hs = G.HeapSet(k, [cap] * H, stream=torch.cuda.Stream())
     res = {}
     with torch.cuda.stream(hs.stream):
@@ -326,8 +327,9 @@ def run_batched(args, wg_default, th, plain_value):
             one.close()
     value = moved / (ms / 1e3)
     res = {
-        "workload": "%d heaps, k=1024, each prefilled with %d keys then a 50/50 mix of insert "
-                    "U[1,1024] and deleteMin(1024) until %d keys requested" % (H, pre_each, req_each),
+        "workload": "%d heaps, k=1024, prefill sizes log-uniform over a 64x range (%d..%d, "
+                    "total %d), then each a 50/50 mix of insert U[1,1024] and deleteMin(1024) "
+                    "until %d keys requested" % (H, min(sizes), max(sizes), sum(sizes), req_each),
         "ops": nops, "workgroups": wgb, "threads": th,
         "value": value, "unit": "keys/s", "ms_per_step": ms,
         "graph_ms_per_step": float(np.mean(gt)),

@@ -308,17 +308,29 @@ def multi_heap(lists, k: int, st: Stream) -> OpList:
     return out
 
 
-def batched_mixed(nheaps: int, k: int, prefill_each: int, requested_each: int, seed: int):
-    """nheaps independent heaps, each prefilled with `prefill_each` keys and
-    then given a 50/50 insert U[1,k] / deleteMin(k) mix requesting
-    `requested_each` keys; returns (prefill list, mixed list), both over all
-    heaps (ids unique across heaps)."""
+def uneven_sizes(nheaps: int, total: int, spread_log2: int, seed: int) -> list[int]:
+    """Heap sizes log-uniform over a 2^spread_log2 range, scaled so that they
+    sum to `total` (the last heap takes the rounding remainder)."""
+    u = Stream(seed).unit(nheaps)
+    w = 2.0 ** (spread_log2 * u)
+    sizes = np.floor(w / w.sum() * total).astype(np.int64)
+    sizes[-1] += total - int(sizes.sum())
+    return [int(x) for x in sizes]
+
+
+def batched_mixed(nheaps: int, k: int, prefill_each, requested_each: int, seed: int):
+    """nheaps independent heaps, each prefilled (`prefill_each` keys, or
+    prefill_each[h] for heap h: heaps of uneven sizes) and then given a 50/50
+    insert U[1,k] / deleteMin(k) mix requesting `requested_each` keys;
+    returns (prefill list, mixed list, per-heap prefill lists, per-heap mixed
+    lists), the first two over all heaps (ids unique across heaps)."""
     st = Stream(seed)
     pres, mixes = [], []
     next_id = 0
+    sizes = (list(prefill_each) if np.ndim(prefill_each) else [int(prefill_each)] * nheaps)
     for h in range(nheaps):
-        p = prefill_ops(prefill_each, k, seed + 101 * (h + 1), first_id=next_id)
-        next_id += prefill_each
+        p = prefill_ops(sizes[h], k, seed + 101 * (h + 1), first_id=next_id)
+        next_id += sizes[h]
         m = mixed_ops(requested_each, k, seed + 101 * (h + 1) + 7, first_id=next_id)
         next_id += int(m.n.sum())
         pres.append(p)

@@ -37,9 +37,11 @@ def _p(*a):
 
 def test_batched_many_heaps_replay_and_alone(G):
     k, nh = 64, 16
-    pre, mix, pres, mixes = W.batched_mixed(nh, k, 10 * k, 60 * k, seed=21)
-    _p("batched heaps=%d prefill ops=%d mixed ops=%d" % (nh, len(pre), len(mix)))
-    cap = 10 * k + 60 * k
+    sizes = W.uneven_sizes(nh, nh * 10 * k, 5, seed=20)   # heaps of uneven sizes
+    pre, mix, pres, mixes = W.batched_mixed(nh, k, sizes, 60 * k, seed=21)
+    _p("batched heaps=%d sizes %d..%d prefill ops=%d mixed ops=%d"
+       % (nh, min(sizes), max(sizes), len(pre), len(mix)))
+    cap = max(sizes) + 60 * k
     hs, _, _, prelog = run_gpu(pre, k, max_keys=cap, workgroups=128, nheaps=nh)
     hs, out, counts, log = run_gpu(mix, k, max_keys=cap, workgroups=256, heapset=hs)
     for h in range(nh):
@@ -70,12 +72,14 @@ def test_batched_many_heaps_replay_and_alone(G):
 
 def test_batched_full_size(G):
     """The benchmark's batched workload and launch shape: 64 heaps, k = 1024,
-    2^16 prefill and 2^18 keys requested each, 256 workgroups of 512
-    threads; every heap's log replayed on its own oracle."""
+    prefill sizes log-uniform over a 64x range summing to 2^22, 2^18 keys
+    requested each, 256 workgroups of 512 threads; every heap's log replayed
+    on its own oracle."""
     k, nh = 1024, 64
-    pre, mix, pres, mixes = W.batched_mixed(nh, k, 1 << 16, 1 << 18, seed=0x5EED0002)
+    sizes = W.uneven_sizes(nh, 1 << 22, 6, seed=0x5EED0012)
+    pre, mix, pres, mixes = W.batched_mixed(nh, k, sizes, 1 << 18, seed=0x5EED0002)
     _p("batched-full heaps=%d prefill ops=%d mixed ops=%d" % (nh, len(pre), len(mix)))
-    cap = (1 << 16) + (1 << 18) + k
+    cap = max(sizes) + (1 << 18) + k
     hs, _, _, _ = run_gpu(pre, k, max_keys=cap, workgroups=256, threads=512, nheaps=nh)
     hs, out, counts, log = run_gpu(mix, k, max_keys=cap, workgroups=256, threads=512, heapset=hs)
     for h in range(nh):
@@ -91,8 +95,9 @@ def test_batched_graph_replays(G):
     times (arena restored between replays, eager work in between): every
     replay gives the eager results."""
     k, nh = 64, 8
-    pre, mix, pres, mixes = W.batched_mixed(nh, k, 8 * k, 40 * k, seed=33)
-    cap = 8 * k + 40 * k
+    sizes = W.uneven_sizes(nh, nh * 8 * k, 4, seed=32)
+    pre, mix, pres, mixes = W.batched_mixed(nh, k, sizes, 40 * k, seed=33)
+    cap = max(sizes) + 40 * k
     hs = G.HeapSet(k, [cap] * nh, stream=torch.cuda.Stream())
     with torch.cuda.stream(hs.stream):
         d = G.ops_to_device(pre)

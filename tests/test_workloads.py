@@ -78,3 +78,13 @@ def test_ordered_insert_then_drain():
             assert np.array_equal(keys, np.arange(999, -1, -1).astype(np.uint64))
         else:
             assert np.unique(keys).size > 990
+
+
+def test_uneven_sizes():
+    """Log-uniform heap sizes over the stated range, summing to the total."""
+    sizes = W.uneven_sizes(64, 1 << 22, 6, seed=5)
+    assert sum(sizes) == 1 << 22 and len(sizes) == 64
+    assert min(sizes) > 0 and max(sizes) / min(sizes) <= 2 ** 6 * 1.01
+    assert max(sizes) / min(sizes) > 2 ** 4     # actually spread
+    pre, mix, pres, mixes = W.batched_mixed(3, 8, [5, 17, 40], 64, seed=1)
+    assert [int(p.n.sum()) for p in pres] == [5, 17, 40]
