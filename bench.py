@@ -267,6 +267,7 @@ def run_batched(args, wg_default, th, plain_value):
     from paper_1906_06504_amd import gheap as G
     from paper_1906_06504_amd import metrics as M
     from paper_1906_06504_amd import workloads as W
+    from paper_1906_06504_amd import autotune as A
     k = 1024
     H = args.batched_heaps
     sizes = W.uneven_sizes(H, args.prefill, 6, seed=0x5EED0012)
@@ -284,7 +285,20 @@ def run_batched(args, wg_default, th, plain_value):
         dmix = G.ops_to_device(mix)
         nops = dmix[1]
         dlog = G.new_log(nops)
-        wgb = min(4 * H, 1024)
+
+        # launch shape by the autotuner; the results (fixed by each heap's
+        # tickets) must not change with it
+        def trial(kk, t, wg):
+            hs.arena.copy_(snap)
+            dmix[3].fill_(-1)
+            torch.cuda.synchronize()
+            ms = _timed_submit(hs, dmix, wg, t)
+            chk = hash((dmix[3].cpu().numpy().tobytes(), dmix[4].cpu().numpy().tobytes()))
+            return ms, chk
+        best, table = A.tune("batched-%d-heaps" % H, trial, ks=(k,), threads=(256, 512, 1024),
+                             workgroups=(H, 2 * H, 4 * H, 8 * H), repeats=2, use_cache=False,
+                             log=log)
+        th, wgb = best["threads"], best["workgroups"]
         times = []
         for i in range(args.warmup + args.steps):
             hs.arena.copy_(snap)
@@ -330,7 +344,7 @@ def run_batched(args, wg_default, th, plain_value):
         "workload": "%d heaps, k=1024, prefill sizes log-uniform over a 64x range (%d..%d, "
                     "total %d), then each a 50/50 mix of insert U[1,1024] and deleteMin(1024) "
                     "until %d keys requested" % (H, min(sizes), max(sizes), sum(sizes), req_each),
-        "ops": nops, "workgroups": wgb, "threads": th,
+        "ops": nops, "workgroups": wgb, "threads": th, "tuning_table": table,
         "value": value, "unit": "keys/s", "ms_per_step": ms,
         "graph_ms_per_step": float(np.mean(gt)),
         "plain_one_heap_per_launch_keys_per_s": plain_moved / (plain_ms / 1e3),
