@@ -390,11 +390,28 @@ __device__ __forceinline__ OpResult op_insert(const HeapDesc& H, u64 ticket, con
     if (child == t) break;
     cur = child;
     {
+      // the next path node, and in the same round trip a look at the
+      // target: a deleteMin that claimed it gets the carry now, before this
+      // level's merge (the carry has not entered this subtree yet)
       NodeRegs<K, T> nr;
       nr.load(node_ptr<K>(H, cur));
+      u64 tw = 0;
+      if (tid == 0) tw = ld_relaxed(tlock);
       nr.store(N);
+      if (tid == 0) sh.flag0 = lw_state(tw) == ST_MARKED ? 1u : 0u;
     }
     __syncthreads();
+    if (sh.flag0) {
+      store_node<K, T>(node_ptr<K>(H, t), F);
+      publish();
+      if (tid == 0) {
+        unlock(lock_ptr(H, cur));
+        st_relaxed(tlock, lockword(ST_HANDED, ticket));
+      }
+      res.levels = level;
+      res.flags |= F_HANDOFF;
+      return res;
+    }
   }
   // fill the target
   store_node<K, T>(node_ptr<K>(H, t), F);
