@@ -221,7 +221,7 @@ int run_ops(gh_heap* h, const gh_op* d_ops, u32 nops, const OpParams& p, const u
   if (wg > nops) wg = nops;
   if (wg == 0) wg = 1;
   if (launch_prep(h->descs, h->nheaps, h->ctl, h->stream) != hipSuccess) return GH_EDEVICE;
-  LaunchArgs a;
+  LaunchArgs a{};
   a.descs = h->descs;
   a.ops = d_ops;
   a.nops = nops;
@@ -449,7 +449,7 @@ int heap_serve(gh_heap_t h, const gh_op* d_reqs, uint32_t nreq, const uint64_t* 
   if ((u64)h->nheaps * 32 + (u64)threads * 8 + (u64)h->k * 40 + 1024 > 65536) return GH_EINVAL;
   h->size0_known = false;
   unsigned char* base = reinterpret_cast<unsigned char*>(d_work);
-  ServeArgs a;
+  ServeArgs a{};
   a.descs = h->descs;
   a.nheaps = h->nheaps;
   a.reqs = d_reqs;
@@ -491,7 +491,7 @@ int heap_knapsack(gh_heap_t h, uint32_t ninst, const uint32_t* d_item_off, const
   if (!heap_supported_shape(h->k, threads)) return GH_EINVAL;
   u32 wg = (t && t->workgroups) ? t->workgroups : (ninst < 1024 ? ninst : 1024);
   h->size0_known = false;
-  KnapArgs a;
+  KnapArgs a{};
   a.descs = h->descs;
   a.ninst = ninst;
   a.item_off = d_item_off;
@@ -531,7 +531,7 @@ int heap_sssp(gh_heap_t h, uint32_t V, const uint32_t* d_rowptr, const uint32_t*
   if (launch_sssp_init(h->descs, h->sssp, d_dist, V, src, d_push, d_stats, h->stream) !=
       hipSuccess)
     return GH_EDEVICE;
-  LaunchArgs la;
+  LaunchArgs la{};
   la.descs = h->descs;
   la.ops = nullptr;
   la.nops = 1;
@@ -543,9 +543,10 @@ int heap_sssp(gh_heap_t h, uint32_t V, const uint32_t* d_rowptr, const uint32_t*
   la.ctl = h->ctl;
   la.workgroups = 1;
   la.threads = threads;
+  la.var_delete = 0;
   la.stream = h->stream;
   if (launch_ops(h, la) != hipSuccess) return GH_EDEVICE;
-  SsspArgs a;
+  SsspArgs a{};
   a.descs = h->descs;
   a.V = V;
   a.rowptr = d_rowptr;
