@@ -176,7 +176,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / M.HBM_PEAK_GBS,
             "traffic": M.stored_traffic(TRAFFIC_FILE, wg, th),
-            "kernel": "gh::k_ops<1024,%d>" % th,
+            "kernel": "gh::k_ops<1024,%d,false>" % th,
             "algorithmic_bytes_per_launch": alg,
         },
         "wall_s_timed_steps": wall,
