@@ -64,7 +64,7 @@ def parse():
     return ap.parse_args()
 
 
-DEFAULT_SHAPE = {"workgroups": 64, "threads": 512}
+DEFAULT_SHAPE = {"workgroups": 64, "threads": 1024}
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                             "k_ops_1024_plain_heap_traffic.txt")
 
@@ -583,7 +583,7 @@ def run_paper_table(args):
             with torch.cuda.stream(hs.stream):
                 d = G.ops_to_device(ops)
                 lg = G.new_log(d[1])
-                ms = _timed_submit(hs, d, wg, 512, lg)
+                ms = _timed_submit(hs, d, wg, 0, lg)
                 if wg == 128:
                     # deleteMin outputs in ticket order = all keys sorted
                     res = G.to_host_u64(d[3])

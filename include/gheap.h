@@ -141,7 +141,7 @@ typedef struct gh_reqrec {
 
 /* Launch shape of a submission: workgroups = number of operations in flight
  * (0 = library default), threads = workgroup size (0 = library default: 64
- * for k = 32, 128 for k = 64..256, 512 for k = 512 and 1024; must be one of
+ * for k = 32, 128 for k = 64..256, 512 for k = 512, 1024 for k = 1024; must be one of
  * the shapes heap_supported_shape accepts for k).  flags: 0, or
  * GH_TUNE_VARIABLE_DELETE when the submission holds deleteMins of fewer than
  * k entries; they run in a kernel of their own, so that submissions of

@@ -150,14 +150,14 @@ def test_config2_reduced(G):
 
 def test_config2_full_size(G):
     """The benchmark's workload and launch shape (k = 1024, prefill 2^22, 2^24
-    keys requested, 64 workgroups of 512 threads): every deleteMin of the
+    keys requested, 64 workgroups of 1024 threads): every deleteMin of the
     timed launch equals the oracle's replay of the ticket log, and the final
     state satisfies Properties 1-3 with the oracle's live multiset."""
     pre, mix, k = W.config2()
     _print("config2-full prefill ops=%d mixed ops=%d" % (len(pre), len(mix)))
     cap = (1 << 22) + int(mix.n.astype(np.int64).sum()) + k
-    hs, _, _, prelog = run_gpu(pre, k, max_keys=cap, workgroups=64, threads=512)
-    hs, out, counts, log = run_gpu(mix, k, max_keys=cap, workgroups=64, threads=512, heapset=hs)
+    hs, _, _, prelog = run_gpu(pre, k, max_keys=cap, workgroups=64, threads=1024)
+    hs, out, counts, log = run_gpu(mix, k, max_keys=cap, workgroups=64, threads=1024, heapset=hs)
     oh = oracle.OracleHeap(k)
     oh.replay(pre.kind, pre.n, pre.off, pre.keys, 1)
     replay_and_compare(mix, k, out, counts, log, base_ticket=len(pre), oracle_heap=oh)
