@@ -731,8 +731,8 @@ def run_sssp(args):
     table = []
     best = None
     dist = None
-    for t in (256, 512):
-        for wg in (16, 32, 64, 128, 256):
+    for t in (256, 512, 1024):
+        for wg in (8, 16, 32, 64, 128, 256):
             sol = SP.Solver(g, k, workgroups=wg, threads=t, stream=torch.cuda.Stream())
             sol.run(src)   # warm
             times, stats = [], None

@@ -83,11 +83,14 @@ def test_sssp_workgroup_shapes(S, threads):
     _check(S, rowptr, col, w, 3, 512, 96, threads)[0].close()
 
 
-def test_sssp_full_size(S):
+@pytest.mark.parametrize("wg,threads", [(8, 1024), (16, 1024), (16, 512), (256, 512)])
+def test_sssp_full_size(S, wg, threads):
     """The full workload (2^20 vertices, Poisson(8) out-degree, k = 512) at
-    the benchmark's launch shape: all distances equal CPU Dijkstra's."""
+    the launch shapes the benchmark's sweep finds fastest (few workgroups of
+    512 or 1024 threads) and at a wide one: all distances equal CPU
+    Dijkstra's."""
     rowptr, col, w, src, k = W.config3()
-    _check(S, rowptr, col, w, src, k, 256, 512)[0].close()
+    _check(S, rowptr, col, w, src, k, wg, threads)[0].close()
 
 
 TRACE_CASES = [(3000, 64, 32, 0, 1), (8000, 512, 96, 256, 2), (8000, 512, 96, 512, 3),
