@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--served-requests", type=int, default=1 << 20)
     ap.add_argument("--served-max-log2", type=int, default=22)
     ap.add_argument("--served-slots", type=int, default=2048)
+    ap.add_argument("--served-threads", type=int, default=0,
+                    help="workgroup size of the served form (0 = library default)")
     ap.add_argument("--served-budget", type=int, default=1 << 20,
                     help="memory budget per heap beyond its prefill (entries)")
     ap.add_argument("--no-knapsack", action="store_true", help="skip the knapsack leg")
@@ -397,7 +399,7 @@ def run_served(args):
             ev1 = torch.cuda.Event(enable_timing=True)
             ev0.record(hs.stream)
             work = hs.serve(r, nreq, keys, outb, recs, max_ops, work=work,
-                            workgroups=args.served_slots)
+                            workgroups=args.served_slots, threads=args.served_threads)
             ev1.record(hs.stream)
             rc = hs.sync()
             torch.cuda.synchronize()

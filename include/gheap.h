@@ -141,8 +141,9 @@ typedef struct gh_reqrec {
 
 /* Launch shape of a submission: workgroups = number of operations in flight
  * (0 = library default), threads = workgroup size (0 = library default: 64
- * for k = 32, 128 for k = 64..256, 512 for k = 512, 1024 for k = 1024; must be one of
- * the shapes heap_supported_shape accepts for k).  flags: 0, or
+ * for k = 32, 128 for k = 64 and 128, 512 for k = 256 and 512, 1024 for
+ * k = 1024; heap_serve: 256 for k >= 256; must be one of the shapes
+ * heap_supported_shape accepts for k).  flags: 0, or
  * GH_TUNE_VARIABLE_DELETE when the submission holds deleteMins of fewer than
  * k entries; they run in a kernel of their own, so that submissions of
  * whole-root deleteMins keep a kernel compiled without that code path.
