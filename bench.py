@@ -405,6 +405,7 @@ def run_served(args):
             torch.cuda.synchronize()
             if rc != 0:
                 raise SystemExit("serving failed: %d" % rc)
+            serve_once.last_out = outb
             return ev0.elapsed_time(ev1), G.recs_to_host(recs, nreq)
 
         def summarize(ms, recs, stream_reqs):
@@ -422,6 +423,7 @@ def run_served(args):
 
         serve_once(reqs)  # warmup
         ms, recs = serve_once(reqs)
+        sat_out = G.to_host_u64(serve_once.last_out)
         sat = summarize(ms, recs, reqs)
         out["saturated"] = sat
         log("served saturated: %.3g keys/s, %.3g req/s" % (sat["keys_per_s"], sat["requests_per_s"]))
@@ -472,7 +474,75 @@ def run_served(args):
         out["plain_one_heap_per_launch_keys_per_s"] = plain_keys / (plain_ms / 1e3)
         out["vs_plain_per_launch"] = sat["keys_per_s"] / out["plain_one_heap_per_launch_keys_per_s"]
     hs.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = served_cpu_baseline(pre, reqs, sat_recs, sat_out, k, H)
     return out
+
+
+def served_cpu_baseline(pre, reqs, recs, gpu_out, k, H):
+    """Every heap's admitted requests of the saturated run replayed in
+    ticket order on its own oracle heap (after an untimed replay of its
+    prefill): one core for a sample of 16 heaps, all host cores for all
+    heaps (one replay call per heap; ctypes releases the interpreter lock).
+    Every deleteMin output is compared with the GPU's."""
+    import concurrent.futures as cf
+    import oracle
+    from paper_1906_06504_amd import gheap as G
+    oracle.build(force=False)
+    adm = (recs["flags"] & G.REQ_ADMITTED) != 0
+
+    def prepare(h):
+        oh = oracle.OracleHeap(k)
+        ps = np.flatnonzero(pre.heap == h)
+        oh.replay(pre.kind[ps], pre.n[ps], pre.off[ps], pre.keys, 1)
+        sel = np.flatnonzero((reqs.heap == h) & adm)
+        sel = sel[np.argsort(recs["first_ticket"][sel], kind="stable")]
+        dels = reqs.kind[sel] == 1
+        coff = np.zeros(sel.size, np.uint64)   # compact output slots of k entries
+        coff[dels] = np.arange(int(dels.sum()), dtype=np.uint64) * np.uint64(k)
+        off = np.where(dels, coff, reqs.off[sel]).astype(np.uint64)
+        return oh, sel, dels, off
+
+    def replay(item):
+        oh, sel, dels, off = item
+        t0 = time.perf_counter()
+        out, cnt = oh.replay(reqs.kind[sel], reqs.n[sel], off, reqs.keys,
+                             max(1, int(dels.sum()) * k))
+        dt = time.perf_counter() - t0
+        moved = int(reqs.n[sel][~dels].astype(np.int64).sum()) + int(cnt.astype(np.int64).sum())
+        ok = True
+        for j in np.flatnonzero(dels):
+            c = int(cnt[j])
+            o, g = int(off[j]), int(reqs.off[sel[j]])
+            if c != int(recs["count"][sel[j]]) or not np.array_equal(out[o:o + c],
+                                                                       gpu_out[g:g + c]):
+                ok = False
+                break
+        oh.close()
+        return dt, moved, ok
+
+    sample = list(range(0, H, max(1, H // 16)))
+    t1, m1, ok1 = 0.0, 0, True
+    for h in sample:
+        dt, mv, ok = replay(prepare(h))
+        t1 += dt
+        m1 += mv
+        ok1 = ok1 and ok
+    nt = _host_threads()
+    with cf.ThreadPoolExecutor(nt) as ex:
+        items = list(ex.map(prepare, range(H)))
+        t0 = time.perf_counter()
+        rs = list(ex.map(replay, items))
+        wall = time.perf_counter() - t0
+    moved = sum(r[1] for r in rs)
+    equal = ok1 and all(r[2] for r in rs)
+    log("served cpu baseline: %.3g keys/s on 1 core (%d heaps), %.3g keys/s on %d threads "
+        "(all %d heaps); outputs equal: %s" % (m1 / t1, len(sample), moved / wall, nt, H, equal))
+    return {"value": moved / wall, "unit": "keys/s", "cores": nt, "kind": "oracle",
+            "sample": "every heap's admitted requests of the saturated run replayed in ticket "
+                      "order on %d threads (prefill replay untimed); one core: %.3g keys/s over "
+                      "%d heaps" % (nt, m1 / t1, len(sample)),
+            "one_core_keys_per_s": m1 / t1, "outputs_equal": bool(equal)}
 
 
 def run_knapsack(args):
@@ -522,7 +592,7 @@ def run_knapsack(args):
         torch.cuda.synchronize()
         times.append(ev0.elapsed_time(ev1))
     ms = float(np.median(times))
-    moved = 2 * int(res["created"].astype(np.int64).sum())
+    moved = int(res["created"].astype(np.int64).sum()) + int(res["popped"].astype(np.int64).sum())
     # plain form: each instance alone, one launch each (a sample of 64)
     sample = list(range(0, N, max(1, N // 64)))
     one = KS.Solver(1, k, pool_per_inst=pool)
@@ -538,7 +608,7 @@ def run_knapsack(args):
         ev1.record()
         torch.cuda.synchronize()
         plain_ms += ev0.elapsed_time(ev1)
-        plain_moved += 2 * int(r1["created"][0])
+        plain_moved += int(r1["created"][0]) + int(r1["popped"][0])
         if int(r1["best"][0]) != int(res["best"][i]):
             raise SystemExit("knapsack optimum differs between forms")
     one.close()
@@ -556,7 +626,46 @@ def run_knapsack(args):
     }
     log("knapsack: k=%d threads=%d %.2f ms, %.3g keys/s (plain per launch %.3g)"
         % (k, t, ms, out["keys_per_s"], out["plain_one_instance_per_launch_keys_per_s"]))
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = knapsack_cpu_baseline(inst, res["best"])
     return out
+
+
+def _host_threads():
+    """Worker threads for the CPU baselines: the host's cores, at most 16."""
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def knapsack_cpu_baseline(inst, gpu_best):
+    """The oracle's dynamic program (O(n C) per instance) on one core for a
+    sample of 64 instances and on all host cores for all of them (ctypes
+    releases the interpreter lock during each call); the optima must equal
+    the GPU's."""
+    import concurrent.futures as cf
+    import oracle
+    oracle.build(force=False)
+    sample = list(range(0, len(inst), max(1, len(inst) // 64)))
+    t0 = time.perf_counter()
+    for i in sample:
+        w, v, c = inst[i]
+        if oracle.knapsack_dp(w, v, c) != int(gpu_best[i]):
+            raise SystemExit("knapsack cpu baseline: optimum differs from the GPU's")
+    one = time.perf_counter() - t0
+    nt = _host_threads()
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(nt) as ex:
+        opt = list(ex.map(lambda x: oracle.knapsack_dp(*x), inst))
+    allc = time.perf_counter() - t0
+    equal = all(int(a) == int(b) for a, b in zip(opt, gpu_best))
+    log("knapsack cpu baseline: DP %.1f ms per instance on 1 core; all %d instances in %.1f ms "
+        "on %d threads; optima equal: %s" % (one / len(sample) * 1e3, len(inst), allc * 1e3, nt,
+                                             equal))
+    return {"value": allc * 1e3, "unit": "ms", "cores": nt, "kind": "oracle",
+            "sample": "dynamic program for all %d instances on %d threads; one core: %.2f ms per "
+                      "instance over %d instances" % (len(inst), nt, one / len(sample) * 1e3,
+                                                      len(sample)),
+            "one_core_ms_per_instance": one / len(sample) * 1e3,
+            "optima_equal": bool(equal)}
 
 
 # The paper's Table vscpu: TD-INS/TD-DEL heap, 2^29 keys inserted then all

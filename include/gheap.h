@@ -274,10 +274,12 @@ int heap_serve(gh_heap_t h, const gh_op *d_reqs, uint32_t nreq, const uint64_t *
                uint64_t *d_out, gh_reqrec *d_recs, void *d_work, uint64_t work_bytes,
                uint64_t max_ops, const gh_tuning *tuning);
 
-/* Result of one knapsack instance solved by heap_knapsack (32 bytes).
+/* Result of one knapsack instance solved by heap_knapsack (40 bytes).
  *   best      optimal value found
  *   explored  nodes taken from the heap and expanded (bound above best)
  *   created   nodes pushed into the heap
+ *   popped    nodes taken from the heap (the search stops before popping
+ *             those whose bound cannot beat best)
  *   ops       heap operations (inserts + deleteMins) the instance ran
  *   flags     bit 0: finished; bit 6: the node pool overflowed (best is
  *             then only a lower bound) */
@@ -285,6 +287,7 @@ typedef struct gh_knapres {
     uint64_t best;
     uint64_t explored;
     uint64_t created;
+    uint64_t popped;
     uint32_t ops;
     uint32_t flags;
 } gh_knapres;

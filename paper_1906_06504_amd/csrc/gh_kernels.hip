@@ -38,6 +38,7 @@ struct KnapShared {
   u64 explored;
   u64 created;
   u64 pool_next;
+  u64 popped_total;     // entries taken from the heap
   u32 n;
   u32 cnt;              // children produced in this round
   u32 popped;
@@ -102,6 +103,7 @@ __global__ __launch_bounds__(T) void k_knap(const HeapDesc* __restrict__ descs, 
       ks.cap = caps[inst];
       ks.explored = 0;
       ks.created = 0;
+      ks.popped_total = 0;
       ks.overflow = 0;
     }
     __syncthreads();
@@ -143,6 +145,7 @@ __global__ __launch_bounds__(T) void k_knap(const HeapDesc* __restrict__ descs, 
       // take the most promising nodes
       OpResult r = op_delete<K, T>(H, ticket++, out, (u32)K, L, sh, ctl);
       ++ops;
+      if (tid == 0) ks.popped_total += r.count;
       __syncthreads();
       if (!r.ok || r.count == 0) break;
       // best-first stopping rule: the batch's first entry has the largest
@@ -221,6 +224,7 @@ __global__ __launch_bounds__(T) void k_knap(const HeapDesc* __restrict__ descs, 
       o.best = ks.best;
       o.explored = ks.explored;
       o.created = ks.created;
+      o.popped = ks.popped_total;
       o.ops = ops;
       o.flags = 1u | (ks.overflow ? 0x40u : 0u);
       res[inst] = o;

@@ -40,6 +40,8 @@ def test_full_size_sample_matches_dp(K):
     res = s.run(K.Instances(inst), workgroups=24)
     assert not np.any(res["flags"] & 0x40), "node pool overflow"
     assert [int(b) for b in res["best"]] == ref
+    # every expanded node was popped, every popped node had been pushed
+    assert np.all(res["explored"] <= res["popped"]) and np.all(res["popped"] <= res["created"])
     print("explored", res["explored"].tolist(), flush=True)
     s.close()
 
