@@ -413,13 +413,16 @@ def run_served(args):
             keys = int(recs["count"][adm].astype(np.int64).sum())
             arr_ticks = stream_reqs.arrival.astype(np.float64) * hz / 1e9
             lat_us = (recs["t_done"][adm].astype(np.float64) - arr_ticks[adm]) * 1e6 / hz
+            resp_us = (recs["t_resp"][adm].astype(np.float64) - arr_ticks[adm]) * 1e6 / hz
             return {"ms": ms, "keys_per_s": keys / (ms / 1e3),
                     "requests_per_s": int(adm.sum()) / (ms / 1e3),
                     "admitted": int(adm.sum()),
                     "deferred_for_memory": int(((recs["flags"] & G.REQ_DEFERRED) != 0).sum()),
                     "rejected": int(((recs["flags"] & G.REQ_REJECTED) != 0).sum()),
                     "latency_us": {"p50": float(np.percentile(lat_us, 50)),
-                                   "p99": float(np.percentile(lat_us, 99))}}
+                                   "p99": float(np.percentile(lat_us, 99))},
+                    "response_latency_us": {"p50": float(np.percentile(resp_us, 50)),
+                                            "p99": float(np.percentile(resp_us, 99))}}
 
         serve_once(reqs)  # warmup
         ms, recs = serve_once(reqs)
@@ -438,8 +441,9 @@ def run_served(args):
             res = summarize(ms, recs, rq)
             res["offered_requests_per_s"] = rate
             out["poisson_%.1fx" % frac] = res
-            log("served at %.1fx: p50 %.1f us p99 %.1f us" % (frac, res["latency_us"]["p50"],
-                                                             res["latency_us"]["p99"]))
+            log("served at %.1fx: completion p50 %.1f us p99 %.1f us; answer p50 %.1f us p99 "
+                "%.1f us" % (frac, res["latency_us"]["p50"], res["latency_us"]["p99"],
+                             res["response_latency_us"]["p50"], res["response_latency_us"]["p99"]))
         # plain comparison: a sample of heaps, each heap's admitted requests
         # as its own launch (same operations, same order)
         hs.arena.copy_(snap)

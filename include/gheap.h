@@ -125,9 +125,13 @@ typedef struct gh_logrec {
  *   flags         bit 0: admitted; bit 1: an insert waited for heap memory;
  *                 bit 6: rejected (larger than the heap's capacity, never
  *                 fitted before the stream ended, or a malformed record)
- *   t_admit, t_done  device wall clock in ticks after the start of the
- *                 serving launch: admission, and completion of the last
- *                 operation (32-bit) */
+ *   t_admit, t_resp, t_done  device wall clock in ticks after the start of
+ *                 the serving launch (32-bit): admission; the answer (the
+ *                 last operation released the root: a deleteMin's entries
+ *                 are in d_out, an insert's entries are seen by every later
+ *                 operation on the heap); completion of the last operation
+ *                 (the node updates below the root that follow the answer
+ *                 are done) */
 typedef struct gh_reqrec {
     uint64_t first_ticket;
     uint32_t count;
@@ -136,7 +140,8 @@ typedef struct gh_reqrec {
     uint8_t flags;
     uint32_t t_admit;
     uint32_t t_done;
-    uint64_t reserved;
+    uint32_t t_resp;
+    uint32_t reserved;
 } gh_reqrec;
 
 /* Launch shape of a submission: workgroups = number of operations in flight

@@ -55,6 +55,7 @@ struct OpShared {
   u64 m, s;            // root metadata read at root acquire
   u64 t_claim;         // clock when the operation was claimed
   u64 t_root;          // clock at root acquire
+  u64 t_rel;           // clock at root release (stamped variants only)
   u32 flag0, flag1;    // broadcast results from wave 0
   u32 ok;
   u32 op;
@@ -93,6 +94,17 @@ __device__ __forceinline__ bool root_acquire(HeapMeta* meta, u64 ticket, Ctl* ct
 // Node and partial-buffer stores were made visible by publish() before.
 __device__ __forceinline__ void release_root(HeapMeta* meta, u64 ticket, u64 m, u64 s) {
   st_relaxed(&meta->root, rootword(ticket + 1, m, s));
+}
+
+// The same, and with Stamp the release clock goes to sh.t_rel: an insert is
+// then linearized (its entries are seen by every later operation) and a
+// deleteMin's entries are in its output buffer (stamped variants wait for
+// their stores before every release).
+template <bool Stamp>
+__device__ __forceinline__ void release_root_at(HeapMeta* meta, u64 ticket, u64 m, u64 s,
+                                                OpShared& sh) {
+  release_root(meta, ticket, m, s);
+  if constexpr (Stamp) sh.t_rel = now_ticks();
 }
 
 // How a lane wants to take a lock word.
@@ -225,7 +237,7 @@ __device__ __forceinline__ bool acquire_root(const HeapDesc& H, u64 ticket, OpSh
 // cooperation).  `keys` holds n (1..K) entries in global memory.
 // LDS: five buffers of K entries.
 // ---------------------------------------------------------------------------
-template <int K, int T>
+template <int K, int T, bool Stamp = false>
 __device__ __forceinline__ OpResult op_insert(const HeapDesc& H, u64 ticket, const u64* __restrict__ keys, u32 n,
                               lu64* lds, OpShared& sh, Ctl* ctl) {
   constexpr int E = (2 * K) / T >= 1 ? (2 * K) / T : 1;
@@ -252,7 +264,7 @@ __device__ __forceinline__ OpResult op_insert(const HeapDesc& H, u64 ticket, con
     // no room for another node: reject the insert, leave the heap unchanged
     if (tid == 0) {
       note_error(ctl, ERR_NOMEM);
-      release_root(meta, ticket, m, s);
+      release_root_at<Stamp>(meta, ticket, m, s, sh);
     }
     res.count = 0;
     res.flags |= F_REJECT;
@@ -313,7 +325,7 @@ __device__ __forceinline__ OpResult op_insert(const HeapDesc& H, u64 ticket, con
       store_heap_n<K, T>(H.pb, F, tot);
     }
     publish();
-    if (tid == 0) release_root(meta, ticket, m, tot);
+    if (tid == 0) release_root_at<Stamp>(meta, ticket, m, tot, sh);
     return res;
   }
 
@@ -324,7 +336,7 @@ __device__ __forceinline__ OpResult op_insert(const HeapDesc& H, u64 ticket, con
   if (L == 0) {
     store_node<K, T>(root, F);
     publish();
-    if (tid == 0) release_root(meta, ticket, m2, rest);
+    if (tid == 0) release_root_at<Stamp>(meta, ticket, m2, rest, sh);
     return res;
   }
 
@@ -384,7 +396,7 @@ __device__ __forceinline__ OpResult op_insert(const HeapDesc& H, u64 ticket, con
     publish();
     if (at_root) GH_TRACE(4);
     if (tid == 0) {
-      if (at_root) release_root(meta, ticket, m2, rest);
+      if (at_root) release_root_at<Stamp>(meta, ticket, m2, rest, sh);
       else unlock(lock_ptr(H, cur));
     }
     if (child == t) break;
@@ -441,7 +453,7 @@ __device__ __forceinline__ OpResult op_insert(const HeapDesc& H, u64 ticket, con
 // everything left becomes the partial buffer.  Var = false compiles the
 // whole-root deleteMin only (want is K); callers pick Var = true for want < K.
 // ---------------------------------------------------------------------------
-template <int K, int T, bool Var = false>
+template <int K, int T, bool Var = false, bool Stamp = false>
 __device__ __forceinline__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ out, u32 want_n,
                               lu64* lds, OpShared& sh, Ctl* ctl) {
   constexpr int E = (2 * K) / T >= 1 ? (2 * K) / T : 1;
@@ -468,10 +480,12 @@ __device__ __forceinline__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64
       __syncthreads();   // every read of the pb is done before it is rewritten
       store_heap_n<K, T>(H.pb, P, s - cnt);
       publish();
+    } else if constexpr (Stamp) {
+      publish();         // the output is in memory before the stamp
     } else {
       __syncthreads();   // every read of the pb is done before the root moves on
     }
-    if (tid == 0) release_root(meta, ticket, 0, s - cnt);
+    if (tid == 0) release_root_at<Stamp>(meta, ticket, 0, s - cnt, sh);
     res.count = cnt;
     return res;
   }
@@ -504,7 +518,8 @@ __device__ __forceinline__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64
   GH_TRACE(1);
   store_n<T>(out, bufs[1], want);   // the root's smallest are the answer
   if (m == 1 && !part) {
-    if (tid == 0) release_root(meta, ticket, 0, s);
+    if constexpr (Stamp) publish();   // the output is in memory before the stamp
+    if (tid == 0) release_root_at<Stamp>(meta, ticket, 0, s, sh);
     return res;
   }
   if (part) {
@@ -519,7 +534,7 @@ __device__ __forceinline__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64
       merge_split<E, T>(bufs[1] + want, K - want, PB0, (int)s, (int)nrest,
                         HeapSink(H.pb, K * 8), Sink{bufs[0]});
       publish();
-      if (tid == 0) release_root(meta, ticket, 0, nrest);
+      if (tid == 0) release_root_at<Stamp>(meta, ticket, 0, nrest, sh);
       return res;
     } else {
       // waits in P for the last node
@@ -665,7 +680,7 @@ __device__ __forceinline__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64
       if (tid == 0) {
         if (hl) unlock(lock_ptr(H, (u32)l));
         if (hr) unlock(lock_ptr(H, (u32)r));
-        if (c == 1) release_root(meta, ticket, m2, s2);
+        if (c == 1) release_root_at<Stamp>(meta, ticket, m2, s2, sh);
         else unlock(lock_ptr(H, c));
       }
       return res;
@@ -706,7 +721,7 @@ __device__ __forceinline__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64
       if (c == 1) GH_TRACE(7);
       if (tid == 0) {
         unlock(lock_ptr(H, big));
-        if (c == 1) release_root(meta, ticket, m2, s2);
+        if (c == 1) release_root_at<Stamp>(meta, ticket, m2, s2, sh);
         else unlock(lock_ptr(H, c));
       }
       next = small;
@@ -725,7 +740,7 @@ __device__ __forceinline__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64
       }
       publish();
       if (tid == 0) {
-        if (c == 1) release_root(meta, ticket, m2, s2);
+        if (c == 1) release_root_at<Stamp>(meta, ticket, m2, s2, sh);
         else unlock(lock_ptr(H, c));
       }
       next = x;

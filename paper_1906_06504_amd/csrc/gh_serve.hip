@@ -127,6 +127,7 @@ struct Scheduler {
     rec.flags = 0x40;
     rec.t_admit = (u32)(ss->now - t0);
     rec.t_done = rec.t_admit;
+    rec.t_resp = rec.t_admit;
     rec.reserved = 0;
     write_rec(r, rec);
   }
@@ -154,8 +155,9 @@ struct Scheduler {
     rec.flags = (uint8_t)(flags | 1u);
     rec.t_admit = (u32)(ss->now - t0);
     rec.t_done = rec.t_admit;
+    rec.t_resp = rec.t_admit;
     rec.reserved = 0;
-    // slots write count and t_done of this record: every word goes out
+    // slots write count, t_resp and t_done of this record: every word goes out
     // coherently and is complete before the queue entries are published
     write_rec(r, rec);
     __hip_atomic_store(w.left + r, nops, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -451,16 +453,21 @@ __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs,
     const u64 ticket = *gptr(&H.meta->base) + op.seq;
     OpResult res;
     if (op.kind == GH_OP_INSERT) {
-      res = op_insert<K, T>(H, ticket, in + op.off, op.n, L, sh, ctl);
+      res = op_insert<K, T, true>(H, ticket, in + op.off, op.n, L, sh, ctl);
     } else {
       if (__builtin_expect(op.n == (u32)K, 1))
-        res = op_delete<K, T>(H, ticket, out + op.off, K, L, sh, ctl);
+        res = op_delete<K, T, false, true>(H, ticket, out + op.off, K, L, sh, ctl);
       else
-        res = op_delete<K, T, true>(H, ticket, out + op.off, op.n, L, sh, ctl);
+        res = op_delete<K, T, true, true>(H, ticket, out + op.off, op.n, L, sh, ctl);
     }
     if (tid == 0) {
       if (op.kind == GH_OP_DELETE_MIN)
         __hip_atomic_store(&recs[r].count, res.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // the request is answered when its last operation releases the root
+      // (operations of one request release it in ticket order)
+      if (res.ok)
+        __hip_atomic_fetch_max(&recs[r].t_resp, (u32)(sh.t_rel - ctl->t0), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
       if (atomicSub(&w.left[r], 1u) == 1u)
         __hip_atomic_store(&recs[r].t_done, (u32)(now_ticks() - ctl->t0), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);

@@ -35,7 +35,8 @@ LOG_DTYPE = np.dtype([("ticket", "<u8"), ("count", "<u4"), ("levels", "<u2"), ("
                       ("flags", "u1"), ("pb", "<u2"), ("reserved", "<u2"), ("t_claim", "<u4"),
                       ("t_root", "<u4"), ("t_done", "<u4")])
 REQ_DTYPE = np.dtype([("first_ticket", "<u8"), ("count", "<u4"), ("nops", "<u2"), ("kind", "u1"),
-                      ("flags", "u1"), ("t_admit", "<u4"), ("t_done", "<u4"), ("reserved", "<u8")])
+                      ("flags", "u1"), ("t_admit", "<u4"), ("t_done", "<u4"), ("t_resp", "<u4"),
+                      ("reserved", "<u4")])
 KNAP_DTYPE = np.dtype([("best", "<u8"), ("explored", "<u8"), ("created", "<u8"),
                        ("popped", "<u8"), ("ops", "<u4"), ("flags", "<u4")])
 assert OP_DTYPE.itemsize == 32 and LOG_DTYPE.itemsize == 32 and REQ_DTYPE.itemsize == 32

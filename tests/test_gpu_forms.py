@@ -172,6 +172,9 @@ def test_served_replay(G, rate):
         _replay_served(G, pre, reqs, recs, out, k, h, caps)
     done = recs["flags"] & G.REQ_ADMITTED != 0
     assert np.all(recs["t_done"][done] >= recs["t_admit"][done])
+    # answered (last root release) after admission and no later than done
+    assert np.all(recs["t_resp"][done] > recs["t_admit"][done])
+    assert np.all(recs["t_resp"][done] <= recs["t_done"][done])
     hs.close()
 
 
