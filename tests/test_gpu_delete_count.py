@@ -196,3 +196,35 @@ def test_variable_count_needs_the_flag(G):
     oh = replay_and_compare(ref, k, out, counts, log)
     assert np.array_equal(check_gpu_state(hs, 0, k), _live(oh))
     hs.close()
+
+
+def test_variable_count_graph_replays(G):
+    """A submission with deleteMin(c) records captured once as a HIP graph
+    (GH_TUNE_VARIABLE_DELETE) and replayed three times, the arena restored
+    and eager work done in between: every replay equals the eager run."""
+    k = 64
+    pre = W.prefill_ops(20 * k, k, seed=81)
+    mix = W.mixed_ops(80 * k, k, seed=82, first_id=20 * k, var_delete=True)
+    hs = G.HeapSet(k, [200 * k], stream=torch.cuda.Stream())
+    with torch.cuda.stream(hs.stream):
+        d = G.ops_to_device(pre)
+        hs.submit(*d[:5], workgroups=32)
+        assert hs.sync() == 0
+        snap = hs.arena.clone()
+        ops, n, keys, out, counts = G.ops_to_device(mix)
+        hs.submit(ops, n, keys, out, counts, workgroups=32, var_delete=True)
+        assert hs.sync() == 0
+        ref_out, ref_counts = out.clone(), counts.clone()
+        g = hs.submit_graph(ops, n, keys, out, counts, workgroups=32, var_delete=True)
+        for rep in range(3):
+            hs.arena.copy_(snap)
+            out.fill_(-1)
+            counts.zero_()
+            torch.cuda.synchronize()
+            hs.graph_launch(g)
+            assert hs.sync() == 0
+            torch.cuda.synchronize()
+            assert torch.equal(counts, ref_counts), "replay %d counts" % rep
+            assert torch.equal(out, ref_out), "replay %d outputs" % rep
+            _ = (keys.sum() + 1).item()   # unrelated eager work between replays
+    hs.close()
