@@ -6,6 +6,8 @@ the submission's ticket log in ticket order (the root is the linearization
 point, Sec. 3.3.3 Theorem 1); quiescent GPU states are checked against
 Properties 1-3 (Sec. 3.1) and against the live multiset.
 """
+import re
+
 import numpy as np
 import pytest
 
@@ -56,6 +58,23 @@ def test_single_calls_insert_then_drain(G):
         outs.append(G.to_host_u64(out)[:c].copy())
     assert np.array_equal(np.concatenate(outs), np.sort(keys))
     assert h.close() == G.GH_OK
+
+
+def test_readme_example(G):
+    """The Python example of the README runs as written and gives the
+    entries a sort of the inserted keys gives."""
+    import pathlib
+    text = (pathlib.Path(__file__).resolve().parent.parent / "README.md").read_text()
+    block = re.search(r"```python\n(.*?)```", text, re.S).group(1)
+    torch.manual_seed(1234)
+    ns = {}
+    exec(compile(block, "README.md", "exec"), ns)
+    want = np.sort(ns["keys"].numpy().view(np.uint64))
+    out, cnt = ns["out"], ns["cnt"]
+    assert int(cnt.item()) == 100
+    assert np.array_equal(G.to_host_u64(out)[:100], want[1024:1124])
+    rest = want[1124:]
+    assert int(ns["kept"].item()) == int(np.sum(rest < np.uint64(1 << 62)))
 
 
 @pytest.mark.parametrize("k", [32, 64, 128, 256, 512, 1024])
