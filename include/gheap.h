@@ -162,7 +162,8 @@ typedef struct gh_tuning {
 
 /* Bytes of arena needed for nheaps heaps of node capacity k, heap i holding
  * up to max_keys[i] entries (max_keys == NULL: every heap holds up to
- * max_keys_each).  Returns 0 if k is unsupported. */
+ * max_keys_each).  Returns 0 if k is unsupported, nheaps is 0 or above
+ * 2^20, or a heap would need 2^30 - 1 nodes or more. */
 uint64_t heap_arena_bytes(uint32_t k, uint32_t nheaps, const uint64_t *max_keys,
                           uint64_t max_keys_each);
 
@@ -178,8 +179,9 @@ int heap_supported_shape(uint32_t k, uint32_t threads);
 int heap_create(gh_heap_t *out, uint32_t k, uint64_t max_keys, void *d_arena,
                 uint64_t arena_bytes, void *stream);
 
-/* Create a set of nheaps independent heaps of node capacity k; heap i holds
- * up to max_keys[i] entries.  Same arena and stream rules as heap_create. */
+/* Create a set of nheaps (1..2^20) independent heaps of node capacity k;
+ * heap i holds up to max_keys[i] entries.  Same arena and stream rules as
+ * heap_create. */
 int heap_create_many(gh_heap_t *out, uint32_t k, uint32_t nheaps,
                      const uint64_t *max_keys, void *d_arena,
                      uint64_t arena_bytes, void *stream);
@@ -253,7 +255,8 @@ int heap_graph_launch(gh_heap_t h, void *graph);
 int heap_graph_destroy(void *graph);
 
 /* Bytes of device workspace heap_serve needs for nreq requests that expand
- * into at most max_ops operations on a set of nheaps heaps. */
+ * into at most max_ops operations on a set of nheaps heaps; 0 if nheaps is
+ * 0 or above 2^20, or max_ops is 0 or above 2^24 - 1 (heap_serve's limits). */
 uint64_t heap_serve_workspace_bytes(uint32_t nheaps, uint32_t nreq, uint64_t max_ops);
 
 /* Serve a request stream with a device-resident loop (one persistent

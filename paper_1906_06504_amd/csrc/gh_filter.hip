@@ -105,16 +105,28 @@ __global__ __launch_bounds__(FT) void k_filter_tiles(const FilterHead* fh, u64* 
   }
 }
 
+// Merge passes that a sort of n entries takes after the tile sort: one per
+// run width w = TILE, 2 TILE, ... below n.  The sorted result is in the first
+// sort buffer after an even count, in the second after an odd one.
+__device__ __forceinline__ u32 merge_passes(u64 n) {
+  u32 p = 0;
+  for (u64 w = TILE; w < n; w *= 2) ++p;
+  return p;
+}
+
 // One merge pass: adjacent sorted runs of w entries (w a multiple of TILE)
 // are merged pairwise from src to dst.  Each workgroup writes TILE outputs:
 // its two merge-path splits are found by binary search in global memory,
-// the input ranges between them are staged in LDS and merged there.
+// the input ranges between them are staged in LDS and merged there.  The
+// host sizes the passes for the heap's capacity; a pass whose runs already
+// span the kept entries does nothing.
 __global__ __launch_bounds__(FT) void k_filter_merge(const FilterHead* fh,
                                                      const u64* __restrict__ src,
                                                      u64* __restrict__ dst, u64 w) {
   __shared__ __align__(16) u64 lds[2 * TILE];
   __shared__ u64 split[4];
   const u64 n = fh->kept;
+  if (w >= n) return;
   for (u64 o = (u64)blockIdx.x * TILE; o < n; o += (u64)gridDim.x * TILE) {
     const u64 ps = o / (2 * w) * (2 * w);
     const u64 na = n - ps < w ? n - ps : w;
@@ -156,9 +168,10 @@ __global__ __launch_bounds__(FT) void k_filter_merge(const FilterHead* fh,
 // order, the rest the partial buffer; the lock words of every position that
 // held a node are cleared.
 __global__ void k_filter_build(const HeapDesc* __restrict__ d, const FilterHead* fh,
-                               const u64* __restrict__ sorted) {
+                               const u64* __restrict__ bufA, const u64* __restrict__ bufB) {
   const HeapDesc H = *d;
   const u64 n = fh->kept;
+  const u64* __restrict__ sorted = (merge_passes(n) & 1u) ? bufB : bufA;
   const u64 body = n / H.k * H.k;
   const u64 stride = (u64)gridDim.x * blockDim.x;
   const u64 i0 = (u64)blockIdx.x * blockDim.x + threadIdx.x;
@@ -220,7 +233,8 @@ hipError_t launch_filter(const HeapDesc* d, u64 max_nodes, u32 k, u64 bound, voi
     src = dst;
     dst = t;
   }
-  hipLaunchKernelGGL(k_filter_build, dim3(grid(cap, FT, 2048)), dim3(FT), 0, st, d, fh, src);
+  hipLaunchKernelGGL(k_filter_build, dim3(grid(cap, FT, 2048)), dim3(FT), 0, st, d, fh, bufA,
+                     bufB);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_filter_root, dim3(1), dim3(64), 0, st, d, fh);
   if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -78,7 +78,12 @@ struct Layout {
   std::vector<u64> meta_off, pb_off, lock_off, node_off, max_nodes;
 };
 
+// Heaps per set.  With at most 2^30 nodes of at most 1024 entries a heap,
+// every arena offset fits in 64 bits.
+constexpr u32 MAX_HEAPS = 1u << 20;
+
 bool make_layout(u32 k, u32 nheaps, const u64* max_keys, u64 each, Layout& L) {
+  if (nheaps == 0 || nheaps > MAX_HEAPS) return false;
   L.ctl_off = 0;
   L.sssp_off = align_up(sizeof(Ctl));
   L.desc_off = align_up(L.sssp_off + sizeof(SsspState));
@@ -332,8 +337,8 @@ int heap_insert(gh_heap_t h, const uint64_t* d_keys, uint64_t n) {
     int rc = heap_size(h, 0, &sz);
     if (rc != GH_OK) return rc;
   }
-  if (h->size0 + n > h->max_keys[0]) return GH_ENOMEM;
-  u64 nops = (n + h->k - 1) / h->k;
+  if (h->size0 > h->max_keys[0] || n > h->max_keys[0] - h->size0) return GH_ENOMEM;
+  const u64 nops = n / h->k + (n % h->k != 0 ? 1 : 0);
   if (nops > 0xFFFFFFFFull) return GH_EINVAL;
   OpParams p{GH_OP_INSERT, 0, n, 0, 0};
   gh_tuning t{(u32)(nops < 64 ? nops : 64), 0, 0};
@@ -435,6 +440,7 @@ int heap_graph_destroy(void* graph) {
 }
 
 uint64_t heap_serve_workspace_bytes(uint32_t nheaps, uint32_t nreq, uint64_t max_ops) {
+  if (nheaps == 0 || nheaps > MAX_HEAPS || max_ops == 0 || max_ops > RW_TICKET_MASK) return 0;
   return serve_layout(nheaps, nreq, max_ops).total;
 }
 

@@ -205,6 +205,11 @@ def test_edge_cases(G):
     c = torch.zeros(1, dtype=torch.int32, device="cuda")
     assert lib.heap_delete_min(h.h, o.data_ptr(), k + 1, c.data_ptr()) == G.GH_EINVAL
     assert lib.heap_delete_min(h.h, None, k, c.data_ptr()) == G.GH_EINVAL
+    # counts whose sum with the heap size wraps 64 bits: refused, nothing runs
+    h.insert(G.to_device_u64(keys))
+    for n in ((1 << 64) - 1, (1 << 64) - 2, (1 << 64) - k):
+        assert lib.heap_insert(h.h, o.data_ptr(), n) == G.GH_ENOMEM
+    assert h.size() == 3
     assert h.close() == G.GH_OK
 
 

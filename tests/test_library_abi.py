@@ -48,6 +48,19 @@ def test_host_only_calls(lib):
     a = lib.heap_arena_bytes(1024, 1, None, 1 << 22)
     b = lib.heap_arena_bytes(1024, 1, None, 1 << 23)
     assert a > (1 << 22) * 8 and b > a
+    assert lib.heap_arena_bytes(1024, 0, None, 1024) == 0
+    assert lib.heap_arena_bytes(64, 1 << 20, None, 64) > 0
+    assert lib.heap_arena_bytes(64, (1 << 20) + 1, None, 64) == 0     # heaps per set
+    assert lib.heap_arena_bytes(64, 0xFFFFFFFF, None, 1 << 40) == 0
+    assert lib.heap_arena_bytes(32, 1, None, ((1 << 30) - 2) * 32) == 0   # 2^30 - 1 nodes
+    assert lib.heap_arena_bytes(32, 1, None, ((1 << 30) - 3) * 32) > (1 << 37)
+    f = lib.heap_serve_workspace_bytes
+    f.restype = ctypes.c_uint64
+    f.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64]
+    assert f(256, 1000, 4000) > 4000 * 32
+    assert f(256, 1000, 0) == 0 and f(0, 1000, 4000) == 0
+    assert f(256, 1000, 1 << 24) == 0 and f(256, 1000, (1 << 24) - 1) > 0
+    assert f(256, 1000, (1 << 64) - 1) == 0
     lib.heap_supported_shape.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
     assert lib.heap_supported_shape(1024, 256) == 1
     assert lib.heap_supported_shape(1024, 64) == 0
