@@ -145,13 +145,24 @@ def _check(rc: int, what: str):
         raise GHeapError(rc, what)
 
 
-def _ptr(t) -> int | None:
+_U64 = tuple(d for d in (torch.int64, getattr(torch, "uint64", None)) if d is not None)
+
+
+def _ptr(t, dtypes=None, min_bytes: int = 0, what: str = "tensor") -> int | None:
+    """Device address of a contiguous tensor for the C ABI.  The library
+    reads and writes device memory by the counts it is given, so the dtype
+    (entries are 8 bytes) and the size are checked here, before any launch."""
     if t is None:
         return None
+    if dtypes is not None and t.dtype not in dtypes:
+        raise TypeError("%s: dtype %s, expected one of %s" % (what, t.dtype, dtypes))
+    nbytes = t.numel() * t.element_size()
+    if nbytes < min_bytes:
+        raise ValueError("%s: %d bytes, at least %d needed" % (what, nbytes, min_bytes))
     if not t.is_cuda:
-        raise ValueError("device tensor expected")
+        raise ValueError("%s: device tensor expected" % what)
     if not t.is_contiguous():
-        raise ValueError("contiguous tensor expected")
+        raise ValueError("%s: contiguous tensor expected" % what)
     return t.data_ptr()
 
 
@@ -207,7 +218,8 @@ class HeapSet:
     # -- single-heap calls (heap 0) -------------------------------------
     def insert(self, keys: torch.Tensor) -> None:
         """Insert a 1-D int64/uint64 device tensor of entries into heap 0."""
-        _check(self.lib.heap_insert(self.h, _ptr(keys), keys.numel()), "heap_insert")
+        _check(self.lib.heap_insert(self.h, _ptr(keys, _U64, what="keys"), keys.numel()),
+               "heap_insert")
 
     def delete_min(self, out: torch.Tensor | None = None, count: torch.Tensor | None = None,
                    c: int | None = None):
@@ -218,7 +230,8 @@ class HeapSet:
             out = torch.empty(max(c, 1), dtype=torch.int64, device=self.device)
         if count is None:
             count = torch.zeros(1, dtype=torch.int32, device=self.device)
-        _check(self.lib.heap_delete_min(self.h, _ptr(out), c, _ptr(count)),
+        _check(self.lib.heap_delete_min(self.h, _ptr(out, _U64, 8 * c, "out"), c,
+                                        _ptr(count, (torch.int32,), 4, "count")),
                "heap_delete_min")
         return out, count
 
@@ -230,20 +243,31 @@ class HeapSet:
         """Run the op records on the set's stream.  var_delete: the records
         may hold deleteMins of fewer than k entries (n in 1..k-1)."""
         t = _Tuning(workgroups, threads, GH_TUNE_VARIABLE_DELETE if var_delete else 0)
-        rc = self.lib.heap_submit(self.h, _ptr(ops), nops, _ptr(d_in), _ptr(d_out),
-                                  _ptr(counts), _ptr(log), ctypes.byref(t))
+        rc = self.lib.heap_submit(self.h, *self._op_ptrs(ops, nops, d_in, d_out, counts, log),
+                                  ctypes.byref(t))
         _check(rc, "heap_submit")
 
     def submit_graph(self, ops, nops, d_in, d_out, counts=None, log=None, workgroups=0,
                      threads=0, var_delete: bool = False) -> int:
         t = _Tuning(workgroups, threads, GH_TUNE_VARIABLE_DELETE if var_delete else 0)
         g = ctypes.c_void_p()
-        rc = self.lib.heap_submit_graph(self.h, _ptr(ops), nops, _ptr(d_in), _ptr(d_out),
-                                        _ptr(counts), _ptr(log), ctypes.byref(t),
-                                        ctypes.byref(g))
+        rc = self.lib.heap_submit_graph(self.h, *self._op_ptrs(ops, nops, d_in, d_out, counts,
+                                                               log),
+                                        ctypes.byref(t), ctypes.byref(g))
         _check(rc, "heap_submit_graph")
         self._graphs.append(g.value)
         return g.value
+
+    @staticmethod
+    def _op_ptrs(ops, nops, d_in, d_out, counts, log):
+        """Arguments of heap_submit after the handle: the records, their count
+        and the buffers.  Entry buffers are addressed by the records' offsets,
+        so only their dtype is checked; per-operation arrays by nops."""
+        nops = int(nops)
+        return (_ptr(ops, None, nops * OP_DTYPE.itemsize, "ops"), nops,
+                _ptr(d_in, _U64, 0, "d_in"), _ptr(d_out, _U64, 0, "d_out"),
+                _ptr(counts, (torch.int32,), 4 * nops, "counts"),
+                _ptr(log, None, nops * LOG_DTYPE.itemsize, "log"))
 
     def graph_launch(self, g: int) -> None:
         _check(self.lib.heap_graph_launch(self.h, ctypes.c_void_p(g)), "heap_graph_launch")
@@ -257,15 +281,17 @@ class HeapSet:
         if work is None or work.numel() < need:
             work = torch.empty(need, dtype=torch.uint8, device=self.device)
         t = _Tuning(workgroups, threads)
-        rc = self.lib.heap_serve(self.h, _ptr(reqs), nreq, _ptr(d_in), _ptr(d_out), _ptr(recs),
+        rc = self.lib.heap_serve(self.h, _ptr(reqs, None, nreq * OP_DTYPE.itemsize, "reqs"), nreq,
+                                 _ptr(d_in, _U64, 0, "d_in"), _ptr(d_out, _U64, 0, "d_out"),
+                                 _ptr(recs, None, nreq * REQ_DTYPE.itemsize, "recs"),
                                  work.data_ptr(), work.numel(), max_ops, ctypes.byref(t))
         _check(rc, "heap_serve")
         return work
 
     def build(self, i: int, sorted_keys: torch.Tensor):
         """Bulk-build empty heap i from an ascending int64 tensor of entries."""
-        _check(self.lib.heap_build(self.h, i, _ptr(sorted_keys), sorted_keys.numel()),
-               "heap_build")
+        _check(self.lib.heap_build(self.h, i, _ptr(sorted_keys, _U64, what="sorted_keys"),
+                                   sorted_keys.numel()), "heap_build")
 
     def filter(self, i: int, bound: int, work: torch.Tensor | None = None):
         """Remove every entry >= bound from heap i (stream-ordered).  Returns

@@ -210,6 +210,14 @@ def test_edge_cases(G):
     for n in ((1 << 64) - 1, (1 << 64) - 2, (1 << 64) - k):
         assert lib.heap_insert(h.h, o.data_ptr(), n) == G.GH_ENOMEM
     assert h.size() == 3
+    # tensors the library would read or write past: refused by the binding
+    with pytest.raises(TypeError):
+        h.insert(torch.zeros(4, dtype=torch.int32, device="cuda"))
+    with pytest.raises(ValueError):
+        h.delete_min(torch.empty(10, dtype=torch.int64, device="cuda"), c, c=11)
+    with pytest.raises(TypeError):
+        h.delete_min(o, torch.zeros(1, dtype=torch.int64, device="cuda"))
+    assert h.size() == 3
     assert h.close() == G.GH_OK
 
 

@@ -77,6 +77,20 @@ def test_host_only_calls(lib):
     assert lib.heap_destroy(None) == -1
 
 
+def test_binding_checks_tensors_before_the_library():
+    """The library takes counts and trusts the buffers; the binding refuses a
+    tensor of the wrong dtype or too few bytes before any call."""
+    import torch
+    from paper_1906_06504_amd import gheap
+    assert gheap._ptr(None) is None
+    with pytest.raises(TypeError):
+        gheap._ptr(torch.zeros(4, dtype=torch.int32), gheap._U64, what="keys")
+    with pytest.raises(ValueError, match="at least 32"):
+        gheap._ptr(torch.zeros(3, dtype=torch.int64), gheap._U64, 32, "out")
+    with pytest.raises(ValueError, match="device tensor"):
+        gheap._ptr(torch.zeros(4, dtype=torch.int64), gheap._U64, 32, "out")
+
+
 def test_struct_layouts_match_header():
     from paper_1906_06504_amd import gheap
     text = open(HEADER).read()
