@@ -45,11 +45,12 @@ class Solver:
                  device="cuda", stream=None):
         self.g = graph
         self.k = k
-        self.workgroups = workgroups
+        # the push buffer is sized per workgroup; 0 means the library's 256
+        self.workgroups = int(workgroups) if workgroups > 0 else 256
         self.threads = threads
         self.hs = G.HeapSet(k, [graph.E + 1], device=device, stream=stream)
         self.push_per_wg = max(1, k * max(1, graph.max_degree))
-        self.push = torch.empty(workgroups * (self.push_per_wg + k), dtype=torch.int64,
+        self.push = torch.empty(self.workgroups * (self.push_per_wg + k), dtype=torch.int64,
                                 device=device)
         self.dist = torch.empty(max(1, graph.V), dtype=torch.int32, device=device)
         self.stats = torch.zeros(G.SSSP_DTYPE.itemsize, dtype=torch.uint8, device=device)

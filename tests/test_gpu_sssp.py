@@ -67,6 +67,16 @@ def test_sssp_other_source_and_reuse(S):
     sol.close()
 
 
+def test_sssp_library_default_workgroups(S):
+    """workgroups = 0 takes the library's default (256), and the push buffer
+    is sized for that many workgroups."""
+    rowptr, col, w = W.sssp_graph(4000, seed=63)
+    sol, _ = _check(S, rowptr, col, w, 5, 64, 0)
+    assert sol.workgroups == 256
+    assert sol.push.numel() == 256 * (sol.push_per_wg + 64)
+    sol.close()
+
+
 def test_sssp_unreachable_and_heavy_ties(S):
     """A graph with an unreachable half and all weights equal (many equal
     distances, ties broken by vertex id)."""
