@@ -407,7 +407,8 @@ int heap_size(gh_heap_t h, uint32_t i, uint64_t *out_host);
  * meta_host[0..3] = {nodes in use m, partial-buffer size s, tickets served,
  * node capacity}; nodes_host (may be NULL) receives max_nodes * k entries,
  * slot p-1 holding the node added p-th (bit-reversal order, Sec. 4.3);
- * pb_host (may be NULL) receives s entries. */
+ * pb_host (may be NULL) receives s entries (s < k: room for k - 1 entries
+ * always suffices). */
 int heap_read_state(gh_heap_t h, uint32_t i, uint64_t *meta_host,
                     uint64_t *nodes_host, uint64_t *pb_host);
 

@@ -50,16 +50,25 @@ __global__ void k_filter_count(const HeapDesc* __restrict__ d, u64 bound, Filter
 }
 
 // Exclusive scan of cnt[0..m] in place (one workgroup); the total is the
-// number of entries kept.
+// number of entries kept.  Each thread takes SI consecutive counts, all
+// loaded before any is used, so a heap of up to FT * SI nodes costs one
+// memory round trip.
+constexpr int SI = 16;
 __global__ __launch_bounds__(FT) void k_filter_scan(FilterHead* fh, u64* __restrict__ cnt) {
   __shared__ u64 part[FT];
   const u64 n = fh->m + 1;
   const int tid = threadIdx.x;
   u64 carry = 0;
-  for (u64 base = 0; base < n; base += FT) {
-    const u64 i = base + tid;
-    const u64 v = i < n ? cnt[i] : 0;
-    part[tid] = v;
+  for (u64 base = 0; base < n; base += (u64)FT * SI) {
+    const u64 b = base + (u64)tid * SI;
+    u64 v[SI];
+    u64 sum = 0;
+#pragma unroll
+    for (int j = 0; j < SI; ++j) {
+      v[j] = b + j < n ? cnt[b + j] : 0;
+      sum += v[j];
+    }
+    part[tid] = sum;
     __syncthreads();
     for (int off = 1; off < FT; off <<= 1) {
       const u64 t = tid >= off ? part[tid - off] : 0;
@@ -67,7 +76,12 @@ __global__ __launch_bounds__(FT) void k_filter_scan(FilterHead* fh, u64* __restr
       part[tid] += t;
       __syncthreads();
     }
-    if (i < n) cnt[i] = carry + part[tid] - v;
+    u64 run = carry + part[tid] - sum;
+#pragma unroll
+    for (int j = 0; j < SI; ++j) {
+      if (b + j < n) cnt[b + j] = run;
+      run += v[j];
+    }
     carry += part[FT - 1];
     __syncthreads();
   }
@@ -115,18 +129,35 @@ __device__ __forceinline__ u32 merge_passes(u64 n) {
 }
 
 // One merge pass: adjacent sorted runs of w entries (w a multiple of TILE)
-// are merged pairwise from src to dst.  Each workgroup writes TILE outputs:
-// its two merge-path splits are found by binary search in global memory,
-// the input ranges between them are staged in LDS and merged there.  The
-// host sizes the passes for the heap's capacity; a pass whose runs already
-// span the kept entries does nothing.
+// are merged pairwise from src to dst.  Each workgroup writes TILE outputs
+// between two merge-path diagonals; the input ranges between the two splits
+// are staged in LDS and merged there.  The host sizes the passes for the
+// heap's capacity; a pass whose runs already span the kept entries does
+// nothing.
+//
+// A split is the number of entries of A among the first dd outputs (A first
+// on ties): the boundary of the predicate A[i] <= B[dd - 1 - i], which holds
+// for every i below it and for none from it on.  Half of the workgroup (SG
+// lanes) finds each of the two splits.  With NP = 1 one lane bisects (log2(r)
+// dependent loads for a range of r entries); with NP > 1 every round probes
+// NP evenly spaced points of the remaining range at once and keeps the gap
+// between the last probe that holds and the first that does not: about
+// log(r) / log(NP + 1) rounds of one memory round trip, but NP scattered
+// cache lines fetched from each run per round.
+constexpr int SG = FT / 2;
+constexpr int NP = 16;
+static_assert(SG % 64 == 0 && NP >= 1 && NP <= SG, "split search lanes");
+
 __global__ __launch_bounds__(FT) void k_filter_merge(const FilterHead* fh,
                                                      const u64* __restrict__ src,
                                                      u64* __restrict__ dst, u64 w) {
   __shared__ __align__(16) u64 lds[2 * TILE];
-  __shared__ u64 split[4];
+  __shared__ u64 rng[2][2];        // [search][lo, hi]
+  __shared__ u32 hits[FT / 64];    // probes that hold, per wavefront
   const u64 n = fh->kept;
   if (w >= n) return;
+  const int half = threadIdx.x / SG;
+  const int g = threadIdx.x % SG;
   for (u64 o = (u64)blockIdx.x * TILE; o < n; o += (u64)gridDim.x * TILE) {
     const u64 ps = o / (2 * w) * (2 * w);
     const u64 na = n - ps < w ? n - ps : w;
@@ -135,21 +166,58 @@ __global__ __launch_bounds__(FT) void k_filter_merge(const FilterHead* fh,
     const u64* B = src + ps + na;
     const u64 d0 = o - ps;
     const u64 d1 = d0 + TILE < na + nb ? d0 + TILE : na + nb;
-    if (threadIdx.x < 2) {
-      const u64 dd = threadIdx.x == 0 ? d0 : d1;
-      // entries of A among the first dd outputs (A first on ties)
-      u64 lo = dd > nb ? dd - nb : 0;
-      u64 hi = dd < na ? dd : na;
-      while (lo < hi) {
-        const u64 mid = (lo + hi) >> 1;
-        if (A[mid] <= B[dd - 1 - mid]) lo = mid + 1;
-        else hi = mid;
+    const u64 dd = half ? d1 : d0;
+    if (g == 0) {
+      rng[half][0] = dd > nb ? dd - nb : 0;
+      rng[half][1] = dd < na ? dd : na;
+    }
+    if constexpr (NP == 1) {
+      if (g == 0) {
+        u64 lo = rng[half][0], hi = rng[half][1];
+        while (lo < hi) {
+          const u64 mid = (lo + hi) >> 1;
+          if (A[mid] <= B[dd - 1 - mid]) lo = mid + 1;
+          else hi = mid;
+        }
+        rng[half][0] = lo;
       }
-      split[threadIdx.x * 2] = lo;
-      split[threadIdx.x * 2 + 1] = dd - lo;
+    } else {
+      __syncthreads();
+      for (;;) {
+        if (rng[0][0] == rng[0][1] && rng[1][0] == rng[1][1]) break;
+        const u64 lo = rng[half][0], hi = rng[half][1];
+        const u64 span = hi - lo;
+        bool t = false;
+        if (g < NP) {
+          if (span > (u64)NP) {
+            const u64 i = lo + ((u64)(g + 1) * span) / (NP + 1);
+            t = A[i] <= B[dd - 1 - i];
+          } else if ((u64)g < span) {
+            const u64 i = lo + g;
+            t = A[i] <= B[dd - 1 - i];
+          }
+        }
+        const u64 m = __ballot(t);
+        if ((threadIdx.x & 63) == 0) hits[threadIdx.x >> 6] = (u32)__popcll(m);
+        __syncthreads();
+        if (g == 0 && span > 0) {
+          u32 c = 0;
+          for (int v = 0; v < SG / 64; ++v) c += hits[half * (SG / 64) + v];
+          u64 nlo, nhi;
+          if (span <= (u64)NP) {
+            nlo = nhi = lo + c;
+          } else {
+            nlo = c == 0 ? lo : lo + ((u64)c * span) / (NP + 1) + 1;
+            nhi = c == (u32)NP ? hi : lo + ((u64)(c + 1) * span) / (NP + 1);
+          }
+          rng[half][0] = nlo;
+          rng[half][1] = nhi;
+        }
+        __syncthreads();
+      }
     }
     __syncthreads();
-    const u64 a0 = split[0], b0 = split[1], a1 = split[2], b1 = split[3];
+    const u64 a0 = rng[0][0], b0 = d0 - a0, a1 = rng[1][0], b1 = d1 - a1;
     const int la = (int)(a1 - a0), lb = (int)(b1 - b0);
     lu64* const LA = (lu64*)lds;
     lu64* const LB = LA + la;

@@ -64,14 +64,17 @@ def percentiles_us(ticks: np.ndarray, clock_hz: int, qs=(50, 99)) -> dict:
 
 
 def kernel_source_hash() -> str:
-    """Short hash of the HIP sources, used to tell whether stored counter
-    readings still describe the kernel that is built."""
+    """Short hash of the HIP sources and the public header they include,
+    used to tell whether stored counter readings still describe the kernel
+    that is built."""
     import glob
     import hashlib
     import os
-    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    pkg = os.path.dirname(os.path.abspath(__file__))
+    files = sorted(glob.glob(os.path.join(pkg, "csrc", "*")))
+    files += sorted(glob.glob(os.path.join(os.path.dirname(pkg), "include", "*.h")))
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(here, "*"))):
+    for f in files:
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
             h.update(fh.read())
