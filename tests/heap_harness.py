@@ -89,3 +89,14 @@ def gpu_state_by_index(hs, heap, k):
     for p in range(1, m + 1):
         byidx[oracle.idx(p)] = nodes[p - 1]
     return m, s, byidx, pb
+
+
+def assert_same_state(hs, heap, oh, k):
+    """Heap `heap` of the GPU set equals oracle heap `oh` bit for bit: m, s,
+    the partial buffer and every node (compared by tree node index)."""
+    m, s, byidx, pb = gpu_state_by_index(hs, heap, k)
+    assert (m, s) == (oh.m, oh.s)
+    onodes, opb = oh.export()
+    assert np.array_equal(pb, opb)
+    for c, row in byidx.items():
+        assert np.array_equal(row, onodes[c - 1]), "node %d differs" % c

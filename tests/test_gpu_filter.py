@@ -10,7 +10,7 @@ import pytest
 import oracle
 from paper_1906_06504_amd import workloads as W
 
-from heap_harness import check_gpu_state, gpu_state_by_index, replay_and_compare, run_gpu
+from heap_harness import assert_same_state, check_gpu_state, replay_and_compare, run_gpu
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -33,12 +33,7 @@ def _p(*a):
 
 
 def _same_state(G, hs, heap, oh, k):
-    m, s, byidx, pb = gpu_state_by_index(hs, heap, k)
-    assert (m, s) == (oh.m, oh.s)
-    onodes, opb = oh.export()
-    assert np.array_equal(pb, opb)
-    for c, row in byidx.items():
-        assert np.array_equal(row, onodes[c - 1]), "node %d differs" % c
+    assert_same_state(hs, heap, oh, k)
 
 
 def _mixed_heap(G, k, seed, wg=64):

@@ -14,8 +14,8 @@ import pytest
 import oracle
 from paper_1906_06504_amd import workloads as W
 
-from heap_harness import (MAXE, check_gpu_state, gpu_state_by_index, replay_and_compare,
-                          run_gpu)
+from heap_harness import (MAXE, assert_same_state, check_gpu_state, gpu_state_by_index,
+                          replay_and_compare, run_gpu)
 
 pytestmark = pytest.mark.gpu
 
@@ -125,6 +125,36 @@ def test_concurrent_near_empty(G, k, threads, wg):
     replay_and_compare(ops, k, out, counts, log)
     check_gpu_state(hs, 0, k)
     hs.close()
+
+
+@pytest.mark.parametrize("order", ["ascending", "descending"])
+@pytest.mark.parametrize("k,wg", [(64, 64), (1024, 32)])
+def test_sorted_key_orders_state_equals_oracle(G, k, wg, order):
+    """The key orders of the paper's comparison with CPU heaps (Table vscpu).
+    Sorted keys take the shortcuts of Sec. 4.3 at nearly every level: an
+    ascending batch leaves every node on its path as it is, a descending one
+    swaps with each; sifting such a heap down swaps whole batches too.  After
+    a concurrent insert phase and after a concurrent half drain the node
+    array and partial buffer equal the oracle's (which always merges) bit
+    for bit."""
+    total = 200 * k + 17
+    ids = np.arange(total, dtype=np.uint64)
+    keys = ids if order == "ascending" else np.uint64(total - 1) - ids
+    entries = (keys << np.uint64(32)) | ids
+    nins = -(-total // k)
+    ins = W.build_oplist([W.OP_INSERT] * nins, [k] * (total // k) + [total % k],
+                         lambda c: entries[:c], k)
+    _print("sorted keys: %s k=%d total=%d workgroups=%d" % (order, k, total, wg))
+    hs, out, counts, log = run_gpu(ins, k, max_keys=total, workgroups=wg)
+    oh = replay_and_compare(ins, k, out, counts, log)
+    assert_same_state(hs, 0, oh, k)
+    ndel = nins // 2
+    drain = W.build_oplist([W.OP_DELETE_MIN] * ndel, [0] * ndel,
+                           lambda c: np.zeros(c, dtype=np.uint64), k)
+    hs, out, counts, log = run_gpu(drain, k, max_keys=total, workgroups=wg, heapset=hs)
+    oh = replay_and_compare(drain, k, out, counts, log, base_ticket=nins, oracle_heap=oh)
+    assert_same_state(hs, 0, oh, k)
+    assert hs.close() == G.GH_OK
 
 
 def test_concurrent_small_k_heavy_contention(G):
