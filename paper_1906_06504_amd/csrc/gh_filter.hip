@@ -12,7 +12,7 @@
 
 namespace gh {
 
-constexpr int FT = 256;      // threads of the filter kernels
+constexpr int FT = 512;      // threads of the filter kernels
 constexpr int TILE = 2048;   // entries sorted in LDS, and merged, per workgroup
 
 // The workspace starts with this header; then the per-node counts (one u64
