@@ -227,6 +227,17 @@ def _rev_by_string(p):
     return (1 << l) + int(format(off, "0%db" % l)[::-1], 2)
 
 
+def test_bit_reversal_golden_table():
+    """The hand-typed table of the first 32 positions (Sec. 4.3)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                         "bitrev_order_1_32.txt")
+    rows = [tuple(int(x) for x in line.split()) for line in open(path)
+            if line.strip() and not line.startswith("#")]
+    assert [p for p, _ in rows] == list(range(1, 33))
+    for p, c in rows:
+        assert oracle.idx(p) == c, "position %d" % p
+
+
 def test_bit_reversal_order():
     for p in range(1, 5000):
         assert oracle.idx(p) == _rev_by_string(p)
