@@ -60,6 +60,10 @@ def parse():
                     help="also run the parameter sweeps of the paper's experiments (node "
                          "capacity, operations in flight, partial batches); not in the default run")
     ap.add_argument("--sssp-log2v", type=int, default=20)
+    ap.add_argument("--util-sweep", action="store_true",
+                    help="also run the paper's initial-utilization study (heaps of 6 to 18 "
+                         "levels, then ins-del pairs)")
+    ap.add_argument("--util-pairs", type=int, default=1 << 15)
     ap.add_argument("--filter", action="store_true",
                     help="also time heap_filter on a 2^22-entry heap (k = 1024) at several "
                          "cut points; not in the default run")
@@ -194,6 +198,8 @@ def main():
         result["paper_table"] = run_paper_table(args)
     if args.sweep:
         result["sweep"] = run_sweep(args)
+    if args.util_sweep:
+        result["utilization"] = run_util_sweep(args)
     if args.filter:
         result["filter"] = run_filter(args)
     sssp_graph = None
@@ -776,6 +782,58 @@ def run_filter(args):
         log("filter at the %d%% point: kept %d of %d in %.3f ms"
             % (int(q * 100), int(kept.item()), live.size, ms))
     hs.close()
+    return out
+
+
+def run_util_sweep(args):
+    """The paper's initial-utilization study (Sec. 5, heap utilization):
+    the heap starts with 2^L full nodes (L = 6 .. 18 levels, 64K to 256M
+    entries at k = 1024), then 128 workgroups run ins-del pairs (insert 1024
+    random entries, deleteMin 1024), so the heap keeps its size.  The paper
+    runs 2^18 pairs; here 2^15 (--util-pairs) and the time per pair is
+    reported.  The initial heap is a bulk build of a sorted array (a sorted
+    array is a generalized heap, Sec. 3.1), generated and sorted on the
+    device from a seeded generator; keys are 31 bits so that signed and
+    unsigned order agree."""
+    import torch
+    from paper_1906_06504_amd import gheap as G
+    from paper_1906_06504_amd import workloads as W
+    k, wg, pairs = 1024, 128, args.util_pairs
+    rng = np.random.default_rng(0x5EED000C)
+    out = {"workload": "initial heap of 2^L nodes (k = 1024), then %d ins-del pairs on %d "
+                       "workgroups" % (pairs, wg), "rows": []}
+    for L in (6, 8, 10, 12, 14, 16, 18):
+        n0 = k << L
+        ins_keys = ((rng.integers(0, 1 << 31, pairs * k, dtype=np.uint64) << np.uint64(32))
+                    | np.arange(n0, n0 + pairs * k, dtype=np.uint64))
+        ops = W.build_oplist([W.OP_INSERT, W.OP_DELETE_MIN] * pairs, [k, 0] * pairs,
+                             lambda c: ins_keys[:c], k)
+        hs = G.HeapSet(k, [n0 + 4 * wg * k], stream=torch.cuda.Stream())
+        with torch.cuda.stream(hs.stream):
+            gen = torch.Generator(device="cuda")
+            gen.manual_seed(0x5EED000D + L)
+            ent = torch.randint(0, 1 << 31, (n0,), generator=gen, device="cuda",
+                                dtype=torch.int64)
+            ent = torch.sort((ent << 32) | torch.arange(n0, device="cuda",
+                                                        dtype=torch.int64)).values
+            hs.build(0, ent)
+            d = G.ops_to_device(ops)
+        if hs.sync() != 0:
+            raise SystemExit("utilization sweep: build failed")
+        del ent
+        with torch.cuda.stream(hs.stream):
+            ms = _timed_submit(hs, d, wg, 0)
+        size = hs.size(0)
+        hs.close()
+        del d, hs
+        torch.cuda.empty_cache()
+        if size != n0:
+            raise SystemExit("utilization sweep: heap size %d after the pairs, expected %d"
+                             % (size, n0))
+        out["rows"].append({"levels": L, "initial_keys": n0, "ms": ms,
+                            "us_per_pair": ms * 1e3 / pairs})
+        log("utilization sweep: %d levels (%d keys): %.1f ms, %.2f us per pair"
+            % (L, n0, ms, ms * 1e3 / pairs))
     return out
 
 
