@@ -26,16 +26,30 @@ _lib = None
 U64P = ctypes.POINTER(ctypes.c_uint64)
 U32P = ctypes.POINTER(ctypes.c_uint32)
 U8P = ctypes.POINTER(ctypes.c_uint8)
+MAXE = np.uint64(0xFFFFFFFFFFFFFFFF)
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle C sources into liboracle.so (gcc, -O2)."""
+    """Compile the oracle C sources into liboracle.so (gcc, -O2): the heap
+    oracle twice, for 8-byte entries (gho_*) and for 16-byte entries
+    (-DGHO_WIDE, ghow_*), and the application oracles."""
     if not force and os.path.exists(_LIB_PATH):
         return _LIB_PATH
     srcs = [os.path.join(_HERE, s) for s in _SOURCES if os.path.exists(os.path.join(_HERE, s))]
     tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC", "-o", tmp] + srcs
-    subprocess.check_call(cmd)
+    flags = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC"]
+    objs = []
+    for i, src in enumerate(srcs + [os.path.join(_HERE, "gheap_oracle.c")]):
+        obj = tmp + ".%d.o" % i
+        wide = ["-DGHO_WIDE"] if i == len(srcs) else []
+        subprocess.check_call(flags + wide + ["-c", src, "-o", obj])
+        objs.append(obj)
+    try:
+        subprocess.check_call(["gcc", "-shared", "-o", tmp] + objs)
+    finally:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -51,35 +65,11 @@ def build_variant(defines: list[str], out_name: str) -> str:
 
 
 def _declare(lib):
-    lib.gho_new.restype = ctypes.c_void_p
-    lib.gho_new.argtypes = [ctypes.c_uint32]
-    lib.gho_free.restype = None
-    lib.gho_free.argtypes = [ctypes.c_void_p]
-    for name in ("gho_size", "gho_nodes", "gho_pb_size", "gho_node_slots"):
-        f = getattr(lib, name)
-        f.restype = ctypes.c_uint64
-        f.argtypes = [ctypes.c_void_p]
-    lib.gho_idx.restype = ctypes.c_uint64
-    lib.gho_idx.argtypes = [ctypes.c_uint64]
-    lib.gho_insert.restype = ctypes.c_int
-    lib.gho_insert.argtypes = [ctypes.c_void_p, U64P, ctypes.c_uint64]
-    lib.gho_delete_min.restype = ctypes.c_uint64
-    lib.gho_delete_min.argtypes = [ctypes.c_void_p, U64P]
-    lib.gho_delete_min_n.restype = ctypes.c_uint64
-    lib.gho_delete_min_n.argtypes = [ctypes.c_void_p, U64P, ctypes.c_uint64]
-    lib.gho_build.restype = ctypes.c_int
-    lib.gho_build.argtypes = [ctypes.c_void_p, U64P, ctypes.c_uint64]
-    lib.gho_filter.restype = ctypes.c_uint64
-    lib.gho_filter.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
-    lib.gho_check.restype = ctypes.c_int
-    lib.gho_check.argtypes = [ctypes.c_void_p]
-    lib.gho_export.restype = None
-    lib.gho_export.argtypes = [ctypes.c_void_p, U64P, U64P]
-    lib.gho_counters.restype = None
-    lib.gho_counters.argtypes = [ctypes.c_void_p, U64P]
-    lib.gho_replay.restype = ctypes.c_int64
-    lib.gho_replay.argtypes = [ctypes.c_void_p, ctypes.c_uint64, U8P, U32P, U64P,
-                               U64P, U64P, U32P, ctypes.c_int]
+    _declare_heap(lib, "gho_")
+    if hasattr(lib, "ghow_new"):
+        _declare_heap(lib, "ghow_")
+        lib.ghow_filter_key.restype = ctypes.c_uint64
+        lib.ghow_filter_key.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
     if hasattr(lib, "gho_dijkstra"):
         lib.gho_dijkstra.restype = ctypes.c_int
         lib.gho_dijkstra.argtypes = [ctypes.c_uint32, U64P, U32P, U32P, ctypes.c_uint32, U32P]
@@ -87,6 +77,45 @@ def _declare(lib):
         lib.gho_knapsack_dp.restype = ctypes.c_uint64
         lib.gho_knapsack_dp.argtypes = [ctypes.c_uint32, U32P, U32P, ctypes.c_uint64]
     return lib
+
+
+def _declare_heap(lib, pre):
+    """Signatures of one entry width's heap functions (entry pointers are
+    passed as void pointers: 8 or 16 bytes an entry)."""
+    EP = ctypes.c_void_p
+    f = lambda name: getattr(lib, pre + name)  # noqa: E731
+    f("new").restype = ctypes.c_void_p
+    f("new").argtypes = [ctypes.c_uint32]
+    f("free").restype = None
+    f("free").argtypes = [ctypes.c_void_p]
+    for name in ("size", "nodes", "pb_size", "node_slots"):
+        f(name).restype = ctypes.c_uint64
+        f(name).argtypes = [ctypes.c_void_p]
+    f("idx").restype = ctypes.c_uint64
+    f("idx").argtypes = [ctypes.c_uint64]
+    f("insert").restype = ctypes.c_int
+    f("insert").argtypes = [ctypes.c_void_p, EP, ctypes.c_uint64]
+    f("delete_min").restype = ctypes.c_uint64
+    f("delete_min").argtypes = [ctypes.c_void_p, EP]
+    f("delete_min_n").restype = ctypes.c_uint64
+    f("delete_min_n").argtypes = [ctypes.c_void_p, EP, ctypes.c_uint64]
+    f("build").restype = ctypes.c_int
+    f("build").argtypes = [ctypes.c_void_p, EP, ctypes.c_uint64]
+    f("check").restype = ctypes.c_int
+    f("check").argtypes = [ctypes.c_void_p]
+    f("export").restype = None
+    f("export").argtypes = [ctypes.c_void_p, EP, EP]
+    f("counters").restype = None
+    f("counters").argtypes = [ctypes.c_void_p, U64P]
+    f("replay").restype = ctypes.c_int64
+    f("replay").argtypes = [ctypes.c_void_p, ctypes.c_uint64, U8P, U32P, U64P, EP, EP, U32P,
+                            ctypes.c_int]
+    f("merge_and_sort").restype = None
+    f("merge_and_sort").argtypes = [ctypes.c_void_p, EP, ctypes.c_uint64, EP, ctypes.c_uint64,
+                                    EP, EP]
+    if pre == "gho_":
+        f("filter").restype = ctypes.c_uint64
+        f("filter").argtypes = [ctypes.c_void_p, ctypes.c_uint64]
 
 
 def load(path: str | None = None):
@@ -115,19 +144,56 @@ def idx(p: int) -> int:
     return int(load().gho_idx(p))
 
 
-class OracleHeap:
-    """Sequential generalized heap with node capacity k (any k >= 1)."""
+def _vp(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
 
-    def __init__(self, k: int, lib=None):
+
+def wide_to_c(a) -> np.ndarray:
+    """16-byte entries from the device layout ([n, 2] uint64: key word, id
+    word) to the oracle's (an unsigned 128-bit integer, low half first in
+    memory: id word, key word)."""
+    a = np.asarray(a, dtype=np.uint64).reshape(-1, 2)
+    return np.ascontiguousarray(a[:, ::-1])
+
+
+def wide_from_c(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.uint64).reshape(-1, 2)[:, ::-1])
+
+
+class OracleHeap:
+    """Sequential generalized heap with node capacity k (any k >= 1).
+
+    wide=False: 8-byte entries, 1-D uint64 arrays.  wide=True: 16-byte
+    entries as [n, 2] uint64 arrays in the device layout (biased key word,
+    id word), ordered by key word, then id word."""
+
+    def __init__(self, k: int, lib=None, wide: bool = False):
         self.lib = lib if lib is not None else load()
         self.k = int(k)
-        self.h = self.lib.gho_new(self.k)
+        self.wide = bool(wide)
+        self.pre = "ghow_" if self.wide else "gho_"
+        self.h = self._f("new")(self.k)
         if not self.h:
             raise MemoryError("gho_new failed")
 
+    def _f(self, name):
+        return getattr(self.lib, self.pre + name)
+
+    def _in(self, keys) -> np.ndarray:
+        """Caller entries -> the oracle's C layout (contiguous)."""
+        if self.wide:
+            return wide_to_c(keys)
+        return np.ascontiguousarray(np.asarray(keys, dtype=np.uint64).reshape(-1))
+
+    def _out(self, a: np.ndarray) -> np.ndarray:
+        return wide_from_c(a) if self.wide else a
+
+    def _empty(self, n: int) -> np.ndarray:
+        return np.empty((max(n, 1), 2) if self.wide else max(n, 1), dtype=np.uint64)
+
     def close(self):
         if self.h:
-            self.lib.gho_free(self.h)
+            self._f("free")(self.h)
             self.h = None
 
     def __del__(self):
@@ -137,66 +203,74 @@ class OracleHeap:
             pass
 
     def insert(self, keys) -> None:
-        a = np.ascontiguousarray(np.asarray(keys, dtype=np.uint64))
-        if a.size and np.any(a == np.uint64(0xFFFFFFFFFFFFFFFF)):
+        a = self._in(keys)
+        n = a.shape[0]
+        if n and np.any(np.all(a.reshape(n, -1) == MAXE, axis=1)):
             raise ValueError("the all-ones entry is reserved")
-        if self.lib.gho_insert(self.h, _p64(a), a.size) != 0:
+        if self._f("insert")(self.h, _vp(a) if n else None, n) != 0:
             raise MemoryError("gho_insert failed")
 
     def delete_min(self, c: int | None = None) -> np.ndarray:
         """Remove and return the min(c, size) smallest entries (c = k when
         None; 1 <= c <= k)."""
-        out = np.empty(self.k, dtype=np.uint64)
+        out = self._empty(self.k)
         if c is None:
-            got = self.lib.gho_delete_min(self.h, _p64(out))
+            got = self._f("delete_min")(self.h, _vp(out))
         else:
-            got = self.lib.gho_delete_min_n(self.h, _p64(out), int(c))
+            got = self._f("delete_min_n")(self.h, _vp(out), int(c))
             if got == 0xFFFFFFFFFFFFFFFF:
                 raise ValueError("deleteMin count must be in [1, k]")
-        return out[:got].copy()
+        return self._out(out[:got]).copy()
 
     def build(self, sorted_keys) -> None:
         """Bulk build of an empty heap from ascending entries (Sec. 3.1)."""
-        a = np.ascontiguousarray(np.asarray(sorted_keys, dtype=np.uint64))
-        rc = self.lib.gho_build(self.h, _p64(a) if a.size else None, a.size)
+        a = self._in(sorted_keys)
+        rc = self._f("build")(self.h, _vp(a) if a.shape[0] else None, a.shape[0])
         if rc == -2:
             raise ValueError("entries must be ascending and not the reserved value")
         if rc != 0:
             raise RuntimeError("gho_build failed (heap not empty or no memory)")
 
     def filter(self, bound: int) -> int:
-        """Remove every entry >= bound; returns the number kept."""
-        kept = self.lib.gho_filter(self.h, int(bound))
+        """Remove every entry >= bound (16-byte entries: every entry whose
+        key word is >= bound); returns the number kept."""
+        if self.wide:
+            kept = self.lib.ghow_filter_key(self.h, int(bound))
+        else:
+            kept = self.lib.gho_filter(self.h, int(bound))
         if kept == 0xFFFFFFFFFFFFFFFF:
             raise MemoryError("gho_filter failed")
         return int(kept)
 
     def check(self) -> int:
-        return int(self.lib.gho_check(self.h))
+        return int(self._f("check")(self.h))
 
     @property
     def size(self) -> int:
-        return int(self.lib.gho_size(self.h))
+        return int(self._f("size")(self.h))
 
     @property
     def m(self) -> int:
-        return int(self.lib.gho_nodes(self.h))
+        return int(self._f("nodes")(self.h))
 
     @property
     def s(self) -> int:
-        return int(self.lib.gho_pb_size(self.h))
+        return int(self._f("pb_size")(self.h))
 
     def export(self):
-        """Return (nodes[slots, k], pb[s]) copies of the internal state."""
-        slots = int(self.lib.gho_node_slots(self.h))
-        nodes = np.empty(slots * self.k, dtype=np.uint64)
-        pb = np.empty(max(self.s, 1), dtype=np.uint64)
-        self.lib.gho_export(self.h, _p64(nodes), _p64(pb))
+        """Return (nodes[slots, k], pb[s]) copies of the internal state
+        (16-byte entries: nodes[slots, k, 2], pb[s, 2] in the device layout)."""
+        slots = int(self._f("node_slots")(self.h))
+        nodes = self._empty(slots * self.k)
+        pb = self._empty(self.s)
+        self._f("export")(self.h, _vp(nodes), _vp(pb))
+        if self.wide:
+            return (self._out(nodes).reshape(slots, self.k, 2), self._out(pb)[: self.s].copy())
         return nodes.reshape(slots, self.k), pb[: self.s].copy()
 
     def counters(self) -> dict:
         c = np.zeros(5, dtype=np.uint64)
-        self.lib.gho_counters(self.h, _p64(c))
+        self._f("counters")(self.h, _p64(c))
         return dict(ins_ops=int(c[0]), ins_full=int(c[1]), ins_path_nodes=int(c[2]),
                     del_ops=int(c[3]), del_levels=int(c[4]))
 
@@ -207,17 +281,17 @@ class OracleHeap:
         types = np.ascontiguousarray(types, dtype=np.uint8)
         n = np.ascontiguousarray(n, dtype=np.uint32)
         off = np.ascontiguousarray(off, dtype=np.uint64)
-        in_keys = np.ascontiguousarray(in_keys, dtype=np.uint64)
-        if in_keys.size == 0:
-            in_keys = np.zeros(1, dtype=np.uint64)
-        out = np.full(max(out_capacity, 1), np.uint64(0xFFFFFFFFFFFFFFFF), dtype=np.uint64)
+        keys = self._in(in_keys)
+        if keys.shape[0] == 0:
+            keys = self._empty(1)
+        out = self._empty(out_capacity)
+        out.fill(np.uint64(0xFFFFFFFFFFFFFFFF))
         counts = np.zeros(types.size, dtype=np.uint32)
-        rc = self.lib.gho_replay(self.h, types.size, types.ctypes.data_as(U8P), _p32(n),
-                                 _p64(off), _p64(in_keys), _p64(out), _p32(counts),
-                                 1 if check else 0)
+        rc = self._f("replay")(self.h, types.size, types.ctypes.data_as(U8P), _p32(n), _p64(off),
+                               _vp(keys), _vp(out), _p32(counts), 1 if check else 0)
         if rc != 0:
             raise RuntimeError("oracle replay failed at op %d" % (-rc - 1))
-        return out, counts
+        return self._out(out), counts
 
 
 def dijkstra(V: int, rowptr: np.ndarray, col: np.ndarray, w: np.ndarray, src: int) -> np.ndarray:
@@ -246,13 +320,10 @@ def merge_and_sort(a, b):
     a = np.ascontiguousarray(a, dtype=np.uint64)
     b = np.ascontiguousarray(b, dtype=np.uint64)
     lib = load()
-    lib.gho_merge_and_sort.restype = None
-    lib.gho_merge_and_sort.argtypes = [ctypes.c_void_p, U64P, ctypes.c_uint64, U64P,
-                                       ctypes.c_uint64, U64P, U64P]
     h = OracleHeap(max(a.size, b.size, 1))
     hi = np.empty(max(a.size, 1), dtype=np.uint64)
     lo = np.empty(max(b.size, 1), dtype=np.uint64)
     aa = a if a.size else np.zeros(1, dtype=np.uint64)
     bb = b if b.size else np.zeros(1, dtype=np.uint64)
-    lib.gho_merge_and_sort(h.h, _p64(aa), a.size, _p64(bb), b.size, _p64(hi), _p64(lo))
+    lib.gho_merge_and_sort(h.h, _vp(aa), a.size, _vp(bb), b.size, _vp(hi), _vp(lo))
     return hi[: a.size].copy(), lo[: b.size].copy()

@@ -6,11 +6,11 @@
  *
  *  - gho_dijkstra: textbook Dijkstra single-source shortest paths with a
  *    binary heap and lazy deletion; exact uint32 distances.  The paper's
- *    SSSP application (Sec. 5.6.1) prioritises frontier vertices by their
+ *    SSSP application (Sec. 5.7.1) prioritises frontier vertices by their
  *    tentative distance; shortest-path distances themselves are unique, so
  *    any correct method must reproduce these values exactly.
  *  - gho_knapsack_dp: 0/1 knapsack optimum by dynamic programming over
- *    capacities (the problem statement of Sec. 5.6.2); exact.
+ *    capacities (the problem statement of Sec. 5.7.2); exact.
  */
 #include <stdint.h>
 #include <stdlib.h>

@@ -30,13 +30,18 @@
  *     the root's c smallest, then the root's rest and the partial buffer
  *     refill the top, taking the last node only when they are fewer than k;
  *   - bulk build from an ascending array (Sec. 3.1) and a filter that keeps
- *     the entries below a bound (garbage collection, Sec. 5.6.2);
+ *     the entries below a bound (garbage collection, Sec. 5.7.2);
  *   - target order by bit-reversal permutation (Sec. 4.3, "Bit-Reversal
  *     Permutation"), DEL taking the last node in the reverse order.
  *
  * Entries are unsigned 64-bit integers compared as integers; the all-ones
  * value is reserved as the MAX filler and never inserted.  Callers that need
- * (key, id) pairs pack them as key<<32 | id.
+ * (key, id) pairs pack them as key<<32 | id.  Compiled with -DGHO_WIDE the
+ * same file gives the oracle for 16-byte entries (a signed 64-bit key and a
+ * 32-bit id, ordered by key, then id): an entry is then an unsigned 128-bit
+ * integer whose high half is the biased key (key XOR 2^63) and whose low half
+ * is the id, so that integer order is that lexicographic order, and every
+ * exported name starts with ghow_ instead of gho_.
  *
  * Everything here is deliberately plain: two-pointer merges, qsort, no
  * blocking and no reordering beyond what the paper's steps state.
@@ -45,8 +50,31 @@
 #include <stdlib.h>
 #include <string.h>
 
+#ifdef GHO_WIDE
+typedef unsigned __int128 gho_ent;
+#define GHO_MAX (~(gho_ent)0)
+#define gho_idx ghow_idx
+#define gho_new ghow_new
+#define gho_free ghow_free
+#define gho_size ghow_size
+#define gho_nodes ghow_nodes
+#define gho_pb_size ghow_pb_size
+#define gho_insert ghow_insert
+#define gho_delete_min ghow_delete_min
+#define gho_delete_min_n ghow_delete_min_n
+#define gho_build ghow_build
+#define gho_filter ghow_filter
+#define gho_filter_key ghow_filter_key
+#define gho_check ghow_check
+#define gho_node_slots ghow_node_slots
+#define gho_export ghow_export
+#define gho_merge_and_sort ghow_merge_and_sort
+#define gho_counters ghow_counters
+#define gho_replay ghow_replay
+#else
 typedef uint64_t gho_ent;
 #define GHO_MAX UINT64_MAX
+#endif
 
 typedef struct gho_heap {
     uint32_t k;        /* node capacity */
@@ -373,7 +401,7 @@ int gho_build(gho_heap *h, const gho_ent *sorted, uint64_t n) {
 }
 
 /* Filter: remove every entry >= bound (the garbage collection of a
- * branch-and-bound search, Sec. 5.6.2, with the bound as the cut).  The
+ * branch-and-bound search, Sec. 5.7.2, with the bound as the cut).  The
  * entries kept are gathered, sorted and built again as above.  Returns the
  * number kept, or UINT64_MAX when memory runs out. */
 uint64_t gho_filter(gho_heap *h, gho_ent bound) {
@@ -396,6 +424,14 @@ uint64_t gho_filter(gho_heap *h, gho_ent bound) {
     free(buf);
     return rc == 0 ? kept : UINT64_MAX;
 }
+
+#ifdef GHO_WIDE
+/* Filter of a 16-byte heap by a key word: every entry whose biased key is
+ * >= key_word goes (the entry bound is (key_word, id 0)). */
+uint64_t gho_filter_key(gho_heap *h, uint64_t key_word) {
+    return gho_filter(h, (gho_ent)key_word << 64);
+}
+#endif
 
 /* ---- invariant checker (Sec. 3.1, Properties 1-3) ---------------------- */
 

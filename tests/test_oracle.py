@@ -414,3 +414,127 @@ def test_sorted_array_in_addition_order_is_a_heap():
             if m and pb:
                 assert node[1][-1] <= pb[0]                          # Property 3
             assert len(pb) < k
+
+
+# ---------------------------------------------------------------------------
+# 16-byte entries (signed 64-bit key, 32-bit id), ordered by key, then id
+# ---------------------------------------------------------------------------
+
+SIGN = 1 << 63
+
+
+def _wide(pairs):
+    """[(signed key, id)] -> [n, 2] uint64 in the device layout (key XOR 2^63,
+    then the id), written out here independently of the library."""
+    a = np.zeros((len(pairs), 2), dtype=np.uint64)
+    for i, (key, ident) in enumerate(pairs):
+        a[i, 0] = (key + (1 << 64) if key < 0 else key) ^ SIGN
+        a[i, 1] = ident
+    return a
+
+
+def _pairs(a):
+    out = []
+    for w0, w1 in np.asarray(a, dtype=np.uint64).reshape(-1, 2):
+        u = int(w0) ^ SIGN
+        out.append((u - (1 << 64) if u >= SIGN else u, int(w1)))
+    return out
+
+
+def run_wide_against_brute_force(k, ops, lib=None):
+    """As run_against_brute_force with 16-byte entries: the live multiset is
+    a sorted list of (key, id) tuples (Python's tuple order is the
+    lexicographic order the entry defines)."""
+    h = oracle.OracleHeap(k, lib=lib, wide=True)
+    live = []
+    for i, op in enumerate(ops):
+        if op[0] == "ins":
+            h.insert(_wide(op[1]))
+            live = sorted(live + list(op[1]))
+        elif op[0] == "filter":
+            key = op[1]
+            live = [p for p in live if p[0] < key]
+            word = (key + (1 << 64) if key < 0 else key) ^ SIGN
+            if h.filter(word) != len(live):
+                return "op %d: filter kept the wrong number" % i
+        else:
+            want_n = op[1] if len(op) > 1 else k
+            got = _pairs(h.delete_min(op[1] if len(op) > 1 else None))
+            c = min(want_n, len(live))
+            if got != live[:c]:
+                return "op %d: deleteMin mismatch" % i
+            live = live[c:]
+        rc = h.check()
+        if rc:
+            return "op %d: invariant code %d" % (i, rc)
+        if h.size != len(live) or h.m != len(live) // k or h.s != len(live) % k:
+            return "op %d: size bookkeeping" % i
+    return None
+
+
+def wide_trace(rng, k, nops, key_span, next_id):
+    """Random ops on (key, id) pairs: keys signed, uniform on
+    [-key_span, key_span) (a small span gives many equal keys), ids unique."""
+    ops = []
+    for _ in range(nops):
+        r = rng.random()
+        if r < 0.08:
+            ops.append(("filter", int(rng.integers(-key_span, key_span + 1))))
+        elif r < 0.6:
+            n = int(rng.integers(0, 3 * k + 1))
+            keys = rng.integers(-key_span, key_span, n)
+            ops.append(("ins", [(int(x), next_id + j) for j, x in enumerate(keys)]))
+            next_id += n
+        elif r < 0.8:
+            ops.append(("del", int(rng.integers(1, k + 1))))
+        else:
+            ops.append(("del",))
+    return ops
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 8, 16])
+def test_wide_brute_force_random_traces(k):
+    """16-byte entries: every deleteMin returns the min(c, size) smallest
+    (key, id) pairs, with negative keys, keys near the ends of the 64-bit
+    range and many equal keys told apart by the id only."""
+    rng = np.random.default_rng(7000 + k)
+    for trial in range(50):
+        span = [3, 1000, 1 << 62][trial % 3]
+        ops = wide_trace(rng, k, int(rng.integers(5, 70)), span, next_id=trial * 100000)
+        msg = run_wide_against_brute_force(k, ops)
+        assert msg is None, "k=%d trial=%d %s" % (k, trial, msg)
+
+
+def test_wide_extreme_keys_and_drain():
+    """The most negative and most positive keys, and equal keys with ids in
+    descending insertion order, drain in (key, id) order."""
+    k = 4
+    pairs = [(-(1 << 63), 9), ((1 << 63) - 1, 1), (0, 5), (0, 2), (-1, 7), (1, 0),
+             ((1 << 63) - 1, 0), (-(1 << 63), 3), (0, 4)]
+    h = oracle.OracleHeap(k, wide=True)
+    h.insert(_wide(pairs))
+    got = []
+    while True:
+        out = _pairs(h.delete_min())
+        if not out:
+            break
+        got += out
+    assert got == sorted(pairs)
+
+
+def test_wide_layout_conversion_is_pinned(monkeypatch):
+    """Planted mistake in the wrapper's layout conversion (the key and id
+    words not swapped into the oracle's 128-bit order, so that entries order
+    by id first): the brute-force pin must catch it."""
+    monkeypatch.setattr(oracle, "wide_to_c", lambda a: np.ascontiguousarray(
+        np.asarray(a, dtype=np.uint64).reshape(-1, 2)))
+    monkeypatch.setattr(oracle, "wide_from_c", lambda a: np.ascontiguousarray(
+        np.asarray(a, dtype=np.uint64).reshape(-1, 2)))
+    rng = np.random.default_rng(5)
+    caught = False
+    for trial in range(20):
+        ops = wide_trace(rng, 4, 40, 1000, next_id=0)
+        if run_wide_against_brute_force(4, ops) is not None:
+            caught = True
+            break
+    assert caught
