@@ -9,11 +9,21 @@
  * and deleteMin run top-down under per-node locks with many operations in
  * flight (Sec. 3.3, TD-INS/TD-DEL heap).
  *
- * Entries.  An entry is an unsigned 64-bit integer and entries are ordered as
- * integers.  The all-ones value (UINT64_MAX) is reserved as the empty-slot
- * filler and must never be inserted.  (key, id) pairs are packed by the
- * caller, e.g. (uint64_t)key << 32 | id with id != 0xFFFFFFFF; equal entries
- * are indistinguishable, so results are unique even with repeated keys.
+ * Entries.  A heap set has one key type, fixed at creation:
+ *   GH_U32_ID  8-byte entries, an unsigned 64-bit integer ordered as an
+ *              integer; (key, id) pairs are packed by the caller as
+ *              (uint64_t)key << 32 | id;
+ *   GH_I64_ID  16-byte entries, two 64-bit words ordered lexicographically,
+ *              the word at the lower address first: a signed 64-bit key
+ *              stored biased (key XOR 2^63, so that it orders as unsigned),
+ *              then a 32-bit id and 32 zero bits (the second word is
+ *              id | 0 << 32 on a little-endian device).
+ * Every buffer of entries (d_keys, d_sorted, d_in, d_out, ...) holds entries
+ * of the set's width, and entry offsets and counts are in entries.  The
+ * all-ones entry of either width is reserved as the empty-slot filler and
+ * must never be inserted (an id of 0xFFFFFFFF never forms it with a real
+ * key).  Equal entries are indistinguishable, so results are unique even
+ * with repeated keys.
  *
  * Memory and streams.  Every pointer named d_* is a device pointer on the
  * current HIP device.  The caller owns all device buffers, including the
@@ -56,6 +66,10 @@ extern "C" {
 
 #define GH_OP_INSERT 0u
 #define GH_OP_DELETE_MIN 1u
+
+/* Key types (entry layouts) of a heap set; see "Entries" above. */
+#define GH_U32_ID 0   /* 8 bytes: u32 key above u32 id */
+#define GH_I64_ID 1   /* 16 bytes: biased i64 key, then u32 id and u32 zero */
 
 /* Opaque handle to a set of one or more heaps that share k, an arena and a
  * stream.  heap_create makes a set of one heap. */
@@ -160,38 +174,40 @@ typedef struct gh_tuning {
     uint32_t flags;
 } gh_tuning;
 
-/* Bytes of arena needed for nheaps heaps of node capacity k, heap i holding
- * up to max_keys[i] entries (max_keys == NULL: every heap holds up to
- * max_keys_each).  Returns 0 if k is unsupported, nheaps is 0 or above
- * 2^20, or a heap would need 2^30 - 1 nodes or more. */
-uint64_t heap_arena_bytes(uint32_t k, uint32_t nheaps, const uint64_t *max_keys,
+/* Bytes of arena needed for nheaps heaps of node capacity k and key type
+ * keytype, heap i holding up to max_keys[i] entries (max_keys == NULL: every
+ * heap holds up to max_keys_each).  Returns 0 if k or keytype is
+ * unsupported, nheaps is 0 or above 2^20, or a heap would need 2^30 - 1
+ * nodes or more. */
+uint64_t heap_arena_bytes(uint32_t k, int keytype, uint32_t nheaps, const uint64_t *max_keys,
                           uint64_t max_keys_each);
 
 /* Nonzero if the library has a kernel for node capacity k with workgroups
  * of `threads` threads.  Supported k: 32, 64, 128, 256, 512, 1024. */
 int heap_supported_shape(uint32_t k, uint32_t threads);
 
-/* Create one heap (Sec. 3.1) of node capacity k holding up to max_keys
- * entries in the caller's arena d_arena (arena_bytes >= heap_arena_bytes;
- * 256-byte aligned; borrowed, must outlive the handle).  Initializes the
- * arena on `stream`.  Errors: GH_EINVAL, GH_ENOMEM (arena too small),
- * GH_EDEVICE. */
-int heap_create(gh_heap_t *out, uint32_t k, uint64_t max_keys, void *d_arena,
+/* Create one heap (Sec. 3.1) of node capacity k and key type keytype
+ * (GH_U32_ID or GH_I64_ID) holding up to max_keys entries in the caller's
+ * arena d_arena (arena_bytes >= heap_arena_bytes; 256-byte aligned;
+ * borrowed, must outlive the handle).  Initializes the arena on `stream`.
+ * Errors: GH_EINVAL (also for an unknown keytype), GH_ENOMEM (arena too
+ * small), GH_EDEVICE. */
+int heap_create(gh_heap_t *out, uint32_t k, uint64_t max_keys, int keytype, void *d_arena,
                 uint64_t arena_bytes, void *stream);
 
-/* Create a set of nheaps (1..2^20) independent heaps of node capacity k;
- * heap i holds up to max_keys[i] entries.  Same arena and stream rules as
- * heap_create. */
-int heap_create_many(gh_heap_t *out, uint32_t k, uint32_t nheaps,
+/* Create a set of nheaps (1..2^20) independent heaps of node capacity k and
+ * key type keytype; heap i holds up to max_keys[i] entries.  Same arena and
+ * stream rules as heap_create. */
+int heap_create_many(gh_heap_t *out, uint32_t k, int keytype, uint32_t nheaps,
                      const uint64_t *max_keys, void *d_arena,
                      uint64_t arena_bytes, void *stream);
 
-/* Insert n entries from d_keys (device, n * 8 bytes) into heap 0 of the set:
+/* Insert n entries from d_keys (device, n entries of the set's width) into heap 0 of the set:
  * ceil(n / k) insert operations of up to k entries each, full chunks first
  * (Sec. 3.2.2 footnote), each run top-down (Sec. 3.3.2).  n = 0 is a no-op.
  * Errors: GH_EINVAL (null, reserved entry is not checked), GH_ENOMEM (the
  * heap would exceed max_keys; nothing is inserted). */
-int heap_insert(gh_heap_t h, const uint64_t *d_keys, uint64_t n);
+int heap_insert(gh_heap_t h, const void *d_keys, uint64_t n);
 
 /* Bulk build (Sec. 3.1: a sorted array already satisfies Properties 1-3):
  * heap i of the set, which must be empty, takes the n entries of d_sorted
@@ -202,14 +218,15 @@ int heap_insert(gh_heap_t h, const uint64_t *d_keys, uint64_t n);
  * Errors: GH_EINVAL (null, i out of range; from the device: d_sorted not
  * ascending), GH_ENOMEM (n > max_keys of heap i), GH_ESTATE (from the
  * device: heap i not empty).  Device errors are sticky. */
-int heap_build(gh_heap_t h, uint32_t i, const uint64_t *d_sorted, uint64_t n);
+int heap_build(gh_heap_t h, uint32_t i, const void *d_sorted, uint64_t n);
 
 /* Bytes of device workspace heap_filter needs for heap i of the set (0 for
  * a bad handle or index). */
 uint64_t heap_filter_workspace_bytes(gh_heap_t h, uint32_t i);
 
-/* Filter heap i of the set: every entry >= bound is removed (the garbage
- * collection of a branch-and-bound search, Sec. 5.6.2, which drops nodes
+/* Filter heap i of the set: every entry >= bound is removed (for GH_I64_ID
+ * sets every entry whose first word, the biased key, is >= bound; the garbage
+ * collection of a branch-and-bound search, Sec. 5.7.2, which drops nodes
  * whose bound can no longer beat the incumbent).  The entries kept are
  * gathered, sorted and laid out again as by heap_build (Sec. 3.1), all on
  * the set's stream; the number kept goes to *d_kept (device, may be NULL).
@@ -230,7 +247,7 @@ int heap_filter(gh_heap_t h, uint32_t i, uint64_t bound, void *d_work, uint64_t 
  * are fewer than k (the variable-count deleteMin that a heap sharded over
  * several devices needs to remove a globally selected share).
  * Errors: GH_EINVAL (null pointer, c = 0 or c > k). */
-int heap_delete_min(gh_heap_t h, uint64_t *d_out, uint32_t c, uint32_t *d_count);
+int heap_delete_min(gh_heap_t h, void *d_out, uint32_t c, uint32_t *d_count);
 
 /* Run nops operations (d_ops, device) on the set's heaps in one persistent
  * launch with many operations in flight (Sec. 3.3): each workgroup claims the
@@ -241,7 +258,7 @@ int heap_delete_min(gh_heap_t h, uint64_t *d_out, uint32_t c, uint32_t *d_count)
  * NULL) receives one gh_logrec per operation.  Capacity overruns are
  * detected on the device (sticky GH_ENOMEM).  nops < 2^24. */
 int heap_submit(gh_heap_t h, const gh_op *d_ops, uint32_t nops,
-                const uint64_t *d_in, uint64_t *d_out, uint32_t *d_counts,
+                const void *d_in, void *d_out, uint32_t *d_counts,
                 gh_logrec *d_log, const gh_tuning *tuning);
 
 /* Like heap_submit, but records the launch into a HIP graph once and returns
@@ -249,7 +266,7 @@ int heap_submit(gh_heap_t h, const gh_op *d_ops, uint32_t nops,
  * replays it on the set's stream with the same arguments, and
  * heap_graph_destroy frees it. */
 int heap_submit_graph(gh_heap_t h, const gh_op *d_ops, uint32_t nops,
-                      const uint64_t *d_in, uint64_t *d_out, uint32_t *d_counts,
+                      const void *d_in, void *d_out, uint32_t *d_counts,
                       gh_logrec *d_log, const gh_tuning *tuning, void **graph_out);
 int heap_graph_launch(gh_heap_t h, void *graph);
 int heap_graph_destroy(void *graph);
@@ -274,53 +291,75 @@ uint64_t heap_serve_workspace_bytes(uint32_t nheaps, uint32_t nreq, uint64_t max
  * workgroups (the slots, tuning->workgroups of them) run as in heap_submit.
  * d_recs (device, nreq records) receives one gh_reqrec per request.
  * d_work is a caller-owned device workspace of heap_serve_workspace_bytes.
- * The scheduler keeps 32 bytes per heap in LDS: nheaps * 32 + k * 40 must
- * stay below 64 KiB (1024 heaps at k = 256; 256 heaps at k = 1024).
+ * The scheduler keeps 32 bytes per heap in LDS: nheaps * 32 + threads * 8 +
+ * k * 5 * (entry bytes) + 1024 must not exceed 64 KiB (1024 heaps at
+ * k = 256 with 8-byte entries; 256 heaps at k = 1024).
  * Errors: GH_EINVAL (bad sizes, max_ops too small is reported as a sticky
  * GH_ENOMEM and the requests that did not fit are rejected). */
-int heap_serve(gh_heap_t h, const gh_op *d_reqs, uint32_t nreq, const uint64_t *d_in,
-               uint64_t *d_out, gh_reqrec *d_recs, void *d_work, uint64_t work_bytes,
+int heap_serve(gh_heap_t h, const gh_op *d_reqs, uint32_t nreq, const void *d_in,
+               void *d_out, gh_reqrec *d_recs, void *d_work, uint64_t work_bytes,
                uint64_t max_ops, const gh_tuning *tuning);
 
-/* Result of one knapsack instance solved by heap_knapsack (40 bytes).
- *   best      optimal value found
- *   explored  nodes taken from the heap and expanded (bound above best)
- *   created   nodes pushed into the heap
- *   popped    nodes taken from the heap (the search stops before popping
- *             those whose bound cannot beat best)
- *   ops       heap operations (inserts + deleteMins) the instance ran
- *   flags     bit 0: finished; bit 6: the node pool overflowed (best is
- *             then only a lower bound) */
+/* Result of one knapsack instance solved by heap_knapsack (56 bytes).
+ *   best        optimal value found
+ *   explored    nodes taken from the heap and expanded (bound above best)
+ *   created     nodes pushed into the heap
+ *   popped      nodes taken from the heap by the search (the search stops
+ *               before popping those whose bound cannot beat best)
+ *   gc_dropped  heap entries removed by garbage collections
+ *   ops         heap operations the instance ran (inserts, deleteMins and
+ *               the operations of its collections)
+ *   flags       bit 0: finished; bit 5: refused (more than 255 items, a
+ *               capacity of 2^28 or more, or values summing beyond what the
+ *               entry encodes: 2^18 for GH_U32_ID sets, 2^28 for GH_I64_ID);
+ *               bit 6: the node pool overflowed (best is then only a lower
+ *               bound)
+ *   gc_runs     garbage collections of the instance's heap */
 typedef struct gh_knapres {
     uint64_t best;
     uint64_t explored;
     uint64_t created;
     uint64_t popped;
+    uint64_t gc_dropped;
     uint32_t ops;
     uint32_t flags;
+    uint32_t gc_runs;
+    uint32_t reserved;
 } gh_knapres;
 
 /* Solve ninst 0/1 knapsack instances by best-first branch and bound, one
  * heap of the set per instance, all in one persistent launch (the
- * application of Sec. 5.6.2).  Instance i has d_n[i] <= 255 items starting
+ * application of Sec. 5.7.2).  Instance i has d_n[i] <= 255 items starting
  * at d_item_off[i] in d_w / d_v (uint32, sorted by value/weight
- * descending), capacity d_cap[i].  Heap entries carry the negated
- * fractional upper bound in fixed point (scale 2^16) above a 29-bit node id,
- * so deleteMin returns the k most promising nodes; a node is expanded only if
- * its bound exceeds the best value found, children are pushed only if their
- * bound does, and an instance stops (its heap emptied without reading the
- * rest) once the best bound left cannot beat the best value found.  d_pool (device, ninst * pool_per_inst uint64) holds the nodes;
- * d_scratch (device, ninst * 3 * k uint64) holds per-instance batches;
- * d_res (device, ninst gh_knapres).  Heap i must hold pool_per_inst entries
- * (pool_per_inst < 2^29).  The sum of an instance's values must stay below
- * 2^18 and its capacity below 2^28 (so bounds fit 35 bits).  Instances are
- * claimed by the workgroups in order; a submission may not overlap another
- * submission on the same set.  Errors: GH_EINVAL, GH_ENOMEM (a heap smaller
- * than pool_per_inst). */
+ * descending), capacity d_cap[i] < 2^28.  A heap entry orders the search
+ * nodes by their fractional upper bound in fixed point (scale 2^16), largest
+ * first: in a GH_I64_ID set the key is the negated bound as a signed 64-bit
+ * integer and the id the node's pool index; in a GH_U32_ID set the entry
+ * packs (2^35 - 1 - bound) above a 29-bit pool index.  So deleteMin returns
+ * the k most promising nodes; a node is expanded only if its bound exceeds
+ * the best value found, children are pushed only if their bound does, and an
+ * instance stops (its heap emptied without reading the rest) once the best
+ * bound left cannot beat the best value found.  Garbage collection (Sec.
+ * 5.7.2): with gc_min > 0, when an instance's heap holds gc_min entries or
+ * more and the best value has improved since its last collection, every
+ * entry whose bound cannot beat the best value leaves the heap (the kept
+ * entries are laid out as by heap_build); it runs only when nodes that are
+ * entirely dead hold at least a quarter of the heap and the heap's free
+ * node slots can stage the kept entries.  gc_min = 0 never collects.
+ * d_pool (device, ninst * pool_per_inst uint64) holds the nodes; d_scratch
+ * (device, ninst * 3 * k entries of the set's width) holds per-instance
+ * batches; d_res (device, ninst gh_knapres).  Heap i must hold
+ * pool_per_inst entries (pool_per_inst < 2^29 for GH_U32_ID sets, < 2^32
+ * for GH_I64_ID).  An instance beyond the limits above or the entry's value
+ * range is refused on the device (flags bit 5, sticky GH_EINVAL).
+ * Instances are claimed by the workgroups in order; a submission may not
+ * overlap another submission on the same set.  Errors: GH_EINVAL,
+ * GH_ENOMEM (a heap smaller than pool_per_inst). */
 int heap_knapsack(gh_heap_t h, uint32_t ninst, const uint32_t *d_item_off,
                   const uint32_t *d_n, const uint64_t *d_cap, const uint32_t *d_w,
                   const uint32_t *d_v, uint64_t *d_pool, uint64_t pool_per_inst,
-                  uint64_t *d_scratch, gh_knapres *d_res, const gh_tuning *tuning);
+                  void *d_scratch, gh_knapres *d_res, uint32_t gc_min,
+                  const gh_tuning *tuning);
 
 /* Counters of a heap_sssp run (64 bytes, device memory).
  *   popped      entries taken from the heap
@@ -370,8 +409,9 @@ typedef struct gh_sssptrace {
     uint64_t key_cap;
 } gh_sssptrace;
 
-/* Single-source shortest paths (the application of Sec. 5.6.1) with heap 0
- * of the set as a shared priority queue: entries are dist << 32 | vertex;
+/* Single-source shortest paths (the application of Sec. 5.7.1) with heap 0
+ * of a GH_U32_ID set (GH_EINVAL for other key types) as a shared priority
+ * queue: entries are dist << 32 | vertex;
  * every workgroup repeatedly takes the k nearest entries, skips those whose
  * vertex has since been reached by a shorter path, relaxes the out-edges of
  * the rest with an atomic minimum on the distance, and inserts an entry for
@@ -405,12 +445,13 @@ int heap_size(gh_heap_t h, uint32_t i, uint64_t *out_host);
 
 /* Synchronous: copy heap i's state to host memory for inspection:
  * meta_host[0..3] = {nodes in use m, partial-buffer size s, tickets served,
- * node capacity}; nodes_host (may be NULL) receives max_nodes * k entries,
+ * node capacity}; nodes_host (may be NULL) receives max_nodes * k entries
+ * of the set's width,
  * slot p-1 holding the node added p-th (bit-reversal order, Sec. 4.3);
  * pb_host (may be NULL) receives s entries (s < k: room for k - 1 entries
  * always suffices). */
 int heap_read_state(gh_heap_t h, uint32_t i, uint64_t *meta_host,
-                    uint64_t *nodes_host, uint64_t *pb_host);
+                    void *nodes_host, void *pb_host);
 
 /* Synchronous: wait for the stream, release the handle, and return the
  * sticky device error.  The arena may be freed afterwards. */

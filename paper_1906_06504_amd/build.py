@@ -1,8 +1,8 @@
 """Build libgheap.so (HIP, gfx950) in-tree with hipcc.
 
 Usage: python -m paper_1906_06504_amd.build   (or call build()).
-Each supported node capacity k gets its own object of gh_kernels.hip so the
-objects compile in parallel.
+Each supported node capacity k and entry width (8 or 16 bytes) gets its own
+objects of gh_kernels.hip and gh_serve.hip, so they compile in parallel.
 """
 from __future__ import annotations
 
@@ -41,10 +41,11 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     jobs = jobs or min(8, os.cpu_count() or 4)
     tasks = []
     for k in KS:
-        for name in ("gh_kernels", "gh_serve"):
-            obj = os.path.join(BUILD, "%s_k%d.o" % (name, k))
-            tasks.append([HIPCC] + COMMON + ["-DGH_K=%d" % k, "-c",
-                                             os.path.join(CSRC, name + ".hip"), "-o", obj])
+        for eb in (8, 16):
+            for name in ("gh_kernels", "gh_serve"):
+                obj = os.path.join(BUILD, "%s_k%d_e%d.o" % (name, k, eb))
+                tasks.append([HIPCC] + COMMON + ["-DGH_K=%d" % k, "-DGH_ENT_BYTES=%d" % eb, "-c",
+                                                 os.path.join(CSRC, name + ".hip"), "-o", obj])
     for name in ("gh_setup", "gh_filter"):
         tasks.append([HIPCC] + COMMON + ["-c", os.path.join(CSRC, name + ".hip"),
                                          "-o", os.path.join(BUILD, name + ".o")])

@@ -10,16 +10,53 @@ namespace gh {
 
 typedef uint64_t u64;
 typedef uint32_t u32;
+typedef u64 u64x2 __attribute__((ext_vector_type(2)));
 
-// LDS (workgroup-local) entries.  Buffers in LDS are always reached through
-// pointers of this type, so that every access is an LDS instruction: a
+// LDS (workgroup-local) data.  Buffers in LDS are always reached through
+// pointers of these types, so that every access is an LDS instruction: a
 // generic pointer would make the compiler emit flat accesses, each of which
 // also waits for every outstanding global memory operation.
-typedef __attribute__((address_space(3))) u64 lu64;
-typedef u64 u64x2 __attribute__((ext_vector_type(2)));
-typedef __attribute__((address_space(3))) u64x2 lu64x2;
+template <class X>
+using lds_t = __attribute__((address_space(3))) X;
+typedef lds_t<u64> lu64;
+typedef lds_t<u64x2> lu64x2;
 
-constexpr u64 ENT_MAX = ~0ull;  // reserved filler; never a live entry
+// ---------------------------------------------------------------------------
+// Entries.  Two widths, fixed per heap set and compiled separately:
+//  * u64: 8 bytes, ordered as an unsigned integer (a 32-bit key above a
+//    32-bit id);
+//  * e128: 16 bytes, two 64-bit words ordered lexicographically, the word at
+//    the lower address first (a biased signed 64-bit key, then a 32-bit id
+//    and 32 zero bits).
+// The all-ones value of either width is the reserved filler (never live).
+// ---------------------------------------------------------------------------
+typedef u64x2 e128;
+
+constexpr u64 ENT_MAX = ~0ull;  // the 8-byte filler
+
+__device__ __forceinline__ bool ent_lt(u64 a, u64 b) { return a < b; }
+__device__ __forceinline__ bool ent_le(u64 a, u64 b) { return a <= b; }
+__device__ __forceinline__ bool ent_lt(e128 a, e128 b) {
+  return a.x < b.x || (a.x == b.x && a.y < b.y);
+}
+__device__ __forceinline__ bool ent_le(e128 a, e128 b) {
+  return a.x < b.x || (a.x == b.x && a.y <= b.y);
+}
+template <class Ent>
+__device__ __forceinline__ Ent ent_max();
+template <>
+__device__ __forceinline__ u64 ent_max<u64>() {
+  return ~0ull;
+}
+template <>
+__device__ __forceinline__ e128 ent_max<e128>() {
+  e128 v;
+  v.x = ~0ull;
+  v.y = ~0ull;
+  return v;
+}
+__device__ __forceinline__ bool ent_is_max(u64 a) { return a == ~0ull; }
+__device__ __forceinline__ bool ent_is_max(e128 a) { return (a.x & a.y) == ~0ull; }
 
 // ---------------------------------------------------------------------------
 // Heap state in device memory
@@ -59,7 +96,8 @@ struct alignas(64) HeapDesc {
   u32 max_nodes;
   u32 k;
   u64 max_keys;       // capacity in entries (the served form admits by it)
-  u64 pad;
+  u32 ewords;         // 8-byte words per entry: 1 (u64) or 2 (e128)
+  u32 pad;
 };
 static_assert(sizeof(HeapDesc) == 64, "desc layout");
 
@@ -112,12 +150,18 @@ __device__ __forceinline__ u64 lw_ticket(u64 w) { return w >> 3; }
 // Global memory through global-address-space pointers: global instructions
 // count only against the vector memory counter, while flat ones (generic
 // pointers) also hold up every later LDS wait.
-typedef __attribute__((address_space(1))) u64 gu64;
-typedef __attribute__((address_space(1))) u32 gu32;
-__device__ __forceinline__ gu64* gptr(u64* p) { return (gu64*)p; }
-__device__ __forceinline__ const gu64* gptr(const u64* p) { return (const gu64*)p; }
-__device__ __forceinline__ gu32* gptr(u32* p) { return (gu32*)p; }
-__device__ __forceinline__ const gu32* gptr(const u32* p) { return (const gu32*)p; }
+template <class X>
+using glob_t = __attribute__((address_space(1))) X;
+typedef glob_t<u64> gu64;
+typedef glob_t<u32> gu32;
+template <class X>
+__device__ __forceinline__ glob_t<X>* gptr(X* p) {
+  return (glob_t<X>*)p;
+}
+template <class X>
+__device__ __forceinline__ const glob_t<X>* gptr(const X* p) {
+  return (const glob_t<X>*)p;
+}
 
 __device__ __forceinline__ u64 ld_relaxed(const u64* p) {
   return __hip_atomic_load(gptr(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -195,6 +239,15 @@ struct HeapRegion {
     v.y = (u32)(a >> 32);
     __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, CP_DEVICE);
   }
+  // one entry at byte offset off
+  __device__ __forceinline__ void load_ent(u32 off, u64& e) const { e = load8(off); }
+  __device__ __forceinline__ void load_ent(u32 off, e128& e) const {
+    const ulonglong2 v = load16(off);
+    e.x = v.x;
+    e.y = v.y;
+  }
+  __device__ __forceinline__ void store_ent(u32 off, u64 e) const { store8(off, e); }
+  __device__ __forceinline__ void store_ent(u32 off, e128 e) const { store16(off, e.x, e.y); }
 };
 
 __device__ __forceinline__ u64 now_ticks() { return wall_clock64(); }
@@ -257,76 +310,107 @@ __device__ __forceinline__ bool node_exists(u64 c, u64 m) {
   return (u64)bitrev_pos((u32)c) <= m;
 }
 
-template <int K>
-__device__ __forceinline__ u64* node_ptr(const HeapDesc& H, u32 c) {
-  return H.nodes + (u64)(bitrev_pos(c) - 1) * K;
+// Node c's slot and the partial buffer, as arrays of entries.
+template <int K, class Ent = u64>
+__device__ __forceinline__ Ent* node_ptr(const HeapDesc& H, u32 c) {
+  return reinterpret_cast<Ent*>(H.nodes) + (u64)(bitrev_pos(c) - 1) * K;
+}
+template <int K, class Ent>
+__device__ __forceinline__ Ent* slot_ptr(const HeapDesc& H, u64 pos) {
+  return reinterpret_cast<Ent*>(H.nodes) + (pos - 1) * (u64)K;
+}
+template <class Ent>
+__device__ __forceinline__ Ent* pb_ptr(const HeapDesc& H) {
+  return reinterpret_cast<Ent*>(H.pb);
 }
 __device__ __forceinline__ u64* lock_ptr(const HeapDesc& H, u32 c) {
   return H.locks + bitrev_pos(c);
 }
 
 // ---------------------------------------------------------------------------
-// Coalesced node transfers between heap memory and LDS (16 bytes a lane).
+// Coalesced node transfers between heap memory and LDS (16 bytes a lane:
+// two 8-byte entries or one 16-byte entry).
 // ---------------------------------------------------------------------------
-template <int K, int T>
-__device__ __forceinline__ void store_node(u64* g, const lu64* __restrict__ lds) {
-  const HeapRegion R(g, K * 8);
-  for (int i = threadIdx.x * 2; i < K; i += 2 * T) {
-    const u64x2 v = *reinterpret_cast<const lu64x2*>(lds + i);
-    R.store16(i * 8, v.x, v.y);
+template <int K, int T, class Ent = u64>
+__device__ __forceinline__ void store_node(Ent* g, const lds_t<Ent>* __restrict__ lds) {
+  constexpr int CH = K * (int)sizeof(Ent) / 16;   // 16-byte chunks per node
+  const HeapRegion R(reinterpret_cast<const u64*>(g), K * sizeof(Ent));
+  const lu64x2* l = reinterpret_cast<const lu64x2*>(lds);
+  for (int c = threadIdx.x; c < CH; c += T) {
+    const u64x2 v = l[c];
+    R.store16(c * 16, v.x, v.y);
   }
 }
 // A node's share per thread held in registers, so that several node loads
 // (and lock atomics) can be in flight before anything is written to LDS.
-template <int K, int T>
+template <int K, int T, class Ent = u64>
 struct NodeRegs {
-  static constexpr int C = (K / 2 + T - 1) / T;  // 16-byte chunks per thread
+  static constexpr int CH = K * (int)sizeof(Ent) / 16;   // 16-byte chunks per node
+  static constexpr int C = (CH + T - 1) / T;             // chunks per thread
   ulonglong2 v[C];
-  __device__ __forceinline__ void load(const u64* g) {
-    const HeapRegion R(g, K * 8);
+  __device__ __forceinline__ void load(const Ent* g) {
+    const HeapRegion R(reinterpret_cast<const u64*>(g), K * sizeof(Ent));
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      const int i = (threadIdx.x + c * T) * 2;
-      if (i < K) v[c] = R.load16(i * 8);
+      const int i = threadIdx.x + c * T;
+      if (i < CH) v[c] = R.load16(i * 16);
     }
   }
-  __device__ __forceinline__ void store(lu64* __restrict__ lds) const {
+  __device__ __forceinline__ void store(lds_t<Ent>* __restrict__ lds) const {
+    lu64x2* l = reinterpret_cast<lu64x2*>(lds);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      const int i = (threadIdx.x + c * T) * 2;
-      if (i < K) {
+      const int i = threadIdx.x + c * T;
+      if (i < CH) {
         u64x2 t;
         t.x = v[c].x;
         t.y = v[c].y;
-        *reinterpret_cast<lu64x2*>(lds + i) = t;
+        l[i] = t;
       }
     }
   }
 };
 
-// n entries, any n, 8 bytes a lane: caller memory to LDS and back
-template <int T>
-__device__ __forceinline__ void load_n(lu64* __restrict__ lds, const u64* __restrict__ g, u32 n) {
-  const gu64* gg = gptr(g);
+// n entries, any n, one entry a lane: caller memory to LDS and back
+template <int T, class Ent>
+__device__ __forceinline__ void load_n(lds_t<Ent>* __restrict__ lds, const Ent* __restrict__ g,
+                                       u32 n) {
+  const glob_t<Ent>* gg = gptr(g);
   for (u32 i = threadIdx.x; i < n; i += T) lds[i] = gg[i];
 }
-template <int T>
-__device__ __forceinline__ void store_n(u64* __restrict__ g, const lu64* __restrict__ lds, u32 n) {
-  gu64* gg = gptr(g);
+template <int T, class Ent>
+__device__ __forceinline__ void store_n(Ent* __restrict__ g, const lds_t<Ent>* __restrict__ lds,
+                                        u32 n) {
+  glob_t<Ent>* gg = gptr(g);
   for (u32 i = threadIdx.x; i < n; i += T) gg[i] = lds[i];
 }
 // n entries from LDS to heap memory (the partial buffer)
-template <int K, int T>
-__device__ __forceinline__ void store_heap_n(u64* g, const lu64* __restrict__ lds, u32 n) {
-  const HeapRegion R(g, K * 8);
-  for (u32 i = threadIdx.x; i < n; i += T) R.store8(i * 8, lds[i]);
+template <int K, int T, class Ent>
+__device__ __forceinline__ void store_heap_n(Ent* g, const lds_t<Ent>* __restrict__ lds, u32 n) {
+  const HeapRegion R(reinterpret_cast<const u64*>(g), K * sizeof(Ent));
+  for (u32 i = threadIdx.x; i < n; i += T) R.store_ent(i * sizeof(Ent), (Ent)lds[i]);
 }
 // n entries from heap memory (the partial buffer) to caller memory
-template <int K, int T>
-__device__ __forceinline__ void copy_heap_n(u64* __restrict__ dst, const u64* src, u32 n) {
-  const HeapRegion R(src, K * 8);
-  gu64* gd = gptr(dst);
-  for (u32 i = threadIdx.x; i < n; i += T) gd[i] = R.load8(i * 8);
+template <int K, int T, class Ent>
+__device__ __forceinline__ void copy_heap_n(Ent* __restrict__ dst, const Ent* src, u32 n) {
+  const HeapRegion R(reinterpret_cast<const u64*>(src), K * sizeof(Ent));
+  glob_t<Ent>* gd = gptr(dst);
+  for (u32 i = threadIdx.x; i < n; i += T) {
+    Ent e;
+    R.load_ent(i * sizeof(Ent), e);
+    gd[i] = e;
+  }
+}
+// n entries from heap memory (the partial buffer) to LDS
+template <int K, int T, class Ent>
+__device__ __forceinline__ void load_heap_n(lds_t<Ent>* __restrict__ lds, const Ent* src, u32 n,
+                                            u32 first = 0) {
+  const HeapRegion R(reinterpret_cast<const u64*>(src), K * sizeof(Ent));
+  for (u32 i = threadIdx.x; i < n; i += T) {
+    Ent e;
+    R.load_ent((first + i) * sizeof(Ent), e);
+    lds[i] = e;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -338,48 +422,49 @@ __device__ __forceinline__ void copy_heap_n(u64* __restrict__ dst, const u64* sr
 // is bound by dependent LDS latency, and the extra probes cost more than the
 // rounds they save.)
 // ---------------------------------------------------------------------------
-template <int E>
-__device__ __forceinline__ void merge_path(const lu64* A, int na, const lu64* B, int nb, int d,
-                                           u64 (&v)[E]) {
+template <int E, class Ent>
+__device__ __forceinline__ void merge_path(const lds_t<Ent>* A, int na, const lds_t<Ent>* B, int nb,
+                                           int d, Ent (&v)[E]) {
   const int total = na + nb;
   if (d >= total) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = ENT_MAX;
+    for (int e = 0; e < E; ++e) v[e] = ent_max<Ent>();
     return;
   }
   int lo = d > nb ? d - nb : 0;
   int hi = d < na ? d : na;
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
-    if (A[mid] <= B[d - 1 - mid]) lo = mid + 1;
+    if (ent_le((Ent)A[mid], (Ent)B[d - 1 - mid])) lo = mid + 1;
     else hi = mid;
   }
   int i = lo, j = d - lo;
-  u64 a = i < na ? A[i] : ENT_MAX;
-  u64 b = j < nb ? B[j] : ENT_MAX;
+  Ent a = i < na ? (Ent)A[i] : ent_max<Ent>();
+  Ent b = j < nb ? (Ent)B[j] : ent_max<Ent>();
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    if (a <= b) {
+    if (ent_le(a, b)) {
       v[e] = a;
       ++i;
-      a = i < na ? A[i] : ENT_MAX;
+      a = i < na ? (Ent)A[i] : ent_max<Ent>();
     } else {
       v[e] = b;
       ++j;
-      b = j < nb ? B[j] : ENT_MAX;
+      b = j < nb ? (Ent)B[j] : ent_max<Ent>();
     }
   }
 }
 
 // Destinations for merge output, written E entries a thread: LDS or caller
 // memory (Sink), or a region of heap memory (HeapSink, device scope).
+template <class Ent = u64>
 struct Sink {
-  lu64* p;
-  __device__ __forceinline__ void put1(int off, u64 x) const { p[off] = x; }
+  lds_t<Ent>* p;
+  __device__ __forceinline__ void put1(int off, Ent x) const { p[off] = x; }
   template <int E>
-  __device__ __forceinline__ void put_range(int off, const u64 (&v)[E]) const {
-    lu64* q = p + off;
-    if constexpr (E % 2 == 0) {
+  __device__ __forceinline__ void put_range(int off, const Ent (&v)[E]) const {
+    lds_t<Ent>* q = p + off;
+    if constexpr (sizeof(Ent) == 8 && E % 2 == 0) {
       if ((off & 1) == 0) {   // LDS buffers are 16-byte aligned
 #pragma unroll
         for (int e = 0; e < E; e += 2) {
@@ -395,13 +480,19 @@ struct Sink {
     for (int e = 0; e < E; ++e) q[e] = v[e];
   }
 };
+template <class Ent>
+__device__ __forceinline__ Sink<Ent> sink(lds_t<Ent>* p) {
+  return Sink<Ent>{p};
+}
+template <class Ent = u64>
 struct HeapSink {
   HeapRegion R;
-  __device__ __forceinline__ HeapSink(u64* p, u32 bytes) : R(p, bytes) {}
-  __device__ __forceinline__ void put1(int off, u64 x) const { R.store8(off * 8, x); }
+  __device__ __forceinline__ HeapSink(Ent* p, u32 bytes)
+      : R(reinterpret_cast<const u64*>(p), bytes) {}
+  __device__ __forceinline__ void put1(int off, Ent x) const { R.store_ent(off * sizeof(Ent), x); }
   template <int E>
-  __device__ __forceinline__ void put_range(int off, const u64 (&v)[E]) const {
-    if constexpr (E % 2 == 0) {
+  __device__ __forceinline__ void put_range(int off, const Ent (&v)[E]) const {
+    if constexpr (sizeof(Ent) == 8 && E % 2 == 0) {
       if ((off & 1) == 0) {
 #pragma unroll
         for (int e = 0; e < E; e += 2) R.store16((off + e) * 8, v[e], v[e + 1]);
@@ -409,7 +500,7 @@ struct HeapSink {
       }
     }
 #pragma unroll
-    for (int e = 0; e < E; ++e) R.store8((off + e) * 8, v[e]);
+    for (int e = 0; e < E; ++e) R.store_ent((off + e) * sizeof(Ent), v[e]);
   }
 };
 
@@ -418,12 +509,13 @@ struct HeapSink {
 // `split`; positions < split go to lo[p], the rest to hi[p - split].  Inputs
 // must be in LDS and must not overlap the outputs.  No barrier inside: the
 // caller synchronizes before reusing inputs or reading outputs.
-template <int E, int T, class SinkLo, class SinkHi>
-__device__ __forceinline__ void merge_split(const lu64* A, int na, const lu64* B, int nb, int split,
-                                            const SinkLo& lo, const SinkHi& hi) {
+template <int E, int T, class Ent, class SinkLo, class SinkHi>
+__device__ __forceinline__ void merge_split(const lds_t<Ent>* A, int na, const lds_t<Ent>* B,
+                                            int nb, int split, const SinkLo& lo,
+                                            const SinkHi& hi) {
   const int total = na + nb;
   for (int d = threadIdx.x * E; d < total; d += T * E) {
-    u64 v[E];
+    Ent v[E];
     merge_path<E>(A, na, B, nb, d, v);
     if (d + E <= total && d + E <= split) {
       lo.template put_range<E>(d, v);
@@ -446,20 +538,20 @@ __device__ __forceinline__ void merge_split(const lu64* A, int na, const lu64* B
 // Workgroup merge sort of up to K entries in LDS (sorts the insert batch,
 // Sec. 4.1): every thread sorts EPT entries in registers, then rounds of
 // merge path double the sorted run length.  A holds the n inputs; it is
-// padded with ENT_MAX to a power of two.  Returns the buffer (A or B) that
-// holds the sorted result.
+// padded with the filler to a power of two.  Returns the buffer (A or B)
+// that holds the sorted result.
 // ---------------------------------------------------------------------------
-template <int K, int T>
-__device__ lu64* block_sort(lu64* A, lu64* B, int n) {
+template <int K, int T, class Ent>
+__device__ lds_t<Ent>* block_sort(lds_t<Ent>* A, lds_t<Ent>* B, int n) {
   constexpr int EPT = (K >= T) ? (K / T) : 1;
   int np = EPT;
   while (np < n) np <<= 1;
-  for (int i = n + threadIdx.x; i < np; i += T) A[i] = ENT_MAX;
+  for (int i = n + threadIdx.x; i < np; i += T) A[i] = ent_max<Ent>();
   __syncthreads();
   const int active = np / EPT;
   const int tid = threadIdx.x;
   if (tid < active) {
-    u64 v[EPT];
+    Ent v[EPT];
 #pragma unroll
     for (int e = 0; e < EPT; ++e) v[e] = A[tid * EPT + e];
     // odd-even transposition sort of EPT registers
@@ -467,28 +559,29 @@ __device__ lu64* block_sort(lu64* A, lu64* B, int n) {
     for (int r = 0; r < EPT; ++r) {
 #pragma unroll
       for (int e = (r & 1); e + 1 < EPT; e += 2) {
-        u64 x = v[e], y = v[e + 1];
-        v[e] = x < y ? x : y;
-        v[e + 1] = x < y ? y : x;
+        Ent x = v[e], y = v[e + 1];
+        const bool o = ent_lt(x, y);
+        v[e] = o ? x : y;
+        v[e + 1] = o ? y : x;
       }
     }
 #pragma unroll
     for (int e = 0; e < EPT; ++e) A[tid * EPT + e] = v[e];
   }
   __syncthreads();
-  lu64* src = A;
-  lu64* dst = B;
+  lds_t<Ent>* src = A;
+  lds_t<Ent>* dst = B;
   for (int w = EPT; w < np; w <<= 1) {
     if (tid < active) {
       int d0 = tid * EPT;
       int base = d0 & ~(2 * w - 1);
-      u64 v[EPT];
+      Ent v[EPT];
       merge_path<EPT>(src + base, w, src + base + w, w, d0 - base, v);
 #pragma unroll
       for (int e = 0; e < EPT; ++e) dst[d0 + e] = v[e];
     }
     __syncthreads();
-    lu64* t = src;
+    lds_t<Ent>* t = src;
     src = dst;
     dst = t;
   }

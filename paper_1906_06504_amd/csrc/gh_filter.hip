@@ -1,5 +1,5 @@
 // gh_filter.hip -- filter of one quiescent heap: every entry >= a bound is
-// removed (the garbage collection of a branch-and-bound search, Sec. 5.6.2:
+// removed (the garbage collection of a branch-and-bound search, Sec. 5.7.2:
 // nodes whose bound can no longer beat the incumbent are dropped while the
 // search runs).  The entries kept are the heap's smallest; in a generalized
 // heap they are the whole of a top subtree of nodes plus a prefix of each
@@ -27,7 +27,8 @@ static_assert(sizeof(FilterHead) == 256, "filter head layout");
 
 // Entries below the bound in every node (a binary search: nodes are sorted)
 // and in the partial buffer; slot m of cnt is the pb.
-__global__ void k_filter_count(const HeapDesc* __restrict__ d, u64 bound, FilterHead* fh,
+template <class Ent>
+__global__ void k_filter_count(const HeapDesc* __restrict__ d, Ent bound, FilterHead* fh,
                                u64* __restrict__ cnt) {
   const HeapDesc H = *d;
   const u64 w = ld_relaxed(&H.meta->root);
@@ -38,11 +39,12 @@ __global__ void k_filter_count(const HeapDesc* __restrict__ d, u64 bound, Filter
   }
   const u64 stride = (u64)gridDim.x * blockDim.x;
   for (u64 p = (u64)blockIdx.x * blockDim.x + threadIdx.x; p <= m; p += stride) {
-    const u64* e = p < m ? H.nodes + p * H.k : H.pb;
+    const Ent* e = p < m ? reinterpret_cast<const Ent*>(H.nodes) + p * H.k
+                         : reinterpret_cast<const Ent*>(H.pb);
     u32 lo = 0, hi = p < m ? H.k : (u32)s;
     while (lo < hi) {
       const u32 mid = (lo + hi) >> 1;
-      if (e[mid] < bound) lo = mid + 1;
+      if (ent_lt(e[mid], bound)) lo = mid + 1;
       else hi = mid;
     }
     cnt[p] = lo;
@@ -89,14 +91,16 @@ __global__ __launch_bounds__(FT) void k_filter_scan(FilterHead* fh, u64* __restr
 }
 
 // Each node's (and the pb's) kept prefix to its offset in out.
+template <class Ent>
 __global__ __launch_bounds__(FT) void k_filter_gather(const HeapDesc* __restrict__ d,
                                                       const FilterHead* fh,
                                                       const u64* __restrict__ off,
-                                                      u64* __restrict__ out) {
+                                                      Ent* __restrict__ out) {
   const HeapDesc H = *d;
   const u64 m = fh->m;
   for (u64 p = blockIdx.x; p <= m; p += gridDim.x) {
-    const u64* e = p < m ? H.nodes + p * H.k : H.pb;
+    const Ent* e = p < m ? reinterpret_cast<const Ent*>(H.nodes) + p * H.k
+                         : reinterpret_cast<const Ent*>(H.pb);
     const u64 o = off[p];
     const u64 n = (p < m ? off[p + 1] : fh->kept) - o;
     for (u64 i = threadIdx.x; i < n; i += FT) out[o + i] = e[i];
@@ -104,16 +108,17 @@ __global__ __launch_bounds__(FT) void k_filter_gather(const HeapDesc* __restrict
 }
 
 // Sort every TILE-entry tile of buf in place.
-__global__ __launch_bounds__(FT) void k_filter_tiles(const FilterHead* fh, u64* __restrict__ buf) {
-  __shared__ __align__(16) u64 lds[2 * TILE];
-  lu64* const A = (lu64*)lds;
-  lu64* const B = A + TILE;
+template <class Ent>
+__global__ __launch_bounds__(FT) void k_filter_tiles(const FilterHead* fh, Ent* __restrict__ buf) {
+  __shared__ __align__(16) Ent lds[2 * TILE];
+  lds_t<Ent>* const A = (lds_t<Ent>*)lds;
+  lds_t<Ent>* const B = A + TILE;
   const u64 n = fh->kept;
   for (u64 t0 = (u64)blockIdx.x * TILE; t0 < n; t0 += (u64)gridDim.x * TILE) {
     const int c = n - t0 < (u64)TILE ? (int)(n - t0) : TILE;
     load_n<FT>(A, buf + t0, (u32)c);
     __syncthreads();
-    const lu64* r = block_sort<TILE, FT>(A, B, c);
+    const lds_t<Ent>* r = block_sort<TILE, FT, Ent>(A, B, c);
     store_n<FT>(buf + t0, r, (u32)c);
     __syncthreads();
   }
@@ -148,10 +153,11 @@ constexpr int SG = FT / 2;
 constexpr int NP = 16;
 static_assert(SG % 64 == 0 && NP >= 1 && NP <= SG, "split search lanes");
 
+template <class Ent>
 __global__ __launch_bounds__(FT) void k_filter_merge(const FilterHead* fh,
-                                                     const u64* __restrict__ src,
-                                                     u64* __restrict__ dst, u64 w) {
-  __shared__ __align__(16) u64 lds[2 * TILE];
+                                                     const Ent* __restrict__ src,
+                                                     Ent* __restrict__ dst, u64 w) {
+  __shared__ __align__(16) Ent lds[2 * TILE];
   __shared__ u64 rng[2][2];        // [search][lo, hi]
   __shared__ u32 hits[FT / 64];    // probes that hold, per wavefront
   const u64 n = fh->kept;
@@ -162,8 +168,8 @@ __global__ __launch_bounds__(FT) void k_filter_merge(const FilterHead* fh,
     const u64 ps = o / (2 * w) * (2 * w);
     const u64 na = n - ps < w ? n - ps : w;
     const u64 nb = n - ps > w ? (n - ps - w < w ? n - ps - w : w) : 0;
-    const u64* A = src + ps;
-    const u64* B = src + ps + na;
+    const Ent* A = src + ps;
+    const Ent* B = src + ps + na;
     const u64 d0 = o - ps;
     const u64 d1 = d0 + TILE < na + nb ? d0 + TILE : na + nb;
     const u64 dd = half ? d1 : d0;
@@ -176,7 +182,7 @@ __global__ __launch_bounds__(FT) void k_filter_merge(const FilterHead* fh,
         u64 lo = rng[half][0], hi = rng[half][1];
         while (lo < hi) {
           const u64 mid = (lo + hi) >> 1;
-          if (A[mid] <= B[dd - 1 - mid]) lo = mid + 1;
+          if (ent_le(A[mid], B[dd - 1 - mid])) lo = mid + 1;
           else hi = mid;
         }
         rng[half][0] = lo;
@@ -191,10 +197,10 @@ __global__ __launch_bounds__(FT) void k_filter_merge(const FilterHead* fh,
         if (g < NP) {
           if (span > (u64)NP) {
             const u64 i = lo + ((u64)(g + 1) * span) / (NP + 1);
-            t = A[i] <= B[dd - 1 - i];
+            t = ent_le(A[i], B[dd - 1 - i]);
           } else if ((u64)g < span) {
             const u64 i = lo + g;
-            t = A[i] <= B[dd - 1 - i];
+            t = ent_le(A[i], B[dd - 1 - i]);
           }
         }
         const u64 m = __ballot(t);
@@ -219,13 +225,13 @@ __global__ __launch_bounds__(FT) void k_filter_merge(const FilterHead* fh,
     __syncthreads();
     const u64 a0 = rng[0][0], b0 = d0 - a0, a1 = rng[1][0], b1 = d1 - a1;
     const int la = (int)(a1 - a0), lb = (int)(b1 - b0);
-    lu64* const LA = (lu64*)lds;
-    lu64* const LB = LA + la;
-    lu64* const LO = (lu64*)lds + TILE;
+    lds_t<Ent>* const LA = (lds_t<Ent>*)lds;
+    lds_t<Ent>* const LB = LA + la;
+    lds_t<Ent>* const LO = (lds_t<Ent>*)lds + TILE;
     load_n<FT>(LA, A + a0, (u32)la);
     load_n<FT>(LB, B + b0, (u32)lb);
     __syncthreads();
-    merge_split<TILE / FT, FT>(LA, la, LB, lb, la + lb, Sink{LO}, Sink{LO});
+    merge_split<TILE / FT, FT>(LA, la, LB, lb, la + lb, sink(LO), sink(LO));
     __syncthreads();
     store_n<FT>(dst + o, LO, (u32)(la + lb));
     __syncthreads();
@@ -235,17 +241,20 @@ __global__ __launch_bounds__(FT) void k_filter_merge(const FilterHead* fh,
 // The kept entries, ascending, become the heap again: nodes in addition
 // order, the rest the partial buffer; the lock words of every position that
 // held a node are cleared.
+template <class Ent>
 __global__ void k_filter_build(const HeapDesc* __restrict__ d, const FilterHead* fh,
-                               const u64* __restrict__ bufA, const u64* __restrict__ bufB) {
+                               const Ent* __restrict__ bufA, const Ent* __restrict__ bufB) {
   const HeapDesc H = *d;
   const u64 n = fh->kept;
-  const u64* __restrict__ sorted = (merge_passes(n) & 1u) ? bufB : bufA;
+  const Ent* __restrict__ sorted = (merge_passes(n) & 1u) ? bufB : bufA;
+  Ent* nodes = reinterpret_cast<Ent*>(H.nodes);
+  Ent* pb = reinterpret_cast<Ent*>(H.pb);
   const u64 body = n / H.k * H.k;
   const u64 stride = (u64)gridDim.x * blockDim.x;
   const u64 i0 = (u64)blockIdx.x * blockDim.x + threadIdx.x;
   for (u64 i = i0; i < n; i += stride) {
-    if (i < body) H.nodes[i] = sorted[i];
-    else H.pb[i - body] = sorted[i];
+    if (i < body) nodes[i] = sorted[i];
+    else pb[i - body] = sorted[i];
   }
   for (u64 p = i0 + 1; p <= fh->m; p += stride) H.locks[p] = 0;
 }
@@ -260,48 +269,49 @@ __global__ void k_filter_root(const HeapDesc* __restrict__ d, const FilterHead* 
   }
 }
 
-u64 filter_workspace_bytes(u64 max_nodes, u32 k) {
+u64 filter_workspace_bytes(u64 max_nodes, u32 k, u32 ebytes) {
   const u64 cnt = (max_nodes + 1) * 8;
   const u64 cap = (max_nodes * k + k + TILE - 1) / TILE * TILE;
-  return sizeof(FilterHead) + (cnt + 255) / 256 * 256 + 2 * cap * 8;
+  return sizeof(FilterHead) + (cnt + 255) / 256 * 256 + 2 * cap * ebytes;
 }
 
-hipError_t launch_filter(const HeapDesc* d, u64 max_nodes, u32 k, u64 bound, void* work,
-                         u64* kept_out, hipStream_t st) {
+template <class Ent>
+static hipError_t launch_filter_t(const HeapDesc* d, u64 max_nodes, u32 k, Ent bound, void* work,
+                                  u64* kept_out, hipStream_t st) {
   unsigned char* base = static_cast<unsigned char*>(work);
   FilterHead* fh = reinterpret_cast<FilterHead*>(base);
   u64* cnt = reinterpret_cast<u64*>(base + sizeof(FilterHead));
   const u64 cap = (max_nodes * k + k + TILE - 1) / TILE * TILE;
-  u64* bufA = reinterpret_cast<u64*>(base + sizeof(FilterHead) +
+  Ent* bufA = reinterpret_cast<Ent*>(base + sizeof(FilterHead) +
                                      ((max_nodes + 1) * 8 + 255) / 256 * 256);
-  u64* bufB = bufA + cap;
+  Ent* bufB = bufA + cap;
   auto grid = [](u64 items, u64 per, u64 most) {
     u64 g = (items + per - 1) / per;
     if (g > most) g = most;
     return (u32)(g == 0 ? 1 : g);
   };
-  hipLaunchKernelGGL(k_filter_count, dim3(grid(max_nodes + 1, FT, 1024)), dim3(FT), 0, st, d,
+  hipLaunchKernelGGL(k_filter_count<Ent>, dim3(grid(max_nodes + 1, FT, 1024)), dim3(FT), 0, st, d,
                      bound, fh, cnt);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_filter_scan, dim3(1), dim3(FT), 0, st, fh, cnt);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_filter_gather, dim3(grid(max_nodes + 1, 1, 4096)), dim3(FT), 0, st, d, fh,
-                     cnt, bufA);
+  hipLaunchKernelGGL(k_filter_gather<Ent>, dim3(grid(max_nodes + 1, 1, 4096)), dim3(FT), 0, st, d,
+                     fh, cnt, bufA);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_filter_tiles, dim3(grid(cap, TILE, 4096)), dim3(FT), 0, st, fh, bufA);
+  hipLaunchKernelGGL(k_filter_tiles<Ent>, dim3(grid(cap, TILE, 4096)), dim3(FT), 0, st, fh, bufA);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  u64* src = bufA;
-  u64* dst = bufB;
+  Ent* src = bufA;
+  Ent* dst = bufB;
   for (u64 w = TILE; w < cap; w *= 2) {
-    hipLaunchKernelGGL(k_filter_merge, dim3(grid(cap, TILE, 4096)), dim3(FT), 0, st, fh, src, dst,
-                       w);
+    hipLaunchKernelGGL(k_filter_merge<Ent>, dim3(grid(cap, TILE, 4096)), dim3(FT), 0, st, fh, src,
+                       dst, w);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    u64* t = src;
+    Ent* t = src;
     src = dst;
     dst = t;
   }
-  hipLaunchKernelGGL(k_filter_build, dim3(grid(cap, FT, 2048)), dim3(FT), 0, st, d, fh, bufA,
+  hipLaunchKernelGGL(k_filter_build<Ent>, dim3(grid(cap, FT, 2048)), dim3(FT), 0, st, d, fh, bufA,
                      bufB);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_filter_root, dim3(1), dim3(64), 0, st, d, fh);
@@ -311,6 +321,19 @@ hipError_t launch_filter(const HeapDesc* d, u64 max_nodes, u32 k, u64 bound, voi
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// 16-byte entries: an entry is removed when its key word is >= bound (the
+// entry is >= the entry (bound, 0)).
+hipError_t launch_filter(const HeapDesc* d, u64 max_nodes, u32 k, u32 ebytes, u64 bound,
+                         void* work, u64* kept_out, hipStream_t st) {
+  if (ebytes == 16) {
+    e128 b;
+    b.x = bound;
+    b.y = 0;
+    return launch_filter_t<e128>(d, max_nodes, k, b, work, kept_out, st);
+  }
+  return launch_filter_t<u64>(d, max_nodes, k, bound, work, kept_out, st);
 }
 
 }  // namespace gh

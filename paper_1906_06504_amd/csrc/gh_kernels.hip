@@ -1,32 +1,79 @@
-// gh_kernels.hip -- kernels of the generalized heap for one node capacity:
-// the persistent operation loop with whole-root deleteMins, and the
-// knapsack and SSSP drivers.  Compiled once per supported k with
-// -DGH_K=<k>; each object exports gh::launch_ops_k<k>(),
-// gh::launch_knap_k<k>() and gh::launch_sssp_k<k>().
+// gh_kernels.hip -- kernels of the generalized heap for one node capacity
+// and entry width: the persistent operation loop with whole-root deleteMins,
+// the knapsack driver, and (8-byte entries) the SSSP driver.  Compiled once
+// per supported k and width with -DGH_K=<k> -DGH_ENT_BYTES=<8|16>; each
+// object exports gh::launch_ops_k<k, Ent>() and gh::launch_knap_k<k, Ent>(),
+// the 8-byte objects also gh::launch_sssp_k<k>().
 #include "gh_kops.h"
 
 #ifndef GH_K
 #error "compile with -DGH_K=<node capacity>"
+#endif
+#if GH_ENT_BYTES == 8
+#define GH_ENT u64
+#elif GH_ENT_BYTES == 16
+#define GH_ENT e128
+#else
+#error "compile with -DGH_ENT_BYTES=8 or 16"
 #endif
 
 namespace gh {
 
 // ---------------------------------------------------------------------------
 // 0/1 knapsack by best-first branch and bound on the heap (the application
-// of Sec. 5.6.2).  One heap per instance; a workgroup claims an instance,
+// of Sec. 5.7.2).  One heap per instance; a workgroup claims an instance,
 // pushes the root node, and repeats: deleteMin(K) the most promising nodes,
 // expand those whose bound still exceeds the best value found, insert their
 // promising children.  Items are sorted by value/weight descending.
 //   bound(level, V, W): V plus the items from `level` on while they fit plus
 //   the fitting fraction of the next one, in fixed point with scale 2^16
 //   (floored, so never below the true bound);
-//   entry = (2^35 - 1 - bound) << 29 | node id  (deleteMin = largest bound);
-//   node  = level << 56 | V << 28 | W.
+//   node  = level << 56 | V << 28 | W  (the node pool, 8 bytes a node);
+//   entry: the smallest entry is the node with the largest bound (KnapKey).
 // ---------------------------------------------------------------------------
-constexpr u64 KN_KEYMAX = (1ull << 35) - 1;
-constexpr u32 KN_IDBITS = 29;
-constexpr u64 KN_IDMASK = (1ull << KN_IDBITS) - 1;
 constexpr u32 KN_MAXN = 255;
+constexpr u64 KN_VW_LIMIT = 1ull << 28;   // V and W fields of a pool node
+
+// Heap entry of a search node with fixed-point bound b and pool index id.
+template <class Ent>
+struct KnapKey;
+// 8 bytes: (2^35 - 1 - b) << 29 | id; b needs the instance's values to sum
+// below 2^18 (b < 2^34), ids stay below 2^29.
+template <>
+struct KnapKey<u64> {
+  static constexpr u64 KEYMAX = (1ull << 35) - 1;
+  static constexpr u32 IDBITS = 29;
+  static constexpr u64 VSUM_LIMIT = 1ull << 18;
+  static constexpr u64 ID_LIMIT = 1ull << IDBITS;
+  __device__ static u64 make(u64 b, u64 id) { return ((KEYMAX - b) << IDBITS) | id; }
+  __device__ static u64 bound(u64 e) { return KEYMAX - (e >> IDBITS); }
+  __device__ static u64 id(u64 e) { return e & (ID_LIMIT - 1); }
+  // the smallest entry whose bound is <= best_fp
+  __device__ static u64 cut(u64 best_fp) { return (KEYMAX - best_fp) << IDBITS; }
+};
+// 16 bytes: the key word is -b as a signed 64-bit fixed-point number, biased
+// by 2^63 so that it orders as unsigned; the id word holds the pool index.
+// Values are limited only by the pool node's 28-bit fields.
+template <>
+struct KnapKey<e128> {
+  static constexpr u64 SIGN = 1ull << 63;
+  static constexpr u64 VSUM_LIMIT = KN_VW_LIMIT;
+  static constexpr u64 ID_LIMIT = 1ull << 32;
+  __device__ static e128 make(u64 b, u64 id) {
+    e128 e;
+    e.x = (0ull - b) ^ SIGN;
+    e.y = id;
+    return e;
+  }
+  __device__ static u64 bound(e128 e) { return 0ull - (e.x ^ SIGN); }
+  __device__ static u64 id(e128 e) { return e.y & 0xFFFFFFFFull; }
+  __device__ static e128 cut(u64 best_fp) {
+    e128 e;
+    e.x = (0ull - best_fp) ^ SIGN;
+    e.y = 0;
+    return e;
+  }
+};
 
 struct KnapShared {
   u32 w[KN_MAXN + 1];
@@ -38,12 +85,20 @@ struct KnapShared {
   u64 explored;
   u64 created;
   u64 pool_next;
-  u64 popped_total;     // entries taken from the heap
+  u64 popped_total;     // entries taken from the heap by the search
+  u64 hsize;            // entries in the heap
+  u64 gc_best;          // incumbent at the last garbage collection
+  u64 gc_dropped;       // entries the collections removed
+  u64 gm, gs;           // heap shape seen by a collection
+  u32 gdead;            // nodes found dead by a collection
+  u32 gkept;            // entries of a drained batch below the cut
+  u32 gc_runs;
   u32 n;
   u32 cnt;              // children produced in this round
   u32 popped;
   u32 inst;
   u32 overflow;
+  u32 refused;
 };
 
 __device__ __forceinline__ u64 kn_bound(const KnapShared& ks, u32 level, u64 V, u64 W) {
@@ -63,17 +118,90 @@ __device__ __forceinline__ u64 kn_bound(const KnapShared& ks, u32 level, u64 V, 
   return b;
 }
 
-template <int K, int T>
+// Garbage collection of the instance's own heap (Sec. 5.7.2: nodes whose
+// bound cannot beat the incumbent leave the heap while the search runs).
+// The heap belongs to this workgroup alone.  Every entry below the cut is
+// kept: the collection takes the heap's batches in order with deleteMin
+// (ascending, so the kept entries come first) into the free node slots
+// after the heap until a batch reaches the cut, empties the heap, and lays
+// the kept entries out again as a bulk build (Sec. 3.1), which is the
+// layout a filter of the same heap at the same cut gives.  It runs only when
+// nodes whose first entry is already dead (their subtrees are all dead)
+// hold at least a quarter of the heap, and when the staged batches fit the
+// heap's free slots.  Returns false after a failed heap operation.
+template <int K, int T, class Ent>
+__device__ bool knap_collect(const HeapDesc& H, u64& ticket, u32& ops, lds_t<Ent>* L,
+                             OpShared& sh, KnapShared& ks, Ctl* ctl) {
+  typedef KnapKey<Ent> KK;
+  const int tid = threadIdx.x;
+  const Ent cut = KK::cut(ks.best << 16);
+  if (tid == 0) {
+    const u64 w = ld_relaxed(&H.meta->root);   // this workgroup's own last release
+    ks.gm = rw_m(w);
+    ks.gs = rw_s(w);
+    ks.gdead = 0;
+    ks.gc_best = ks.best;
+  }
+  __syncthreads();
+  const u64 m = ks.gm;
+  for (u64 p = tid + 1; p <= m; p += T) {
+    Ent e;
+    const HeapRegion R(reinterpret_cast<const u64*>(slot_ptr<K, Ent>(H, p)), sizeof(Ent));
+    R.load_ent(0, e);
+    if (!ent_lt(e, cut)) atomicAdd(&ks.gdead, 1u);
+  }
+  __syncthreads();
+  const u64 total = m * K + ks.gs;
+  const u64 dead_nodes = ks.gdead;
+  // the drain writes at most ceil(kept / K) + 1 batches, kept <= total - dead_nodes * K
+  if (dead_nodes == 0 || 4 * dead_nodes * K < total || m + (m - dead_nodes) + 2 > H.max_nodes)
+    return true;
+  Ent* stage = slot_ptr<K, Ent>(H, m + 1);
+  u64 staged = 0;
+  for (;;) {
+    const OpResult r = op_delete<K, T, Ent>(H, ticket++, stage + staged, (u32)K, L, sh, ctl);
+    ++ops;
+    if (!r.ok) return false;
+    if (tid == 0) ks.gkept = 0;
+    __syncthreads();
+    if (r.count == 0) break;
+    u32 mine = 0;
+    for (u32 e = tid; e < r.count; e += T)
+      if (ent_lt(gptr(stage + staged)[e], cut)) ++mine;
+    if (mine) atomicAdd(&ks.gkept, mine);
+    __syncthreads();
+    const u32 kept = ks.gkept;
+    staged += kept;
+    if (kept < r.count) break;
+  }
+  const OpResult rd = op_discard(H, ticket++, sh, ctl);
+  ++ops;
+  if (!rd.ok) return false;
+  const OpResult rb = op_build_from<K, T, Ent>(H, ticket++, stage, staged, sh, ctl);
+  ++ops;
+  if (!rb.ok) return false;
+  if (tid == 0) {
+    ks.gc_dropped += ks.hsize - staged;
+    ks.hsize = staged;
+    ++ks.gc_runs;
+  }
+  __syncthreads();
+  return true;
+}
+
+template <int K, int T, class Ent>
 __global__ __launch_bounds__(T) void k_knap(const HeapDesc* __restrict__ descs, u32 ninst,
                                             const u32* __restrict__ item_off,
                                             const u32* __restrict__ nitems,
                                             const u64* __restrict__ caps,
                                             const u32* __restrict__ wts,
                                             const u32* __restrict__ vals, u64* __restrict__ pool,
-                                            u64 pool_per_inst, u64* __restrict__ scratch,
-                                            gh_knapres* __restrict__ res, Ctl* __restrict__ ctl) {
-  __shared__ __align__(16) u64 lds[5 * K];
-  lu64* const L = (lu64*)lds;
+                                            u64 pool_per_inst, Ent* __restrict__ scratch,
+                                            gh_knapres* __restrict__ res, u32 gc_min,
+                                            Ctl* __restrict__ ctl) {
+  typedef KnapKey<Ent> KK;
+  __shared__ __align__(16) Ent lds[5 * K];
+  lds_t<Ent>* const L = (lds_t<Ent>*)lds;
   __shared__ OpShared sh;
   __shared__ KnapShared ks;
   const int tid = threadIdx.x;
@@ -89,31 +217,54 @@ __global__ __launch_bounds__(T) void k_knap(const HeapDesc* __restrict__ descs, 
     const HeapDesc H = descs[inst];
     u64 ticket = *gptr(&H.meta->base);
     u64* ipool = pool + (u64)inst * pool_per_inst;
-    u64* out = scratch + (u64)inst * 3 * K;   // K popped entries, then 2K children
-    u64* kids = out + K;
-    // stage the instance
-    const u32 n = nitems[inst] < KN_MAXN ? nitems[inst] : KN_MAXN;
+    Ent* out = scratch + (u64)inst * 3 * K;   // K popped entries, then 2K children
+    Ent* kids = out + K;
+    const u64 id_limit = pool_per_inst < KK::ID_LIMIT ? pool_per_inst : KK::ID_LIMIT;
+    // stage the instance; one the entry cannot encode is refused
+    const u32 n = nitems[inst];
     const u32 base = item_off[inst];
-    for (u32 j = tid; j < n; j += T) {
-      ks.w[j] = wts[base + j];
-      ks.v[j] = vals[base + j];
-    }
     if (tid == 0) {
+      ks.refused = n > KN_MAXN || caps[inst] >= KN_VW_LIMIT ? 1u : 0u;
       ks.n = n;
+    }
+    __syncthreads();
+    if (!ks.refused)
+      for (u32 j = tid; j < n; j += T) {
+        ks.w[j] = wts[base + j];
+        ks.v[j] = vals[base + j];
+      }
+    if (tid == 0) {
       ks.cap = caps[inst];
       ks.explored = 0;
       ks.created = 0;
       ks.popped_total = 0;
       ks.overflow = 0;
+      ks.hsize = 0;
+      ks.gc_dropped = 0;
+      ks.gc_runs = 0;
     }
     __syncthreads();
-    if (tid == 0) {
+    if (tid == 0 && !ks.refused) {
       ks.pw[0] = 0;
       ks.pv[0] = 0;
       for (u32 j = 0; j < n; ++j) {
         ks.pw[j + 1] = ks.pw[j] + ks.w[j];
         ks.pv[j + 1] = ks.pv[j] + ks.v[j];
       }
+      if (ks.pv[n] >= KK::VSUM_LIMIT) ks.refused = 1;
+    }
+    __syncthreads();
+    if (ks.refused) {
+      if (tid == 0) {
+        note_error(ctl, ERR_INVAL);
+        gh_knapres o{};
+        o.flags = 0x20u;
+        res[inst] = o;
+      }
+      __syncthreads();
+      continue;
+    }
+    if (tid == 0) {
       // greedy incumbent: items in ratio order while they fit
       u64 W = 0, V = 0;
       for (u32 j = 0; j < n; ++j)
@@ -122,36 +273,49 @@ __global__ __launch_bounds__(T) void k_knap(const HeapDesc* __restrict__ descs, 
           V += ks.v[j];
         }
       ks.best = V;
+      ks.gc_best = V;
       // the root node
       const u64 b = kn_bound(ks, 0, 0, 0);
       ipool[0] = 0;
-      kids[0] = ((KN_KEYMAX - b) << KN_IDBITS) | 0ull;
+      kids[0] = KK::make(b, 0);
       ks.pool_next = 1;
       ks.cnt = (b > (V << 16)) ? 1u : 0u;
       ks.created = ks.cnt;
     }
     __syncthreads();
     u32 ops = 0;
+    bool ok = true;
     for (;;) {
       // push this round's children (at most 2K: two inserts)
       const u32 c = ks.cnt;
       for (u32 j = 0; j < c; j += K) {
         const u32 nn = c - j < (u32)K ? c - j : (u32)K;
-        OpResult r = op_insert<K, T>(H, ticket++, kids + j, nn, L, sh, ctl);
+        OpResult r = op_insert<K, T, Ent>(H, ticket++, kids + j, nn, L, sh, ctl);
         ++ops;
-        if (!r.ok) break;
+        if (tid == 0 && !(r.flags & F_REJECT)) ks.hsize += nn;
+        if (!r.ok) {
+          ok = false;
+          break;
+        }
         __syncthreads();
       }
+      if (!ok) break;
+      if (gc_min != 0 && ks.hsize >= gc_min && ks.gc_best != ks.best &&
+          !knap_collect<K, T, Ent>(H, ticket, ops, L, sh, ks, ctl))
+        break;
       // take the most promising nodes
-      OpResult r = op_delete<K, T>(H, ticket++, out, (u32)K, L, sh, ctl);
+      OpResult r = op_delete<K, T, Ent>(H, ticket++, out, (u32)K, L, sh, ctl);
       ++ops;
-      if (tid == 0) ks.popped_total += r.count;
+      if (tid == 0) {
+        ks.popped_total += r.count;
+        ks.hsize -= r.count;
+      }
       __syncthreads();
       if (!r.ok || r.count == 0) break;
       // best-first stopping rule: the batch's first entry has the largest
       // bound left in the heap; if it cannot beat the incumbent, nothing
       // left can, and the rest of the heap is dropped unread
-      if (KN_KEYMAX - (out[0] >> KN_IDBITS) <= (ks.best << 16)) {
+      if (KK::bound(out[0]) <= (ks.best << 16)) {
         op_discard(H, ticket++, sh, ctl);
         ++ops;
         break;
@@ -164,15 +328,15 @@ __global__ __launch_bounds__(T) void k_knap(const HeapDesc* __restrict__ descs, 
       // expand
       const u32 popped = r.count;
       for (u32 e = tid; e < popped; e += T) {
-        const u64 ent = out[e];
-        const u64 id = ent & KN_IDMASK;
-        const u64 b = KN_KEYMAX - (ent >> KN_IDBITS);
+        const Ent ent = out[e];
+        const u64 id = KK::id(ent);
+        const u64 b = KK::bound(ent);
         if (b <= (__hip_atomic_load(&ks.best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) << 16))
           continue;   // cannot beat the incumbent any more
         const u64 node = ipool[id];
         const u32 level = (u32)(node >> 56);
-        const u64 V = (node >> 28) & ((1ull << 28) - 1);
-        const u64 W = node & ((1ull << 28) - 1);
+        const u64 V = (node >> 28) & (KN_VW_LIMIT - 1);
+        const u64 W = node & (KN_VW_LIMIT - 1);
         atomicAdd(reinterpret_cast<unsigned long long*>(&ks.explored), 1ull);
         if (level >= ks.n) {
           atomicMax(reinterpret_cast<unsigned long long*>(&ks.best), (unsigned long long)V);
@@ -196,12 +360,12 @@ __global__ __launch_bounds__(T) void k_knap(const HeapDesc* __restrict__ descs, 
           if (cb[q] <= bestnow) continue;
           const u32 slot = atomicAdd(&ks.cnt, 1u);
           const u64 nid = ks.pool_next + slot;
-          if (nid >= pool_per_inst || nid > KN_IDMASK) {
+          if (nid >= id_limit) {
             atomicOr(&ks.overflow, 1u);
             continue;
           }
           ipool[nid] = cand[q];
-          kids[slot] = ((KN_KEYMAX - cb[q]) << KN_IDBITS) | nid;
+          kids[slot] = KK::make(cb[q], nid);
         }
       }
       __syncthreads();
@@ -209,7 +373,7 @@ __global__ __launch_bounds__(T) void k_knap(const HeapDesc* __restrict__ descs, 
         u32 c2 = ks.cnt;
         if (ks.overflow) {
           // children beyond the pool were dropped; keep the ones written
-          const u64 room = pool_per_inst > ks.pool_next ? pool_per_inst - ks.pool_next : 0;
+          const u64 room = id_limit > ks.pool_next ? id_limit - ks.pool_next : 0;
           if ((u64)c2 > room) c2 = (u32)room;
           ks.cnt = c2;
         }
@@ -225,29 +389,32 @@ __global__ __launch_bounds__(T) void k_knap(const HeapDesc* __restrict__ descs, 
       o.explored = ks.explored;
       o.created = ks.created;
       o.popped = ks.popped_total;
+      o.gc_dropped = ks.gc_dropped;
       o.ops = ops;
-      o.flags = 1u | (ks.overflow ? 0x40u : 0u);
+      o.flags = (ok ? 1u : 0u) | (ks.overflow ? 0x40u : 0u);
+      o.gc_runs = ks.gc_runs;
+      o.reserved = 0;
       res[inst] = o;
     }
     __syncthreads();
   }
 }
 
-template <int K, int T>
+template <int K, int T, class Ent>
 static hipError_t launch_knap_t(const KnapArgs& a) {
-  hipLaunchKernelGGL((k_knap<K, T>), dim3(a.workgroups), dim3(T), 0, a.stream, a.descs, a.ninst,
-                     a.item_off, a.n, a.cap, a.w, a.v, a.pool, a.pool_per_inst, a.scratch, a.res,
-                     a.ctl);
+  hipLaunchKernelGGL((k_knap<K, T, Ent>), dim3(a.workgroups), dim3(T), 0, a.stream, a.descs,
+                     a.ninst, a.item_off, a.n, a.cap, a.w, a.v, a.pool, a.pool_per_inst,
+                     reinterpret_cast<Ent*>(a.scratch), a.res, a.gc_min, a.ctl);
   return hipGetLastError();
 }
 
 template <>
-hipError_t launch_knap_k<GH_K>(const KnapArgs& a) {
+hipError_t launch_knap_k<GH_K, GH_ENT>(const KnapArgs& a) {
   constexpr int K = GH_K;
   switch (a.threads) {
-#define GH_CASE(TT)                                                \
-  case TT:                                                         \
-    if constexpr (shape_ok(K, TT)) return launch_knap_t<K, TT>(a); \
+#define GH_CASE(TT)                                                        \
+  case TT:                                                                 \
+    if constexpr (shape_ok(K, TT)) return launch_knap_t<K, TT, GH_ENT>(a); \
     break;
     GH_CASE(64)
     GH_CASE(128)
@@ -261,9 +428,10 @@ hipError_t launch_knap_k<GH_K>(const KnapArgs& a) {
   return hipErrorInvalidValue;
 }
 
+#if GH_ENT_BYTES == 8
 // ---------------------------------------------------------------------------
 // Single-source shortest paths with the heap as a shared priority queue (the
-// application of Sec. 5.6.1), lazy deletion: entries are dist << 32 | vertex;
+// application of Sec. 5.7.1), lazy deletion: entries are dist << 32 | vertex;
 // every workgroup takes the K nearest, skips entries whose vertex was since
 // reached by a shorter path, relaxes out-edges with an atomic minimum, and
 // inserts one entry per strict improvement.  Tickets are taken dynamically.
@@ -346,7 +514,7 @@ __global__ __launch_bounds__(T) void k_sssp(const HeapDesc* __restrict__ descs, 
     OpResult r{0, 0, 0, true};
     if (!s_idle) {
       const u64 t0 = now_ticks();
-      r = op_delete<K, T>(H, s_ticket, out, (u32)K, L, sh, ctl);
+      r = op_delete<K, T, u64>(H, s_ticket, out, (u32)K, L, sh, ctl);
       ++ops;
       __syncthreads();
       heap_t += now_ticks() - t0;
@@ -434,7 +602,7 @@ __global__ __launch_bounds__(T) void k_sssp(const HeapDesc* __restrict__ descs, 
         s_ticket = atomicAdd(reinterpret_cast<unsigned long long*>(&st->next_ticket), 1ull);
       __syncthreads();
       const u32 nn = c - j < (u32)K ? c - j : (u32)K;
-      const OpResult ri = op_insert<K, T>(H, s_ticket, mine + j, nn, L, sh, ctl);
+      const OpResult ri = op_insert<K, T, u64>(H, s_ticket, mine + j, nn, L, sh, ctl);
       ++ops;
       // (the batch in `mine` is unchanged by the insert)
       if (tr.d_ops && ri.ok)
@@ -495,9 +663,11 @@ hipError_t launch_sssp_k<GH_K>(const SsspArgs& a) {
   return hipErrorInvalidValue;
 }
 
+#endif  // GH_ENT_BYTES == 8
+
 template <>
-hipError_t launch_ops_k<GH_K>(const LaunchArgs& a) {
-  return launch_kops_shape<GH_K, false>(a);
+hipError_t launch_ops_k<GH_K, GH_ENT>(const LaunchArgs& a) {
+  return launch_kops_shape<GH_K, false, GH_ENT>(a);
 }
 
 }  // namespace gh

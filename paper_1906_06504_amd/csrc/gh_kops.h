@@ -17,14 +17,14 @@ namespace gh {
 // kind given to a record the kernel refuses (> GH_OP_DELETE_MIN)
 constexpr u32 KIND_REFUSED = 0xFFu;
 
-template <int K, int T, bool VarDel>
+template <int K, int T, bool VarDel, class Ent>
 __global__ __launch_bounds__(T) void k_ops(const HeapDesc* __restrict__ descs,
                                            const gh_op* __restrict__ ops, u32 nops,
-                                           OpParams direct, const u64* __restrict__ in,
-                                           u64* __restrict__ out, u32* __restrict__ counts,
+                                           OpParams direct, const Ent* __restrict__ in,
+                                           Ent* __restrict__ out, u32* __restrict__ counts,
                                            gh_logrec* __restrict__ log, Ctl* __restrict__ ctl) {
-  __shared__ __align__(16) u64 lds[5 * K];
-  lu64* const L = (lu64*)lds;
+  __shared__ __align__(16) Ent lds[5 * K];
+  lds_t<Ent>* const L = (lds_t<Ent>*)lds;
   __shared__ OpShared sh;
   const int tid = threadIdx.x;
   for (;;) {
@@ -91,12 +91,14 @@ __global__ __launch_bounds__(T) void k_ops(const HeapDesc* __restrict__ descs,
       r = op_pass_root(H, ticket, sh, ctl);
       if (malformed) r.flags |= F_REJECT;
     } else if (op.kind == GH_OP_INSERT) {
-      r = op_insert<K, T>(H, ticket, in + op.off, op.n, L, sh, ctl);
+      r = op_insert<K, T, Ent>(H, ticket, in + op.off, op.n, L, sh, ctl);
     } else if constexpr (VarDel) {
-      if (op.n == 0 || op.n == (u32)K) r = op_delete<K, T>(H, ticket, out + op.off, K, L, sh, ctl);
-      else r = op_delete<K, T, true>(H, ticket, out + op.off, op.n, L, sh, ctl);
+      if (op.n == 0 || op.n == (u32)K)
+        r = op_delete<K, T, Ent>(H, ticket, out + op.off, K, L, sh, ctl);
+      else
+        r = op_delete<K, T, Ent, true>(H, ticket, out + op.off, op.n, L, sh, ctl);
     } else {
-      r = op_delete<K, T>(H, ticket, out + op.off, K, L, sh, ctl);
+      r = op_delete<K, T, Ent>(H, ticket, out + op.off, K, L, sh, ctl);
     }
     if (tid == 0) {
       if (counts) counts[i] = op.kind == GH_OP_INSERT ? 0u : r.count;
@@ -120,19 +122,20 @@ __global__ __launch_bounds__(T) void k_ops(const HeapDesc* __restrict__ descs,
   }
 }
 
-template <int K, int T, bool VarDel>
+template <int K, int T, bool VarDel, class Ent>
 static hipError_t launch_kops_t(const LaunchArgs& a) {
-  hipLaunchKernelGGL((k_ops<K, T, VarDel>), dim3(a.workgroups), dim3(T), 0, a.stream, a.descs,
-                     a.ops, a.nops, a.direct, a.in, a.out, a.counts, a.log, a.ctl);
+  hipLaunchKernelGGL((k_ops<K, T, VarDel, Ent>), dim3(a.workgroups), dim3(T), 0, a.stream,
+                     a.descs, a.ops, a.nops, a.direct, reinterpret_cast<const Ent*>(a.in),
+                     reinterpret_cast<Ent*>(a.out), a.counts, a.log, a.ctl);
   return hipGetLastError();
 }
 
-template <int K, bool VarDel>
+template <int K, bool VarDel, class Ent>
 static hipError_t launch_kops_shape(const LaunchArgs& a) {
   switch (a.threads) {
-#define GH_CASE(TT)                                                        \
-  case TT:                                                                 \
-    if constexpr (shape_ok(K, TT)) return launch_kops_t<K, TT, VarDel>(a); \
+#define GH_CASE(TT)                                                             \
+  case TT:                                                                      \
+    if constexpr (shape_ok(K, TT)) return launch_kops_t<K, TT, VarDel, Ent>(a); \
     break;
     GH_CASE(64)
     GH_CASE(128)

@@ -41,16 +41,17 @@ constexpr bool shape_ok(int K, int T) {
   return T >= 64 && T <= 1024 && (T & (T - 1)) == 0 && 2 * K >= T && 2 * K <= 16 * T;
 }
 
-// the persistent operation loop: whole-root deleteMins only (gh_kernels.hip),
-// or also deleteMins of fewer than K entries (gh_serve.hip)
-template <int K>
+// the persistent operation loop for entries of type Ent (u64 or e128):
+// whole-root deleteMins only (gh_kernels.hip), or also deleteMins of fewer
+// than K entries (gh_serve.hip)
+template <int K, class Ent>
 hipError_t launch_ops_k(const LaunchArgs& a);
 
 // heap filter (gh_filter.hip): workspace size and the launch sequence
-u64 filter_workspace_bytes(u64 max_nodes, u32 k);
-hipError_t launch_filter(const HeapDesc* d, u64 max_nodes, u32 k, u64 bound, void* work,
-                         u64* kept_out, hipStream_t st);
-template <int K>
+u64 filter_workspace_bytes(u64 max_nodes, u32 k, u32 ebytes);
+hipError_t launch_filter(const HeapDesc* d, u64 max_nodes, u32 k, u32 ebytes, u64 bound,
+                         void* work, u64* kept_out, hipStream_t st);
+template <int K, class Ent>
 hipError_t launch_ops_var_k(const LaunchArgs& a);
 
 // ---------------------------------------------------------------------------
@@ -102,7 +103,7 @@ struct ServeArgs {
   hipStream_t stream;
 };
 
-template <int K>
+template <int K, class Ent>
 hipError_t launch_serve_k(const ServeArgs& a);
 
 // Knapsack branch and bound driver (one heap per instance).
@@ -116,7 +117,8 @@ struct KnapArgs {
   const u32* v;
   u64* pool;
   u64 pool_per_inst;
-  u64* scratch;
+  void* scratch;      // 3K entries per instance
+  u32 gc_min;         // collect an instance's heap from this many entries (0: never)
   gh_knapres* res;
   Ctl* ctl;
   u32 workgroups;
@@ -124,7 +126,7 @@ struct KnapArgs {
   hipStream_t stream;
 };
 
-template <int K>
+template <int K, class Ent>
 hipError_t launch_knap_k(const KnapArgs& a);
 
 // SSSP driver (one shared heap, dynamic tickets).

@@ -217,6 +217,43 @@ __device__ __forceinline__ OpResult op_discard(const HeapDesc& H, u64 ticket, Op
   return res;
 }
 
+// Take the root in turn and lay n ascending entries from src (global
+// memory) out as the heap: the first floor(n / K) * K become the nodes in
+// addition order, the rest the partial buffer (the bulk build of Sec. 3.1),
+// and the lock words of the node positions are cleared.  Only for an empty
+// heap with no other operation in flight, such as a branch-and-bound
+// instance's own heap after op_discard.
+template <int K, int T, class Ent>
+__device__ __forceinline__ OpResult op_build_from(const HeapDesc& H, u64 ticket,
+                                                  const Ent* __restrict__ src, u64 n,
+                                                  OpShared& sh, Ctl* ctl) {
+  OpResult res{0, 0, 0, true};
+  if (threadIdx.x == 0) {
+    u64 w = 0;
+    sh.ok = root_acquire(H.meta, ticket, ctl, w) ? 1u : 0u;
+  }
+  __syncthreads();
+  if (!sh.ok) {
+    res.ok = false;
+    return res;
+  }
+  const u64 m = n / K, body = m * K;
+  const glob_t<Ent>* gs = gptr(src);
+  Ent* nodes = slot_ptr<K, Ent>(H, 1);
+  const HeapRegion R(reinterpret_cast<const u64*>(nodes), (u32)(body * sizeof(Ent)));
+  const HeapRegion P(reinterpret_cast<const u64*>(pb_ptr<Ent>(H)), K * sizeof(Ent));
+  for (u64 i = threadIdx.x; i < n; i += T) {
+    const Ent e = gs[i];
+    if (i < body) R.store_ent((u32)(i * sizeof(Ent)), e);
+    else P.store_ent((u32)((i - body) * sizeof(Ent)), e);
+  }
+  for (u64 p = threadIdx.x + 1; p <= m; p += T) st_relaxed(H.locks + p, lockword(ST_AVAIL, 0));
+  publish();
+  if (threadIdx.x == 0) release_root(H.meta, ticket, m, n - body);
+  res.count = (u32)n;
+  return res;
+}
+
 // Thread 0 takes the root; everyone learns (m, s) from the root word.
 __device__ __forceinline__ bool acquire_root(const HeapDesc& H, u64 ticket, OpShared& sh,
                                              Ctl* ctl) {
@@ -237,23 +274,24 @@ __device__ __forceinline__ bool acquire_root(const HeapDesc& H, u64 ticket, OpSh
 // cooperation).  `keys` holds n (1..K) entries in global memory.
 // LDS: five buffers of K entries.
 // ---------------------------------------------------------------------------
-template <int K, int T, bool Stamp = false>
-__device__ __forceinline__ OpResult op_insert(const HeapDesc& H, u64 ticket, const u64* __restrict__ keys, u32 n,
-                              lu64* lds, OpShared& sh, Ctl* ctl) {
+template <int K, int T, class Ent, bool Stamp = false>
+__device__ __forceinline__ OpResult op_insert(const HeapDesc& H, u64 ticket,
+                                              const Ent* __restrict__ keys, u32 n,
+                                              lds_t<Ent>* lds, OpShared& sh, Ctl* ctl) {
   constexpr int E = (2 * K) / T >= 1 ? (2 * K) / T : 1;
   const int tid = threadIdx.x;
   OpResult res{n, 0, 0, true};
-  lu64* b0 = lds;
-  lu64* b1 = lds + K;
-  lu64* P = lds + 2 * K;   // partial buffer
-  lu64* F = lds + 3 * K;   // full batch / merged head
-  lu64* N = lds + 4 * K;   // node being merged (root first)
+  lds_t<Ent>* b0 = lds;
+  lds_t<Ent>* b1 = lds + K;
+  lds_t<Ent>* P = lds + 2 * K;   // partial buffer
+  lds_t<Ent>* F = lds + 3 * K;   // full batch / merged head
+  lds_t<Ent>* N = lds + 4 * K;   // node being merged (root first)
   HeapMeta* meta = H.meta;
 
   // sort the batch before touching the heap (holds no lock)
   load_n<T>(b0, keys, n);
-  lu64* xs = block_sort<K, T>(b0, b1, (int)n);
-  lu64* xfree = (xs == b0) ? b1 : b0;
+  lds_t<Ent>* xs = block_sort<K, T, Ent>(b0, b1, (int)n);
+  lds_t<Ent>* xfree = (xs == b0) ? b1 : b0;
 
   if (!acquire_root(H, ticket, sh, ctl)) { res.ok = false; return res; }
   const u64 m = sh.m;
@@ -282,9 +320,9 @@ __device__ __forceinline__ OpResult op_insert(const HeapDesc& H, u64 ticket, con
   // insert's target lies at or below position m, and only the root holder
   // reserves new ones.
   {
-    NodeRegs<K, T> pr, rr;
-    pr.load(H.pb);
-    if (m >= 1) rr.load(H.nodes);
+    NodeRegs<K, T, Ent> pr, rr;
+    pr.load(pb_ptr<Ent>(H));
+    if (m >= 1) rr.load(slot_ptr<K, Ent>(H, 1));
     u64 old = 0;
     if (tid == 0 && L >= 1) old = xchg_relaxed(tlock, lockword(ST_TARGET, ticket));
     if (tid == 1 && L >= 2) old = cas_old(lock_ptr(H, child1), 0, lockword(ST_INUSE, ticket));
@@ -312,17 +350,17 @@ __device__ __forceinline__ OpResult op_insert(const HeapDesc& H, u64 ticket, con
 
   // merged = merge(sorted input, partial buffer): first K -> F, rest -> xfree
   const u32 tot = n + s;
-  merge_split<E, T>(xs, (int)n, P, (int)s, K, Sink{F}, Sink{xfree});
+  merge_split<E, T>(xs, (int)n, P, (int)s, K, sink(F), sink(xfree));
   __syncthreads();
   GH_TRACE(2);
 
-  u64* root = H.nodes;  // position 1
+  Ent* root = slot_ptr<K, Ent>(H, 1);  // position 1
   if (!full) {
     // the partial buffer keeps everything; restore Property 3 against the root
-    if (m >= 1 && !(N[K - 1] <= F[0])) {
-      merge_split<E, T>(N, K, F, (int)tot, K, HeapSink(root, K * 8), HeapSink(H.pb, K * 8));
+    if (m >= 1 && !ent_le(N[K - 1], F[0])) {
+      merge_split<E, T>(N, K, F, (int)tot, K, HeapSink<Ent>(root, K * sizeof(Ent)), HeapSink<Ent>(pb_ptr<Ent>(H), K * sizeof(Ent)));
     } else {
-      store_heap_n<K, T>(H.pb, F, tot);
+      store_heap_n<K, T, Ent>(pb_ptr<Ent>(H), F, tot);
     }
     publish();
     if (tid == 0) release_root_at<Stamp>(meta, ticket, m, tot, sh);
@@ -332,9 +370,9 @@ __device__ __forceinline__ OpResult op_insert(const HeapDesc& H, u64 ticket, con
   // a full batch F goes down from the root; the rest stays in the pb
   res.flags |= F_FULL;
   const u32 rest = tot - K;
-  store_heap_n<K, T>(H.pb, xfree, rest);
+  store_heap_n<K, T, Ent>(pb_ptr<Ent>(H), xfree, rest);
   if (L == 0) {
-    store_node<K, T>(root, F);
+    store_node<K, T, Ent>(root, F);
     publish();
     if (tid == 0) release_root_at<Stamp>(meta, ticket, m2, rest, sh);
     return res;
@@ -342,21 +380,21 @@ __device__ __forceinline__ OpResult op_insert(const HeapDesc& H, u64 ticket, con
 
   // LDS buffers in play: N (node), F (carry), spare (free; xfree is read by
   // the pb store above and stays untouched)
-  lu64* spare = xfree == b0 ? b1 : b0;
+  lds_t<Ent>* spare = xfree == b0 ? b1 : b0;
   u32 cur = 1;
   int level = 0;
   for (;;) {
     const bool at_root = cur == 1;
     // (node, F) = MergeAndSort(node, F) with the shortcuts of Sec. 4.3
-    u64* cur_ptr = node_ptr<K>(H, cur);
-    if (N[K - 1] <= F[0]) {
+    Ent* cur_ptr = node_ptr<K, Ent>(H, cur);
+    if (ent_le(N[K - 1], F[0])) {
       // node already holds the smallest: nothing moves
-    } else if (F[K - 1] <= N[0]) {
-      store_node<K, T>(cur_ptr, F);  // swap
-      lu64* x = F; F = N; N = x;
+    } else if (ent_le(F[K - 1], N[0])) {
+      store_node<K, T, Ent>(cur_ptr, F);  // swap
+      lds_t<Ent>* x = F; F = N; N = x;
     } else {
-      merge_split<E, T>(N, K, F, K, K, HeapSink(cur_ptr, K * 8), Sink{spare});
-      lu64* x = F; F = spare; spare = x;
+      merge_split<E, T>(N, K, F, K, K, HeapSink<Ent>(cur_ptr, K * sizeof(Ent)), sink(spare));
+      lds_t<Ent>* x = F; F = spare; spare = x;
     }
     ++level;
     if (at_root) GH_TRACE(3);
@@ -381,7 +419,7 @@ __device__ __forceinline__ OpResult op_insert(const HeapDesc& H, u64 ticket, con
       if (!sh.ok) { res.ok = false; return res; }
       if (sh.flag0) {
         // cooperation: leave the batch in the target slot for the deleteMin
-        store_node<K, T>(node_ptr<K>(H, t), F);
+        store_node<K, T, Ent>(node_ptr<K, Ent>(H, t), F);
         publish();
         if (tid == 0) {
           if (child != t) unlock(lock_ptr(H, child));
@@ -405,8 +443,8 @@ __device__ __forceinline__ OpResult op_insert(const HeapDesc& H, u64 ticket, con
       // the next path node, and in the same round trip a look at the
       // target: a deleteMin that claimed it gets the carry now, before this
       // level's merge (the carry has not entered this subtree yet)
-      NodeRegs<K, T> nr;
-      nr.load(node_ptr<K>(H, cur));
+      NodeRegs<K, T, Ent> nr;
+      nr.load(node_ptr<K, Ent>(H, cur));
       u64 tw = 0;
       if (tid == 0) tw = ld_relaxed(tlock);
       nr.store(N);
@@ -414,7 +452,7 @@ __device__ __forceinline__ OpResult op_insert(const HeapDesc& H, u64 ticket, con
     }
     __syncthreads();
     if (sh.flag0) {
-      store_node<K, T>(node_ptr<K>(H, t), F);
+      store_node<K, T, Ent>(node_ptr<K, Ent>(H, t), F);
       publish();
       if (tid == 0) {
         unlock(lock_ptr(H, cur));
@@ -426,7 +464,7 @@ __device__ __forceinline__ OpResult op_insert(const HeapDesc& H, u64 ticket, con
     }
   }
   // fill the target
-  store_node<K, T>(node_ptr<K>(H, t), F);
+  store_node<K, T, Ent>(node_ptr<K, Ent>(H, t), F);
   publish();
   if (tid == 0) {
     if (!cas_relaxed(tlock, lockword(ST_TARGET, ticket), lockword(ST_AVAIL, 0))) {
@@ -453,16 +491,17 @@ __device__ __forceinline__ OpResult op_insert(const HeapDesc& H, u64 ticket, con
 // everything left becomes the partial buffer.  Var = false compiles the
 // whole-root deleteMin only (want is K); callers pick Var = true for want < K.
 // ---------------------------------------------------------------------------
-template <int K, int T, bool Var = false, bool Stamp = false>
-__device__ __forceinline__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64* __restrict__ out, u32 want_n,
-                              lu64* lds, OpShared& sh, Ctl* ctl) {
+template <int K, int T, class Ent, bool Var = false, bool Stamp = false>
+__device__ __forceinline__ OpResult op_delete(const HeapDesc& H, u64 ticket,
+                                              Ent* __restrict__ out, u32 want_n,
+                                              lds_t<Ent>* lds, OpShared& sh, Ctl* ctl) {
   constexpr int E = (2 * K) / T >= 1 ? (2 * K) / T : 1;
   const u32 want = Var ? want_n : (u32)K;
   const int tid = threadIdx.x;
   OpResult res{0, 0, 0, true};
   HeapMeta* meta = H.meta;
-  lu64* bufs[4] = {lds, lds + K, lds + 2 * K, lds + 3 * K};
-  lu64* P = lds + 4 * K;
+  lds_t<Ent>* bufs[4] = {lds, lds + K, lds + 2 * K, lds + 3 * K};
+  lds_t<Ent>* P = lds + 4 * K;
 
   if (!acquire_root(H, ticket, sh, ctl)) { res.ok = false; return res; }
   const u64 m = sh.m;
@@ -472,13 +511,12 @@ __device__ __forceinline__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64
   if (m == 0) {
     // no node: the partial buffer is the whole heap
     const u32 cnt = Var && want < s ? want : s;   // the pb holds < K entries
-    copy_heap_n<K, T>(out, H.pb, cnt);
+    copy_heap_n<K, T, Ent>(out, pb_ptr<Ent>(H), cnt);
     if (cnt < s) {
       // what is left of the partial buffer moves to its front
-      const HeapRegion R(H.pb, K * 8);
-      for (u32 i = tid; i < s - cnt; i += T) P[i] = R.load8((cnt + i) * 8);
+      load_heap_n<K, T, Ent>(P, pb_ptr<Ent>(H), s - cnt, cnt);
       __syncthreads();   // every read of the pb is done before it is rewritten
-      store_heap_n<K, T>(H.pb, P, s - cnt);
+      store_heap_n<K, T, Ent>(pb_ptr<Ent>(H), P, s - cnt);
       publish();
     } else if constexpr (Stamp) {
       publish();         // the output is in memory before the stamp
@@ -499,17 +537,17 @@ __device__ __forceinline__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64
   const u64 m2 = refill ? m - 1 : (nrest >= (u32)K ? m : 0);
   const u32 s2 = !part ? s : (nrest >= (u32)K ? nrest - K : nrest);
   const bool need_pb = s > 0 && (part || m >= 2);
-  lu64* const PB0 = part ? bufs[3] : P;   // the pb's copy in LDS
+  lds_t<Ent>* const PB0 = part ? bufs[3] : P;   // the pb's copy in LDS
   u64* llock = H.locks + m;
-  u64* lastp = H.nodes + (m - 1) * (u64)K;
+  Ent* lastp = slot_ptr<K, Ent>(H, m);
 
   // Round trip 1: root and partial buffer into registers, first try at the
   // last node's lock.
   u64 old_last = 0;
   {
-    NodeRegs<K, T> rr, pr;
-    rr.load(H.nodes);
-    if (need_pb) pr.load(H.pb);
+    NodeRegs<K, T, Ent> rr, pr;
+    rr.load(slot_ptr<K, Ent>(H, 1));
+    if (need_pb) pr.load(pb_ptr<Ent>(H));
     if (tid == 0 && refill && m >= 2) old_last = cas_old(llock, 0, lockword(ST_INUSE, ticket));
     rr.store(bufs[1]);
     if (need_pb) pr.store(PB0);
@@ -526,25 +564,25 @@ __device__ __forceinline__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64
     // the root's other entries merged with the pb
     if (nrest >= (u32)K) {
       // the K smallest are the new root, the rest the pb; no node goes away
-      merge_split<E, T>(bufs[1] + want, K - want, PB0, (int)s, K, Sink{bufs[0]},
-                        HeapSink(H.pb, K * 8));
+      merge_split<E, T>(bufs[1] + want, K - want, PB0, (int)s, K, sink(bufs[0]),
+                        HeapSink<Ent>(pb_ptr<Ent>(H), K * sizeof(Ent)));
       __syncthreads();
     } else if (!refill) {
       // a single node: everything left becomes the pb
       merge_split<E, T>(bufs[1] + want, K - want, PB0, (int)s, (int)nrest,
-                        HeapSink(H.pb, K * 8), Sink{bufs[0]});
+                        HeapSink<Ent>(pb_ptr<Ent>(H), K * sizeof(Ent)), sink(bufs[0]));
       publish();
       if (tid == 0) release_root_at<Stamp>(meta, ticket, 0, nrest, sh);
       return res;
     } else {
       // waits in P for the last node
-      merge_split<E, T>(bufs[1] + want, K - want, PB0, (int)s, (int)nrest, Sink{P},
-                        Sink{bufs[0]});
+      merge_split<E, T>(bufs[1] + want, K - want, PB0, (int)s, (int)nrest, sink(P),
+                        sink(bufs[0]));
       __syncthreads();
     }
   }
 
-  lu64* C = bufs[0];
+  lds_t<Ent>* C = bufs[0];
   bool hl = false, hr = false;
   bool loaded = false;
   if (refill) {
@@ -566,7 +604,7 @@ __device__ __forceinline__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64
     const bool el1 = node_exists(2, m2), er1 = node_exists(3, m2);
     u64 oc = 0;
     {
-      NodeRegs<K, T> lr;
+      NodeRegs<K, T, Ent> lr;
       lr.load(lastp);
       // lanes 1 and 2 try children 2 and 3 with one vector atomic
       if ((tid == 1 && el1) || (tid == 2 && er1))
@@ -614,14 +652,14 @@ __device__ __forceinline__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64
     hl = sh.flag0;
     hr = sh.flag1;
     {
-      NodeRegs<K, T> lc, rc;
-      if (hl) lc.load(H.nodes + 1 * (u64)K);   // node 2 is position 2
-      if (hr) rc.load(node_ptr<K>(H, 3));
+      NodeRegs<K, T, Ent> lc, rc;
+      if (hl) lc.load(slot_ptr<K, Ent>(H, 2));   // node 2 is position 2
+      if (hr) rc.load(node_ptr<K, Ent>(H, 3));
       const u32 np = part ? nrest : s;
-      if (np > 0 && (part || !(C[K - 1] <= P[0]))) {
-        merge_split<E, T>(C, K, P, (int)np, K, Sink{bufs[3]}, HeapSink(H.pb, K * 8));
+      if (np > 0 && (part || !ent_le(C[K - 1], P[0]))) {
+        merge_split<E, T>(C, K, P, (int)np, K, sink(bufs[3]), HeapSink<Ent>(pb_ptr<Ent>(H), K * sizeof(Ent)));
         __syncthreads();
-        lu64* x = bufs[0]; bufs[0] = bufs[3]; bufs[3] = x;
+        lds_t<Ent>* x = bufs[0]; bufs[0] = bufs[3]; bufs[3] = x;
         C = bufs[0];
       }
       if (hl) lc.store(bufs[1]);
@@ -637,8 +675,8 @@ __device__ __forceinline__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64
   u32 c = 1;
   for (;;) {
     const u64 l = 2ull * c, r = l + 1;
-    lu64* Lb = bufs[1];
-    lu64* Rb = bufs[2];
+    lds_t<Ent>* Lb = bufs[1];
+    lds_t<Ent>* Rb = bufs[2];
     if (!loaded) {
       const bool el = node_exists(l, m2), er = node_exists(r, m2);
       if (tid < 64) {
@@ -659,23 +697,23 @@ __device__ __forceinline__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64
       hl = sh.flag0;
       hr = sh.flag1;
       {
-        NodeRegs<K, T> lc, rc;
-        if (hl) lc.load(node_ptr<K>(H, (u32)l));
-        if (hr) rc.load(node_ptr<K>(H, (u32)r));
+        NodeRegs<K, T, Ent> lc, rc;
+        if (hl) lc.load(node_ptr<K, Ent>(H, (u32)l));
+        if (hr) rc.load(node_ptr<K, Ent>(H, (u32)r));
         if (hl) lc.store(Lb);
         if (hr) rc.store(Rb);
       }
       __syncthreads();
     }
     loaded = false;
-    const u64 lmin = hl ? Lb[0] : ENT_MAX;
-    const u64 rmin = hr ? Rb[0] : ENT_MAX;
-    const u64 cmin = lmin < rmin ? lmin : rmin;
-    u64* cptr = node_ptr<K>(H, c);
+    const Ent lmin = hl ? (Ent)Lb[0] : ent_max<Ent>();
+    const Ent rmin = hr ? (Ent)Rb[0] : ent_max<Ent>();
+    const Ent cmin = ent_lt(lmin, rmin) ? lmin : rmin;
+    Ent* cptr = node_ptr<K, Ent>(H, c);
 
-    if (C[K - 1] <= cmin) {
+    if (ent_le(C[K - 1], cmin)) {
       // the property holds: place cur and stop (early stop, Sec. 4.3)
-      store_node<K, T>(cptr, C);
+      store_node<K, T, Ent>(cptr, C);
       publish();
       if (tid == 0) {
         if (hl) unlock(lock_ptr(H, (u32)l));
@@ -687,32 +725,32 @@ __device__ __forceinline__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64
     }
 
     u32 next;
-    lu64* newcur;
+    lds_t<Ent>* newcur;
     if (hl && hr) {
       // (hi, lo) = MergeAndSort(l, r); lo stays in the child whose max was
       // larger (on a tie the right child counts as larger), hi merges with
       // cur; cur's k smallest stay here
-      const bool big_is_l = Lb[K - 1] > Rb[K - 1];
+      const bool big_is_l = ent_lt(Rb[K - 1], Lb[K - 1]);
       const u32 big = big_is_l ? (u32)l : (u32)r;
       const u32 small = big_is_l ? (u32)r : (u32)l;
-      lu64* Bg = big_is_l ? Lb : Rb;
-      lu64* Sm = big_is_l ? Rb : Lb;
-      lu64* hi;
-      lu64* freeb;
-      if (Sm[K - 1] <= Bg[0]) {
+      lds_t<Ent>* Bg = big_is_l ? Lb : Rb;
+      lds_t<Ent>* Sm = big_is_l ? Rb : Lb;
+      lds_t<Ent>* hi;
+      lds_t<Ent>* freeb;
+      if (ent_le(Sm[K - 1], Bg[0])) {
         hi = Sm;             // lo is the big child's batch, already in place
         freeb = bufs[3];
       } else {
-        merge_split<E, T>(Lb, K, Rb, K, K, Sink{bufs[3]}, HeapSink(node_ptr<K>(H, big), K * 8));
+        merge_split<E, T>(Lb, K, Rb, K, K, sink(bufs[3]), HeapSink<Ent>(node_ptr<K, Ent>(H, big), K * sizeof(Ent)));
         __syncthreads();
         hi = bufs[3];
         freeb = Lb;
       }
-      if (hi[K - 1] <= C[0]) {
-        store_node<K, T>(cptr, hi);
+      if (ent_le(hi[K - 1], C[0])) {
+        store_node<K, T, Ent>(cptr, hi);
         newcur = C;
       } else {
-        merge_split<E, T>(C, K, hi, K, K, HeapSink(cptr, K * 8), Sink{freeb});
+        merge_split<E, T>(C, K, hi, K, K, HeapSink<Ent>(cptr, K * sizeof(Ent)), sink(freeb));
         __syncthreads();
         newcur = freeb;
       }
@@ -728,13 +766,13 @@ __device__ __forceinline__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64
     } else {
       // one live child x
       const u32 x = hl ? (u32)l : (u32)r;
-      lu64* X = hl ? Lb : Rb;
-      lu64* freeb = bufs[3];
-      if (X[K - 1] <= C[0]) {
-        store_node<K, T>(cptr, X);
+      lds_t<Ent>* X = hl ? Lb : Rb;
+      lds_t<Ent>* freeb = bufs[3];
+      if (ent_le(X[K - 1], C[0])) {
+        store_node<K, T, Ent>(cptr, X);
         newcur = C;
       } else {
-        merge_split<E, T>(C, K, X, K, K, HeapSink(cptr, K * 8), Sink{freeb});
+        merge_split<E, T>(C, K, X, K, K, HeapSink<Ent>(cptr, K * sizeof(Ent)), sink(freeb));
         __syncthreads();
         newcur = freeb;
       }
@@ -749,10 +787,10 @@ __device__ __forceinline__ OpResult op_delete(const HeapDesc& H, u64 ticket, u64
     // rotate buffers: newcur becomes C, the other three are free (in
     // their old order; newcur is one of the four)
     {
-      lu64* const a0 = bufs[0];
-      lu64* const a1 = bufs[1];
-      lu64* const a2 = bufs[2];
-      lu64* const a3 = bufs[3];
+      lds_t<Ent>* const a0 = bufs[0];
+      lds_t<Ent>* const a1 = bufs[1];
+      lds_t<Ent>* const a2 = bufs[2];
+      lds_t<Ent>* const a3 = bufs[3];
       const bool n0 = newcur == a0, n1 = newcur == a1, n2 = newcur == a2;
       bufs[0] = newcur;
       bufs[1] = n0 ? a1 : a0;

@@ -1,12 +1,19 @@
 // gh_serve.hip -- the served form (device-resident request loop) and the
 // persistent operation loop that also runs deleteMins of fewer than k
-// entries, for one node capacity.  Compiled once per supported k with
-// -DGH_K=<k>; each object exports gh::launch_serve_k<k>() and
-// gh::launch_ops_var_k<k>().
+// entries, for one node capacity and entry width.  Compiled once per
+// supported k and width with -DGH_K=<k> -DGH_ENT_BYTES=<8|16>; each object
+// exports gh::launch_serve_k<k, Ent>() and gh::launch_ops_var_k<k, Ent>().
 #include "gh_kops.h"
 
 #ifndef GH_K
 #error "compile with -DGH_K=<node capacity>"
+#endif
+#if GH_ENT_BYTES == 8
+#define GH_ENT u64
+#elif GH_ENT_BYTES == 16
+#define GH_ENT e128
+#else
+#error "compile with -DGH_ENT_BYTES=8 or 16"
 #endif
 
 namespace gh {
@@ -229,14 +236,14 @@ __device__ __forceinline__ void load_ids16(const lu32* p, u32 (&ids)[16]) {
   ids[12] = d.x; ids[13] = d.y; ids[14] = d.z; ids[15] = d.w;
 }
 
-template <int K, int T>
+template <int K, int T, class Ent>
 __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs, u32 nheaps,
                                              const gh_op* __restrict__ reqs, u32 nreq,
-                                             const u64* __restrict__ in, u64* __restrict__ out,
+                                             const Ent* __restrict__ in, Ent* __restrict__ out,
                                              gh_reqrec* __restrict__ recs, ServeWork w,
                                              Ctl* __restrict__ ctl, u32 clock_mhz) {
-  __shared__ __align__(16) u64 lds[5 * K];
-  lu64* const L = (lu64*)lds;
+  __shared__ __align__(16) Ent lds[5 * K];
+  lds_t<Ent>* const L = (lds_t<Ent>*)lds;
   __shared__ OpShared sh;
   const int tid = threadIdx.x;
 
@@ -453,12 +460,12 @@ __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs,
     const u64 ticket = *gptr(&H.meta->base) + op.seq;
     OpResult res;
     if (op.kind == GH_OP_INSERT) {
-      res = op_insert<K, T, true>(H, ticket, in + op.off, op.n, L, sh, ctl);
+      res = op_insert<K, T, Ent, true>(H, ticket, in + op.off, op.n, L, sh, ctl);
     } else {
       if (__builtin_expect(op.n == (u32)K, 1))
-        res = op_delete<K, T, false, true>(H, ticket, out + op.off, K, L, sh, ctl);
+        res = op_delete<K, T, Ent, false, true>(H, ticket, out + op.off, K, L, sh, ctl);
       else
-        res = op_delete<K, T, true, true>(H, ticket, out + op.off, op.n, L, sh, ctl);
+        res = op_delete<K, T, Ent, true, true>(H, ticket, out + op.off, op.n, L, sh, ctl);
     }
     if (tid == 0) {
       if (op.kind == GH_OP_DELETE_MIN)
@@ -476,21 +483,22 @@ __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs,
   }
 }
 
-template <int K, int T>
+template <int K, int T, class Ent>
 static hipError_t launch_serve_t(const ServeArgs& a) {
-  hipLaunchKernelGGL((k_serve<K, T>), dim3(a.workgroups + 1), dim3(T),
+  hipLaunchKernelGGL((k_serve<K, T, Ent>), dim3(a.workgroups + 1), dim3(T),
                      (size_t)a.nheaps * sizeof(SchedHot) + 2 * T * sizeof(u32), a.stream, a.descs,
-                     a.nheaps, a.reqs, a.nreq, a.in, a.out, a.recs, a.w, a.ctl, a.clock_mhz);
+                     a.nheaps, a.reqs, a.nreq, reinterpret_cast<const Ent*>(a.in),
+                     reinterpret_cast<Ent*>(a.out), a.recs, a.w, a.ctl, a.clock_mhz);
   return hipGetLastError();
 }
 
 template <>
-hipError_t launch_serve_k<GH_K>(const ServeArgs& a) {
+hipError_t launch_serve_k<GH_K, GH_ENT>(const ServeArgs& a) {
   constexpr int K = GH_K;
   switch (a.threads) {
-#define GH_CASE(TT)                                                 \
-  case TT:                                                          \
-    if constexpr (shape_ok(K, TT)) return launch_serve_t<K, TT>(a); \
+#define GH_CASE(TT)                                                         \
+  case TT:                                                                  \
+    if constexpr (shape_ok(K, TT)) return launch_serve_t<K, TT, GH_ENT>(a); \
     break;
     GH_CASE(64)
     GH_CASE(128)
@@ -505,8 +513,8 @@ hipError_t launch_serve_k<GH_K>(const ServeArgs& a) {
 }
 
 template <>
-hipError_t launch_ops_var_k<GH_K>(const LaunchArgs& a) {
-  return launch_kops_shape<GH_K, true>(a);
+hipError_t launch_ops_var_k<GH_K, GH_ENT>(const LaunchArgs& a) {
+  return launch_kops_shape<GH_K, true, GH_ENT>(a);
 }
 
 }  // namespace gh

@@ -4,18 +4,19 @@
 
 namespace gh {
 
-// Fill every node and partial-buffer slot with ENT_MAX, every lock with
+// Fill every node and partial-buffer slot with the filler, every lock with
 // AVAIL, and zero the metadata, for one heap per y-block row.
 __global__ void k_init_heap(const HeapDesc* __restrict__ descs, u32 nheaps) {
   const u32 h = blockIdx.y;
   if (h >= nheaps) return;
   const HeapDesc d = descs[h];
-  const u64 n_nodes = (u64)d.max_nodes * d.k;
+  // the filler is all ones in either entry width
+  const u64 n_words = (u64)d.max_nodes * d.k * d.ewords;
   const u64 stride = (u64)gridDim.x * blockDim.x;
   const u64 start = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-  for (u64 i = start; i < n_nodes; i += stride) d.nodes[i] = ENT_MAX;
+  for (u64 i = start; i < n_words; i += stride) d.nodes[i] = ENT_MAX;
   for (u64 i = start; i <= d.max_nodes; i += stride) d.locks[i] = 0;
-  for (u64 i = start; i < d.k; i += stride) d.pb[i] = ENT_MAX;
+  for (u64 i = start; i < (u64)d.k * d.ewords; i += stride) d.pb[i] = ENT_MAX;
   if (start < sizeof(HeapMeta) / 8) reinterpret_cast<u64*>(d.meta)[start] = 0;
 }
 
@@ -112,19 +113,22 @@ __global__ void k_build_check(const HeapDesc* __restrict__ d, Ctl* ctl) {
   }
 }
 
-__global__ void k_build_copy(const HeapDesc* __restrict__ d, const u64* __restrict__ keys, u64 n,
+template <class Ent>
+__global__ void k_build_copy(const HeapDesc* __restrict__ d, const Ent* __restrict__ keys, u64 n,
                              Ctl* ctl) {
   if (!ctl->build_ok) return;
   const HeapDesc H = *d;
   const u64 m = n / H.k, body = m * H.k;
   const u64 stride = (u64)gridDim.x * blockDim.x;
   const u64 i0 = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+  Ent* nodes = reinterpret_cast<Ent*>(H.nodes);
+  Ent* pb = reinterpret_cast<Ent*>(H.pb);
   bool sorted = true;
   for (u64 i = i0; i < n; i += stride) {
-    const u64 x = keys[i];
-    if (i + 1 < n && x > keys[i + 1]) sorted = false;
-    if (i < body) H.nodes[i] = x;
-    else H.pb[i - body] = x;
+    const Ent x = keys[i];
+    if (i + 1 < n && ent_lt(keys[i + 1], x)) sorted = false;
+    if (i < body) nodes[i] = x;
+    else pb[i - body] = x;
   }
   if (!sorted) note_error(ctl, ERR_INVAL);
   for (u64 p = i0 + 1; p <= m; p += stride) H.locks[p] = 0;
@@ -139,14 +143,20 @@ __global__ void k_build_root(const HeapDesc* __restrict__ d, u64 n, Ctl* ctl) {
   }
 }
 
-hipError_t launch_build(const HeapDesc* d, const u64* keys, u64 n, Ctl* ctl, hipStream_t st) {
+hipError_t launch_build(const HeapDesc* d, const void* keys, u64 n, u32 ewords, Ctl* ctl,
+                        hipStream_t st) {
   u64 blocks = (n + 255) / 256;
   if (blocks > 2048) blocks = 2048;
   if (blocks == 0) blocks = 1;
   hipLaunchKernelGGL(k_build_check, dim3(1), dim3(64), 0, st, d, ctl);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_build_copy, dim3((u32)blocks), dim3(256), 0, st, d, keys, n, ctl);
+  if (ewords == 2)
+    hipLaunchKernelGGL(k_build_copy<e128>, dim3((u32)blocks), dim3(256), 0, st, d,
+                       static_cast<const e128*>(keys), n, ctl);
+  else
+    hipLaunchKernelGGL(k_build_copy<u64>, dim3((u32)blocks), dim3(256), 0, st, d,
+                       static_cast<const u64*>(keys), n, ctl);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_build_root, dim3(1), dim3(64), 0, st, d, n, ctl);
@@ -160,7 +170,7 @@ hipError_t launch_init(HeapDesc* descs_dev, const HeapDesc* descs_host, u32 nhea
   if (e != hipSuccess) return e;
   u64 biggest = 0;
   for (u32 i = 0; i < nheaps; ++i) {
-    u64 n = (u64)descs_host[i].max_nodes * descs_host[i].k;
+    u64 n = (u64)descs_host[i].max_nodes * descs_host[i].k * descs_host[i].ewords;
     if (n > biggest) biggest = n;
   }
   u32 gx = (u32)((biggest + 255) / 256);

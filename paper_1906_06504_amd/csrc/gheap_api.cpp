@@ -17,7 +17,8 @@ hipError_t launch_init(HeapDesc* descs_dev, const HeapDesc* descs_host, u32 nhea
                        u64 timeout_ticks, hipStream_t st);
 hipError_t launch_prep(const HeapDesc* descs, u32 nheaps, Ctl* ctl, hipStream_t st);
 hipError_t launch_serve_reset(ServeHead* head, hipStream_t st);
-hipError_t launch_build(const HeapDesc* d, const u64* keys, u64 n, Ctl* ctl, hipStream_t st);
+hipError_t launch_build(const HeapDesc* d, const void* keys, u64 n, u32 ewords, Ctl* ctl,
+                        hipStream_t st);
 hipError_t launch_sssp_init(const HeapDesc* descs, SsspState* st, u32* dist, u32 V, u32 src,
                             u64* push, gh_ssspstats* stats, hipStream_t stream);
 hipError_t launch_sssp_fini(const HeapDesc* descs, const SsspState* st, gh_ssspstats* stats,
@@ -26,6 +27,7 @@ hipError_t launch_sssp_fini(const HeapDesc* descs, const SsspState* st, gh_sssps
 
 struct gh_heap {
   u32 k;
+  u32 ebytes;                      // entry bytes: 8 (GH_U32_ID) or 16 (GH_I64_ID)
   u32 nheaps;
   hipStream_t stream;
   unsigned char* arena;
@@ -73,6 +75,11 @@ u32 serve_default_threads(u32 k) { return k <= 128 ? default_threads(k) : 256; }
 
 u64 max_nodes_for(u64 max_keys, u32 k) { return max_keys / k + 1; }
 
+// Entry bytes of a key type, 0 if unknown.
+u32 entry_bytes(int keytype) {
+  return keytype == GH_U32_ID ? 8u : (keytype == GH_I64_ID ? 16u : 0u);
+}
+
 struct Layout {
   u64 ctl_off, sssp_off, desc_off, total;
   std::vector<u64> meta_off, pb_off, lock_off, node_off, max_nodes;
@@ -82,8 +89,8 @@ struct Layout {
 // every arena offset fits in 64 bits.
 constexpr u32 MAX_HEAPS = 1u << 20;
 
-bool make_layout(u32 k, u32 nheaps, const u64* max_keys, u64 each, Layout& L) {
-  if (nheaps == 0 || nheaps > MAX_HEAPS) return false;
+bool make_layout(u32 k, u32 eb, u32 nheaps, const u64* max_keys, u64 each, Layout& L) {
+  if (nheaps == 0 || nheaps > MAX_HEAPS || (eb != 8 && eb != 16)) return false;
   L.ctl_off = 0;
   L.sssp_off = align_up(sizeof(Ctl));
   L.desc_off = align_up(L.sssp_off + sizeof(SsspState));
@@ -101,11 +108,11 @@ bool make_layout(u32 k, u32 nheaps, const u64* max_keys, u64 each, Layout& L) {
     L.meta_off[i] = off;
     off = align_up(off + sizeof(HeapMeta));
     L.pb_off[i] = off;
-    off = align_up(off + (u64)k * 8);
+    off = align_up(off + (u64)k * eb);
     L.lock_off[i] = off;
     off = align_up(off + (mn + 1) * 8);
     L.node_off[i] = off;
-    off = align_up(off + mn * (u64)k * 8);
+    off = align_up(off + mn * (u64)k * eb);
   }
   L.total = off;
   return true;
@@ -121,17 +128,46 @@ int from_status(u32 st) {
   }
 }
 
-hipError_t launch_serve(const gh_heap* h, const ServeArgs& a) {
+// Per (k, entry width) kernels: F<K, Ent>::run(args) for the set's shape.
+template <template <int, class> class F, class A>
+hipError_t by_shape(const gh_heap* h, const A& a) {
+  if (h->ebytes == 16) {
+    switch (h->k) {
+      case 32: return F<32, e128>::run(a);
+      case 64: return F<64, e128>::run(a);
+      case 128: return F<128, e128>::run(a);
+      case 256: return F<256, e128>::run(a);
+      case 512: return F<512, e128>::run(a);
+      case 1024: return F<1024, e128>::run(a);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (h->k) {
-    case 32: return launch_serve_k<32>(a);
-    case 64: return launch_serve_k<64>(a);
-    case 128: return launch_serve_k<128>(a);
-    case 256: return launch_serve_k<256>(a);
-    case 512: return launch_serve_k<512>(a);
-    case 1024: return launch_serve_k<1024>(a);
+    case 32: return F<32, u64>::run(a);
+    case 64: return F<64, u64>::run(a);
+    case 128: return F<128, u64>::run(a);
+    case 256: return F<256, u64>::run(a);
+    case 512: return F<512, u64>::run(a);
+    case 1024: return F<1024, u64>::run(a);
     default: return hipErrorInvalidValue;
   }
 }
+template <int K, class Ent>
+struct ServeF {
+  static hipError_t run(const ServeArgs& a) { return launch_serve_k<K, Ent>(a); }
+};
+template <int K, class Ent>
+struct KnapF {
+  static hipError_t run(const KnapArgs& a) { return launch_knap_k<K, Ent>(a); }
+};
+template <int K, class Ent>
+struct OpsF {
+  static hipError_t run(const LaunchArgs& a) {
+    return a.var_delete ? launch_ops_var_k<K, Ent>(a) : launch_ops_k<K, Ent>(a);
+  }
+};
+
+hipError_t launch_serve(const gh_heap* h, const ServeArgs& a) { return by_shape<ServeF>(h, a); }
 
 hipError_t launch_sssp(const gh_heap* h, const SsspArgs& a) {
   switch (h->k) {
@@ -145,17 +181,7 @@ hipError_t launch_sssp(const gh_heap* h, const SsspArgs& a) {
   }
 }
 
-hipError_t launch_knap(const gh_heap* h, const KnapArgs& a) {
-  switch (h->k) {
-    case 32: return launch_knap_k<32>(a);
-    case 64: return launch_knap_k<64>(a);
-    case 128: return launch_knap_k<128>(a);
-    case 256: return launch_knap_k<256>(a);
-    case 512: return launch_knap_k<512>(a);
-    case 1024: return launch_knap_k<1024>(a);
-    default: return hipErrorInvalidValue;
-  }
-}
+hipError_t launch_knap(const gh_heap* h, const KnapArgs& a) { return by_shape<KnapF>(h, a); }
 
 struct ServeLayout {
   u64 head, heaps, next, left, queue, qreq, total;
@@ -180,28 +206,7 @@ ServeLayout serve_layout(u32 nheaps, u32 nreq, u64 max_ops) {
   return L;
 }
 
-hipError_t launch_ops(const gh_heap* h, const LaunchArgs& a) {
-  if (a.var_delete) {
-    switch (h->k) {
-      case 32: return launch_ops_var_k<32>(a);
-      case 64: return launch_ops_var_k<64>(a);
-      case 128: return launch_ops_var_k<128>(a);
-      case 256: return launch_ops_var_k<256>(a);
-      case 512: return launch_ops_var_k<512>(a);
-      case 1024: return launch_ops_var_k<1024>(a);
-      default: return hipErrorInvalidValue;
-    }
-  }
-  switch (h->k) {
-    case 32: return launch_ops_k<32>(a);
-    case 64: return launch_ops_k<64>(a);
-    case 128: return launch_ops_k<128>(a);
-    case 256: return launch_ops_k<256>(a);
-    case 512: return launch_ops_k<512>(a);
-    case 1024: return launch_ops_k<1024>(a);
-    default: return hipErrorInvalidValue;
-  }
-}
+hipError_t launch_ops(const gh_heap* h, const LaunchArgs& a) { return by_shape<OpsF>(h, a); }
 
 u32 clock_mhz_of_device() {
   int dev = 0;
@@ -223,8 +228,8 @@ u64 watchdog_ticks(u32 clock_mhz) {
 
 // Launch the prep kernel (ticket bases, claim counter, start clock) and the
 // operation loop on the set's stream.
-int run_ops(gh_heap* h, const gh_op* d_ops, u32 nops, const OpParams& p, const u64* d_in,
-            u64* d_out, u32* d_counts, gh_logrec* d_log, const gh_tuning* t) {
+int run_ops(gh_heap* h, const gh_op* d_ops, u32 nops, const OpParams& p, const void* d_in,
+            void* d_out, u32* d_counts, gh_logrec* d_log, const gh_tuning* t) {
   if (nops == 0) return GH_OK;
   if (nops > RW_TICKET_MASK) return GH_EINVAL;   // tickets of one submission fit 24 bits
   u32 threads = (t && t->threads) ? t->threads : default_threads(h->k);
@@ -240,8 +245,8 @@ int run_ops(gh_heap* h, const gh_op* d_ops, u32 nops, const OpParams& p, const u
   a.direct = p;
   a.direct.clock_mhz = h->clock_mhz;
   a.direct.nheaps = h->nheaps;
-  a.in = d_in;
-  a.out = d_out;
+  a.in = static_cast<const u64*>(d_in);
+  a.out = static_cast<u64*>(d_out);
   a.counts = d_counts;
   a.log = d_log;
   a.ctl = h->ctl;
@@ -267,11 +272,11 @@ int refresh_status(gh_heap* h) {
 
 extern "C" {
 
-uint64_t heap_arena_bytes(uint32_t k, uint32_t nheaps, const uint64_t* max_keys,
+uint64_t heap_arena_bytes(uint32_t k, int keytype, uint32_t nheaps, const uint64_t* max_keys,
                           uint64_t max_keys_each) {
-  if (!k_supported(k) || nheaps == 0) return 0;
+  if (!k_supported(k) || nheaps == 0 || entry_bytes(keytype) == 0) return 0;
   Layout L;
-  if (!make_layout(k, nheaps, max_keys, max_keys_each, L)) return 0;
+  if (!make_layout(k, entry_bytes(keytype), nheaps, max_keys, max_keys_each, L)) return 0;
   return L.total;
 }
 
@@ -279,16 +284,20 @@ int heap_supported_shape(uint32_t k, uint32_t threads) {
   return k_supported(k) && shape_ok((int)k, (int)threads) ? 1 : 0;
 }
 
-int heap_create_many(gh_heap_t* out, uint32_t k, uint32_t nheaps, const uint64_t* max_keys,
-                     void* d_arena, uint64_t arena_bytes, void* stream) {
-  if (!out || !d_arena || !max_keys || nheaps == 0 || !k_supported(k)) return GH_EINVAL;
+int heap_create_many(gh_heap_t* out, uint32_t k, int keytype, uint32_t nheaps,
+                     const uint64_t* max_keys, void* d_arena, uint64_t arena_bytes,
+                     void* stream) {
+  const u32 eb = entry_bytes(keytype);
+  if (!out || !d_arena || !max_keys || nheaps == 0 || !k_supported(k) || eb == 0)
+    return GH_EINVAL;
   if ((reinterpret_cast<uintptr_t>(d_arena) & (ALIGN - 1)) != 0) return GH_EINVAL;
   Layout L;
-  if (!make_layout(k, nheaps, max_keys, 0, L)) return GH_EINVAL;
+  if (!make_layout(k, eb, nheaps, max_keys, 0, L)) return GH_EINVAL;
   if (arena_bytes < L.total) return GH_ENOMEM;
   gh_heap* h = new (std::nothrow) gh_heap();
   if (!h) return GH_ENOMEM;
   h->k = k;
+  h->ebytes = eb;
   h->nheaps = nheaps;
   h->stream = reinterpret_cast<hipStream_t>(stream);
   h->arena = reinterpret_cast<unsigned char*>(d_arena);
@@ -312,6 +321,7 @@ int heap_create_many(gh_heap_t* out, uint32_t k, uint32_t nheaps, const uint64_t
     d.max_nodes = (u32)L.max_nodes[i];
     d.k = k;
     d.max_keys = max_keys[i];
+    d.ewords = eb / 8;
   }
   if (launch_init(h->descs, h->host_descs.data(), nheaps, h->ctl, watchdog_ticks(h->clock_mhz),
                   h->stream) != hipSuccess) {
@@ -322,12 +332,12 @@ int heap_create_many(gh_heap_t* out, uint32_t k, uint32_t nheaps, const uint64_t
   return GH_OK;
 }
 
-int heap_create(gh_heap_t* out, uint32_t k, uint64_t max_keys, void* d_arena,
+int heap_create(gh_heap_t* out, uint32_t k, uint64_t max_keys, int keytype, void* d_arena,
                 uint64_t arena_bytes, void* stream) {
-  return heap_create_many(out, k, 1, &max_keys, d_arena, arena_bytes, stream);
+  return heap_create_many(out, k, keytype, 1, &max_keys, d_arena, arena_bytes, stream);
 }
 
-int heap_insert(gh_heap_t h, const uint64_t* d_keys, uint64_t n) {
+int heap_insert(gh_heap_t h, const void* d_keys, uint64_t n) {
   if (!h) return GH_EINVAL;
   if (h->sticky != GH_OK) return h->sticky;
   if (n == 0) return GH_OK;
@@ -347,7 +357,7 @@ int heap_insert(gh_heap_t h, const uint64_t* d_keys, uint64_t n) {
   return rc;
 }
 
-int heap_build(gh_heap_t h, uint32_t i, const uint64_t* d_sorted, uint64_t n) {
+int heap_build(gh_heap_t h, uint32_t i, const void* d_sorted, uint64_t n) {
   if (!h) return GH_EINVAL;
   if (h->sticky != GH_OK) return h->sticky;
   if (i >= h->nheaps) return GH_EINVAL;
@@ -355,13 +365,14 @@ int heap_build(gh_heap_t h, uint32_t i, const uint64_t* d_sorted, uint64_t n) {
   if (!d_sorted) return GH_EINVAL;
   if (n > h->max_keys[i]) return GH_ENOMEM;
   if (i == 0) h->size0_known = false;
-  if (launch_build(h->descs + i, d_sorted, n, h->ctl, h->stream) != hipSuccess) return GH_EDEVICE;
+  if (launch_build(h->descs + i, d_sorted, n, h->ebytes / 8, h->ctl, h->stream) != hipSuccess)
+    return GH_EDEVICE;
   return GH_OK;
 }
 
 uint64_t heap_filter_workspace_bytes(gh_heap_t h, uint32_t i) {
   if (!h || i >= h->nheaps) return 0;
-  return filter_workspace_bytes(h->host_descs[i].max_nodes, h->k);
+  return filter_workspace_bytes(h->host_descs[i].max_nodes, h->k, h->ebytes);
 }
 
 int heap_filter(gh_heap_t h, uint32_t i, uint64_t bound, void* d_work, uint64_t work_bytes,
@@ -369,15 +380,16 @@ int heap_filter(gh_heap_t h, uint32_t i, uint64_t bound, void* d_work, uint64_t 
   if (!h || i >= h->nheaps || !d_work) return GH_EINVAL;
   if (h->sticky != GH_OK) return h->sticky;
   if ((reinterpret_cast<uintptr_t>(d_work) & (ALIGN - 1)) != 0) return GH_EINVAL;
-  if (work_bytes < filter_workspace_bytes(h->host_descs[i].max_nodes, h->k)) return GH_EINVAL;
+  if (work_bytes < filter_workspace_bytes(h->host_descs[i].max_nodes, h->k, h->ebytes))
+    return GH_EINVAL;
   if (i == 0) h->size0_known = false;
-  if (launch_filter(h->descs + i, h->host_descs[i].max_nodes, h->k, bound, d_work, d_kept,
-                    h->stream) != hipSuccess)
+  if (launch_filter(h->descs + i, h->host_descs[i].max_nodes, h->k, h->ebytes, bound, d_work,
+                    d_kept, h->stream) != hipSuccess)
     return GH_EDEVICE;
   return GH_OK;
 }
 
-int heap_delete_min(gh_heap_t h, uint64_t* d_out, uint32_t c, uint32_t* d_count) {
+int heap_delete_min(gh_heap_t h, void* d_out, uint32_t c, uint32_t* d_count) {
   if (!h || !d_out || !d_count || c == 0 || c > h->k) return GH_EINVAL;
   if (h->sticky != GH_OK) return h->sticky;
   OpParams p{GH_OP_DELETE_MIN, 0, c, 0, 0};
@@ -387,8 +399,8 @@ int heap_delete_min(gh_heap_t h, uint64_t* d_out, uint32_t c, uint32_t* d_count)
   return rc;
 }
 
-int heap_submit(gh_heap_t h, const gh_op* d_ops, uint32_t nops, const uint64_t* d_in,
-                uint64_t* d_out, uint32_t* d_counts, gh_logrec* d_log, const gh_tuning* tuning) {
+int heap_submit(gh_heap_t h, const gh_op* d_ops, uint32_t nops, const void* d_in, void* d_out,
+                uint32_t* d_counts, gh_logrec* d_log, const gh_tuning* tuning) {
   if (!h) return GH_EINVAL;
   if (h->sticky != GH_OK) return h->sticky;
   if (nops == 0) return GH_OK;
@@ -398,8 +410,8 @@ int heap_submit(gh_heap_t h, const gh_op* d_ops, uint32_t nops, const uint64_t* 
   return run_ops(h, d_ops, nops, p, d_in, d_out, d_counts, d_log, tuning);
 }
 
-int heap_submit_graph(gh_heap_t h, const gh_op* d_ops, uint32_t nops, const uint64_t* d_in,
-                      uint64_t* d_out, uint32_t* d_counts, gh_logrec* d_log,
+int heap_submit_graph(gh_heap_t h, const gh_op* d_ops, uint32_t nops, const void* d_in,
+                      void* d_out, uint32_t* d_counts, gh_logrec* d_log,
                       const gh_tuning* tuning, void** graph_out) {
   if (!h || !graph_out || !d_ops || nops == 0) return GH_EINVAL;
   if (h->sticky != GH_OK) return h->sticky;
@@ -444,9 +456,9 @@ uint64_t heap_serve_workspace_bytes(uint32_t nheaps, uint32_t nreq, uint64_t max
   return serve_layout(nheaps, nreq, max_ops).total;
 }
 
-int heap_serve(gh_heap_t h, const gh_op* d_reqs, uint32_t nreq, const uint64_t* d_in,
-               uint64_t* d_out, gh_reqrec* d_recs, void* d_work, uint64_t work_bytes,
-               uint64_t max_ops, const gh_tuning* t) {
+int heap_serve(gh_heap_t h, const gh_op* d_reqs, uint32_t nreq, const void* d_in, void* d_out,
+               gh_reqrec* d_recs, void* d_work, uint64_t work_bytes, uint64_t max_ops,
+               const gh_tuning* t) {
   if (!h) return GH_EINVAL;
   if (h->sticky != GH_OK) return h->sticky;
   if (nreq == 0) return GH_OK;
@@ -459,7 +471,8 @@ int heap_serve(gh_heap_t h, const gh_op* d_reqs, uint32_t nreq, const uint64_t* 
   u32 wg = (t && t->workgroups) ? t->workgroups : 512;
   // the scheduler keeps 32 bytes per heap and 8 per thread in LDS next to
   // the k-entry buffers
-  if ((u64)h->nheaps * 32 + (u64)threads * 8 + (u64)h->k * 40 + 1024 > 65536) return GH_EINVAL;
+  if ((u64)h->nheaps * 32 + (u64)threads * 8 + (u64)h->k * 5 * h->ebytes + 1024 > 65536)
+    return GH_EINVAL;
   h->size0_known = false;
   unsigned char* base = reinterpret_cast<unsigned char*>(d_work);
   ServeArgs a{};
@@ -467,8 +480,8 @@ int heap_serve(gh_heap_t h, const gh_op* d_reqs, uint32_t nreq, const uint64_t* 
   a.nheaps = h->nheaps;
   a.reqs = d_reqs;
   a.nreq = nreq;
-  a.in = d_in;
-  a.out = d_out;
+  a.in = static_cast<const u64*>(d_in);
+  a.out = static_cast<u64*>(d_out);
   a.recs = d_recs;
   a.w.head = reinterpret_cast<ServeHead*>(base + L.head);
   a.w.heaps = reinterpret_cast<HeapSched*>(base + L.heaps);
@@ -490,13 +503,14 @@ int heap_serve(gh_heap_t h, const gh_op* d_reqs, uint32_t nreq, const uint64_t* 
 
 int heap_knapsack(gh_heap_t h, uint32_t ninst, const uint32_t* d_item_off, const uint32_t* d_n,
                   const uint64_t* d_cap, const uint32_t* d_w, const uint32_t* d_v,
-                  uint64_t* d_pool, uint64_t pool_per_inst, uint64_t* d_scratch,
-                  gh_knapres* d_res, const gh_tuning* t) {
+                  uint64_t* d_pool, uint64_t pool_per_inst, void* d_scratch, gh_knapres* d_res,
+                  uint32_t gc_min, const gh_tuning* t) {
   if (!h) return GH_EINVAL;
   if (h->sticky != GH_OK) return h->sticky;
   if (ninst == 0) return GH_OK;
   if (ninst > h->nheaps || !d_item_off || !d_n || !d_cap || !d_w || !d_v || !d_pool ||
-      !d_scratch || !d_res || pool_per_inst == 0 || pool_per_inst >= (1ull << 29))
+      !d_scratch || !d_res || pool_per_inst == 0 ||
+      pool_per_inst >= (h->ebytes == 8 ? (1ull << 29) : (1ull << 32)))
     return GH_EINVAL;
   for (u32 i = 0; i < ninst; ++i)
     if (h->max_keys[i] < pool_per_inst) return GH_ENOMEM;
@@ -515,6 +529,7 @@ int heap_knapsack(gh_heap_t h, uint32_t ninst, const uint32_t* d_item_off, const
   a.pool = d_pool;
   a.pool_per_inst = pool_per_inst;
   a.scratch = d_scratch;
+  a.gc_min = gc_min;
   a.res = d_res;
   a.ctl = h->ctl;
   a.workgroups = wg;
@@ -532,7 +547,7 @@ int heap_sssp(gh_heap_t h, uint32_t V, const uint32_t* d_rowptr, const uint32_t*
   if (!h) return GH_EINVAL;
   if (h->sticky != GH_OK) return h->sticky;
   if (V == 0 || src >= V || !d_rowptr || !d_col || !d_w || !d_dist || !d_push || !d_stats ||
-      push_per_wg == 0)
+      push_per_wg == 0 || h->ebytes != 8)
     return GH_EINVAL;
   if (trace && (!trace->d_ops || !trace->d_keys)) return GH_EINVAL;
   u32 threads = (t && t->threads) ? t->threads : default_threads(h->k);
@@ -602,8 +617,8 @@ int heap_size(gh_heap_t h, uint32_t i, uint64_t* out_host) {
   return rc;
 }
 
-int heap_read_state(gh_heap_t h, uint32_t i, uint64_t* meta_host, uint64_t* nodes_host,
-                    uint64_t* pb_host) {
+int heap_read_state(gh_heap_t h, uint32_t i, uint64_t* meta_host, void* nodes_host,
+                    void* pb_host) {
   if (!h || !meta_host || i >= h->nheaps) return GH_EINVAL;
   if (hipStreamSynchronize(h->stream) != hipSuccess) return GH_EDEVICE;
   const HeapDesc& d = h->host_descs[i];
@@ -615,11 +630,11 @@ int heap_read_state(gh_heap_t h, uint32_t i, uint64_t* meta_host, uint64_t* node
   meta_host[2] = m.base + ((rw_ticket(m.root) - m.base) & RW_TICKET_MASK);
   meta_host[3] = d.max_nodes;
   if (nodes_host &&
-      hipMemcpy(nodes_host, d.nodes, (u64)d.max_nodes * h->k * 8, hipMemcpyDeviceToHost) !=
+      hipMemcpy(nodes_host, d.nodes, (u64)d.max_nodes * h->k * h->ebytes, hipMemcpyDeviceToHost) !=
           hipSuccess)
     return GH_EDEVICE;
   if (pb_host && ss > 0 &&
-      hipMemcpy(pb_host, d.pb, ss * 8, hipMemcpyDeviceToHost) != hipSuccess)
+      hipMemcpy(pb_host, d.pb, ss * h->ebytes, hipMemcpyDeviceToHost) != hipSuccess)
     return GH_EDEVICE;
   return GH_OK;
 }

@@ -25,6 +25,9 @@ GH_ESTATE = -5
 
 OP_INSERT = 0
 OP_DELETE_MIN = 1
+GH_U32_ID = 0    # 8-byte entries: u32 key above u32 id
+GH_I64_ID = 1    # 16-byte entries: biased i64 key word, then u32 id and u32 zero
+ENTRY_WORDS = {GH_U32_ID: 1, GH_I64_ID: 2}
 SUPPORTED_K = (32, 64, 128, 256, 512, 1024)
 ENTRY_MAX = 0xFFFFFFFFFFFFFFFF
 
@@ -38,9 +41,10 @@ REQ_DTYPE = np.dtype([("first_ticket", "<u8"), ("count", "<u4"), ("nops", "<u2")
                       ("flags", "u1"), ("t_admit", "<u4"), ("t_done", "<u4"), ("t_resp", "<u4"),
                       ("reserved", "<u4")])
 KNAP_DTYPE = np.dtype([("best", "<u8"), ("explored", "<u8"), ("created", "<u8"),
-                       ("popped", "<u8"), ("ops", "<u4"), ("flags", "<u4")])
+                       ("popped", "<u8"), ("gc_dropped", "<u8"), ("ops", "<u4"), ("flags", "<u4"),
+                       ("gc_runs", "<u4"), ("reserved", "<u4")])
 assert OP_DTYPE.itemsize == 32 and LOG_DTYPE.itemsize == 32 and REQ_DTYPE.itemsize == 32
-assert KNAP_DTYPE.itemsize == 40
+assert KNAP_DTYPE.itemsize == 56
 SSSP_DTYPE = np.dtype([("popped", "<u8"), ("stale", "<u8"), ("pushed", "<u8"), ("heap_ops", "<u8"),
                        ("heap_ticks", "<u8"), ("relax_ticks", "<u8"), ("rounds", "<u8"),
                        ("traced", "<u8")])
@@ -101,10 +105,10 @@ def load_library(path: str = LIB_PATH):
     lib = ctypes.CDLL(path)
     vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
     sig = {
-        "heap_arena_bytes": (u64, [u32, u32, vp, u64]),
+        "heap_arena_bytes": (u64, [u32, i32, u32, vp, u64]),
         "heap_supported_shape": (i32, [u32, u32]),
-        "heap_create": (i32, [ctypes.POINTER(vp), u32, u64, vp, u64, vp]),
-        "heap_create_many": (i32, [ctypes.POINTER(vp), u32, u32, vp, vp, u64, vp]),
+        "heap_create": (i32, [ctypes.POINTER(vp), u32, u64, i32, vp, u64, vp]),
+        "heap_create_many": (i32, [ctypes.POINTER(vp), u32, i32, u32, vp, vp, u64, vp]),
         "heap_insert": (i32, [vp, vp, u64]),
         "heap_delete_min": (i32, [vp, vp, u32, vp]),
         "heap_submit": (i32, [vp, vp, u32, vp, vp, vp, vp, ctypes.POINTER(_Tuning)]),
@@ -120,7 +124,7 @@ def load_library(path: str = LIB_PATH):
         "heap_clock_hz": (u64, []),
         "heap_serve_workspace_bytes": (u64, [u32, u32, u64]),
         "heap_serve": (i32, [vp, vp, u32, vp, vp, vp, vp, u64, u64, ctypes.POINTER(_Tuning)]),
-        "heap_knapsack": (i32, [vp, u32, vp, vp, vp, vp, vp, vp, u64, vp, vp,
+        "heap_knapsack": (i32, [vp, u32, vp, vp, vp, vp, vp, vp, u64, vp, vp, u32,
                                 ctypes.POINTER(_Tuning)]),
         "heap_sssp": (i32, [vp, u32, vp, vp, vp, u32, vp, vp, u64, vp,
                             ctypes.POINTER(_Tuning), ctypes.POINTER(SsspTrace)]),
@@ -167,19 +171,37 @@ def _ptr(t, dtypes=None, min_bytes: int = 0, what: str = "tensor") -> int | None
 
 
 def to_device_u64(a: np.ndarray, device="cuda") -> torch.Tensor:
-    """uint64 numpy array -> int64 device tensor holding the same bits."""
-    a = np.ascontiguousarray(a, dtype=np.uint64)
+    """uint64 numpy array -> int64 device tensor holding the same bits (a
+    2-D array of 16-byte entries [n, 2] is flattened, entry by entry)."""
+    a = np.ascontiguousarray(a, dtype=np.uint64).reshape(-1)
     return torch.from_numpy(a.view(np.int64)).to(device)
 
 
-def to_host_u64(t: torch.Tensor) -> np.ndarray:
-    return t.cpu().numpy().view(np.uint64)
+def to_host_u64(t: torch.Tensor, ewords: int = 1) -> np.ndarray:
+    """Device entries -> uint64 numpy array ([n, 2] for 16-byte entries)."""
+    a = t.cpu().numpy().view(np.uint64).reshape(-1)
+    return a.reshape(-1, 2) if ewords == 2 else a
 
 
-def arena_bytes(k: int, max_keys) -> int:
+def pack_i64(keys, ids) -> np.ndarray:
+    """16-byte entries [n, 2] uint64 from signed 64-bit keys and 32-bit ids:
+    the key word is the key XOR 2^63 (so it orders as unsigned), the id word
+    the id with 32 zero bits above it."""
+    k = np.asarray(keys, dtype=np.int64).view(np.uint64) ^ np.uint64(1 << 63)
+    i = np.asarray(ids, dtype=np.uint64) & np.uint64(0xFFFFFFFF)
+    return np.ascontiguousarray(np.stack([k, i], axis=1))
+
+
+def unpack_i64(entries):
+    """(keys int64, ids uint32) of [n, 2] 16-byte entries."""
+    e = np.asarray(entries, dtype=np.uint64).reshape(-1, 2)
+    return (e[:, 0] ^ np.uint64(1 << 63)).view(np.int64), (e[:, 1] & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+
+
+def arena_bytes(k: int, max_keys, keytype: int = GH_U32_ID) -> int:
     lib = load_library()
     mk = np.ascontiguousarray(np.atleast_1d(np.asarray(max_keys, dtype=np.uint64)))
-    return int(lib.heap_arena_bytes(k, mk.size, mk.ctypes.data, 0))
+    return int(lib.heap_arena_bytes(k, keytype, mk.size, mk.ctypes.data, 0))
 
 
 def supported_shape(k: int, threads: int) -> bool:
@@ -194,21 +216,27 @@ class HeapSet:
     """One or more device heaps sharing node capacity k, an arena and a stream."""
 
     def __init__(self, k: int, max_keys, device: str | torch.device = "cuda",
-                 stream: torch.cuda.Stream | None = None):
+                 stream: torch.cuda.Stream | None = None, keytype: int = GH_U32_ID):
         self.lib = load_library()
         self.k = int(k)
+        if keytype not in ENTRY_WORDS:
+            raise GHeapError(GH_EINVAL, "keytype")
+        self.keytype = int(keytype)
+        self.ewords = ENTRY_WORDS[self.keytype]   # 8-byte words per entry
+        self.ebytes = 8 * self.ewords
         mk = np.ascontiguousarray(np.atleast_1d(np.asarray(max_keys, dtype=np.uint64)))
         self.nheaps = int(mk.size)
         self.max_keys = mk
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        nbytes = int(self.lib.heap_arena_bytes(self.k, self.nheaps, mk.ctypes.data, 0))
+        nbytes = int(self.lib.heap_arena_bytes(self.k, self.keytype, self.nheaps, mk.ctypes.data, 0))
         if nbytes == 0:
             raise GHeapError(GH_EINVAL, "heap_arena_bytes")
         # 256-byte alignment: torch's caching allocator returns 512-aligned blocks
         self.arena = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         h = ctypes.c_void_p()
-        rc = self.lib.heap_create_many(ctypes.byref(h), self.k, self.nheaps, mk.ctypes.data,
+        rc = self.lib.heap_create_many(ctypes.byref(h), self.k, self.keytype, self.nheaps,
+                                       mk.ctypes.data,
                                        self.arena.data_ptr(), nbytes,
                                        ctypes.c_void_p(self.stream.cuda_stream))
         _check(rc, "heap_create_many")
@@ -217,9 +245,10 @@ class HeapSet:
 
     # -- single-heap calls (heap 0) -------------------------------------
     def insert(self, keys: torch.Tensor) -> None:
-        """Insert a 1-D int64/uint64 device tensor of entries into heap 0."""
-        _check(self.lib.heap_insert(self.h, _ptr(keys, _U64, what="keys"), keys.numel()),
-               "heap_insert")
+        """Insert a contiguous int64/uint64 device tensor of entries (one
+        word an entry, or two for 16-byte entries) into heap 0."""
+        _check(self.lib.heap_insert(self.h, _ptr(keys, _U64, what="keys"),
+                                    keys.numel() // self.ewords), "heap_insert")
 
     def delete_min(self, out: torch.Tensor | None = None, count: torch.Tensor | None = None,
                    c: int | None = None):
@@ -227,10 +256,10 @@ class HeapSet:
         tensor with room for c, count int32 tensor)."""
         c = self.k if c is None else int(c)
         if out is None:
-            out = torch.empty(max(c, 1), dtype=torch.int64, device=self.device)
+            out = torch.empty(max(c, 1) * self.ewords, dtype=torch.int64, device=self.device)
         if count is None:
             count = torch.zeros(1, dtype=torch.int32, device=self.device)
-        _check(self.lib.heap_delete_min(self.h, _ptr(out, _U64, 8 * c, "out"), c,
+        _check(self.lib.heap_delete_min(self.h, _ptr(out, _U64, self.ebytes * c, "out"), c,
                                         _ptr(count, (torch.int32,), 4, "count")),
                "heap_delete_min")
         return out, count
@@ -284,14 +313,15 @@ class HeapSet:
         rc = self.lib.heap_serve(self.h, _ptr(reqs, None, nreq * OP_DTYPE.itemsize, "reqs"), nreq,
                                  _ptr(d_in, _U64, 0, "d_in"), _ptr(d_out, _U64, 0, "d_out"),
                                  _ptr(recs, None, nreq * REQ_DTYPE.itemsize, "recs"),
-                                 work.data_ptr(), work.numel(), max_ops, ctypes.byref(t))
+                                 _ptr(work, (torch.uint8,), need, "work"), work.numel(), max_ops,
+                                 ctypes.byref(t))
         _check(rc, "heap_serve")
         return work
 
     def build(self, i: int, sorted_keys: torch.Tensor):
         """Bulk-build empty heap i from an ascending int64 tensor of entries."""
         _check(self.lib.heap_build(self.h, i, _ptr(sorted_keys, _U64, what="sorted_keys"),
-                                   sorted_keys.numel()), "heap_build")
+                                   sorted_keys.numel() // self.ewords), "heap_build")
 
     def filter(self, i: int, bound: int, work: torch.Tensor | None = None):
         """Remove every entry >= bound from heap i (stream-ordered).  Returns
@@ -302,7 +332,8 @@ class HeapSet:
         if work is None or work.numel() < need:
             work = torch.empty(need, dtype=torch.uint8, device=self.device)
         kept = torch.zeros(1, dtype=torch.int64, device=self.device)
-        _check(self.lib.heap_filter(self.h, i, int(bound), work.data_ptr(), work.numel(),
+        _check(self.lib.heap_filter(self.h, i, int(bound), _ptr(work, (torch.uint8,), need, "work"),
+                                    work.numel(),
                                     _ptr(kept)), "heap_filter")
         return kept, work
 
@@ -315,16 +346,20 @@ class HeapSet:
         return int(v.value)
 
     def read_state(self, i: int = 0):
-        """(m, s, served, max_nodes, nodes[max_nodes, k] uint64, pb[s] uint64)."""
+        """(m, s, served, max_nodes, nodes[max_nodes, k] uint64, pb[s] uint64);
+        16-byte entries: nodes[max_nodes, k, 2], pb[s, 2]."""
         meta = np.zeros(4, dtype=np.uint64)
         _check(self.lib.heap_read_state(self.h, i, meta.ctypes.data, None, None),
                "heap_read_state")
-        nodes = np.empty(int(meta[3]) * self.k, dtype=np.uint64)
-        pb = np.empty(max(int(meta[1]), 1), dtype=np.uint64)
+        w = self.ewords
+        nodes = np.empty(int(meta[3]) * self.k * w, dtype=np.uint64)
+        pb = np.empty(max(int(meta[1]), 1) * w, dtype=np.uint64)
         _check(self.lib.heap_read_state(self.h, i, meta.ctypes.data, nodes.ctypes.data,
                                         pb.ctypes.data), "heap_read_state")
+        shape = (int(meta[3]), self.k) + ((2,) if w == 2 else ())
+        pb = pb.reshape(-1, 2) if w == 2 else pb
         return (int(meta[0]), int(meta[1]), int(meta[2]), int(meta[3]),
-                nodes.reshape(int(meta[3]), self.k), pb[: int(meta[1])].copy())
+                nodes.reshape(shape), pb[: int(meta[1])].copy())
 
     def close(self) -> int:
         rc = GH_OK
@@ -346,8 +381,8 @@ class HeapSet:
 class Heap(HeapSet):
     """A single device heap (heap_create)."""
 
-    def __init__(self, k: int, max_keys: int, device="cuda", stream=None):
-        super().__init__(k, [max_keys], device=device, stream=stream)
+    def __init__(self, k: int, max_keys: int, device="cuda", stream=None, keytype=GH_U32_ID):
+        super().__init__(k, [max_keys], device=device, stream=stream, keytype=keytype)
 
 
 def ops_to_device(oplist, device="cuda"):
@@ -363,10 +398,16 @@ def ops_to_device(oplist, device="cuda"):
     if oplist.arrival is not None:
         rec["arrival_ns"] = oplist.arrival
     ops = torch.from_numpy(rec.view(np.uint8).copy()).to(device)
-    keys = to_device_u64(oplist.keys if oplist.keys.size else np.zeros(1, np.uint64), device)
-    out = torch.full((max(oplist.out_entries, 1),), -1, dtype=torch.int64, device=device)
+    w = entry_words(oplist)
+    keys = to_device_u64(oplist.keys if oplist.keys.size else np.zeros(w, np.uint64), device)
+    out = torch.full((max(oplist.out_entries, 1) * w,), -1, dtype=torch.int64, device=device)
     counts = torch.zeros(max(n, 1), dtype=torch.int32, device=device)
     return ops, n, keys, out, counts
+
+
+def entry_words(oplist) -> int:
+    """8-byte words per entry of an op list: 2 when its keys are [n, 2]."""
+    return 2 if oplist.keys.ndim == 2 else 1
 
 
 def new_log(nops: int, device="cuda") -> torch.Tensor:
@@ -393,8 +434,9 @@ def requests_to_device(oplist, device="cuda"):
     ins = oplist.kind == OP_INSERT
     max_ops = int(np.sum(-(-oplist.n[ins].astype(np.int64) // k))) + int((~ins).sum())
     reqs = torch.from_numpy(rec.view(np.uint8).copy()).to(device)
-    keys = to_device_u64(oplist.keys if oplist.keys.size else np.zeros(1, np.uint64), device)
-    out = torch.full((max(oplist.out_entries, 1),), -1, dtype=torch.int64, device=device)
+    w = entry_words(oplist)
+    keys = to_device_u64(oplist.keys if oplist.keys.size else np.zeros(w, np.uint64), device)
+    out = torch.full((max(oplist.out_entries, 1) * w,), -1, dtype=torch.int64, device=device)
     recs = torch.zeros(max(n, 1) * REQ_DTYPE.itemsize, dtype=torch.uint8, device=device)
     return reqs, n, keys, out, recs, max(max_ops, 1)
 

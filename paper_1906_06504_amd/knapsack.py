@@ -1,5 +1,5 @@
 """0/1 knapsack by best-first branch and bound on the device heaps (the
-application of Sec. 5.6.2): host-side preparation and the call into
+application of Sec. 5.7.2): host-side preparation and the call into
 heap_knapsack.  The search itself runs in the HIP library."""
 from __future__ import annotations
 
@@ -23,17 +23,25 @@ def ratio_order(w: np.ndarray, v: np.ndarray) -> np.ndarray:
     return np.array(sorted(range(len(w)), key=functools.cmp_to_key(cmp)), dtype=np.int64)
 
 
-class Instances:
-    """Instances packed for the device (items sorted by ratio)."""
+# Largest value sum an instance may have, by key type: the 8-byte entry packs
+# a 35-bit bound, the 16-byte one is limited by the node pool's 28-bit fields.
+VALUE_SUM_LIMIT = {G.GH_U32_ID: 1 << 18, G.GH_I64_ID: 1 << 28}
 
-    def __init__(self, instances, device="cuda"):
+
+class Instances:
+    """Instances packed for the device (items sorted by ratio).  With
+    check=True instances beyond the library's limits raise here; otherwise
+    they reach the device, which refuses them (result flag bit 5)."""
+
+    def __init__(self, instances, device="cuda", keytype: int = G.GH_I64_ID, check: bool = True):
         offs, ns, caps, ws, vs = [], [], [], [], []
         off = 0
         for (w, v, c) in instances:
-            if len(w) > 255:
+            if check and len(w) > 255:
                 raise ValueError("at most 255 items per instance")
-            if int(np.asarray(v, dtype=np.int64).sum()) >= (1 << 18) or c >= (1 << 28):
-                raise ValueError("values or capacity too large for the 35-bit bound")
+            if check and (int(np.asarray(v, dtype=np.int64).sum()) >= VALUE_SUM_LIMIT[keytype]
+                          or c >= (1 << 28)):
+                raise ValueError("values or capacity too large for the entry's bound")
             o = ratio_order(w, v)
             offs.append(off)
             ns.append(len(w))
@@ -55,32 +63,44 @@ class Solver:
     """Heaps, node pools and scratch for solving a batch of instances."""
 
     def __init__(self, ninst: int, k: int, pool_per_inst: int = 1 << 20, device="cuda",
-                 stream=None):
+                 stream=None, keytype: int = G.GH_I64_ID):
         self.k = k
         self.ninst = ninst
         self.pool_per_inst = pool_per_inst
-        self.hs = G.HeapSet(k, [pool_per_inst] * ninst, device=device, stream=stream)
+        self.hs = G.HeapSet(k, [pool_per_inst] * ninst, device=device, stream=stream,
+                            keytype=keytype)
         self.snapshot = self.hs.arena.clone()
         self.pool = torch.empty(ninst * pool_per_inst, dtype=torch.int64, device=device)
-        self.scratch = torch.empty(ninst * 3 * k, dtype=torch.int64, device=device)
+        self.scratch = torch.empty(ninst * 3 * k * self.hs.ewords, dtype=torch.int64,
+                                   device=device)
         self.res = torch.zeros(ninst * G.KNAP_DTYPE.itemsize, dtype=torch.uint8, device=device)
 
-    def run(self, inst: Instances, workgroups: int = 0, threads: int = 0, reset: bool = True):
-        """Solve; returns the per-instance result records (numpy)."""
+    def launch(self, inst: Instances, workgroups: int = 0, threads: int = 0, reset: bool = True,
+               gc_min: int = 0):
+        """Queue the solve on the set's stream (no wait).  gc_min > 0 turns
+        on garbage collection of heaps holding at least gc_min entries."""
+        import ctypes
         if reset:
             self.hs.arena.copy_(self.snapshot)
         t = G._Tuning(workgroups, threads)
-        import ctypes
         rc = self.hs.lib.heap_knapsack(self.hs.h, inst.n, inst.item_off.data_ptr(),
                                        inst.nitems.data_ptr(), inst.caps.data_ptr(),
                                        inst.w.data_ptr(), inst.v.data_ptr(), self.pool.data_ptr(),
                                        self.pool_per_inst, self.scratch.data_ptr(),
-                                       self.res.data_ptr(), ctypes.byref(t))
+                                       self.res.data_ptr(), int(gc_min), ctypes.byref(t))
         G._check(rc, "heap_knapsack")
+
+    def results(self, n: int):
+        return self.res.cpu().numpy().view(G.KNAP_DTYPE)[:n].copy()
+
+    def run(self, inst: Instances, workgroups: int = 0, threads: int = 0, reset: bool = True,
+            gc_min: int = 0, allow_device_error: bool = False):
+        """Solve; returns the per-instance result records (numpy)."""
+        self.launch(inst, workgroups, threads, reset, gc_min)
         rc = self.hs.sync()
-        if rc != G.GH_OK:
+        if rc != G.GH_OK and not allow_device_error:
             raise G.GHeapError(rc, "heap_knapsack (device)")
-        return self.res.cpu().numpy().view(G.KNAP_DTYPE)[: inst.n].copy()
+        return self.results(inst.n)
 
     def close(self):
         self.hs.close()

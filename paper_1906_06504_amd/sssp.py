@@ -1,5 +1,5 @@
 """Single-source shortest paths with a device heap as the shared priority
-queue (the application of Sec. 5.6.1): host-side preparation and the call
+queue (the application of Sec. 5.7.1): host-side preparation and the call
 into heap_sssp.  The search itself runs in the HIP library."""
 from __future__ import annotations
 

@@ -242,6 +242,30 @@ def mixed_ops(total_requested: int, k: int, seed: int, first_id: int,
     return build_oplist(kinds, sizes, _keys_with_ids(key_stream, first_id), k)
 
 
+def wide_entries(keys: np.ndarray, ids: np.ndarray) -> np.ndarray:
+    """16-byte entries [n, 2] uint64 in the device layout: word 0 = the signed
+    64-bit key XOR 2^63 (so that it orders as unsigned), word 1 = the 32-bit
+    id (32 zero bits above it)."""
+    k = np.asarray(keys, dtype=np.int64).view(np.uint64) ^ np.uint64(1 << 63)
+    i = np.asarray(ids, dtype=np.uint64) & np.uint64(0xFFFFFFFF)
+    return np.ascontiguousarray(np.stack([k, i], axis=1))
+
+
+def to_wide(ops: OpList, seed: int, key_bits: int = 64) -> OpList:
+    """The same operation list with 16-byte entries: each entry keeps its id
+    (the low 32 bits of its 8-byte form) and gets a fresh signed key drawn
+    uniformly from [-2^(key_bits-1), 2^(key_bits-1)) (key_bits < 64 makes
+    equal keys with distinct ids common)."""
+    ids = ops.keys & np.uint64(0xFFFFFFFF)
+    raw = Stream(seed).u64(ids.size)
+    if key_bits < 64:
+        raw = (raw >> np.uint64(64 - key_bits)).astype(np.int64) - np.int64(1 << (key_bits - 1))
+    keys = raw.view(np.int64) if raw.dtype == np.uint64 else raw
+    out = OpList(ops.kind, ops.n, ops.off, wide_entries(keys, ids), ops.out_entries,
+                 ops.heap, ops.arrival, dict(ops.meta))
+    return out
+
+
 def concat(a: OpList, b: OpList, k: int) -> OpList:
     """Ops of a followed by ops of b (b's offsets shifted past a's buffers)."""
     kind = np.concatenate([a.kind, b.kind])

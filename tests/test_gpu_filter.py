@@ -1,5 +1,5 @@
 """GPU tests of the heap filter (garbage collection of a branch-and-bound
-search, Sec. 5.6.2): every entry >= a bound is removed and the rest laid
+search, Sec. 5.7.2): every entry >= a bound is removed and the rest laid
 out again as a bulk build (Sec. 3.1).  Both the HIP path and the oracle lay
 the kept entries out as the build of their sorted sequence, so after a
 filter the node array and partial buffer are compared with the oracle's bit

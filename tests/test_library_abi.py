@@ -43,17 +43,24 @@ def test_binding_lists_every_export():
 
 def test_host_only_calls(lib):
     lib.heap_arena_bytes.restype = ctypes.c_uint64
-    lib.heap_arena_bytes.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint64]
-    assert lib.heap_arena_bytes(1000, 1, None, 100) == 0          # unsupported k
-    a = lib.heap_arena_bytes(1024, 1, None, 1 << 22)
-    b = lib.heap_arena_bytes(1024, 1, None, 1 << 23)
+    lib.heap_arena_bytes.argtypes = [ctypes.c_uint32, ctypes.c_int, ctypes.c_uint32,
+                                     ctypes.c_void_p, ctypes.c_uint64]
+    f = lambda *a: lib.heap_arena_bytes(a[0], 0, *a[1:])     # 8-byte entries  # noqa: E731
+    assert f(1000, 1, None, 100) == 0          # unsupported k
+    a = f(1024, 1, None, 1 << 22)
+    b = f(1024, 1, None, 1 << 23)
     assert a > (1 << 22) * 8 and b > a
-    assert lib.heap_arena_bytes(1024, 0, None, 1024) == 0
-    assert lib.heap_arena_bytes(64, 1 << 20, None, 64) > 0
-    assert lib.heap_arena_bytes(64, (1 << 20) + 1, None, 64) == 0     # heaps per set
-    assert lib.heap_arena_bytes(64, 0xFFFFFFFF, None, 1 << 40) == 0
-    assert lib.heap_arena_bytes(32, 1, None, ((1 << 30) - 2) * 32) == 0   # 2^30 - 1 nodes
-    assert lib.heap_arena_bytes(32, 1, None, ((1 << 30) - 3) * 32) > (1 << 37)
+    assert f(1024, 0, None, 1024) == 0
+    assert f(64, 1 << 20, None, 64) > 0
+    assert f(64, (1 << 20) + 1, None, 64) == 0     # heaps per set
+    assert f(64, 0xFFFFFFFF, None, 1 << 40) == 0
+    assert f(32, 1, None, ((1 << 30) - 2) * 32) == 0   # 2^30 - 1 nodes
+    assert f(32, 1, None, ((1 << 30) - 3) * 32) > (1 << 37)
+    # 16-byte entries: nodes and partial buffer take twice the bytes
+    w = lib.heap_arena_bytes(1024, 1, 1, None, 1 << 22)
+    assert w > (1 << 22) * 16 and w - (1 << 22) * 16 < a - (1 << 22) * 8 + (1 << 16)
+    assert lib.heap_arena_bytes(1024, 2, 1, None, 1 << 22) == 0    # unknown key type
+    assert lib.heap_arena_bytes(1024, -1, 1, None, 1 << 22) == 0
     f = lib.heap_serve_workspace_bytes
     f.restype = ctypes.c_uint64
     f.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64]
