@@ -269,10 +269,11 @@ class OracleHeap:
         return nodes.reshape(slots, self.k), pb[: self.s].copy()
 
     def counters(self) -> dict:
-        c = np.zeros(5, dtype=np.uint64)
+        c = np.zeros(7, dtype=np.uint64)
         self._f("counters")(self.h, _p64(c))
         return dict(ins_ops=int(c[0]), ins_full=int(c[1]), ins_path_nodes=int(c[2]),
-                    del_ops=int(c[3]), del_levels=int(c[4]))
+                    del_ops=int(c[3]), del_levels=int(c[4]), del_refill=int(c[5]),
+                    traffic_entries=int(c[6]))
 
     def replay(self, types, n, off, in_keys, out_capacity: int, check: bool = False):
         """Apply ops in order (type 0 = INS n[i] keys from in_keys[off[i]:],

@@ -87,6 +87,10 @@ typedef struct gho_heap {
     gho_ent *tmp2;     /* scratch of 2k entries */
     /* work counters (levels actually traversed), for byte accounting */
     uint64_t ins_ops, ins_full, ins_path_nodes, del_ops, del_levels;
+    /* deleteMins that refilled the root from the last node, and the
+     * algorithmic traffic of every operation in entries (count_insert,
+     * count_delete) */
+    uint64_t del_refill, traffic;
 } gho_heap;
 
 /* ---- bit-reversal target order (Sec. 4.3) ------------------------------ */
@@ -242,13 +246,47 @@ static int insert_batch(gho_heap *h, const gho_ent *x, uint64_t n) {
     return 0;
 }
 
+/* Algorithmic traffic of one operation, counted in entries: what the
+ * method moves between memory and the working copy along the path the
+ * operation took (the node loads and stores, the partial buffer, the input
+ * and the output).  An insert of n entries that found m0 nodes and s0
+ * partial-buffer entries: kept in the partial buffer, 2 (n + s0) plus 2k
+ * for the root merge if a root exists; a full batch to a target on level L,
+ * (n + s0 + (n + s0 - k)) + (2 k L + k). */
+static void count_insert(gho_heap *h, uint64_t n, uint64_t m0, uint64_t s0) {
+    const uint64_t k = h->k;
+    if (h->m > m0) {
+        uint64_t L = (uint64_t)floor_log2(gho_idx(m0 + 1));
+        h->traffic += (n + s0 + (n + s0 - k)) + (2 * k * L + k);
+    } else {
+        h->traffic += 2 * (n + s0) + (m0 >= 1 ? 2 * k : 0);
+    }
+}
+
+/* A deleteMin that found m0 nodes and s0 partial-buffer entries: with no
+ * node 2 s0; from the root alone 2k; refilled from the last node with L
+ * levels merged, k (3 + 4 L) + 2 s0. */
+static void count_delete(gho_heap *h, uint64_t m0, uint64_t s0, uint64_t lv0, int refilled) {
+    const uint64_t k = h->k;
+    if (m0 == 0) {
+        h->traffic += 2 * s0;
+    } else if (refilled) {
+        h->del_refill++;
+        h->traffic += k * (3 + 4 * (h->del_levels - lv0)) + 2 * s0;
+    } else {
+        h->traffic += 2 * k;
+    }
+}
+
 /* Insert n entries: n <= k is one INS; larger inputs are split into
  * consecutive chunks of k (footnote to the INS paragraph, Sec. 3.2.2). */
 int gho_insert(gho_heap *h, const gho_ent *x, uint64_t n) {
     uint64_t done = 0;
     while (done < n) {
         uint64_t c = n - done < h->k ? n - done : h->k;
+        uint64_t m0 = h->m, s0 = h->s;
         if (insert_batch(h, x + done, c)) return -1;
+        count_insert(h, c, m0, s0);
         done += c;
     }
     return 0;
@@ -259,7 +297,7 @@ int gho_insert(gho_heap *h, const gho_ent *x, uint64_t n) {
 static void sift_down(gho_heap *h);
 
 /* Removes and returns the min(k, size) smallest entries, ascending. */
-uint64_t gho_delete_min(gho_heap *h, gho_ent *out) {
+static uint64_t delete_root(gho_heap *h, gho_ent *out) {
     const uint64_t k = h->k;
     h->del_ops++;
     if (h->m == 0) {
@@ -299,7 +337,14 @@ uint64_t gho_delete_min(gho_heap *h, gho_ent *out) {
  * the partial buffer gives its c smallest; with one node and fewer than k
  * entries left at the top, they all become the partial buffer.  For c = k
  * this is exactly gho_delete_min. */
-uint64_t gho_delete_min_n(gho_heap *h, gho_ent *out, uint64_t c) {
+uint64_t gho_delete_min(gho_heap *h, gho_ent *out) {
+    uint64_t m0 = h->m, s0 = h->s, lv0 = h->del_levels;
+    uint64_t got = delete_root(h, out);
+    count_delete(h, m0, s0, lv0, m0 >= 2);
+    return got;
+}
+
+static uint64_t delete_n(gho_heap *h, gho_ent *out, uint64_t c) {
     const uint64_t k = h->k;
     if (c == 0 || c > k) return UINT64_MAX;
     if (c == k) return gho_delete_min(h, out);
@@ -336,6 +381,14 @@ uint64_t gho_delete_min_n(gho_heap *h, gho_ent *out, uint64_t c) {
     }
     sift_down(h);
     return c;
+}
+
+uint64_t gho_delete_min_n(gho_heap *h, gho_ent *out, uint64_t c) {
+    if (c == 0 || c >= h->k) return delete_n(h, out, c);   /* c = k: counted by gho_delete_min */
+    uint64_t m0 = h->m, s0 = h->s, lv0 = h->del_levels;
+    uint64_t got = delete_n(h, out, c);
+    count_delete(h, m0, s0, lv0, m0 >= 2 && h->k - c + s0 < h->k);
+    return got;
 }
 
 /* Sift the root down (Sec. 3.2.1): at each node, stop once its largest
@@ -475,9 +528,10 @@ void gho_merge_and_sort(gho_heap *h, const gho_ent *a, uint64_t na,
     merge_and_sort(h, a, na, b, nb, hi, lo);
 }
 
-void gho_counters(const gho_heap *h, uint64_t out[5]) {
+void gho_counters(const gho_heap *h, uint64_t out[7]) {
     out[0] = h->ins_ops; out[1] = h->ins_full; out[2] = h->ins_path_nodes;
-    out[3] = h->del_ops; out[4] = h->del_levels;
+    out[3] = h->del_ops; out[4] = h->del_levels; out[5] = h->del_refill;
+    out[6] = h->traffic;
 }
 
 /* ---- log replay --------------------------------------------------------

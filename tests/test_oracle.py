@@ -538,3 +538,46 @@ def test_wide_layout_conversion_is_pinned(monkeypatch):
             caught = True
             break
     assert caught
+
+
+# ---------------------------------------------------------------------------
+# traffic counters (the measurement's algorithmic bytes come from them)
+# ---------------------------------------------------------------------------
+
+def test_traffic_counter_hand_computed_trace():
+    """k = 2, worked by hand: insert [5] stays in the partial buffer (2
+    entries moved: 2 (n + s)); insert [3] makes a full batch that becomes
+    the root (n + s + (n + s - k) = 2, plus 2kL + k = 2); insert [9, 1] makes
+    a full batch to node 2 one level down (2 + 2*2*1 + 2 = 8); a deleteMin
+    refills the root from node 2 with nothing to sift (3k = 6); a deleteMin
+    of the only node (2k = 4); a deleteMin of the empty heap (0)."""
+    h = oracle.OracleHeap(2)
+    h.insert([5 << 32])
+    assert h.counters()["traffic_entries"] == 2
+    h.insert([3 << 32 | 1])
+    assert h.counters()["traffic_entries"] == 6
+    h.insert([9 << 32 | 2, 1 << 32 | 3])
+    assert h.counters()["traffic_entries"] == 14
+    h.delete_min()
+    c = h.counters()
+    assert c["traffic_entries"] == 20 and c["del_refill"] == 1 and c["del_levels"] == 0
+    h.delete_min()
+    assert h.counters()["traffic_entries"] == 24
+    assert len(h.delete_min()) == 0
+    assert h.counters()["traffic_entries"] == 24
+
+
+@pytest.mark.parametrize("k", [4, 64])
+def test_traffic_counter_full_batches_closed_form(k):
+    """m full batches into an empty heap: batch p goes to level
+    floor(log2 p), so the traffic is sum over p of 2k + 2k floor(log2 p),
+    and the path nodes are sum of floor(log2 p)."""
+    m = 300
+    h = oracle.OracleHeap(k)
+    keys = (np.arange(m * k, dtype=np.uint64) * np.uint64(2654435761)) % np.uint64(1 << 40)
+    for p in range(m):
+        h.insert(keys[p * k:(p + 1) * k])
+    levels = sum(int(np.floor(np.log2(p))) for p in range(1, m + 1))
+    c = h.counters()
+    assert c["ins_path_nodes"] == levels and c["ins_full"] == m
+    assert c["traffic_entries"] == 2 * k * m + 2 * k * levels
