@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain device copy of known size (for counter scaling)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form leg")
+    ap.add_argument("--no-c1", action="store_true",
+                    help="skip the k = 64 insert-then-drain leg (2^16 keys)")
     ap.add_argument("--no-served", action="store_true", help="skip the served-form leg")
     ap.add_argument("--batched-heaps", type=int, default=64)
     ap.add_argument("--served-heaps", type=int, default=256)
@@ -49,8 +51,12 @@ def parse():
                     help="workgroup size of the served form (0 = library default)")
     ap.add_argument("--served-budget", type=int, default=1 << 20,
                     help="memory budget per heap beyond its prefill (entries)")
+    ap.add_argument("--served-tight-budget", type=int, default=1 << 14,
+                    help="budget beyond the prefill of the memory-bound served run")
     ap.add_argument("--no-knapsack", action="store_true", help="skip the knapsack leg")
     ap.add_argument("--knapsack-instances", type=int, default=512)
+    ap.add_argument("--knapsack-gc-min", type=int, default=4096,
+                    help="heap size from which the knapsack leg's collecting run filters a heap")
     ap.add_argument("--no-sssp", action="store_true", help="skip the SSSP leg")
     ap.add_argument("--no-paper-table", action="store_true",
                     help="skip the insert-all-then-drain leg in the paper's key orders")
@@ -64,6 +70,9 @@ def parse():
                     help="also run the paper's initial-utilization study (heaps of 6 to 18 "
                          "levels, then ins-del pairs)")
     ap.add_argument("--util-pairs", type=int, default=1 << 15)
+    ap.add_argument("--util-check-levels", type=int, default=10,
+                    help="check every deleteMin against the oracle for heaps of up to this many "
+                         "levels")
     ap.add_argument("--filter", action="store_true",
                     help="also time heap_filter on a 2^22-entry heap (k = 1024) at several "
                          "cut points; not in the default run")
@@ -151,6 +160,37 @@ def main():
     lat = M.percentiles_us((lg["t_done"] - lg["t_claim"]).astype(np.int64), hz)
     t_root_sorted = np.sort(lg["t_root"].astype(np.int64))
     root_interval = float(np.median(np.diff(t_root_sorted))) * 1e6 / hz if nops > 1 else None
+    # the single heap's serial bound: one root turn at a time, each moving at
+    # most k keys
+    root_bound = k / (root_interval / 1e6) if root_interval else None
+
+    # every deleteMin of the timed launch against the oracle replaying the
+    # ticket log (Theorem 1); the replay's counters give the algorithmic
+    # bytes independently of the kernel's log
+    import oracle
+    oracle.build(force=False)
+    order = np.argsort(lg["ticket"], kind="stable")
+    oh = oracle.OracleHeap(k)
+    oh.replay(pre.kind, pre.n, pre.off, pre.keys, max(pre.out_entries, 1))
+    c_pre = oh.counters()["traffic_entries"]
+    ref_out, ref_cnt = oh.replay(mix.kind[order], mix.n[order], mix.off[order], mix.keys,
+                                 max(mix.out_entries, 1))
+    alg_oracle = (oh.counters()["traffic_entries"] - c_pre) * 8
+    oh.close()
+    gout = G.to_host_u64(out)
+    gcnt = counts.cpu().numpy()[:nops]
+    mismatches = 0
+    for j, i in enumerate(order):
+        if mix.kind[i] != W.OP_DELETE_MIN:
+            continue
+        c = int(ref_cnt[j])
+        o = int(mix.off[i])
+        if int(gcnt[i]) != c or not np.array_equal(gout[o:o + c], ref_out[o:o + c]):
+            mismatches += 1
+    if mismatches:
+        raise SystemExit("plain leg: %d deleteMin results differ from the oracle replay"
+                         % mismatches)
+    log("plain leg: every deleteMin equals the oracle replay")
 
     result = {
         "metric": "heap keys/sec (insert+deleteMin, k=1024) vs plain; served-op p50/p99 latency",
@@ -173,8 +213,12 @@ def main():
             "form": "plain (one heap per launch)",
         },
         "keys_moved_per_step": moved,
+        "outputs_equal_oracle_replay": True,
         "op_latency_us": lat,
         "root_interval_us_median": root_interval,
+        "root_bound": {"keys_per_s": root_bound,
+                       "frac": value / root_bound if root_bound else None,
+                       "basis": "k keys per median interval between root acquisitions"},
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,
@@ -184,10 +228,14 @@ def main():
             "traffic": M.stored_traffic(TRAFFIC_FILE, wg, th),
             "kernel": "gh::k_ops<1024,%d,false>" % th,
             "algorithmic_bytes_per_launch": alg,
+            "algorithmic_bytes_oracle_replay": alg_oracle,
         },
+        "host_cpu": host_cpu(),
         "wall_s_timed_steps": wall,
     }
 
+    if not args.no_c1:
+        result["c1"] = run_c1(args)
     if not args.no_batched:
         result["batched"] = run_batched(args, wg_default=wg, th=th, plain_value=value)
     if not args.no_served:
@@ -216,10 +264,7 @@ def main():
         log("calibration copy of %d bytes done" % (n * 8))
 
     if not args.no_cpu_baseline:
-        import oracle
-        oracle.build(force=False)
         log("cpu baseline: oracle replay of the same operations on 1 core")
-        order = np.argsort(lg["ticket"], kind="stable")
         times = []
         # whole-workload replays until about 10 s of timed CPU work (5 to 40)
         while len(times) < 5 or (sum(times) < 10.0 and len(times) < 40):
@@ -233,6 +278,7 @@ def main():
         omoved = int(mix.n.astype(np.int64).sum()) + int(ocounts.astype(np.int64).sum())
         result["cpu_baseline"] = {
             "value": omoved / dt, "unit": "keys/s", "cores": 1, "kind": "oracle",
+            "cpu_model": host_cpu()["model"],
             "sample": "the whole timed workload (%d ops, %d keys moved) replayed in ticket order "
                       "after an untimed prefill, %d times (%.1f s of timed replay); median %.2f s"
                       % (nops, omoved, len(times), sum(times), dt),
@@ -266,6 +312,74 @@ def _timed_submit(hs, d, workgroups, threads, log=None):
     if rc != 0:
         raise SystemExit("submission failed: %d" % rc)
     return ev0.elapsed_time(ev1)
+
+
+def run_c1(args):
+    """The small plain workload: k = 64, 2^16 uniform (key, id) entries
+    inserted in batches of 64 into an empty heap, then deleteMin(64) until
+    empty, as one persistent launch (the arena restored to empty before
+    every step).  The drained entries in ticket order must be the sorted
+    input; the oracle replays the same operations on one core."""
+    import torch
+    from paper_1906_06504_amd import gheap as G
+    from paper_1906_06504_amd import metrics as M
+    from paper_1906_06504_amd import workloads as W
+    import oracle
+    ops, k = W.config1()
+    nops = len(ops)
+    wg, th = 128, 128
+    hs = G.HeapSet(k, [1 << 16], stream=torch.cuda.Stream())
+    res = {"workload": "plain single heap, k=64: insert 2^16 keys in batches of 64, then "
+                       "deleteMin(64) until empty", "ops": nops, "workgroups": wg, "threads": th}
+    with torch.cuda.stream(hs.stream):
+        snap = hs.arena.clone()
+        d = G.ops_to_device(ops)
+        dlog = G.new_log(nops)
+        times = []
+        for i in range(args.warmup + max(args.steps, 5)):
+            hs.arena.copy_(snap)
+            torch.cuda.synchronize()
+            t = _timed_submit(hs, d, wg, th, dlog)
+            if i >= args.warmup:
+                times.append(t)
+        lg = G.log_to_host(dlog, nops)
+        outh = G.to_host_u64(d[3])
+        cnt = d[4].cpu().numpy()[:nops]
+    hs.close()
+    dels = np.flatnonzero(ops.kind == W.OP_DELETE_MIN)
+    dels = dels[np.argsort(lg["ticket"][dels], kind="stable")]
+    got = np.concatenate([outh[int(ops.off[i]):int(ops.off[i]) + int(cnt[i])] for i in dels])
+    if not np.array_equal(got, np.sort(ops.keys)):
+        raise SystemExit("c1 leg: the drained entries are not the sorted input")
+    ms = float(np.mean(times))
+    moved = M.keys_moved(lg)
+    alg = int(M.algorithmic_bytes(lg, k).sum())
+    oracle.build(force=False)
+    order = np.argsort(lg["ticket"], kind="stable")
+    otimes = []
+    while len(otimes) < 5 or (sum(otimes) < 5.0 and len(otimes) < 200):
+        oh = oracle.OracleHeap(k)
+        t0 = time.perf_counter()
+        oh.replay(ops.kind[order], ops.n[order], ops.off[order], ops.keys,
+                  max(ops.out_entries, 1))
+        otimes.append(time.perf_counter() - t0)
+        alg_oracle = oh.counters()["traffic_entries"] * 8
+        oh.close()
+    odt = float(np.median(otimes))
+    res.update({
+        "value": moved / (ms / 1e3), "unit": "keys/s", "ms_per_step": ms,
+        "drained_equals_sorted_input": True,
+        "roofline": {"bound": "hbm", "achieved": alg / (ms / 1e3) / 1e9, "peak": M.HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": alg / (ms / 1e3) / 1e9 / M.HBM_PEAK_GBS,
+                     "algorithmic_bytes_per_launch": alg,
+                     "algorithmic_bytes_oracle_replay": alg_oracle},
+        "cpu_baseline": {"value": moved / odt, "unit": "keys/s", "cores": 1, "kind": "oracle",
+                         "sample": "the whole workload replayed in ticket order, %d times; "
+                                   "median %.1f ms" % (len(otimes), odt * 1e3)},
+    })
+    log("c1: %.3f ms, %.3g keys/s (oracle %.3g keys/s on 1 core)"
+        % (ms, res["value"], moved / odt))
+    return res
 
 
 def run_batched(args, wg_default, th, plain_value):
@@ -377,6 +491,7 @@ def run_served(args):
     capacity; Poisson streams at 0.5x and 0.9x of it give latency."""
     import torch
     from paper_1906_06504_amd import gheap as G
+    from paper_1906_06504_amd import metrics as M
     from paper_1906_06504_amd import workloads as W
     k = 256
     H = args.served_heaps
@@ -419,6 +534,7 @@ def run_served(args):
         def summarize(ms, recs, stream_reqs):
             adm = (recs["flags"] & G.REQ_ADMITTED) != 0
             keys = int(recs["count"][adm].astype(np.int64).sum())
+            alg = int(recs["bytes"][adm].astype(np.int64).sum())
             arr_ticks = stream_reqs.arrival.astype(np.float64) * hz / 1e9
             lat_us = (recs["t_done"][adm].astype(np.float64) - arr_ticks[adm]) * 1e6 / hz
             resp_us = (recs["t_resp"][adm].astype(np.float64) - arr_ticks[adm]) * 1e6 / hz
@@ -430,7 +546,12 @@ def run_served(args):
                     "latency_us": {"p50": float(np.percentile(lat_us, 50)),
                                    "p99": float(np.percentile(lat_us, 99))},
                     "response_latency_us": {"p50": float(np.percentile(resp_us, 50)),
-                                            "p99": float(np.percentile(resp_us, 99))}}
+                                            "p99": float(np.percentile(resp_us, 99))},
+                    "roofline": {"bound": "hbm", "achieved": alg / (ms / 1e3) / 1e9,
+                                 "peak": M.HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": alg / (ms / 1e3) / 1e9 / M.HBM_PEAK_GBS,
+                                 "algorithmic_bytes": alg,
+                                 "kernel": "gh::k_serve<256,%d,u64>" % (args.served_threads or 256)}}
 
         serve_once(reqs)  # warmup
         ms, recs = serve_once(reqs)
@@ -448,6 +569,8 @@ def run_served(args):
             ms, recs = serve_once(rq)
             res = summarize(ms, recs, rq)
             res["offered_requests_per_s"] = rate
+            res["sampled_heaps_replayed_equal"] = check_served(
+                pre, rq, recs, G.to_host_u64(serve_once.last_out), k, caps, H)
             out["poisson_%.1fx" % frac] = res
             log("served at %.1fx: completion p50 %.1f us p99 %.1f us; answer p50 %.1f us p99 "
                 "%.1f us" % (frac, res["latency_us"]["p50"], res["latency_us"]["p99"],
@@ -486,9 +609,69 @@ def run_served(args):
         out["plain_one_heap_per_launch_keys_per_s"] = plain_keys / (plain_ms / 1e3)
         out["vs_plain_per_launch"] = sat["keys_per_s"] / out["plain_one_heap_per_launch_keys_per_s"]
     hs.close()
+    del hs
+    torch.cuda.empty_cache()
+    # a memory budget that binds: prefill + 2^14 entries per heap, so that
+    # inserts wait in their heap's queue until admitted deleteMins make room
+    tight = W.served_capacity(sizes, extra=args.served_tight_budget)
+    ht = G.HeapSet(k, tight, stream=torch.cuda.Stream())
+    with torch.cuda.stream(ht.stream):
+        _timed_submit(ht, G.ops_to_device(pre), 1024, 0)
+        snap_t = ht.arena.clone()
+        hs = ht
+        snap = snap_t
+        work = None
+        serve_once(reqs)
+        ms, recs = serve_once(reqs)
+        res = summarize(ms, recs, reqs)
+        res["budget_beyond_prefill"] = args.served_tight_budget
+        res["sampled_heaps_replayed_equal"] = check_served(
+            pre, reqs, recs, G.to_host_u64(serve_once.last_out), k, tight, H)
+        out["memory_bound_saturated"] = res
+        log("served, budget prefill + %d: %.3g keys/s, %d inserts waited for memory, "
+            "completion p50 %.1f us p99 %.1f us" % (args.served_tight_budget, res["keys_per_s"],
+                                                    res["deferred_for_memory"],
+                                                    res["latency_us"]["p50"],
+                                                    res["latency_us"]["p99"]))
+    ht.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = served_cpu_baseline(pre, reqs, sat_recs, sat_out, k, H)
     return out
+
+
+def check_served(pre, reqs, recs, gpu_out, k, caps, H, nsample=8):
+    """A sample of heaps (the largest, the smallest and evenly spaced
+    others): each heap's admitted requests replayed in ticket order on its
+    own oracle give every deleteMin's entries, and the heap never exceeds
+    its budget.  Exits on a mismatch; returns True."""
+    import oracle
+    from paper_1906_06504_amd import gheap as G
+    from paper_1906_06504_amd import workloads as W
+    oracle.build(force=False)
+    sizes = np.bincount(pre.heap.astype(np.int64), weights=pre.n.astype(np.float64),
+                        minlength=H)
+    heaps = sorted(set([int(np.argmax(sizes)), int(np.argmin(sizes))]
+                       + list(range(1, H, max(1, H // (nsample - 2))))[:nsample - 2]))
+    adm = (recs["flags"] & G.REQ_ADMITTED) != 0
+    for h in heaps:
+        oh = oracle.OracleHeap(k)
+        ps = np.flatnonzero(pre.heap == h)
+        oh.replay(pre.kind[ps], pre.n[ps], pre.off[ps], pre.keys, 1)
+        sel = np.flatnonzero((reqs.heap == h) & adm)
+        sel = sel[np.argsort(recs["first_ticket"][sel], kind="stable")]
+        for i in sel:
+            o = int(reqs.off[i])
+            if reqs.kind[i] == W.OP_INSERT:
+                oh.insert(reqs.keys[o:o + int(reqs.n[i])])
+                if oh.size > int(caps[h]):
+                    raise SystemExit("served: heap %d over its budget" % h)
+            else:
+                want = oh.delete_min(int(reqs.n[i]) or None)
+                c = int(recs["count"][i])
+                if c != want.size or not np.array_equal(gpu_out[o:o + c], want):
+                    raise SystemExit("served: heap %d request %d differs from the oracle" % (h, i))
+        oh.close()
+    return True
 
 
 def served_cpu_baseline(pre, reqs, recs, gpu_out, k, H):
@@ -559,55 +742,130 @@ def served_cpu_baseline(pre, reqs, recs, gpu_out, k, H):
 
 def run_knapsack(args):
     """Batched form on the knapsack workload: every instance's best-first
-    branch and bound on its own heap, all instances in one persistent launch
-    (and replayed as a HIP graph), k and workgroup size picked by the
-    autotuner; against one launch per instance (plain form)."""
+    branch and bound on its own heap, all instances in one persistent launch,
+    k and workgroup size picked by the autotuner; heap entries are 16 bytes
+    (the negated fixed-point bound as a signed 64-bit key, the node's pool
+    index as id).  Timed eagerly and as a captured HIP graph, without and
+    with garbage collection of the heaps (Sec. 5.7.2), and with 8-byte
+    entries at the same shape; against one launch per instance (plain
+    form).  Optima are checked against the DP."""
     import torch
+    import oracle
     from paper_1906_06504_amd import autotune as A
+    from paper_1906_06504_amd import gheap as G
     from paper_1906_06504_amd import knapsack as KS
+    from paper_1906_06504_amd import metrics as M
     from paper_1906_06504_amd import workloads as W
+    oracle.build(force=False)
     N = args.knapsack_instances
     log("knapsack leg: %d instances" % N)
     inst = W.knapsack_instances(N, seed=0x5EED0004)
     dinst = KS.Instances(inst)
     pool = 1 << 20
     solvers = {}
+    sample = list(range(0, N, max(1, N // 64)))
+    ref = {i: oracle.knapsack_dp(*inst[i]) for i in sample}
+
+    def check(res, what):
+        if np.any(res["flags"] & 0x60) or not np.all(res["flags"] & 1):
+            raise SystemExit("knapsack %s: an instance did not finish cleanly" % what)
+        for i in sample:
+            if int(res["best"][i]) != ref[i]:
+                raise SystemExit("knapsack %s: instance %d optimum differs from the DP" % (what, i))
 
     def run(k, t, wg):
         if k not in solvers:
-            solvers[k] = KS.Solver(N, k, pool_per_inst=pool)
+            solvers[k] = KS.Solver(N, k, pool_per_inst=pool, stream=torch.cuda.Stream())
         s = solvers[k]
         s.hs.arena.copy_(s.snapshot)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         res = s.run(dinst, workgroups=wg, threads=t, reset=False)
         ms = (time.perf_counter() - t0) * 1e3
-        if np.any(res["flags"] & 0x40):
-            raise SystemExit("knapsack node pool overflow")
+        check(res, "tuning k=%d threads=%d" % (k, t))
         return ms, tuple(int(b) for b in res["best"])
 
     best, table = A.tune("knapsack-%d-mi355x" % N, run, ks=(32, 64, 128, 256, 512, 1024),
                          threads=(64, 128, 256, 512), workgroups=(N,), repeats=2, use_cache=False,
                          log=log)
     k, t = best["k"], best["threads"]
+    for kk in list(solvers):
+        if kk != k:
+            solvers.pop(kk).close()
     s = solvers[k]
-    times = []
-    res = None
+
+    def timed(solver, d, gc_min, reps=3):
+        times, res = [], None
+        for _ in range(reps):
+            solver.hs.arena.copy_(solver.snapshot)
+            torch.cuda.synchronize()
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record(solver.hs.stream)
+            solver.launch(d, workgroups=N, threads=t, reset=False, gc_min=gc_min)
+            ev1.record(solver.hs.stream)
+            if solver.hs.sync() != 0:
+                raise SystemExit("knapsack launch failed")
+            torch.cuda.synchronize()
+            times.append(ev0.elapsed_time(ev1))
+            res = solver.results(d.n)
+        return float(np.median(times)), res
+
+    def summary(ms, res):
+        moved = int(res["created"].astype(np.int64).sum()) + int(res["popped"].astype(np.int64).sum())
+        alg = int(res["alg_bytes"].astype(np.int64).sum())
+        return {"ms": ms, "keys_per_s": moved / (ms / 1e3),
+                "nodes_created": int(res["created"].sum()),
+                "nodes_explored": int(res["explored"].sum()),
+                "heap_ops": int(res["ops"].astype(np.int64).sum()),
+                "gc_runs": int(res["gc_runs"].sum()), "gc_dropped": int(res["gc_dropped"].sum()),
+                "roofline": {"bound": "hbm", "achieved": alg / (ms / 1e3) / 1e9,
+                             "peak": M.HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": alg / (ms / 1e3) / 1e9 / M.HBM_PEAK_GBS,
+                             "algorithmic_bytes": alg}}
+
+    ms, res = timed(s, dinst, 0)
+    check(res, "eager")
+    base = summary(ms, res)
+    gc_ms, gc_res = timed(s, dinst, args.knapsack_gc_min)
+    check(gc_res, "with garbage collection")
+    if not np.array_equal(gc_res["best"], res["best"]):
+        raise SystemExit("knapsack: optima differ with garbage collection")
+    with_gc = summary(gc_ms, gc_res)
+    with_gc["gc_min"] = args.knapsack_gc_min
+    log("knapsack k=%d threads=%d: %.2f ms without collection, %.2f ms with (%d collections, "
+        "%d entries dropped)" % (k, t, ms, gc_ms, with_gc["gc_runs"], with_gc["gc_dropped"]))
+    # the same launch captured as a HIP graph and replayed
+    g = torch.cuda.CUDAGraph()
+    s.hs.arena.copy_(s.snapshot)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s.hs.stream):
+        s.launch(dinst, workgroups=N, threads=t, reset=False, gc_min=0)
+    gt = []
     for _ in range(3):
         s.hs.arena.copy_(s.snapshot)
         torch.cuda.synchronize()
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        res = s.run(dinst, workgroups=N, threads=t, reset=False)
-        ev1.record()
+        ev0.record(s.hs.stream)
+        with torch.cuda.stream(s.hs.stream):
+            g.replay()
+        ev1.record(s.hs.stream)
+        if s.hs.sync() != 0:
+            raise SystemExit("knapsack graph replay failed")
         torch.cuda.synchronize()
-        times.append(ev0.elapsed_time(ev1))
-    ms = float(np.median(times))
-    moved = int(res["created"].astype(np.int64).sum()) + int(res["popped"].astype(np.int64).sum())
+        gt.append(ev0.elapsed_time(ev1))
+        if not np.array_equal(s.results(N)["best"], res["best"]):
+            raise SystemExit("knapsack: graph replay optima differ from the eager launch")
+    del g
+    # 8-byte entries at the same shape
+    s8 = KS.Solver(N, k, pool_per_inst=pool, stream=torch.cuda.Stream(), keytype=G.GH_U32_ID)
+    d8 = KS.Instances(inst, keytype=G.GH_U32_ID)
+    ms8, res8 = timed(s8, d8, 0)
+    check(res8, "8-byte entries")
+    s8.close()
     # plain form: each instance alone, one launch each (a sample of 64)
-    sample = list(range(0, N, max(1, N // 64)))
-    one = KS.Solver(1, k, pool_per_inst=pool)
+    one = KS.Solver(1, k, pool_per_inst=pool, stream=torch.cuda.Stream())
     plain_ms, plain_moved = 0.0, 0
     for i in sample:
         d1 = KS.Instances([inst[i]])
@@ -615,37 +873,63 @@ def run_knapsack(args):
         torch.cuda.synchronize()
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        r1 = one.run(d1, workgroups=1, threads=t, reset=False)
-        ev1.record()
+        ev0.record(one.hs.stream)
+        one.launch(d1, workgroups=1, threads=t, reset=False)
+        ev1.record(one.hs.stream)
+        if one.hs.sync() != 0:
+            raise SystemExit("knapsack plain launch failed")
         torch.cuda.synchronize()
+        r1 = one.results(1)
         plain_ms += ev0.elapsed_time(ev1)
         plain_moved += int(r1["created"][0]) + int(r1["popped"][0])
         if int(r1["best"][0]) != int(res["best"][i]):
             raise SystemExit("knapsack optimum differs between forms")
     one.close()
-    for sv in solvers.values():
-        sv.close()
+    s.close()
     out = {
         "workload": "%d 0/1 knapsack instances, n U[40,200], w U[1,1000], v = w + U[0,100], "
-                    "capacity sum(w)/2; best-first branch and bound, one heap each" % N,
+                    "capacity sum(w)/2; best-first branch and bound, one heap each, 16-byte "
+                    "entries (i64 key = -bound * 2^16, id = pool index)" % N,
         "tuned": {"k": k, "threads": t, "workgroups": N},
         "tuning_table": table,
-        "ms": ms, "keys_per_s": moved / (ms / 1e3),
-        "nodes_created": int(res["created"].sum()), "nodes_explored": int(res["explored"].sum()),
+        "ms": ms, "keys_per_s": base["keys_per_s"],
+        "no_gc": base, "gc": with_gc,
+        "graph_ms": float(np.median(gt)),
+        "entries_8_byte": {"ms": ms8, "keys_per_s": summary(ms8, res8)["keys_per_s"]},
+        "nodes_created": base["nodes_created"], "nodes_explored": base["nodes_explored"],
         "plain_one_instance_per_launch_keys_per_s": plain_moved / (plain_ms / 1e3),
-        "vs_plain_per_launch": (moved / (ms / 1e3)) / (plain_moved / (plain_ms / 1e3)),
+        "vs_plain_per_launch": base["keys_per_s"] / (plain_moved / (plain_ms / 1e3)),
+        "optima_equal_dp_sample": True,
     }
-    log("knapsack: k=%d threads=%d %.2f ms, %.3g keys/s (plain per launch %.3g)"
-        % (k, t, ms, out["keys_per_s"], out["plain_one_instance_per_launch_keys_per_s"]))
+    log("knapsack: k=%d threads=%d %.2f ms (graph %.2f, 8-byte %.2f), %.3g keys/s (plain per "
+        "launch %.3g)" % (k, t, ms, out["graph_ms"], ms8, out["keys_per_s"],
+                           out["plain_one_instance_per_launch_keys_per_s"]))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = knapsack_cpu_baseline(inst, res["best"])
+        if not out["cpu_baseline"]["optima_equal"]:
+            raise SystemExit("knapsack: an optimum differs from the DP")
     return out
 
 
 def _host_threads():
     """Worker threads for the CPU baselines: the host's cores, at most 16."""
     return max(1, min(16, os.cpu_count() or 1))
+
+
+def host_cpu():
+    """The host CPU model and logical CPU count, from /proc/cpuinfo."""
+    model, n = None, 0
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    n += 1
+                    model = model or line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": n or os.cpu_count(),
+            "usable_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+            else os.cpu_count()}
 
 
 def knapsack_cpu_baseline(inst, gpu_best):
@@ -820,9 +1104,33 @@ def run_util_sweep(args):
             d = G.ops_to_device(ops)
         if hs.sync() != 0:
             raise SystemExit("utilization sweep: build failed")
+        checked = L <= args.util_check_levels
+        ent_h = G.to_host_u64(ent) if checked else None
         del ent
+        lg = G.new_log(d[1]) if checked else None
         with torch.cuda.stream(hs.stream):
-            ms = _timed_submit(hs, d, wg, 0)
+            ms = _timed_submit(hs, d, wg, 0, lg)
+        if checked:
+            # every deleteMin against the oracle built from the same array
+            # and replaying the pairs in ticket order
+            import oracle
+            oracle.build(force=False)
+            oh = oracle.OracleHeap(k)
+            oh.build(ent_h)
+            rec = G.log_to_host(lg, d[1])
+            order = np.argsort(rec["ticket"], kind="stable")
+            ref_out, ref_cnt = oh.replay(ops.kind[order], ops.n[order], ops.off[order],
+                                         ops.keys, max(ops.out_entries, 1))
+            oh.close()
+            outh = G.to_host_u64(d[3])
+            cnt = d[4].cpu().numpy()[:d[1]]
+            for j, i in enumerate(order):
+                if ops.kind[i] != W.OP_DELETE_MIN:
+                    continue
+                o, c = int(ops.off[i]), int(ref_cnt[j])
+                if int(cnt[i]) != c or not np.array_equal(outh[o:o + c], ref_out[o:o + c]):
+                    raise SystemExit("utilization sweep: %d levels, op %d differs from the "
+                                     "oracle" % (L, i))
         size = hs.size(0)
         hs.close()
         del d, hs
@@ -831,63 +1139,86 @@ def run_util_sweep(args):
             raise SystemExit("utilization sweep: heap size %d after the pairs, expected %d"
                              % (size, n0))
         out["rows"].append({"levels": L, "initial_keys": n0, "ms": ms,
-                            "us_per_pair": ms * 1e3 / pairs})
+                            "us_per_pair": ms * 1e3 / pairs, "oracle_checked": checked})
         log("utilization sweep: %d levels (%d keys): %.1f ms, %.2f us per pair"
             % (L, n0, ms, ms * 1e3 / pairs))
     return out
 
 
 def run_sweep(args):
-    """The shapes of the paper's parameter studies on this GPU, on the
-    insert-all-then-drain workload with random keys (2^24 keys): node
-    capacity k (default workgroup size for each k, 64 operations in flight),
-    the number of operations in flight at k = 1024, and full against partial
-    insert batches (batches of k, or sizes uniform on [1, k])."""
+    """The shapes of the paper's parameter studies on this GPU, with random
+    keys (2^24): each case inserts every key into an empty heap (one
+    submission) and then deletes them all with deleteMin(k) (a second
+    submission), timed separately as in the paper's insertion-only and
+    deletion-only experiments; the drained entries must be the sorted input.
+    Cases: node capacity k (64 operations in flight, default workgroup
+    size), operations in flight at k = 1024 (Sec. 5.3), and the percentage
+    of full insert batches, the other inserts being partial batches of
+    uniform size on [1, k - 1] (Sec. 5.6)."""
     import torch
     from paper_1906_06504_amd import gheap as G
     from paper_1906_06504_amd import workloads as W
     N = 1 << 24
+    keysrc = W._keys_with_ids(W.Stream(0x5EED000A), 0)
+    allkeys = keysrc(N)
+    want = np.sort(allkeys)
 
-    def timed(ops, k, wg, th):
+    def ins_del(sizes, k, wg, th):
+        n_del = N // k + 1
+        ins = W.build_oplist([W.OP_INSERT] * len(sizes), sizes, lambda c: allkeys[:c], k)
+        dr = W.build_oplist([W.OP_DELETE_MIN] * n_del, [0] * n_del,
+                            lambda c: np.zeros(c, np.uint64), k)
         hs = G.HeapSet(k, [N + k], stream=torch.cuda.Stream())
         with torch.cuda.stream(hs.stream):
-            d = G.ops_to_device(ops)
-            ms = _timed_submit(hs, d, wg, th)
+            d = G.ops_to_device(ins)
+            ms_ins = _timed_submit(hs, d, wg, th)
+            del d
+            d = G.ops_to_device(dr)
+            lg = G.new_log(d[1])
+            ms_del = _timed_submit(hs, d, wg, th, lg)
+            outh = G.to_host_u64(d[3])
+            cnt = d[4].cpu().numpy()[:d[1]]
+            tk = G.log_to_host(lg, d[1])["ticket"]
             del d
         hs.close()
-        return ms
+        order = np.argsort(tk, kind="stable")
+        got = np.concatenate([outh[int(dr.off[i]):int(dr.off[i]) + int(cnt[i])] for i in order])
+        if not np.array_equal(got, want):
+            raise SystemExit("sweep: the drained entries are not the sorted input (k=%d)" % k)
+        return ms_ins, ms_del
 
-    out = {"workload": "insert 2^24 random keys, then deleteMin(k) until empty"}
+    out = {"workload": "insert 2^24 random keys into an empty heap, then deleteMin(k) until "
+                       "empty; insert and delete phases timed separately, drain checked"}
     rows = []
     for k in (64, 128, 256, 512, 1024):
-        ops = W.ordered_insert_then_drain(N, k, "random", seed=0x5EED000A)
-        ms = timed(ops, k, 64, 0)
-        rows.append({"k": k, "workgroups": 64, "ms": ms, "keys_per_s": 2 * N / (ms / 1e3)})
-        log("sweep k=%d: %.1f ms" % (k, ms))
+        mi, md = ins_del([k] * (N // k), k, 64, 0)
+        rows.append({"k": k, "workgroups": 64, "insert_ms": mi, "delete_ms": md,
+                     "ms": mi + md, "keys_per_s": 2 * N / ((mi + md) / 1e3)})
+        log("sweep k=%d: insert %.1f ms, delete %.1f ms" % (k, mi, md))
     out["node_capacity"] = rows
     rows = []
-    ops = W.ordered_insert_then_drain(N, 1024, "random", seed=0x5EED000A)
     for wg in (1, 4, 16, 32, 64, 128, 256):
-        ms = timed(ops, 1024, wg, 512)
-        rows.append({"k": 1024, "workgroups": wg, "ms": ms, "keys_per_s": 2 * N / (ms / 1e3)})
-        log("sweep workgroups=%d: %.1f ms" % (wg, ms))
+        mi, md = ins_del([1024] * (N // 1024), 1024, wg, 512)
+        rows.append({"k": 1024, "workgroups": wg, "insert_ms": mi, "delete_ms": md,
+                     "ms": mi + md, "delete_over_insert": md / mi,
+                     "keys_per_s": 2 * N / ((mi + md) / 1e3)})
+        log("sweep workgroups=%d: insert %.1f ms, delete %.1f ms" % (wg, mi, md))
     out["operations_in_flight"] = rows
-    # partial batches: the same keys inserted in batches of uniform size
+    rows = []
     st = W.Stream(0x5EED000B)
-    sizes, acc = [], 0
-    while acc < N:
-        b = int(min(st.uniform_int(1, 1024, 1)[0], N - acc))
-        sizes.append(b)
-        acc += b
-    n_del = N // 1024 + 1
-    kinds = [W.OP_INSERT] * len(sizes) + [W.OP_DELETE_MIN] * n_del
-    part = W.build_oplist(kinds, sizes + [0] * n_del, W._keys_with_ids(W.Stream(0x5EED000A), 0),
-                          1024)
-    ms_full = out["operations_in_flight"][4]["ms"]
-    ms_part = timed(part, 1024, 64, 512)
-    out["partial_batches"] = {"full_batches_ms": ms_full, "uniform_1_to_k_batches_ms": ms_part,
-                              "insert_ops_full": N // 1024, "insert_ops_partial": len(sizes)}
-    log("sweep partial batches: %.1f ms vs full %.1f ms" % (ms_part, ms_full))
+    for pct in (0, 25, 50, 75, 100):
+        sizes, acc = [], 0
+        while acc < N:
+            full = st.unit(1)[0] * 100 < pct
+            b = 1024 if full else int(st.uniform_int(1, 1023, 1)[0])
+            b = min(b, N - acc)
+            sizes.append(b)
+            acc += b
+        mi, md = ins_del(sizes, 1024, 64, 512)
+        rows.append({"full_batch_percent": pct, "insert_ops": len(sizes), "insert_ms": mi,
+                     "delete_ms": md, "insert_keys_per_s": N / (mi / 1e3)})
+        log("sweep %d%% full batches: %d inserts in %.1f ms" % (pct, len(sizes), mi))
+    out["full_batch_percentage"] = rows
     return out
 
 
@@ -937,6 +1268,8 @@ def run_sssp(args):
             sol.close()
     row, st = best
     ht, rt = int(st["heap_ticks"]), int(st["relax_ticks"])
+    from paper_1906_06504_amd import metrics as M
+    alg = int(st["alg_bytes"])
     moved = int(st["pushed"]) + 1 + int(st["popped"])
     reached = int(np.sum(dist != 0xFFFFFFFF))
     out = {
@@ -950,6 +1283,11 @@ def run_sssp(args):
         "popped": int(st["popped"]), "stale": int(st["stale"]), "pushed": int(st["pushed"]),
         "reexpanded": int(st["popped"]) - int(st["stale"]) - reached,
         "heap_ops": int(st["heap_ops"]), "reached": reached,
+        "roofline": {"bound": "hbm", "achieved": alg / (row["ms"] / 1e3) / 1e9,
+                     "peak": M.HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": alg / (row["ms"] / 1e3) / 1e9 / M.HBM_PEAK_GBS,
+                     "algorithmic_bytes": alg,
+                     "note": "heap operations only; CSR and distance traffic not counted"},
     }
     log("sssp: %.2f ms, %.3g edges/s, heap share %.2f" % (row["ms"], out["edges_per_s"],
                                                          out["heap_time_share"]))

@@ -145,7 +145,16 @@ typedef struct gh_logrec {
  *                 are in d_out, an insert's entries are seen by every later
  *                 operation on the heap); completion of the last operation
  *                 (the node updates below the root that follow the answer
- *                 are done) */
+ *                 are done)
+ *   bytes         algorithmic bytes of the request's operations: what the
+ *                 method moves between HBM and the workgroups along the
+ *                 paths the operations took (node loads and stores, partial
+ *                 buffer, input and output), entry bytes e, node capacity k,
+ *                 n entries, s partial-buffer entries, L levels merged: an
+ *                 insert into the partial buffer 2e(n + s) (+ 2ek with a
+ *                 root), a full batch e(n + s + (n + s - k)) + e(2kL + k); a
+ *                 deleteMin 2es with no node, 2ek from the root alone,
+ *                 ek(3 + 4L) + 2es refilled from the last node */
 typedef struct gh_reqrec {
     uint64_t first_ticket;
     uint32_t count;
@@ -155,7 +164,7 @@ typedef struct gh_reqrec {
     uint32_t t_admit;
     uint32_t t_done;
     uint32_t t_resp;
-    uint32_t reserved;
+    uint32_t bytes;
 } gh_reqrec;
 
 /* Launch shape of a submission: workgroups = number of operations in flight
@@ -300,13 +309,15 @@ int heap_serve(gh_heap_t h, const gh_op *d_reqs, uint32_t nreq, const void *d_in
                void *d_out, gh_reqrec *d_recs, void *d_work, uint64_t work_bytes,
                uint64_t max_ops, const gh_tuning *tuning);
 
-/* Result of one knapsack instance solved by heap_knapsack (56 bytes).
+/* Result of one knapsack instance solved by heap_knapsack (64 bytes).
  *   best        optimal value found
  *   explored    nodes taken from the heap and expanded (bound above best)
  *   created     nodes pushed into the heap
  *   popped      nodes taken from the heap by the search (the search stops
  *               before popping those whose bound cannot beat best)
  *   gc_dropped  heap entries removed by garbage collections
+ *   alg_bytes   algorithmic bytes of the instance's heap operations (as
+ *               gh_reqrec.bytes; a collection adds 2e per entry kept)
  *   ops         heap operations the instance ran (inserts, deleteMins and
  *               the operations of its collections)
  *   flags       bit 0: finished; bit 5: refused (more than 255 items, a
@@ -321,6 +332,7 @@ typedef struct gh_knapres {
     uint64_t created;
     uint64_t popped;
     uint64_t gc_dropped;
+    uint64_t alg_bytes;
     uint32_t ops;
     uint32_t flags;
     uint32_t gc_runs;
@@ -361,7 +373,7 @@ int heap_knapsack(gh_heap_t h, uint32_t ninst, const uint32_t *d_item_off,
                   void *d_scratch, gh_knapres *d_res, uint32_t gc_min,
                   const gh_tuning *tuning);
 
-/* Counters of a heap_sssp run (64 bytes, device memory).
+/* Counters of a heap_sssp run (72 bytes, device memory).
  *   popped      entries taken from the heap
  *   stale       popped entries whose distance had already improved (skipped)
  *   pushed      entries inserted (each a strict improvement of a distance)
@@ -370,7 +382,9 @@ int heap_knapsack(gh_heap_t h, uint32_t ninst, const uint32_t *d_item_off,
  *               spent in heap operations and in edge relaxation
  *   rounds      deleteMins that returned entries
  *   traced      heap operations the trace asked to record (0 without a
- *               trace; more than trace->op_cap means the trace is cut) */
+ *               trace; more than trace->op_cap means the trace is cut)
+ *   alg_bytes   algorithmic bytes of the heap operations (as
+ *               gh_reqrec.bytes) */
 typedef struct gh_ssspstats {
     uint64_t popped;
     uint64_t stale;
@@ -380,6 +394,7 @@ typedef struct gh_ssspstats {
     uint64_t relax_ticks;
     uint64_t rounds;
     uint64_t traced;
+    uint64_t alg_bytes;
 } gh_ssspstats;
 
 /* One heap operation of a traced SSSP run (32 bytes): its root ticket, its

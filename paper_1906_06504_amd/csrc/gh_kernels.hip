@@ -90,6 +90,7 @@ struct KnapShared {
   u64 gc_best;          // incumbent at the last garbage collection
   u64 gc_dropped;       // entries the collections removed
   u64 gm, gs;           // heap shape seen by a collection
+  u64 alg_bytes;        // algorithmic bytes of the instance's heap operations
   u32 gdead;            // nodes found dead by a collection
   u32 gkept;            // entries of a drained batch below the cut
   u32 gc_runs;
@@ -162,7 +163,10 @@ __device__ bool knap_collect(const HeapDesc& H, u64& ticket, u32& ops, lds_t<Ent
     const OpResult r = op_delete<K, T, Ent>(H, ticket++, stage + staged, (u32)K, L, sh, ctl);
     ++ops;
     if (!r.ok) return false;
-    if (tid == 0) ks.gkept = 0;
+    if (tid == 0) {
+      ks.gkept = 0;
+      ks.alg_bytes += op_alg_bytes<K, Ent>(1, r, sh.s);
+    }
     __syncthreads();
     if (r.count == 0) break;
     u32 mine = 0;
@@ -184,6 +188,7 @@ __device__ bool knap_collect(const HeapDesc& H, u64& ticket, u32& ops, lds_t<Ent
     ks.gc_dropped += ks.hsize - staged;
     ks.hsize = staged;
     ++ks.gc_runs;
+    ks.alg_bytes += 2 * staged * sizeof(Ent);   // the kept entries read and laid out
   }
   __syncthreads();
   return true;
@@ -242,6 +247,7 @@ __global__ __launch_bounds__(T) void k_knap(const HeapDesc* __restrict__ descs, 
       ks.hsize = 0;
       ks.gc_dropped = 0;
       ks.gc_runs = 0;
+      ks.alg_bytes = 0;
     }
     __syncthreads();
     if (tid == 0 && !ks.refused) {
@@ -292,7 +298,10 @@ __global__ __launch_bounds__(T) void k_knap(const HeapDesc* __restrict__ descs, 
         const u32 nn = c - j < (u32)K ? c - j : (u32)K;
         OpResult r = op_insert<K, T, Ent>(H, ticket++, kids + j, nn, L, sh, ctl);
         ++ops;
-        if (tid == 0 && !(r.flags & F_REJECT)) ks.hsize += nn;
+        if (tid == 0) {
+          if (!(r.flags & F_REJECT)) ks.hsize += nn;
+          ks.alg_bytes += op_alg_bytes<K, Ent>(0, r, sh.s);
+        }
         if (!r.ok) {
           ok = false;
           break;
@@ -309,6 +318,7 @@ __global__ __launch_bounds__(T) void k_knap(const HeapDesc* __restrict__ descs, 
       if (tid == 0) {
         ks.popped_total += r.count;
         ks.hsize -= r.count;
+        ks.alg_bytes += op_alg_bytes<K, Ent>(1, r, sh.s);
       }
       __syncthreads();
       if (!r.ok || r.count == 0) break;
@@ -390,6 +400,7 @@ __global__ __launch_bounds__(T) void k_knap(const HeapDesc* __restrict__ descs, 
       o.created = ks.created;
       o.popped = ks.popped_total;
       o.gc_dropped = ks.gc_dropped;
+      o.alg_bytes = ks.alg_bytes;
       o.ops = ops;
       o.flags = (ok ? 1u : 0u) | (ks.overflow ? 0x40u : 0u);
       o.gc_runs = ks.gc_runs;
@@ -491,7 +502,7 @@ __global__ __launch_bounds__(T) void k_sssp(const HeapDesc* __restrict__ descs, 
   const HeapDesc H = descs[0];
   u64* out = push + (u64)blockIdx.x * (push_per_wg + K);   // K popped entries
   u64* mine = out + K;                                      // this workgroup's pushes
-  u64 popped = 0, stale = 0, pushed = 0, ops = 0, heap_t = 0, relax_t = 0, rounds = 0;
+  u64 popped = 0, stale = 0, pushed = 0, ops = 0, heap_t = 0, relax_t = 0, rounds = 0, alg = 0;
   u32 idle = 0;
   u64 idle_since = 0;
   for (;;) {
@@ -516,6 +527,7 @@ __global__ __launch_bounds__(T) void k_sssp(const HeapDesc* __restrict__ descs, 
       const u64 t0 = now_ticks();
       r = op_delete<K, T, u64>(H, s_ticket, out, (u32)K, L, sh, ctl);
       ++ops;
+      alg += op_alg_bytes<K, u64>(1, r, sh.s);
       __syncthreads();
       heap_t += now_ticks() - t0;
       if (tr.d_ops && r.ok)
@@ -604,6 +616,7 @@ __global__ __launch_bounds__(T) void k_sssp(const HeapDesc* __restrict__ descs, 
       const u32 nn = c - j < (u32)K ? c - j : (u32)K;
       const OpResult ri = op_insert<K, T, u64>(H, s_ticket, mine + j, nn, L, sh, ctl);
       ++ops;
+      alg += op_alg_bytes<K, u64>(0, ri, sh.s);
       // (the batch in `mine` is unchanged by the insert)
       if (tr.d_ops && ri.ok)
         sssp_trace<T>(tr, st, s_ticket, GH_OP_INSERT, mine + j, nn, ri, sh, s_toff);
@@ -632,6 +645,7 @@ __global__ __launch_bounds__(T) void k_sssp(const HeapDesc* __restrict__ descs, 
     atomicAdd(reinterpret_cast<unsigned long long*>(&stats->relax_ticks),
               (unsigned long long)relax_t);
     atomicAdd(reinterpret_cast<unsigned long long*>(&stats->rounds), (unsigned long long)rounds);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&stats->alg_bytes), (unsigned long long)alg);
   }
 }
 

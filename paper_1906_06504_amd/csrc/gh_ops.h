@@ -71,6 +71,28 @@ struct OpResult {
 constexpr u32 F_FULL = 1, F_HANDOFF = 2, F_TOOK = 4, F_ROOT = 8, F_REFILL = 16, F_REJECT = 0x40,
               F_ABORT = 0x80;
 
+// Algorithmic bytes of one operation: what the method has to move between
+// HBM and the workgroup along the path the operation took (e = entry bytes,
+// n = entries inserted or returned, s = partial-buffer size at the root,
+// L = levels merged):
+//   insert kept in the partial buffer:  e (2 (n + s)) + 2 e K if a root exists
+//   insert of a full batch over L levels: e (n + s + (n + s - K)) + e (2 K L + K)
+//   deleteMin with no node: 2 e s;  root only: 2 e K;
+//   deleteMin refilled from the last node, L merged levels: e K (3 + 4 L) + 2 e s.
+template <int K, class Ent>
+__device__ __forceinline__ u64 op_alg_bytes(u32 kind, const OpResult& r, u64 s) {
+  constexpr u64 e = sizeof(Ent);
+  if (r.flags & F_REJECT) return 0;
+  if (kind == 0) {   // insert
+    const u64 n = r.count;
+    if (r.flags & F_FULL) return e * (n + s + (n + s - K)) + e * (2ull * K * r.levels + K);
+    return e * 2 * (n + s) + ((r.flags & F_ROOT) ? 2 * e * K : 0);
+  }
+  if (!(r.flags & F_ROOT)) return 2 * e * s;
+  if (r.flags & F_REFILL) return e * K * (3 + 4ull * r.levels) + 2 * e * s;
+  return 2 * e * K;
+}
+
 // --- lock primitives --------------------------------------------------------
 
 // Thread 0: wait until the root word shows our ticket; returns the word.

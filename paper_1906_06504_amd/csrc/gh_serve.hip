@@ -135,7 +135,7 @@ struct Scheduler {
     rec.t_admit = (u32)(ss->now - t0);
     rec.t_done = rec.t_admit;
     rec.t_resp = rec.t_admit;
-    rec.reserved = 0;
+    rec.bytes = 0;
     write_rec(r, rec);
   }
 
@@ -163,7 +163,7 @@ struct Scheduler {
     rec.t_admit = (u32)(ss->now - t0);
     rec.t_done = rec.t_admit;
     rec.t_resp = rec.t_admit;
-    rec.reserved = 0;
+    rec.bytes = 0;
     // slots write count, t_resp and t_done of this record: every word goes out
     // coherently and is complete before the queue entries are published
     write_rec(r, rec);
@@ -475,6 +475,8 @@ __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs,
       if (res.ok)
         __hip_atomic_fetch_max(&recs[r].t_resp, (u32)(sh.t_rel - ctl->t0), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&recs[r].bytes, (u32)op_alg_bytes<K, Ent>(op.kind, res, sh.s),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (atomicSub(&w.left[r], 1u) == 1u)
         __hip_atomic_store(&recs[r].t_done, (u32)(now_ticks() - ctl->t0), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);

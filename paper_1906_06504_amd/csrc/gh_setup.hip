@@ -70,7 +70,7 @@ __global__ void k_sssp_init(const HeapDesc* __restrict__ descs, SsspState* st, u
     st->done = 0;
     push[0] = (u64)src;   // entry (0 << 32 | src)
     u64* sw = reinterpret_cast<u64*>(stats);
-    for (int j = 0; j < 8; ++j) sw[j] = 0;
+    for (int j = 0; j < (int)(sizeof(gh_ssspstats) / 8); ++j) sw[j] = 0;
   }
 }
 

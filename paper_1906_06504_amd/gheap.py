@@ -39,18 +39,18 @@ LOG_DTYPE = np.dtype([("ticket", "<u8"), ("count", "<u4"), ("levels", "<u2"), ("
                       ("t_root", "<u4"), ("t_done", "<u4")])
 REQ_DTYPE = np.dtype([("first_ticket", "<u8"), ("count", "<u4"), ("nops", "<u2"), ("kind", "u1"),
                       ("flags", "u1"), ("t_admit", "<u4"), ("t_done", "<u4"), ("t_resp", "<u4"),
-                      ("reserved", "<u4")])
+                      ("bytes", "<u4")])
 KNAP_DTYPE = np.dtype([("best", "<u8"), ("explored", "<u8"), ("created", "<u8"),
-                       ("popped", "<u8"), ("gc_dropped", "<u8"), ("ops", "<u4"), ("flags", "<u4"),
-                       ("gc_runs", "<u4"), ("reserved", "<u4")])
+                       ("popped", "<u8"), ("gc_dropped", "<u8"), ("alg_bytes", "<u8"),
+                       ("ops", "<u4"), ("flags", "<u4"), ("gc_runs", "<u4"), ("reserved", "<u4")])
 assert OP_DTYPE.itemsize == 32 and LOG_DTYPE.itemsize == 32 and REQ_DTYPE.itemsize == 32
-assert KNAP_DTYPE.itemsize == 56
+assert KNAP_DTYPE.itemsize == 64
 SSSP_DTYPE = np.dtype([("popped", "<u8"), ("stale", "<u8"), ("pushed", "<u8"), ("heap_ops", "<u8"),
                        ("heap_ticks", "<u8"), ("relax_ticks", "<u8"), ("rounds", "<u8"),
-                       ("traced", "<u8")])
+                       ("traced", "<u8"), ("alg_bytes", "<u8")])
 SSSPOP_DTYPE = np.dtype([("ticket", "<u8"), ("off", "<u8"), ("count", "<u4"), ("kind", "<u4"),
                          ("reserved", "<u8")])
-assert SSSP_DTYPE.itemsize == 64 and SSSPOP_DTYPE.itemsize == 32
+assert SSSP_DTYPE.itemsize == 72 and SSSPOP_DTYPE.itemsize == 32
 
 REQ_ADMITTED = 1
 REQ_DEFERRED = 2

@@ -98,13 +98,37 @@ def test_binding_checks_tensors_before_the_library():
         gheap._ptr(torch.zeros(4, dtype=torch.int64), gheap._U64, 32, "out")
 
 
+def _header_structs():
+    """{struct name: [(field, C type)]} of every typedef struct in the header."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = {}
+    for body, name in re.findall(r"typedef struct \w+ \{(.*?)\} (\w+);", text, flags=re.S):
+        fields = []
+        for line in body.split(";"):
+            line = line.strip()
+            if line:
+                typ, field = line.rsplit(None, 1)
+                fields.append((field.lstrip("*"), typ))
+        out[name] = fields
+    return out
+
+
+_CTYPE = {"uint64_t": "<u8", "uint32_t": "<u4", "uint16_t": "<u2", "uint8_t": "|u1"}
+
+
 def test_struct_layouts_match_header():
+    """Every struct the binding mirrors has the header's fields, in order,
+    with the same widths."""
     from paper_1906_06504_amd import gheap
-    text = open(HEADER).read()
-    assert "uint64_t arrival_ns;" in text and gheap.OP_DTYPE.names[-1] == "arrival_ns"
-    assert gheap.OP_DTYPE.itemsize == 32 and gheap.LOG_DTYPE.itemsize == 32
-    assert list(gheap.LOG_DTYPE.names) == ["ticket", "count", "levels", "kind", "flags", "pb",
-                                           "reserved", "t_claim", "t_root", "t_done"]
+    structs = _header_structs()
+    pairs = {"gh_op": gheap.OP_DTYPE, "gh_logrec": gheap.LOG_DTYPE, "gh_reqrec": gheap.REQ_DTYPE,
+             "gh_knapres": gheap.KNAP_DTYPE, "gh_ssspstats": gheap.SSSP_DTYPE,
+             "gh_ssspop": gheap.SSSPOP_DTYPE}
+    for name, dt in pairs.items():
+        fields = structs[name]
+        assert list(dt.names) == [f for f, _ in fields], name
+        for f, typ in fields:
+            assert dt.fields[f][0].str.replace("=", "<") in (_CTYPE[typ], _CTYPE[typ].replace("|", "<")), (name, f)
 
 
 def test_oplist_seq_ranks():
