@@ -247,6 +247,24 @@ uint64_t heap_filter_workspace_bytes(gh_heap_t h, uint32_t i);
 int heap_filter(gh_heap_t h, uint32_t i, uint64_t bound, void *d_work, uint64_t work_bytes,
                 uint64_t *d_kept);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): heap_filter
+ * of heap i without a workspace argument.  The workspace is a fixed array of
+ * GH_FILTER_NOALLOC_MAX_BYTES in device memory that the library holds on
+ * every GPU it runs on until the process ends; its address is looked up when
+ * a handle is created on that GPU.  The call allocates nothing: no hipMalloc,
+ * no hipFree, no allocating library routine.  Every call on one GPU shares
+ * that GPU's array, so calls that can overlap on one GPU (different streams,
+ * different handles) race and must be ordered by the caller; calls on one
+ * handle are ordered by its stream.  Otherwise as heap_filter: the same
+ * kernels, the same result, *d_kept (device, may be NULL) receives the
+ * number kept.  Errors: GH_EINVAL (null handle, i out of range), GH_ENOMEM
+ * (heap_filter_workspace_bytes(h, i) exceeds GH_FILTER_NOALLOC_MAX_BYTES:
+ * heaps of up to about 4 million entries fit), GH_EDEVICE (the array's
+ * address could not be found, or a launch failed). */
+#define GH_FILTER_NOALLOC_MAX_BYTES (64ull << 20)
+int heap_filter_noalloc(gh_heap_t h, uint32_t i, uint64_t bound, uint64_t *d_kept);
+
 /* deleteMin on heap 0 of the set (Sec. 3.2.1, Sec. 3.3.2) of c entries,
  * 1 <= c <= k (the node capacity): writes the min(c, size) smallest entries in
  * ascending order to d_out (device, room for c entries) and that number to

@@ -8,6 +8,8 @@
 // LDS, then merge-path passes in global memory) and laid out again as a bulk
 // build (Sec. 3.1: a sorted array is a generalized heap).  Node capacity
 // comes from the heap descriptor, so this object is compiled once.
+#include <mutex>
+
 #include "gh_launch.h"
 
 namespace gh {
@@ -334,6 +336,47 @@ hipError_t launch_filter(const HeapDesc* d, u64 max_nodes, u32 k, u32 ebytes, u6
     return launch_filter_t<e128>(d, max_nodes, k, b, work, kept_out, st);
   }
   return launch_filter_t<u64>(d, max_nodes, k, bound, work, kept_out, st);
+}
+
+// ---------------------------------------------------------------------------
+// Workspace of heap_filter_noalloc, for callers that cannot allocate device
+// memory: a fixed array, one copy on every GPU the library runs on, held
+// until the process ends.  In host code `scratch` names the array only for
+// hipGetSymbolAddress; its device address is looked up once per device,
+// with that device current, and every launch gets that address.  Nothing in
+// it has to start at zero: the count and scan kernels write the header and
+// every count the later kernels read, and the sort buffers are read only
+// below the kept count that the same call wrote.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[GH_FILTER_NOALLOC_MAX_BYTES];
+
+namespace {
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex scratch_mu;
+void* scratch_addr[SCRATCH_DEVICES];
+}  // namespace
+
+hipError_t filter_scratch_init(int dev) {
+  if (dev < 0 || dev >= SCRATCH_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(scratch_mu);
+  if (scratch_addr[dev]) return hipSuccess;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+  void* p = nullptr;
+  e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (cur != dev) (void)hipSetDevice(cur);
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  scratch_addr[dev] = p;
+  return hipSuccess;
+}
+
+void* filter_scratch(int dev) {
+  if (dev < 0 || dev >= SCRATCH_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> g(scratch_mu);
+  return scratch_addr[dev];
 }
 
 }  // namespace gh

@@ -51,6 +51,10 @@ hipError_t launch_ops_k(const LaunchArgs& a);
 u64 filter_workspace_bytes(u64 max_nodes, u32 k, u32 ebytes);
 hipError_t launch_filter(const HeapDesc* d, u64 max_nodes, u32 k, u32 ebytes, u64 bound,
                          void* work, u64* kept_out, hipStream_t st);
+// the library's own filter workspace on device `dev` (heap_filter_noalloc):
+// looked up once per device with that device current; nullptr on failure
+hipError_t filter_scratch_init(int dev);
+void* filter_scratch(int dev);
 template <int K, class Ent>
 hipError_t launch_ops_var_k(const LaunchArgs& a);
 

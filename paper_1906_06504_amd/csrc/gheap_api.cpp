@@ -41,6 +41,7 @@ struct gh_heap {
   bool size0_known;
   int sticky;                      // last device error seen by the host
   u32 clock_mhz;
+  int device;                      // HIP device current at creation
 };
 
 namespace {
@@ -310,6 +311,14 @@ int heap_create_many(gh_heap_t* out, uint32_t k, int keytype, uint32_t nheaps,
   h->size0_known = true;
   h->sticky = GH_OK;
   h->clock_mhz = clock_mhz_of_device();
+  h->device = 0;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return GH_EDEVICE;
+  }
+  // the no-allocation filter's workspace on this device (a failed lookup
+  // is reported by heap_filter_noalloc, which tries again)
+  (void)filter_scratch_init(h->device);
   h->host_descs.resize(nheaps);
   for (u32 i = 0; i < nheaps; ++i) {
     HeapDesc& d = h->host_descs[i];
@@ -384,6 +393,25 @@ int heap_filter(gh_heap_t h, uint32_t i, uint64_t bound, void* d_work, uint64_t 
     return GH_EINVAL;
   if (i == 0) h->size0_known = false;
   if (launch_filter(h->descs + i, h->host_descs[i].max_nodes, h->k, h->ebytes, bound, d_work,
+                    d_kept, h->stream) != hipSuccess)
+    return GH_EDEVICE;
+  return GH_OK;
+}
+
+int heap_filter_noalloc(gh_heap_t h, uint32_t i, uint64_t bound, uint64_t* d_kept) {
+  if (!h || i >= h->nheaps) return GH_EINVAL;
+  if (h->sticky != GH_OK) return h->sticky;
+  if (filter_workspace_bytes(h->host_descs[i].max_nodes, h->k, h->ebytes) >
+      GH_FILTER_NOALLOC_MAX_BYTES)
+    return GH_ENOMEM;
+  void* work = filter_scratch(h->device);
+  if (!work) {
+    if (filter_scratch_init(h->device) != hipSuccess) return GH_EDEVICE;
+    work = filter_scratch(h->device);
+    if (!work) return GH_EDEVICE;
+  }
+  if (i == 0) h->size0_known = false;
+  if (launch_filter(h->descs + i, h->host_descs[i].max_nodes, h->k, h->ebytes, bound, work,
                     d_kept, h->stream) != hipSuccess)
     return GH_EDEVICE;
   return GH_OK;

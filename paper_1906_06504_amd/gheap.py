@@ -69,7 +69,8 @@ EXPORTS = ("heap_arena_bytes", "heap_supported_shape", "heap_create", "heap_crea
            "heap_graph_launch", "heap_graph_destroy", "heap_sync", "heap_size",
            "heap_read_state", "heap_destroy", "heap_strerror", "heap_clock_hz",
            "heap_serve_workspace_bytes", "heap_serve", "heap_knapsack", "heap_sssp",
-           "heap_build", "heap_filter_workspace_bytes", "heap_filter")
+           "heap_build", "heap_filter_workspace_bytes", "heap_filter",
+           "heap_filter_noalloc")
 
 
 class GHeapError(RuntimeError):
@@ -131,6 +132,7 @@ def load_library(path: str = LIB_PATH):
         "heap_build": (i32, [vp, u32, vp, u64]),
         "heap_filter_workspace_bytes": (u64, [vp, u32]),
         "heap_filter": (i32, [vp, u32, u64, vp, u64, vp]),
+        "heap_filter_noalloc": (i32, [vp, u32, u64, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -336,6 +338,15 @@ class HeapSet:
                                     work.numel(),
                                     _ptr(kept)), "heap_filter")
         return kept, work
+
+    def filter_noalloc(self, i: int, bound: int, kept: torch.Tensor | None = None):
+        """heap_filter without a workspace: the library's own device array
+        is the workspace.  Returns kept (int64 device tensor of one element)."""
+        if kept is None:
+            kept = torch.zeros(1, dtype=torch.int64, device=self.device)
+        _check(self.lib.heap_filter_noalloc(self.h, i, int(bound), _ptr(kept, _U64, 8, "kept")),
+               "heap_filter_noalloc")
+        return kept
 
     def sync(self) -> int:
         return int(self.lib.heap_sync(self.h))
