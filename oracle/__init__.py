@@ -95,6 +95,9 @@ def _declare_heap(lib, pre):
     f("idx").argtypes = [ctypes.c_uint64]
     f("insert").restype = ctypes.c_int
     f("insert").argtypes = [ctypes.c_void_p, EP, ctypes.c_uint64]
+    if hasattr(lib, pre + "insert_bu"):
+        f("insert_bu").restype = ctypes.c_int
+        f("insert_bu").argtypes = [ctypes.c_void_p, EP, ctypes.c_uint64]
     f("delete_min").restype = ctypes.c_uint64
     f("delete_min").argtypes = [ctypes.c_void_p, EP]
     f("delete_min_n").restype = ctypes.c_uint64
@@ -202,12 +205,14 @@ class OracleHeap:
         except Exception:
             pass
 
-    def insert(self, keys) -> None:
+    def insert(self, keys, bottom_up: bool = False) -> None:
+        """Insert keys (chunks of k); bottom_up: each full batch climbs from
+        its target (the bottom-up INS) instead of descending from the root."""
         a = self._in(keys)
         n = a.shape[0]
         if n and np.any(np.all(a.reshape(n, -1) == MAXE, axis=1)):
             raise ValueError("the all-ones entry is reserved")
-        if self._f("insert")(self.h, _vp(a) if n else None, n) != 0:
+        if self._f("insert_bu" if bottom_up else "insert")(self.h, _vp(a) if n else None, n) != 0:
             raise MemoryError("gho_insert failed")
 
     def delete_min(self, c: int | None = None) -> np.ndarray:

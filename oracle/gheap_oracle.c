@@ -20,6 +20,10 @@
  *   - top-down INS (Sec. 3.2.2, "Top-down INS" paragraph): merge the batch
  *     with every node on the root-to-target path, the node keeping the k
  *     smallest, and place the carry at the target;
+ *   - bottom-up INS (Sec. 3.2.2, "Bottom-up INS" paragraph): place the batch
+ *     at the target, then MergeAndSort each node on the insert path with its
+ *     parent, the parent keeping the k smallest, until the root or until the
+ *     parent's largest entry is no larger than the node's smallest;
  *   - partial batches (Sec. 3.3.2, last two paragraphs before the
  *     linearizability proof): insert keys merge with the partial buffer
  *     first; a DEL reads the partial buffer only when no node exists; and, as
@@ -60,6 +64,7 @@ typedef unsigned __int128 gho_ent;
 #define gho_nodes ghow_nodes
 #define gho_pb_size ghow_pb_size
 #define gho_insert ghow_insert
+#define gho_insert_bu ghow_insert_bu
 #define gho_delete_min ghow_delete_min
 #define gho_delete_min_n ghow_delete_min_n
 #define gho_build ghow_build
@@ -204,6 +209,21 @@ uint64_t gho_pb_size(const gho_heap *h) { return h->s; }
 
 /* ---- INS: one operation of n <= k entries (Sec. 3.2.2 and 3.3.2) ------- */
 
+/* The partial-buffer rule shared by both INS forms (Sec. 3.3.2): an input
+ * of n entries fits when the partial buffer (capacity k - 1) can take it. */
+static int pb_takes(const gho_heap *h, uint64_t n) { return n + h->s <= h->k - 1; }
+
+/* The pb keeps merged (its old entries and the n new ones); then, if a root
+ * exists, root and pb are merged so that the pb's entries are >= the root's
+ * (Property 3). */
+static void keep_in_pb(gho_heap *h, const gho_ent *merged, uint64_t n) {
+    const uint64_t k = h->k;
+    memcpy(h->pb, merged, (n + h->s) * sizeof(gho_ent));
+    h->s += n;
+    if (h->m >= 1)
+        merge_and_sort(h, node_at(h, 1), k, h->pb, h->s, node_at(h, 1), h->pb);
+}
+
 static int insert_batch(gho_heap *h, const gho_ent *x, uint64_t n) {
     const uint64_t k = h->k;
     gho_ent *in = h->tmp2;          /* sorted copy of the input */
@@ -214,13 +234,9 @@ static int insert_batch(gho_heap *h, const gho_ent *x, uint64_t n) {
     if (!merged) return -1;
     merge_into(in, n, h->pb, h->s, merged);
     h->ins_ops++;
-    if (n + h->s <= k - 1) {
-        /* the partial buffer has room: keep everything there, then make its
-         * entries >= the root's (Property 3) */
-        memcpy(h->pb, merged, (n + h->s) * sizeof(gho_ent));
-        h->s += n;
-        if (h->m >= 1)
-            merge_and_sort(h, node_at(h, 1), k, h->pb, h->s, node_at(h, 1), h->pb);
+    if (pb_takes(h, n)) {
+        /* the partial buffer has room: keep everything there */
+        keep_in_pb(h, merged, n);
         free(merged);
         return 0;
     }
@@ -276,6 +292,77 @@ static void count_delete(gho_heap *h, uint64_t m0, uint64_t s0, uint64_t lv0, in
     } else {
         h->traffic += 2 * k;
     }
+}
+
+/* ---- bottom-up INS (Sec. 3.2.2, "Bottom-up INS" paragraph) ------------
+ * The partial buffer is handled at the root as for the top-down INS (Sec.
+ * 3.3.4 says so for the BU-INS/TD-DEL heap): merged = merge(sorted input,
+ * pb); if it fits the pb (n + s <= k - 1) everything stays there and the pb
+ * is merged with the root, exactly as the top-down INS does.  Otherwise F =
+ * its k smallest goes to the target (the next node position), the rest is
+ * the new pb, and F climbs: the node on the insert path and its parent are
+ * merged, the parent keeping the k smallest, until the root is reached or
+ * the parent's largest entry is <= the node's smallest (the property holds
+ * from there up).  After the climb the root is the k smallest of root and F,
+ * so Property 3 holds again (the pb's entries are >= the k of F). */
+static int insert_batch_bu(gho_heap *h, const gho_ent *x, uint64_t n, uint64_t *levels) {
+    const uint64_t k = h->k;
+    gho_ent *in = h->tmp2;
+    memcpy(in, x, n * sizeof(gho_ent));
+    qsort(in, n, sizeof(gho_ent), cmp_ent);
+    gho_ent *merged = (gho_ent *)malloc((n + h->s) * sizeof(gho_ent) + 8);
+    if (!merged) return -1;
+    merge_into(in, n, h->pb, h->s, merged);
+    h->ins_ops++;
+    *levels = 0;
+    if (pb_takes(h, n)) {
+        keep_in_pb(h, merged, n);
+        free(merged);
+        return 0;
+    }
+    uint64_t rest = n + h->s - k;
+    uint64_t t = gho_idx(h->m + 1);
+    if (ensure_cap(h, t)) { free(merged); return -1; }
+    memcpy(node_at(h, t), merged, k * sizeof(gho_ent));
+    memcpy(h->pb, merged + k, rest * sizeof(gho_ent));
+    h->s = rest;
+    h->m += 1;
+    free(merged);
+    h->ins_full++;
+    uint64_t c = t;
+    while (c > 1) {
+        gho_ent *C = node_at(h, c), *P = node_at(h, c / 2);
+        if (P[k - 1] <= C[0]) break;             /* the property holds from here up */
+        merge_and_sort(h, P, k, C, k, P, C);     /* parent keeps the k smallest */
+        h->ins_path_nodes++;
+        (*levels)++;
+        c /= 2;
+    }
+    return 0;
+}
+
+/* Insert n entries bottom-up: chunks of k as gho_insert takes them.  The
+ * traffic counted for a full batch that merged L times: the input and pb as
+ * for a top-down insert, the target written (k), and per merge the parent
+ * read and both nodes written (3k), plus the parent read by the check that
+ * stopped the climb below the root (k). */
+int gho_insert_bu(gho_heap *h, const gho_ent *x, uint64_t n) {
+    const uint64_t k = h->k;
+    uint64_t done = 0;
+    while (done < n) {
+        uint64_t c = n - done < k ? n - done : k;
+        uint64_t m0 = h->m, s0 = h->s, L = 0;
+        if (insert_batch_bu(h, x + done, c, &L)) return -1;
+        if (h->m > m0) {
+            uint64_t t = gho_idx(m0 + 1);
+            int stopped = (uint64_t)floor_log2(t) > L;   /* a check stopped below the root */
+            h->traffic += (c + s0 + (c + s0 - k)) + k + 3 * k * L + (stopped ? k : 0);
+        } else {
+            h->traffic += 2 * (c + s0) + (m0 >= 1 ? 2 * k : 0);
+        }
+        done += c;
+    }
+    return 0;
 }
 
 /* Insert n entries: n <= k is one INS; larger inputs are split into
@@ -536,7 +623,7 @@ void gho_counters(const gho_heap *h, uint64_t out[7]) {
 
 /* ---- log replay --------------------------------------------------------
  * Apply ops in the given order: type 0 = INS of n[i] entries read from
- * in_keys + off[i]; type 1 = DEL of n[i] entries (0 = k; more than k fails)
+ * in_keys + off[i] (type 2: the same, bottom-up); type 1 = DEL of n[i] entries (0 = k; more than k fails)
  * whose output goes to out_keys + off[i] and whose count goes to
  * out_count[i].  With check != 0 the invariants are
  * verified after every op.  Returns 0, or -(1 + index) of the first op that
@@ -546,8 +633,11 @@ int64_t gho_replay(gho_heap *h, uint64_t nops, const uint8_t *type,
                    const gho_ent *in_keys, gho_ent *out_keys,
                    uint32_t *out_count, int check) {
     for (uint64_t i = 0; i < nops; i++) {
-        if (type[i] == 0) {
-            if (gho_insert(h, in_keys + off[i], n[i])) return -(int64_t)(i + 1);
+        if (type[i] == 0 || type[i] == 2) {
+            /* type 2: the bottom-up INS */
+            int rc = type[i] == 0 ? gho_insert(h, in_keys + off[i], n[i])
+                                  : gho_insert_bu(h, in_keys + off[i], n[i]);
+            if (rc) return -(int64_t)(i + 1);
             if (out_count) out_count[i] = 0;
         } else if (type[i] == 1) {
             /* n[i] = entries requested, 0 meaning k */

@@ -38,9 +38,10 @@ def _built():
     oracle.build(force=False)
 
 
-def random_trace(rng, k, nops, key_range, max_ins=None, var_del=False, filt=False):
+def random_trace(rng, k, nops, key_range, max_ins=None, var_del=False, filt=False, bu=False):
     """Random op sequence: ('ins', array), ('del',), with var_del also
-    ('del', c) with c uniform on [1, k], with filt also ('filter', bound)."""
+    ('del', c) with c uniform on [1, k], with filt also ('filter', bound),
+    with bu also ('insbu', array) (the bottom-up insert)."""
     max_ins = max_ins or 3 * k
     ops = []
     for _ in range(nops):
@@ -48,7 +49,8 @@ def random_trace(rng, k, nops, key_range, max_ins=None, var_del=False, filt=Fals
             ops.append(("filter", int(rng.integers(0, key_range + 1))))
         elif rng.random() < 0.55:
             n = int(rng.integers(0, max_ins + 1))
-            ops.append(("ins", rng.integers(0, key_range, n).astype(np.uint64)))
+            kind = "insbu" if bu and rng.random() < 0.6 else "ins"
+            ops.append((kind, rng.integers(0, key_range, n).astype(np.uint64)))
         elif var_del and rng.random() < 0.7:
             ops.append(("del", int(rng.integers(1, k + 1))))
         else:
@@ -62,8 +64,8 @@ def run_against_brute_force(k, ops, lib=None):
     h = oracle.OracleHeap(k, lib=lib)
     live = []
     for i, op in enumerate(ops):
-        if op[0] == "ins":
-            h.insert(op[1])
+        if op[0] in ("ins", "insbu"):
+            h.insert(op[1], bottom_up=op[0] == "insbu")
             live = sorted(live + [int(v) for v in op[1]])
         elif op[0] == "filter":
             live = [v for v in live if v < op[1]]
@@ -336,11 +338,11 @@ MUTANTS = {
         "if (cur[k - 1] <= cmin) break;",
         "if (cur[0] <= cmin) break;"),
     "partial_insert_skips_root_merge": (
-        "        if (h->m >= 1)\n            merge_and_sort(h, node_at(h, 1), k, h->pb, h->s, node_at(h, 1), h->pb);\n        free(merged);",
-        "        free(merged);"),
+        "    h->s += n;\n    if (h->m >= 1)\n        merge_and_sort(h, node_at(h, 1), k, h->pb, h->s, node_at(h, 1), h->pb);\n}",
+        "    h->s += n;\n}"),
     "pb_capacity_k": (
-        "if (n + h->s <= k - 1) {",
-        "if (n + h->s <= k) {"),
+        "return n + h->s <= h->k - 1; }",
+        "return n + h->s <= h->k; }"),
     "no_max_fill": (
         "    for (uint64_t i = 0; i < k; i++) node_at(h, last)[i] = GHO_MAX;\n    h->m -= 1;",
         "    h->m -= 1;"),
@@ -350,6 +352,21 @@ MUTANTS = {
     "one_child_no_merge": (
         "            if (cur[k - 1] <= X[0]) break;",
         "            break;"),
+    "bu_no_climb": (
+        "        if (P[k - 1] <= C[0]) break;             /* the property holds from here up */",
+        "        break;"),
+    "bu_stop_on_parent_min": (
+        "        if (P[k - 1] <= C[0]) break;             /* the property holds from here up */",
+        "        if (P[0] <= C[0]) break;"),
+    "bu_parent_keeps_largest": (
+        "        merge_and_sort(h, P, k, C, k, P, C);     /* parent keeps the k smallest */",
+        "        merge_and_sort(h, P, k, C, k, C, P);"),
+    "bu_climb_stops_below_root": (
+        "    while (c > 1) {\n        gho_ent *C = node_at(h, c), *P = node_at(h, c / 2);",
+        "    while (c > 3) {\n        gho_ent *C = node_at(h, c), *P = node_at(h, c / 2);"),
+    "bu_target_at_tree_index": (
+        "    uint64_t t = gho_idx(h->m + 1);\n    if (ensure_cap(h, t)) { free(merged); return -1; }",
+        "    uint64_t t = h->m + 1;\n    if (ensure_cap(h, t)) { free(merged); return -1; }"),
     "full_batch_takes_largest": (
         "    memcpy(F, merged, k * sizeof(gho_ent));\n    memcpy(h->pb, merged + k, rest * sizeof(gho_ent));",
         "    memcpy(F, merged + rest, k * sizeof(gho_ent));\n    memcpy(h->pb, merged, rest * sizeof(gho_ent));"),
@@ -374,7 +391,7 @@ def _mutant_caught(lib):
     for k in (1, 2, 3, 4, 8):
         for trial in range(40):
             ops = random_trace(rng, k, 60, 1 << 40 if trial % 2 else 40, var_del=trial % 4 >= 2,
-                               filt=trial % 8 >= 4)
+                               filt=trial % 8 >= 4, bu=trial % 3 == 0)
             try:
                 if run_against_brute_force(k, ops, lib=lib) is not None:
                     return True
@@ -581,3 +598,103 @@ def test_traffic_counter_full_batches_closed_form(k):
     c = h.counters()
     assert c["ins_path_nodes"] == levels and c["ins_full"] == m
     assert c["traffic_entries"] == 2 * k * m + 2 * k * levels
+
+
+# ---------------------------------------------------------------------------
+# bottom-up INS (Sec. 3.2.2, "Bottom-up INS" paragraph)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 8, 16])
+def test_bottom_up_brute_force_random_traces(k):
+    """Traces mixing bottom-up inserts, top-down inserts and deleteMins:
+    every deleteMin returns the min(k, size) smallest live entries, and
+    Properties 1-3 with the m/s closed form hold after every operation."""
+    rng = np.random.default_rng(3000 + k)
+    for trial in range(50):
+        key_range = 50 if trial % 3 == 0 else 1 << 40
+        ops = random_trace(rng, k, int(rng.integers(5, 80)), key_range, bu=True)
+        msg = run_against_brute_force(k, ops)
+        assert msg is None, "k=%d trial=%d %s" % (k, trial, msg)
+
+
+def _path_down(t):
+    """Node indices from the root down to node t."""
+    out = []
+    while t >= 1:
+        out.append(t)
+        t //= 2
+    return out[::-1]
+
+
+@pytest.mark.parametrize("k", [2, 3, 8])
+def test_bottom_up_path_is_the_sorted_union_in_chunks(k):
+    """Closed form of one full-batch bottom-up insert: with F the k smallest
+    of (input + partial buffer), the nodes on the root-to-target path hold,
+    from the root down, consecutive k-chunks of the sorted union of F and
+    their entries before the insert (the heap property orders the path's
+    batches, so climbing merges sort their union; where the climb stops the
+    upper chunks are already in place).  Nodes off the path do not change."""
+    rng = np.random.default_rng(77 + k)
+    for trial in range(40):
+        h = oracle.OracleHeap(k)
+        for _ in range(int(rng.integers(0, 30))):
+            h.insert(rng.integers(0, 1 << 30, int(rng.integers(1, k + 1))).astype(np.uint64))
+        m0, s0 = h.m, h.s
+        nodes0, pb0 = h.export()
+        n = k - s0 + int(rng.integers(0, s0 + 1))          # makes a full batch
+        x = rng.integers(0, 1 << 30, n).astype(np.uint64)
+        merged = np.sort(np.concatenate([x, pb0]))
+        F, rest = merged[:k], merged[k:]
+        h.insert(x, bottom_up=True)
+        nodes1, pb1 = h.export()
+        t = oracle.idx(m0 + 1)
+        path = _path_down(t)
+        union = np.sort(np.concatenate([F] + [nodes0[c - 1] for c in path[:-1]]))
+        for j, c in enumerate(path):
+            assert np.array_equal(nodes1[c - 1], union[j * k:(j + 1) * k]), "trial %d node %d" % (trial, c)
+        assert np.array_equal(pb1, rest)
+        for c in range(1, m0 + 1):
+            if c not in path:
+                assert np.array_equal(nodes1[c - 1], nodes0[c - 1])
+
+
+def test_bottom_up_hand_worked_trace():
+    """k = 2, bottom-up inserts worked by hand (positions 1, 2, 3, 4 are
+    node indices 1, 2, 3, 4):
+      [5,9] -> root [5,9];
+      [1,7] at node 2, merged with the root: root [1,5], node 2 [7,9];
+      [3,4] at node 3, merged with the root: root [1,3], node 3 [4,5];
+      [8,6] at node 4 (child of 2): node 2 [6,7], node 4 [8,9], and the
+            root's largest 3 <= 6 stops the climb;
+      [0,2] at node 5 (idx(5) = 6, child of 3): node 3 [0,2], node 6 [4,5];
+            root [1,3] vs [0,2]: root [0,1], node 3 [2,3]."""
+    h = oracle.OracleHeap(2)
+    steps = [([5, 9], {1: [5, 9]}),
+             ([1, 7], {1: [1, 5], 2: [7, 9]}),
+             ([3, 4], {1: [1, 3], 2: [7, 9], 3: [4, 5]}),
+             ([8, 6], {1: [1, 3], 2: [6, 7], 3: [4, 5], 4: [8, 9]}),
+             ([0, 2], {1: [0, 1], 2: [6, 7], 3: [2, 3], 4: [8, 9], 6: [4, 5]})]
+    for keys, want in steps:
+        h.insert(np.array(keys, dtype=np.uint64), bottom_up=True)
+        nodes, pb = h.export()
+        assert h.m == len(want) and h.s == 0
+        for c, row in want.items():
+            assert [int(v) for v in nodes[c - 1]] == row, (keys, c)
+    c = h.counters()
+    assert c["ins_path_nodes"] == 5   # merges: root; root; node 2; node 3 and the root
+
+
+def test_bottom_up_ascending_batches_never_climb():
+    """Ascending full batches: each new batch is no smaller than its parent,
+    so no merge happens and the layout is the bulk build of the input."""
+    k = 4
+    keys = np.arange(40 * k, dtype=np.uint64)
+    h = oracle.OracleHeap(k)
+    for i in range(40):
+        h.insert(keys[i * k:(i + 1) * k], bottom_up=True)
+    assert h.counters()["ins_path_nodes"] == 0
+    b = oracle.OracleHeap(k)
+    b.build(keys)
+    n1, p1 = h.export()
+    n2, p2 = b.export()
+    assert np.array_equal(n1[:40], n2[:40]) and np.array_equal(p1, p2)
