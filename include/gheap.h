@@ -78,7 +78,9 @@ typedef struct gh_heap *gh_heap_t;
 /* One operation of a multi-operation submission (32 bytes, device memory).
  *   heap   index of the heap within the set, < nheaps
  *   kind   GH_OP_INSERT or GH_OP_DELETE_MIN
- *   n      insert: number of entries, 1..k; deleteMin: number of entries to
+ *   n      insert: number of entries, 1..k, or with GH_TUNE_MULTI_INSERT
+ *          1..heap_insert_max(k) (an insert of more than k entries takes the
+ *          root once: see heap_insert_max); deleteMin: number of entries to
  *          take, 1..k, 0 meaning k (a deleteMin of c < k entries returns
  *          the min(c, size) smallest; heap_submit runs those only with
  *          GH_TUNE_VARIABLE_DELETE); larger n is rejected (GH_EINVAL)
@@ -103,15 +105,17 @@ typedef struct gh_op {
  *   count    insert: n; deleteMin: entries returned (min(c, heap size) for a
  *            deleteMin of c entries)
  *   levels   insert: depth of the target node reached (0 if the keys stayed
- *            in the partial buffer); deleteMin: sift-down levels that merged
+ *            in the partial buffer; the deepest target of an insert of more
+ *            than k entries); deleteMin: sift-down levels that merged
  *   kind     GH_OP_INSERT or GH_OP_DELETE_MIN
  *   flags    bit 0: a full batch was created; bit 1: an insert handed its
  *            batch to a deleteMin that took its target; bit 2: a deleteMin
  *            took the batch of an in-flight insert; bit 3: the heap had at
  *            least one node when the root was taken; bit 4: a deleteMin
- *            refilled the root from the last node; bit 6: the operation
- *            was rejected (capacity or malformed record); bit 7: abandoned
- *            after a device error
+ *            refilled the root from the last node; bit 5: a bottom-up
+ *            insert's climb stopped below the root (GH_TUNE_BOTTOM_UP);
+ *            bit 6: the operation was rejected (capacity or malformed
+ *            record); bit 7: abandoned after a device error
  *   pb       partial-buffer size when the root was taken
  *   t_claim, t_root, t_done  device wall clock in ticks (heap_clock_hz)
  *            relative to the submission's start, when a workgroup claimed
@@ -133,8 +137,8 @@ typedef struct gh_logrec {
  *   first_ticket  root ticket of the request's first operation on its heap
  *   count         deleteMin: entries returned; insert: entries inserted
  *                 (0 if rejected)
- *   nops          operations the request was split into (ceil(n / k) for
- *                 an insert, 1 for a deleteMin)
+ *   nops          operations the request was split into (ceil(n /
+ *                 heap_insert_max(k)) for an insert, 1 for a deleteMin)
  *   kind          GH_OP_INSERT or GH_OP_DELETE_MIN
  *   flags         bit 0: admitted; bit 1: an insert waited for heap memory;
  *                 bit 6: rejected (larger than the heap's capacity, never
@@ -171,12 +175,33 @@ typedef struct gh_reqrec {
  * (0 = library default), threads = workgroup size (0 = library default: 64
  * for k = 32, 128 for k = 64 and 128, 512 for k = 256 and 512, 1024 for
  * k = 1024; heap_serve: 256 for k >= 256; must be one of the shapes
- * heap_supported_shape accepts for k).  flags: 0, or
+ * heap_supported_shape accepts for k).  flags: 0, or any of
  * GH_TUNE_VARIABLE_DELETE when the submission holds deleteMins of fewer than
- * k entries; they run in a kernel of their own, so that submissions of
- * whole-root deleteMins keep a kernel compiled without that code path.
- * Without the flag such a record is rejected (GH_EINVAL). */
+ * k entries and GH_TUNE_MULTI_INSERT when it holds inserts of more than k
+ * entries; such submissions run in a general kernel of their own, so that
+ * submissions of whole-root deleteMins and inserts of up to k entries keep a
+ * kernel compiled without those code paths.  Without the flag such a record
+ * is rejected (GH_EINVAL). */
 #define GH_TUNE_VARIABLE_DELETE 1u
+#define GH_TUNE_MULTI_INSERT 2u
+/* GH_TUNE_BOTTOM_UP: run the submission's inserts bottom-up (Sec. 3.2.2,
+ * "Bottom-up INS" paragraph; the BU-INS of Sec. 3.3.4), for insert phases:
+ * every operation must be an insert of 1..k entries; a deleteMin record is
+ * rejected (GH_EINVAL), and the flag may not be combined with the two above
+ * (GH_EINVAL, nothing runs).  Each insert takes the root in ticket order
+ * only to merge its batch with the partial buffer (and, if everything fits
+ * there, the partial buffer with the root, as the top-down insert does);
+ * a full batch of k entries goes to its target node and climbs, merging
+ * with each parent (the parent keeping the k smallest) until the parent's
+ * largest entry is no larger than the batch's smallest or the root is
+ * merged.  One operation at a time this leaves exactly the top-down
+ * layout; with many in flight the heap satisfies Properties 1-3 with the
+ * same entries when the launch ends, and its layout may differ.  Inserts
+ * do not overlap deleteMins in this form because a climbing insert has no
+ * linearization point that deleteMins in flight would respect (see
+ * DESIGN); deleteMins run in other submissions.  Log records: levels =
+ * merges of the climb; flags bit 5 = the climb stopped below the root. */
+#define GH_TUNE_BOTTOM_UP 4u
 typedef struct gh_tuning {
     uint32_t workgroups;
     uint32_t threads;
@@ -190,6 +215,22 @@ typedef struct gh_tuning {
  * nodes or more. */
 uint64_t heap_arena_bytes(uint32_t k, int keytype, uint32_t nheaps, const uint64_t *max_keys,
                           uint64_t max_keys_each);
+
+/* Largest insert one operation may hold (0 for an unsupported k): 4096
+ * entries, 2048 for k = 32.  An insert of n > k entries (Sec. 3.2.2, footnote
+ * to the INS paragraph: more than k keys are inserted by several INS
+ * operations) takes the root once: under that one root hold it runs the root
+ * phase of every chunk of k entries in input order (the last chunk may be
+ * shorter) exactly as consecutive inserts would, reserving one target per
+ * full batch, and the carries of those batches then descend to their targets
+ * together, each path node meeting them in chunk order.  The heap is left
+ * exactly as by consecutive inserts of the chunks, and the whole insert is
+ * linearized at its root ticket.  The insert is rejected whole (sticky
+ * GH_ENOMEM) if its batches do not all fit the heap's capacity.  One
+ * workgroup then carries every batch through the top levels of the heap, so
+ * on a busy heap such operations are slower than k-entry ones (submissions
+ * and heap_serve use them only with GH_TUNE_MULTI_INSERT). */
+uint32_t heap_insert_max(uint32_t k);
 
 /* Nonzero if the library has a kernel for node capacity k with workgroups
  * of `threads` threads.  Supported k: 32, 64, 128, 256, 512, 1024. */
@@ -213,7 +254,11 @@ int heap_create_many(gh_heap_t *out, uint32_t k, int keytype, uint32_t nheaps,
 
 /* Insert n entries from d_keys (device, n entries of the set's width) into heap 0 of the set:
  * ceil(n / k) insert operations of up to k entries each, full chunks first
- * (Sec. 3.2.2 footnote), each run top-down (Sec. 3.3.2).  n = 0 is a no-op.
+ * (Sec. 3.2.2 footnote), each run top-down (Sec. 3.3.2) with up to 64 in
+ * flight.  (Operations of up to heap_insert_max(k) entries that take the
+ * root once are available through heap_submit with GH_TUNE_MULTI_INSERT;
+ * they leave the same heap but are slower for bulk inserts.)  n = 0 is a
+ * no-op.
  * Errors: GH_EINVAL (null, reserved entry is not checked), GH_ENOMEM (the
  * heap would exceed max_keys; nothing is inserted). */
 int heap_insert(gh_heap_t h, const void *d_keys, uint64_t n);
@@ -313,9 +358,15 @@ uint64_t heap_serve_workspace_bytes(uint32_t nheaps, uint32_t nreq, uint64_t max
  * admitted requests plus n stays within the heap's max_keys; otherwise the
  * insert waits (per heap, first in first out) until admitted deleteMins make
  * room.  Each heap's admitted requests take the root in admission order, so
- * a heap's results do not depend on the other heaps in the stream.  Admitted
- * requests become operations of at most k entries that the other
- * workgroups (the slots, tuning->workgroups of them) run as in heap_submit.
+ * a heap's results do not depend on the other heaps in the stream (while
+ * max_ops has room for every admitted operation).  Admitted requests become
+ * operations (a deleteMin, or an insert cut into operations of k entries,
+ * each its own root turn) that the other workgroups (the slots,
+ * tuning->workgroups of them) run as in heap_submit.  With
+ * GH_TUNE_MULTI_INSERT in tuning->flags an insert is cut into operations of
+ * up to heap_insert_max(k) entries instead, each taking the root once (the
+ * results are the same; the carries of one operation then descend in one
+ * slot, one after another, which lowers the throughput of a busy heap).
  * d_recs (device, nreq records) receives one gh_reqrec per request.
  * d_work is a caller-owned device workspace of heap_serve_workspace_bytes.
  * The scheduler keeps 32 bytes per heap in LDS: nheaps * 32 + threads * 8 +

@@ -2,7 +2,8 @@
 
 Usage: python -m paper_1906_06504_amd.build   (or call build()).
 Each supported node capacity k and entry width (8 or 16 bytes) gets its own
-objects of gh_kernels.hip and gh_serve.hip, so they compile in parallel.
+objects of gh_kernels.hip, gh_serve.hip and gh_bu.hip, so they compile in
+parallel.
 """
 from __future__ import annotations
 
@@ -42,7 +43,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     tasks = []
     for k in KS:
         for eb in (8, 16):
-            for name in ("gh_kernels", "gh_serve"):
+            for name in ("gh_kernels", "gh_serve", "gh_bu"):
                 obj = os.path.join(BUILD, "%s_k%d_e%d.o" % (name, k, eb))
                 tasks.append([HIPCC] + COMMON + ["-DGH_K=%d" % k, "-DGH_ENT_BYTES=%d" % eb, "-c",
                                                  os.path.join(CSRC, name + ".hip"), "-o", obj])

@@ -58,6 +58,13 @@ __device__ __forceinline__ e128 ent_max<e128>() {
 __device__ __forceinline__ bool ent_is_max(u64 a) { return a == ~0ull; }
 __device__ __forceinline__ bool ent_is_max(e128 a) { return (a.x & a.y) == ~0ull; }
 
+// Full batches one insert operation of the general kernels may form: such an
+// operation takes up to multi_max_batches(K) * K entries (4096, or 2048 for
+// K = 32) in one root hold.
+__host__ __device__ constexpr int multi_max_batches(int K) {
+  return (4096 / K) < 64 ? (4096 / K) : 64;
+}
+
 // ---------------------------------------------------------------------------
 // Heap state in device memory
 // ---------------------------------------------------------------------------

@@ -681,7 +681,7 @@ hipError_t launch_sssp_k<GH_K>(const SsspArgs& a) {
 
 template <>
 hipError_t launch_ops_k<GH_K, GH_ENT>(const LaunchArgs& a) {
-  return launch_kops_shape<GH_K, false, GH_ENT>(a);
+  return launch_kops_shape<GH_K, FORM_WHOLE, GH_ENT>(a);
 }
 
 }  // namespace gh

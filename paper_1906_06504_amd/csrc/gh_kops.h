@@ -1,12 +1,18 @@
 // gh_kops.h -- the persistent operation loop (k_ops) and its launch, shared
-// by two objects per node capacity: the whole-root instantiation (VarDel =
-// false, in gh_kernels.hip) and the one that also runs deleteMins of fewer
-// than K entries (VarDel = true, in gh_serve.hip).  They live in separate
-// objects so that the whole-root kernel is compiled without the
-// variable-count code path next to it.
+// by three objects per node capacity, one per form:
+//   FORM_WHOLE   (gh_kernels.hip) inserts of up to K entries, whole-root
+//                deleteMins;
+//   FORM_GENERAL (gh_serve.hip) also deleteMins of fewer than K entries and
+//                inserts of more than K entries in one root hold;
+//   FORM_BU      (gh_bu.hip) bottom-up inserts of up to K entries, and no
+//                deleteMin (insert phases).
+// They live in separate objects so that the whole-root kernel is compiled
+// without the other code paths next to it.
 #pragma once
 #include "gh_launch.h"
 #include "gh_ops.h"
+#include "gh_ops_bu.h"
+#include "gh_ops_multi.h"
 
 namespace gh {
 
@@ -17,7 +23,9 @@ namespace gh {
 // kind given to a record the kernel refuses (> GH_OP_DELETE_MIN)
 constexpr u32 KIND_REFUSED = 0xFFu;
 
-template <int K, int T, bool VarDel, class Ent>
+constexpr int FORM_WHOLE = 0, FORM_GENERAL = 1, FORM_BU = 2;
+
+template <int K, int T, int Form, class Ent>
 __global__ __launch_bounds__(T) void k_ops(const HeapDesc* __restrict__ descs,
                                            const gh_op* __restrict__ ops, u32 nops,
                                            OpParams direct, const Ent* __restrict__ in,
@@ -27,6 +35,7 @@ __global__ __launch_bounds__(T) void k_ops(const HeapDesc* __restrict__ descs,
   lds_t<Ent>* const L = (lds_t<Ent>*)lds;
   __shared__ OpShared sh;
   const int tid = threadIdx.x;
+  constexpr bool VarDel = Form == FORM_GENERAL;
   for (;;) {
     if (tid == 0) {
       u32 i = atomicAdd(&ctl->next_op, 1u);
@@ -40,18 +49,23 @@ __global__ __launch_bounds__(T) void k_ops(const HeapDesc* __restrict__ descs,
     gh_op op;
     if (ops) {
       op = ops[i];
-      // the whole-root kernel refuses deleteMins of other counts: such a
-      // record reads as malformed below (rejected, the root still passes)
-      if (!VarDel && op.kind == GH_OP_DELETE_MIN && op.n != 0 && op.n != (u32)K)
+      // the whole-root kernel refuses deleteMins of other counts, the
+      // bottom-up form every deleteMin: such a record reads as malformed
+      // below (rejected, the root still passes)
+      if (Form == FORM_WHOLE && op.kind == GH_OP_DELETE_MIN && op.n != 0 && op.n != (u32)K)
         op.kind = KIND_REFUSED;
+      if (Form == FORM_BU && op.kind == GH_OP_DELETE_MIN) op.kind = KIND_REFUSED;
     } else {
+      // an insert of n_total entries: operations of up to K entries, or in
+      // the general kernel of up to multi_max_batches(K) * K
+      constexpr u64 CH = VarDel ? (u64)multi_max_batches(K) * K : (u64)K;
       op.heap = 0;
       op.kind = direct.kind;
       op.seq = i;
-      op.off = (u64)i * K;
+      op.off = (u64)i * CH;
       op.arrival_ns = 0;
-      u64 rem = direct.n_total - (u64)i * K;
-      op.n = direct.kind == GH_OP_INSERT ? (u32)(rem < (u64)K ? rem : (u64)K)
+      u64 rem = direct.n_total - (u64)i * CH;
+      op.n = direct.kind == GH_OP_INSERT ? (u32)(rem < CH ? rem : CH)
                                          : (VarDel ? (u32)direct.n_total : 0u);
     }
     if (op.heap >= direct.nheaps) {
@@ -82,16 +96,27 @@ __global__ __launch_bounds__(T) void k_ops(const HeapDesc* __restrict__ descs,
       }
     }
     OpResult r;
-    // n: insert 1..K entries; deleteMin 1..K entries, 0 meaning K (fewer
-    // than K only in the variable-count instantiation, more never)
+    // n: insert 1..K entries (up to multi_max_batches(K) * K in the general
+    // instantiation); deleteMin 1..K entries, 0 meaning K (fewer than K only
+    // in the general instantiation, more never)
+    constexpr u32 INS_MAX = VarDel ? (u32)multi_max_batches(K) * K : (u32)K;
     const bool malformed = op.kind > GH_OP_DELETE_MIN ||
-                           ((VarDel || op.kind == GH_OP_INSERT) && op.n > (u32)K);
+                           (op.kind == GH_OP_INSERT && op.n > INS_MAX) ||
+                           (VarDel && op.kind == GH_OP_DELETE_MIN && op.n > (u32)K);
     if (malformed || (op.kind == GH_OP_INSERT && op.n == 0)) {
       if (malformed && tid == 0) note_error(ctl, ERR_INVAL);
       r = op_pass_root(H, ticket, sh, ctl);
       if (malformed) r.flags |= F_REJECT;
     } else if (op.kind == GH_OP_INSERT) {
-      r = op_insert<K, T, Ent>(H, ticket, in + op.off, op.n, L, sh, ctl);
+      if constexpr (Form == FORM_BU) {
+        r = op_insert_bu<K, T, Ent>(H, ticket, in + op.off, op.n, L, sh, ctl);
+      } else if constexpr (VarDel) {
+        if (op.n > (u32)K)
+          r = op_insert_multi<K, T, Ent>(descs + op.heap, ticket, in + op.off, op.n, L, sh, ctl);
+        else r = op_insert<K, T, Ent>(H, ticket, in + op.off, op.n, L, sh, ctl);
+      } else {
+        r = op_insert<K, T, Ent>(H, ticket, in + op.off, op.n, L, sh, ctl);
+      }
     } else if constexpr (VarDel) {
       if (op.n == 0 || op.n == (u32)K)
         r = op_delete<K, T, Ent>(H, ticket, out + op.off, K, L, sh, ctl);
@@ -122,20 +147,20 @@ __global__ __launch_bounds__(T) void k_ops(const HeapDesc* __restrict__ descs,
   }
 }
 
-template <int K, int T, bool VarDel, class Ent>
+template <int K, int T, int Form, class Ent>
 static hipError_t launch_kops_t(const LaunchArgs& a) {
-  hipLaunchKernelGGL((k_ops<K, T, VarDel, Ent>), dim3(a.workgroups), dim3(T), 0, a.stream,
+  hipLaunchKernelGGL((k_ops<K, T, Form, Ent>), dim3(a.workgroups), dim3(T), 0, a.stream,
                      a.descs, a.ops, a.nops, a.direct, reinterpret_cast<const Ent*>(a.in),
                      reinterpret_cast<Ent*>(a.out), a.counts, a.log, a.ctl);
   return hipGetLastError();
 }
 
-template <int K, bool VarDel, class Ent>
+template <int K, int Form, class Ent>
 static hipError_t launch_kops_shape(const LaunchArgs& a) {
   switch (a.threads) {
 #define GH_CASE(TT)                                                             \
   case TT:                                                                      \
-    if constexpr (shape_ok(K, TT)) return launch_kops_t<K, TT, VarDel, Ent>(a); \
+    if constexpr (shape_ok(K, TT)) return launch_kops_t<K, TT, Form, Ent>(a); \
     break;
     GH_CASE(64)
     GH_CASE(128)

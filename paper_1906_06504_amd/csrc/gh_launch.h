@@ -31,7 +31,9 @@ struct LaunchArgs {
   Ctl* ctl;
   u32 workgroups;
   u32 threads;
-  u32 var_delete;   // the operations may hold deleteMins of fewer than K entries
+  u32 form;         // 0: whole-root kernel; 1: general kernel (deleteMins of
+                    // fewer than K entries, inserts of more than K entries);
+                    // 2: bottom-up inserts
   hipStream_t stream;
 };
 
@@ -57,6 +59,9 @@ hipError_t filter_scratch_init(int dev);
 void* filter_scratch(int dev);
 template <int K, class Ent>
 hipError_t launch_ops_var_k(const LaunchArgs& a);
+// the operation loop with bottom-up inserts (gh_bu.hip)
+template <int K, class Ent>
+hipError_t launch_ops_bu_k(const LaunchArgs& a);
 
 // ---------------------------------------------------------------------------
 // Served form: device workspace layout
@@ -89,6 +94,8 @@ struct ServeWork {
   gh_op* queue;   // admitted operations, in admission order
   u32* qreq;      // request of each queued operation
   u64 max_ops;
+  u32 ins_max;    // entries one insert operation takes (K, or the multi-batch limit)
+  u32 pad;
 };
 
 struct ServeArgs {

@@ -56,6 +56,7 @@ struct OpShared {
   u64 t_claim;         // clock when the operation was claimed
   u64 t_root;          // clock at root acquire
   u64 t_rel;           // clock at root release (stamped variants only)
+  u64 mbytes;          // algorithmic bytes of a multi-batch insert
   u32 flag0, flag1;    // broadcast results from wave 0
   u32 ok;
   u32 op;
@@ -68,8 +69,8 @@ struct OpResult {
   bool ok;
 };
 
-constexpr u32 F_FULL = 1, F_HANDOFF = 2, F_TOOK = 4, F_ROOT = 8, F_REFILL = 16, F_REJECT = 0x40,
-              F_ABORT = 0x80;
+constexpr u32 F_FULL = 1, F_HANDOFF = 2, F_TOOK = 4, F_ROOT = 8, F_REFILL = 16, F_STOPPED = 0x20,
+              F_REJECT = 0x40, F_ABORT = 0x80;
 
 // Algorithmic bytes of one operation: what the method has to move between
 // HBM and the workgroup along the path the operation took (e = entry bytes,

@@ -1,6 +1,7 @@
 // gh_serve.hip -- the served form (device-resident request loop) and the
-// persistent operation loop that also runs deleteMins of fewer than k
-// entries, for one node capacity and entry width.  Compiled once per
+// general persistent operation loop (deleteMins of fewer than k entries,
+// inserts of more than k entries in one root hold), for one node capacity
+// and entry width.  Compiled once per
 // supported k and width with -DGH_K=<k> -DGH_ENT_BYTES=<8|16>; each object
 // exports gh::launch_serve_k<k, Ent>() and gh::launch_ops_var_k<k, Ent>().
 #include "gh_kops.h"
@@ -24,18 +25,23 @@ namespace gh {
 // due: deleteMins always; an insert when the heap's size after everything
 // admitted plus n fits max_keys, otherwise it waits in the heap's FIFO of
 // deferred inserts until admitted deleteMins make room.  An admitted
-// request's operations take the heap's next tickets and are appended to a
-// queue.  Every other workgroup is a slot that claims queue entries in order
-// and runs them exactly like k_ops.
+// request's operations (a deleteMin, or an insert cut into operations of K
+// entries, or of up to multi_max_batches(K) * K entries that each take the
+// root once when the caller asks for that) take the heap's next tickets and
+// are appended to a queue.  Every other workgroup is
+// a slot that claims queue entries in order and runs them exactly like
+// k_ops.
 //
 // The scheduler works lane-parallel: heap h belongs to scheduler thread
 // h mod T.  It takes the requests in windows (the due prefix of a staged
 // chunk), sorts each window's requests stably by owner, and every thread
 // admits its own requests in stream order; queue slots come from a shared
 // counter, so one heap's operations stay in ticket order in the queue.  The
-// queue tail is published at the end of each window.  A heap's admissions
-// depend only on its own requests, so its results are the same alone and in
-// any mix.
+// queue tail is published at the end of each window.  While the queue has
+// room (max_ops at least the operations of every admitted request), a heap's
+// admissions depend only on its own requests, so its results are the same
+// alone and in any mix; once the shared queue overflows, which requests are
+// rejected depends on every heap's traffic.
 // ---------------------------------------------------------------------------
 // Scheduler's per-heap state, kept in LDS (dynamic shared memory sized by the
 // number of heaps) so that admitting a request touches no global memory on
@@ -144,7 +150,8 @@ struct Scheduler {
   // instead (its heap's tickets and size are left as they were; slots it was
   // handed are marked to be skipped).
   __device__ __forceinline__ void admit(u32 r, const gh_op& q, SchedHot& hs, u32 flags) const {
-    const u32 nops = q.kind == GH_OP_DELETE_MIN ? 1u : (q.n + K - 1) / K;
+    const u32 CH = w.ins_max;   // entries per insert operation
+    const u32 nops = q.kind == GH_OP_DELETE_MIN ? 1u : (q.n + CH - 1) / CH;
     const u32 slot =
         __hip_atomic_fetch_add(&ss->qtail, nops, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if ((u64)slot + nops > w.max_ops) {
@@ -174,8 +181,8 @@ struct Scheduler {
       hs.size -= hs.size < (u64)want ? hs.size : (u64)want;
     } else {
       for (u32 c = 0; c < nops; ++c) {
-        const u32 nc = (q.n - c * K) < (u32)K ? (q.n - c * K) : (u32)K;
-        put_op(slot + c, r, q.heap, GH_OP_INSERT, nc, hs.seq++, q.off + (u64)c * K);
+        const u32 nc = (q.n - c * CH) < CH ? (q.n - c * CH) : CH;
+        put_op(slot + c, r, q.heap, GH_OP_INSERT, nc, hs.seq++, q.off + (u64)c * CH);
       }
       hs.size += q.n;
     }
@@ -201,7 +208,7 @@ struct Scheduler {
         if (hs.head == SCHED_NONE) w.heaps[q.heap].last = SCHED_NONE;
         admit(dr, d, hs, 2u);
       }
-    } else if ((u64)q.n > hs.cap || q.n > 65535u * (u32)K) {
+    } else if ((u64)q.n > hs.cap || (u64)q.n > 65535ull * w.ins_max) {
       reject(r, q.kind);
     } else if (hs.head == SCHED_NONE && hs.size + q.n <= hs.cap) {
       admit(r, q, hs, 0);
@@ -236,8 +243,18 @@ __device__ __forceinline__ void load_ids16(const lu32* p, u32 (&ids)[16]) {
   ids[12] = d.x; ids[13] = d.y; ids[14] = d.z; ids[15] = d.w;
 }
 
+// Waves per SIMD the served kernel keeps with 256-thread slots and 8-byte
+// entries at k <= 256: the register budget of six slots per compute unit
+// that it had before the multi-batch insert path joined the slot loop (the
+// compiler meets it there without spilling; other shapes are left free).
 template <int K, int T, class Ent>
-__global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs, u32 nheaps,
+constexpr int serve_waves_per_eu() {
+  return (T == 256 && K <= 256 && sizeof(Ent) == 8) ? 6 : 1;
+}
+
+template <int K, int T, class Ent>
+__global__ __launch_bounds__(T)
+__attribute__((amdgpu_waves_per_eu(serve_waves_per_eu<K, T, Ent>()))) void k_serve(const HeapDesc* __restrict__ descs, u32 nheaps,
                                              const gh_op* __restrict__ reqs, u32 nreq,
                                              const Ent* __restrict__ in, Ent* __restrict__ out,
                                              gh_reqrec* __restrict__ recs, ServeWork w,
@@ -459,8 +476,13 @@ __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs,
     const HeapDesc H = descs[op.heap];
     const u64 ticket = *gptr(&H.meta->base) + op.seq;
     OpResult res;
+    bool multi = false;
     if (op.kind == GH_OP_INSERT) {
-      res = op_insert<K, T, Ent, true>(H, ticket, in + op.off, op.n, L, sh, ctl);
+      multi = op.n > (u32)K;
+      if (multi)
+        res = op_insert_multi<K, T, Ent, true>(descs + op.heap, ticket, in + op.off, op.n, L, sh,
+                                               ctl);
+      else res = op_insert<K, T, Ent, true>(H, ticket, in + op.off, op.n, L, sh, ctl);
     } else {
       if (__builtin_expect(op.n == (u32)K, 1))
         res = op_delete<K, T, Ent, false, true>(H, ticket, out + op.off, K, L, sh, ctl);
@@ -475,8 +497,9 @@ __global__ __launch_bounds__(T) void k_serve(const HeapDesc* __restrict__ descs,
       if (res.ok)
         __hip_atomic_fetch_max(&recs[r].t_resp, (u32)(sh.t_rel - ctl->t0), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&recs[r].bytes, (u32)op_alg_bytes<K, Ent>(op.kind, res, sh.s),
-                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const u64 ob = multi ? ((res.flags & F_REJECT) ? 0ull : sh.mbytes)
+                           : op_alg_bytes<K, Ent>(op.kind, res, sh.s);
+      __hip_atomic_fetch_add(&recs[r].bytes, (u32)ob, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (atomicSub(&w.left[r], 1u) == 1u)
         __hip_atomic_store(&recs[r].t_done, (u32)(now_ticks() - ctl->t0), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
@@ -516,7 +539,7 @@ hipError_t launch_serve_k<GH_K, GH_ENT>(const ServeArgs& a) {
 
 template <>
 hipError_t launch_ops_var_k<GH_K, GH_ENT>(const LaunchArgs& a) {
-  return launch_kops_shape<GH_K, true, GH_ENT>(a);
+  return launch_kops_shape<GH_K, FORM_GENERAL, GH_ENT>(a);
 }
 
 }  // namespace gh

@@ -164,7 +164,8 @@ struct KnapF {
 template <int K, class Ent>
 struct OpsF {
   static hipError_t run(const LaunchArgs& a) {
-    return a.var_delete ? launch_ops_var_k<K, Ent>(a) : launch_ops_k<K, Ent>(a);
+    return a.form == 2 ? launch_ops_bu_k<K, Ent>(a)
+                       : (a.form == 1 ? launch_ops_var_k<K, Ent>(a) : launch_ops_k<K, Ent>(a));
   }
 };
 
@@ -238,6 +239,9 @@ int run_ops(gh_heap* h, const gh_op* d_ops, u32 nops, const OpParams& p, const v
   u32 wg = (t && t->workgroups) ? t->workgroups : 256;
   if (wg > nops) wg = nops;
   if (wg == 0) wg = 1;
+  const u32 fl = t ? t->flags : 0u;
+  if ((fl & GH_TUNE_BOTTOM_UP) && (fl & (GH_TUNE_VARIABLE_DELETE | GH_TUNE_MULTI_INSERT)))
+    return GH_EINVAL;   // bottom-up inserts run in submissions of inserts of up to k entries
   if (launch_prep(h->descs, h->nheaps, h->ctl, h->stream) != hipSuccess) return GH_EDEVICE;
   LaunchArgs a{};
   a.descs = h->descs;
@@ -253,7 +257,9 @@ int run_ops(gh_heap* h, const gh_op* d_ops, u32 nops, const OpParams& p, const v
   a.ctl = h->ctl;
   a.workgroups = wg;
   a.threads = threads;
-  a.var_delete = (t && (t->flags & GH_TUNE_VARIABLE_DELETE)) ? 1u : 0u;
+  a.form = (fl & GH_TUNE_BOTTOM_UP) ? 2u
+                                    : ((fl & (GH_TUNE_VARIABLE_DELETE | GH_TUNE_MULTI_INSERT)) ? 1u
+                                                                                              : 0u);
   a.stream = h->stream;
   if (launch_ops(h, a) != hipSuccess) return GH_EDEVICE;
   return GH_OK;
@@ -279,6 +285,10 @@ uint64_t heap_arena_bytes(uint32_t k, int keytype, uint32_t nheaps, const uint64
   Layout L;
   if (!make_layout(k, entry_bytes(keytype), nheaps, max_keys, max_keys_each, L)) return 0;
   return L.total;
+}
+
+uint32_t heap_insert_max(uint32_t k) {
+  return k_supported(k) ? (uint32_t)multi_max_batches((int)k) * k : 0u;
 }
 
 int heap_supported_shape(uint32_t k, uint32_t threads) {
@@ -357,6 +367,8 @@ int heap_insert(gh_heap_t h, const void* d_keys, uint64_t n) {
     if (rc != GH_OK) return rc;
   }
   if (h->size0 > h->max_keys[0] || n > h->max_keys[0] - h->size0) return GH_ENOMEM;
+  // operations of k entries in the whole-root kernel (their descents run on
+  // several workgroups at once, which beats one root hold per 4096 entries)
   const u64 nops = n / h->k + (n % h->k != 0 ? 1 : 0);
   if (nops > 0xFFFFFFFFull) return GH_EINVAL;
   OpParams p{GH_OP_INSERT, 0, n, 0, 0};
@@ -518,6 +530,7 @@ int heap_serve(gh_heap_t h, const gh_op* d_reqs, uint32_t nreq, const void* d_in
   a.w.queue = reinterpret_cast<gh_op*>(base + L.queue);
   a.w.qreq = reinterpret_cast<u32*>(base + L.qreq);
   a.w.max_ops = max_ops;
+  a.w.ins_max = (t && (t->flags & GH_TUNE_MULTI_INSERT)) ? heap_insert_max(h->k) : h->k;
   a.ctl = h->ctl;
   a.clock_mhz = h->clock_mhz;
   a.workgroups = wg;
@@ -599,7 +612,7 @@ int heap_sssp(gh_heap_t h, uint32_t V, const uint32_t* d_rowptr, const uint32_t*
   la.ctl = h->ctl;
   la.workgroups = 1;
   la.threads = threads;
-  la.var_delete = 0;
+  la.form = 0;
   la.stream = h->stream;
   if (launch_ops(h, la) != hipSuccess) return GH_EDEVICE;
   SsspArgs a{};

@@ -61,6 +61,7 @@ FLAG_HANDOFF = 2
 FLAG_TOOK = 4
 FLAG_ROOT = 8
 FLAG_REFILL = 16
+FLAG_STOPPED = 0x20
 FLAG_REJECTED = 0x40
 FLAG_ABORTED = 0x80
 
@@ -70,7 +71,7 @@ EXPORTS = ("heap_arena_bytes", "heap_supported_shape", "heap_create", "heap_crea
            "heap_read_state", "heap_destroy", "heap_strerror", "heap_clock_hz",
            "heap_serve_workspace_bytes", "heap_serve", "heap_knapsack", "heap_sssp",
            "heap_build", "heap_filter_workspace_bytes", "heap_filter",
-           "heap_filter_noalloc")
+           "heap_filter_noalloc", "heap_insert_max")
 
 
 class GHeapError(RuntimeError):
@@ -83,6 +84,8 @@ _lib = None
 
 
 GH_TUNE_VARIABLE_DELETE = 1
+GH_TUNE_MULTI_INSERT = 2
+GH_TUNE_BOTTOM_UP = 4
 
 
 class _Tuning(ctypes.Structure):
@@ -133,6 +136,7 @@ def load_library(path: str = LIB_PATH):
         "heap_filter_workspace_bytes": (u64, [vp, u32]),
         "heap_filter": (i32, [vp, u32, u64, vp, u64, vp]),
         "heap_filter_noalloc": (i32, [vp, u32, u64, vp]),
+        "heap_insert_max": (u32, [u32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -140,6 +144,17 @@ def load_library(path: str = LIB_PATH):
         f.argtypes = args
     _lib = lib
     return lib
+
+
+def _tune_flags(var_delete: bool, multi_insert: bool, bottom_up: bool = False) -> int:
+    return ((GH_TUNE_VARIABLE_DELETE if var_delete else 0) |
+            (GH_TUNE_MULTI_INSERT if multi_insert else 0) |
+            (GH_TUNE_BOTTOM_UP if bottom_up else 0))
+
+
+def insert_max(k: int) -> int:
+    """Largest insert one operation may hold (heap_insert_max)."""
+    return int(load_library().heap_insert_max(k))
 
 
 def strerror(code: int) -> str:
@@ -270,17 +285,20 @@ class HeapSet:
     def submit(self, ops: torch.Tensor, nops: int, d_in: torch.Tensor | None,
                d_out: torch.Tensor | None, counts: torch.Tensor | None = None,
                log: torch.Tensor | None = None, workgroups: int = 0, threads: int = 0,
-               var_delete: bool = False):
+               var_delete: bool = False, multi_insert: bool = False, bottom_up: bool = False):
         """Run the op records on the set's stream.  var_delete: the records
-        may hold deleteMins of fewer than k entries (n in 1..k-1)."""
-        t = _Tuning(workgroups, threads, GH_TUNE_VARIABLE_DELETE if var_delete else 0)
+        may hold deleteMins of fewer than k entries (n in 1..k-1);
+        multi_insert: inserts of more than k entries (up to insert_max(k));
+        bottom_up: every record is an insert of up to k entries, run
+        bottom-up (GH_TUNE_BOTTOM_UP)."""
+        t = _Tuning(workgroups, threads, _tune_flags(var_delete, multi_insert, bottom_up))
         rc = self.lib.heap_submit(self.h, *self._op_ptrs(ops, nops, d_in, d_out, counts, log),
                                   ctypes.byref(t))
         _check(rc, "heap_submit")
 
     def submit_graph(self, ops, nops, d_in, d_out, counts=None, log=None, workgroups=0,
-                     threads=0, var_delete: bool = False) -> int:
-        t = _Tuning(workgroups, threads, GH_TUNE_VARIABLE_DELETE if var_delete else 0)
+                     threads=0, var_delete: bool = False, multi_insert: bool = False) -> int:
+        t = _Tuning(workgroups, threads, _tune_flags(var_delete, multi_insert))
         g = ctypes.c_void_p()
         rc = self.lib.heap_submit_graph(self.h, *self._op_ptrs(ops, nops, d_in, d_out, counts,
                                                                log),
@@ -305,13 +323,16 @@ class HeapSet:
 
     def serve(self, reqs: torch.Tensor, nreq: int, d_in: torch.Tensor | None,
               d_out: torch.Tensor | None, recs: torch.Tensor, max_ops: int,
-              work: torch.Tensor | None = None, workgroups: int = 0, threads: int = 0):
-        """Run a request stream through the device-resident serving loop.
-        Returns the workspace tensor (reusable for the next call)."""
+              work: torch.Tensor | None = None, workgroups: int = 0, threads: int = 0,
+              multi_insert: bool = False):
+        """Run a request stream through the device-resident serving loop
+        (multi_insert: inserts of up to insert_max(k) entries take the root
+        once, GH_TUNE_MULTI_INSERT).  Returns the workspace tensor (reusable
+        for the next call)."""
         need = int(self.lib.heap_serve_workspace_bytes(self.nheaps, nreq, max_ops))
         if work is None or work.numel() < need:
             work = torch.empty(need, dtype=torch.uint8, device=self.device)
-        t = _Tuning(workgroups, threads)
+        t = _Tuning(workgroups, threads, GH_TUNE_MULTI_INSERT if multi_insert else 0)
         rc = self.lib.heap_serve(self.h, _ptr(reqs, None, nreq * OP_DTYPE.itemsize, "reqs"), nreq,
                                  _ptr(d_in, _U64, 0, "d_in"), _ptr(d_out, _U64, 0, "d_out"),
                                  _ptr(recs, None, nreq * REQ_DTYPE.itemsize, "recs"),
@@ -345,7 +366,7 @@ class HeapSet:
         if kept is None:
             kept = torch.zeros(1, dtype=torch.int64, device=self.device)
         _check(self.lib.heap_filter_noalloc(self.h, i, int(bound), _ptr(kept, _U64, 8, "kept")),
-               "heap_filter_noalloc")
+               "heap_filter_noalloc", "heap_insert_max")
         return kept
 
     def sync(self) -> int:
@@ -443,6 +464,8 @@ def requests_to_device(oplist, device="cuda"):
         rec["arrival_ns"] = oplist.arrival
     k = int(oplist.meta.get("k", 1))
     ins = oplist.kind == OP_INSERT
+    # insert requests become operations of up to heap_insert_max(k) entries,
+    # or of k entries with split inserts: bound by the latter
     max_ops = int(np.sum(-(-oplist.n[ins].astype(np.int64) // k))) + int((~ins).sum())
     reqs = torch.from_numpy(rec.view(np.uint8).copy()).to(device)
     w = entry_words(oplist)

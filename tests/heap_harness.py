@@ -45,11 +45,12 @@ def _is_filler(row, wide):
     return row == MAXE
 
 
-def run_gpu(oplist, k, max_keys, workgroups=0, threads=0, heapset=None, nheaps=1):
+def run_gpu(oplist, k, max_keys, workgroups=0, threads=0, heapset=None, nheaps=1,
+            bottom_up=False):
     """Submit `oplist` on a fresh heap set (or `heapset`); returns
     (heapset, out, counts[uint32], log records), out as uint64 ([n, 2] for
-    16-byte entries).  Lists holding deleteMins of fewer than k entries go
-    to the variable-count kernel."""
+    16-byte entries).  Lists holding deleteMins of fewer than k entries or
+    inserts of more than k entries go to the general kernel."""
     import torch
     from paper_1906_06504_amd import gheap as G
     wide = is_wide(oplist.keys)
@@ -59,8 +60,9 @@ def run_gpu(oplist, k, max_keys, workgroups=0, threads=0, heapset=None, nheaps=1
     log = G.new_log(n)
     dels = oplist.kind == W.OP_DELETE_MIN
     var = bool(np.any(dels & (oplist.n != 0) & (oplist.n != k)))
+    multi = bool(np.any((oplist.kind == W.OP_INSERT) & (oplist.n > k)))
     hs.submit(ops, n, keys, out, counts, log, workgroups=workgroups, threads=threads,
-              var_delete=var)
+              var_delete=var, multi_insert=multi, bottom_up=bottom_up)
     rc = hs.sync()
     assert rc == G.GH_OK, G.strerror(rc)
     torch.cuda.synchronize()

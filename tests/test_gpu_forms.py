@@ -124,13 +124,14 @@ def test_batched_graph_replays(G):
     hs.close()
 
 
-def _serve(G, pre, reqs, k, caps, workgroups, threads=0):
+def _serve(G, pre, reqs, k, caps, workgroups, threads=0, multi_insert=False):
     hs = G.HeapSet(k, caps)
     d = G.ops_to_device(pre)
     hs.submit(*d[:5], workgroups=64)
     assert hs.sync() == 0
     r, nreq, keys, out, recs, max_ops = G.requests_to_device(reqs)
-    hs.serve(r, nreq, keys, out, recs, max_ops, workgroups=workgroups, threads=threads)
+    hs.serve(r, nreq, keys, out, recs, max_ops, workgroups=workgroups, threads=threads,
+             multi_insert=multi_insert)
     rc = hs.sync()
     assert rc == G.GH_OK, G.strerror(rc)
     torch.cuda.synchronize()
