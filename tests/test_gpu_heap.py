@@ -14,8 +14,8 @@ import pytest
 import oracle
 from paper_1906_06504_amd import workloads as W
 
-from heap_harness import (MAXE, assert_same_state, check_gpu_state, gpu_state_by_index,
-                          replay_and_compare, run_gpu)
+from heap_harness import (MAXE, assert_same_state, check_gpu_state, flag_counts,
+                          gpu_state_by_index, replay_and_compare, run_gpu)
 
 pytestmark = pytest.mark.gpu
 
@@ -158,15 +158,98 @@ def test_sorted_key_orders_state_equals_oracle(G, k, wg, order):
 
 
 def test_concurrent_small_k_heavy_contention(G):
-    """k = 32, 512 workgroups on a small heap: many cooperations and absent
-    children; the replay must still be exact."""
+    """k = 32, 512 workgroups on a small heap: many cooperations (an insert
+    hands its batch to a deleteMin that takes its target as the last node:
+    log flag bits 1 and 2) and absent children; the replay must still be
+    exact, and the cooperation path must have run."""
     k = 32
     ops = W.mixed_ops(20000 * k // 32, k, seed=99, first_id=0, p_insert=0.6)
     _print("contention ops=%d" % len(ops))
     hs, out, counts, log = run_gpu(ops, k, max_keys=len(ops) * k, workgroups=512)
     replay_and_compare(ops, k, out, counts, log)
     check_gpu_state(hs, 0, k)
+    fc = flag_counts(log)
+    _print("flag counts", fc)
+    assert fc[1] > 0, "no insert handed its batch over (MARKED -> HANDED)"
+    assert fc[2] > 0, "no deleteMin took an in-flight insert's batch"
+    assert fc[1] == fc[2]
     hs.close()
+
+
+@pytest.mark.parametrize("k", [32, 256])
+def test_repeated_entries_replay(G, k):
+    """Repeated entries (the same (key, id) inserted many times, which the
+    boundary allows: equal entries are indistinguishable) and runs of equal
+    keys: concurrent replay is exact and the drain is the sorted multiset."""
+    st = W.Stream(123 + k)
+    total = 120 * k
+    keys = W.pack((st.u32(total) >> np.uint32(28)).astype(np.uint32),
+                  (st.u32(total) >> np.uint32(29)).astype(np.uint64))   # 16 keys x 8 ids
+    n = st.uniform_int(1, k, total).astype(np.int64)
+    sizes, acc = [], 0
+    for x in n:
+        if acc >= total:
+            break
+        x = int(min(x, total - acc))
+        sizes.append(x)
+        acc += x
+    kinds = [W.OP_INSERT] * len(sizes)
+    ndel = -(-total // k) + 1
+    # inserts interleaved with deleteMins, then a full drain
+    mix_k, mix_n = [], []
+    for i, x in enumerate(sizes):
+        mix_k.append(W.OP_INSERT)
+        mix_n.append(x)
+        if i % 3 == 2:
+            mix_k.append(W.OP_DELETE_MIN)
+            mix_n.append(0)
+    mix_k += [W.OP_DELETE_MIN] * ndel
+    mix_n += [0] * ndel
+    ops = W.build_oplist(mix_k, mix_n, lambda c: keys[:c], k)
+    _print("repeated entries k=%d ops=%d distinct=%d" % (k, len(ops), np.unique(keys).size))
+    hs, out, counts, log = run_gpu(ops, k, max_keys=total, workgroups=64)
+    replay_and_compare(ops, k, out, counts, log)
+    dels = np.flatnonzero(ops.kind == W.OP_DELETE_MIN)
+    order = dels[np.argsort(log["ticket"][dels])]
+    got = np.concatenate([out[int(ops.off[i]):int(ops.off[i]) + int(counts[i])] for i in order])
+    assert np.array_equal(np.sort(got), np.sort(keys))
+    assert hs.close() == G.GH_OK
+
+
+@pytest.mark.parametrize("k", [64, 1024])
+def test_adversarial_batches_serialized(G, k):
+    """Serialized inserts of adversarial batches through the C ABI: all-equal
+    keys with distinct ids, keys interleaved with the heap's, disjoint above
+    and below it, reversed, and a partial batch that straddles the partial
+    buffer; deleteMins between.  The node array and partial buffer equal the
+    oracle's after the run."""
+    base = np.arange(k, dtype=np.uint64)
+    rev = np.arange(k, dtype=np.uint32)[::-1].copy()
+    batches = [
+        W.pack(np.full(k, 1000, dtype=np.uint32), base),                          # equal keys
+        W.pack((np.arange(k) * 2 + 1000).astype(np.uint32), base + k),            # interleaved
+        W.pack(np.arange(k, dtype=np.uint32) + np.uint32(1 << 30), base + 2 * k),  # above all
+        W.pack(np.arange(k, dtype=np.uint32), base + 3 * k),                      # below all
+        W.pack(rev + np.uint32(500), base + 4 * k),                               # reversed
+        W.pack(np.full(k // 2 + 3, 1001, dtype=np.uint32),
+               np.arange(k // 2 + 3, dtype=np.uint64) + 5 * k),                   # partial
+        W.pack((np.arange(k) * 2 + 999).astype(np.uint32), base + 6 * k),         # interleaved
+    ]
+    keys = np.concatenate(batches)
+    kinds, sizes = [], []
+    for i, b in enumerate(batches):
+        kinds.append(W.OP_INSERT)
+        sizes.append(b.size)
+        if i in (1, 4):
+            kinds.append(W.OP_DELETE_MIN)
+            sizes.append(0)
+    kinds += [W.OP_DELETE_MIN] * 2
+    sizes += [0] * 2
+    ops = W.build_oplist(kinds, sizes, lambda c: keys[:c], k)
+    hs, out, counts, log = run_gpu(ops, k, max_keys=keys.size, workgroups=1)
+    oh = replay_and_compare(ops, k, out, counts, log)
+    assert_same_state(hs, 0, oh, k)
+    assert hs.close() == G.GH_OK
 
 
 def test_config1_full_size(G):
@@ -211,6 +294,11 @@ def test_config2_full_size(G):
     oh.replay(pre.kind, pre.n, pre.off, pre.keys, 1)
     replay_and_compare(mix, k, out, counts, log, base_ticket=len(pre), oracle_heap=oh)
     check_gpu_state(hs, 0, k)
+    fc = flag_counts(log)
+    _print("flag counts", fc)
+    # the heap drains in the run's tail, where deleteMins take the targets of
+    # inserts still in flight (MARKED -> HANDED)
+    assert fc[1] > 0 and fc[1] == fc[2], "the insert/deleteMin hand-over never ran"
     hs.close()
 
 
