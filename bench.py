@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--served-slots", type=int, default=2048)
     ap.add_argument("--served-threads", type=int, default=0,
                     help="workgroup size of the served form (0 = library default)")
+    ap.add_argument("--served-multi", action="store_true",
+                    help="served leg with one root hold per insert of up to 4096 entries "
+                         "instead of k-entry operations")
     ap.add_argument("--served-budget", type=int, default=1 << 20,
                     help="memory budget per heap beyond its prefill (entries)")
     ap.add_argument("--served-tight-budget", type=int, default=1 << 14,
@@ -300,12 +303,13 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-def _timed_submit(hs, d, workgroups, threads, log=None):
+def _timed_submit(hs, d, workgroups, threads, log=None, bottom_up=False):
     import torch
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record(hs.stream)
-    hs.submit(d[0], d[1], d[2], d[3], d[4], log, workgroups=workgroups, threads=threads)
+    hs.submit(d[0], d[1], d[2], d[3], d[4], log, workgroups=workgroups, threads=threads,
+              bottom_up=bottom_up)
     ev1.record(hs.stream)
     rc = hs.sync()
     torch.cuda.synchronize()
@@ -506,7 +510,9 @@ def run_served(args):
                        "60%% insert of log-uniform [1,4096] keys, 40%% deleteMin(256); budget per "
                        "heap prefill + %d entries" % (H, args.served_max_log2, int(sizes.sum()), R,
                                                    args.served_budget),
-           "slots": args.served_slots}
+           "slots": args.served_slots,
+           "insert_operations": ("up to 4096 entries each, one root hold" if args.served_multi
+                                 else "k entries each")}
     with torch.cuda.stream(hs.stream):
         dpre = G.ops_to_device(pre)
         _timed_submit(hs, dpre, 1024, 0)
@@ -522,7 +528,8 @@ def run_served(args):
             ev1 = torch.cuda.Event(enable_timing=True)
             ev0.record(hs.stream)
             work = hs.serve(r, nreq, keys, outb, recs, max_ops, work=work,
-                            workgroups=args.served_slots, threads=args.served_threads)
+                            workgroups=args.served_slots, threads=args.served_threads,
+                            multi_insert=args.served_multi)
             ev1.record(hs.stream)
             rc = hs.sync()
             torch.cuda.synchronize()
@@ -967,6 +974,7 @@ def knapsack_cpu_baseline(inst, gpu_best):
 # The paper's Table vscpu: TD-INS/TD-DEL heap, 2^29 keys inserted then all
 # deleted, k = 1024, on its GPU (ms); context for the scaled run here.
 PAPER_TD_MS_2E29 = {"random": 112090.0, "descending": 100163.0, "ascending": 99082.0}
+PAPER_BU_MS_2E29 = {"random": 104417.0, "descending": 97593.0, "ascending": 96247.0}
 
 
 def run_paper_table(args):
@@ -1009,13 +1017,57 @@ def run_paper_table(args):
             hs.close()
             rows["workgroups_%d" % wg] = {"ms": ms, "keys_per_s": 2 * N / (ms / 1e3)}
         best = min(r["ms"] for r in rows.values())
+        rows["phases"] = _paper_table_phases(G, W, ops, k, N, order)
         rows["paper_ms_2e29_titan_x"] = PAPER_TD_MS_2E29[order]
+        rows["paper_bu_ms_2e29_titan_x"] = PAPER_BU_MS_2E29[order]
         rows["paper_ms_scaled_to_this_n"] = PAPER_TD_MS_2E29[order] * N / (1 << 29)
         rows["speedup_vs_paper_scaled"] = rows["paper_ms_scaled_to_this_n"] / best
         out[order] = rows
         log("paper table %s: %.1f ms (paper, scaled: %.1f ms)"
             % (order, best, rows["paper_ms_scaled_to_this_n"]))
     return out
+
+
+def _paper_table_phases(G, W, ops, k, N, order, wg=128):
+    """The same workload as two launches, an insert phase and a drain, with
+    the inserts run top-down (the TD-INS/TD-DEL heap) or bottom-up (the
+    BU-INS of Sec. 3.3.4, insert phases only); the drain is top-down in both
+    and must return the sorted keys."""
+    import torch
+    ins = np.flatnonzero(ops.kind == W.OP_INSERT)
+    dels = np.flatnonzero(ops.kind == W.OP_DELETE_MIN)
+    ops_i = W.OpList(ops.kind[ins], ops.n[ins], ops.off[ins], ops.keys, 0)
+    ops_d = W.OpList(ops.kind[dels], ops.n[dels], ops.off[dels], ops.keys[:0], ops.out_entries)
+    want = {"random": lambda: np.sort(ops.keys), "ascending": lambda: ops.keys,
+            "descending": lambda: ops.keys[::-1]}[order]()
+    res = {}
+    for mode in ("td", "bu"):
+        hs = G.HeapSet(k, [N + k], stream=torch.cuda.Stream())
+        with torch.cuda.stream(hs.stream):
+            di = G.ops_to_device(ops_i)
+            ms_i = _timed_submit(hs, di, wg, 0, bottom_up=mode == "bu")
+            del di
+            dd = G.ops_to_device(ops_d)
+            lg = G.new_log(dd[1])
+            ms_d = _timed_submit(hs, dd, wg, 0, lg)
+            res_h = G.to_host_u64(dd[3])
+            cnt = dd[4].cpu().numpy()[:dd[1]].astype(np.int64)
+            tk = G.log_to_host(lg, dd[1])["ticket"]
+            order_d = np.argsort(tk, kind="stable")
+            got = np.concatenate([res_h[int(ops_d.off[i]):int(ops_d.off[i]) + int(cnt[i])]
+                                  for i in order_d])
+            if not np.array_equal(got, want):
+                raise SystemExit("paper table phases (%s): drained keys are not the sorted input"
+                                 % mode)
+            del dd
+        hs.close()
+        res[mode] = {"insert_ms": ms_i, "drain_ms": ms_d, "total_ms": ms_i + ms_d}
+    res["bu_vs_td_insert_phase"] = res["td"]["insert_ms"] / res["bu"]["insert_ms"]
+    res["bu_vs_td_total"] = res["td"]["total_ms"] / res["bu"]["total_ms"]
+    log("paper table %s phases: TD insert %.1f ms, BU insert %.1f ms, drains %.1f / %.1f ms"
+        % (order, res["td"]["insert_ms"], res["bu"]["insert_ms"], res["td"]["drain_ms"],
+           res["bu"]["drain_ms"]))
+    return res
 
 
 def run_filter(args):
