@@ -36,14 +36,18 @@
 namespace gh {
 
 // Phase timestamps for profiling the root critical section: compiled in only
-// when GH_PHASE_TRACE is defined (never in the library build); slot s of
-// operation i goes to gh_phase_trace[i * 8 + s].
+// when GH_PHASE_TRACE is defined (the tracing build, never the library
+// build).  Thread 0 writes the device clock of slot s of operation i to
+// gh_phase_trace[i * GH_TRACE_SLOTS + s] (operations below 2^18); slot 15 is
+// the root's release.  Each object has its own array (static); the
+// whole-root kernels' copy is read back with heap_phase_trace.
+#define GH_TRACE_SLOTS 16
 #ifdef GH_PHASE_TRACE
-__device__ uint32_t gh_phase_trace[1 << 22];
+static __device__ uint32_t gh_phase_trace[1 << 22];
 #define GH_TRACE(slot)                                                                 \
   do {                                                                                 \
-    if (threadIdx.x == 0 && sh.op < (1u << 19))                                        \
-      gh_phase_trace[sh.op * 8 + (slot)] = (uint32_t)wall_clock64();                   \
+    if (threadIdx.x == 0 && sh.op < (1u << 18))                                        \
+      gh_phase_trace[sh.op * GH_TRACE_SLOTS + (slot)] = (uint32_t)wall_clock64();      \
   } while (0)
 #else
 #define GH_TRACE(slot) \
@@ -60,6 +64,7 @@ struct OpShared {
   u32 flag0, flag1;    // broadcast results from wave 0
   u32 ok;
   u32 op;
+  u32 early;           // an insert's next path node was taken by an early try
 };
 
 struct OpResult {
@@ -126,6 +131,7 @@ __device__ __forceinline__ void release_root(HeapMeta* meta, u64 ticket, u64 m, 
 template <bool Stamp>
 __device__ __forceinline__ void release_root_at(HeapMeta* meta, u64 ticket, u64 m, u64 s,
                                                 OpShared& sh) {
+  GH_TRACE(15);
   release_root(meta, ticket, m, s);
   if constexpr (Stamp) sh.t_rel = now_ticks();
 }
@@ -429,7 +435,8 @@ __device__ __forceinline__ OpResult op_insert(const HeapDesc& H, u64 ticket,
         const bool next_is_path = child != t;
         u64* w = (tid == 0) ? tlock : lock_ptr(H, child);
         const u32 mode = (tid == 0) ? (u32)LM_PEEK : (u32)LM_PATH;
-        const bool active = tid == 0 || (tid == 1 && next_is_path);
+        // the next path node was tried when this node was loaded
+        const bool active = tid == 0 || (tid == 1 && next_is_path && !sh.early);
         int r = 0;
         const bool ok = lock_lanes(w, mode, ticket, active, r, ctl);
         const bool allok = __all(ok);
@@ -463,21 +470,26 @@ __device__ __forceinline__ OpResult op_insert(const HeapDesc& H, u64 ticket,
     if (child == t) break;
     cur = child;
     {
-      // the next path node, and in the same round trip a look at the
-      // target: a deleteMin that claimed it gets the carry now, before this
-      // level's merge (the carry has not entered this subtree yet)
+      // the next path node, in the same round trip a look at the target (a
+      // deleteMin that claimed it gets the carry now, before this level's
+      // merge: the carry has not entered this subtree yet) and a first try
+      // at the lock of the node after it (cur is held: parent before child)
+      const u32 nxt = t >> (L - level - 1);
       NodeRegs<K, T, Ent> nr;
       nr.load(node_ptr<K, Ent>(H, cur));
-      u64 tw = 0;
+      u64 tw = 0, eo = 1;
       if (tid == 0) tw = ld_relaxed(tlock);
+      if (tid == 1 && nxt != t) eo = cas_old(lock_ptr(H, nxt), 0, lockword(ST_INUSE, ticket));
       nr.store(N);
       if (tid == 0) sh.flag0 = lw_state(tw) == ST_MARKED ? 1u : 0u;
+      if (tid == 1) sh.early = eo == 0 ? 1u : 0u;
     }
     __syncthreads();
     if (sh.flag0) {
       store_node<K, T, Ent>(node_ptr<K, Ent>(H, t), F);
       publish();
       if (tid == 0) {
+        if (sh.early) unlock(lock_ptr(H, t >> (L - level - 1)));
         unlock(lock_ptr(H, cur));
         st_relaxed(tlock, lockword(ST_HANDED, ticket));
       }
@@ -694,8 +706,11 @@ __device__ __forceinline__ OpResult op_delete(const HeapDesc& H, u64 ticket,
   }
 
   // sift down; after a refill the root level's children are already locked
-  // and loaded
+  // and loaded.  While a level merges, lanes 0 and 1 make a first try at the
+  // locks of the next node's children (the next node is held), kept in eoc.
   u32 c = 1;
+  u64 eoc = ~0ull;
+  bool early = false;
   for (;;) {
     const u64 l = 2ull * c, r = l + 1;
     lds_t<Ent>* Lb = bufs[1];
@@ -703,11 +718,22 @@ __device__ __forceinline__ OpResult op_delete(const HeapDesc& H, u64 ticket,
     if (!loaded) {
       const bool el = node_exists(l, m2), er = node_exists(r, m2);
       if (tid < 64) {
-        u64* w = (tid == 0) ? (el ? lock_ptr(H, (u32)l) : nullptr)
-                            : (er ? lock_ptr(H, (u32)r) : nullptr);
-        const bool active = (tid == 0 && el) || (tid == 1 && er);
+        const bool mine = (tid == 0 && el) || (tid == 1 && er);
         int got = 0;
-        const bool ok = lock_lanes(w, LM_CHILD, ticket, active, got, ctl);
+        bool need = false;
+        if (mine) {
+          if (!early) need = true;
+          else if (eoc == 0) got = 1;
+          else if (child_view(eoc, ticket) == 0) got = 0;
+          else need = true;
+        }
+        u64* w = need ? lock_ptr(H, (u32)(tid == 0 ? l : r)) : nullptr;
+        bool ok = true;
+        if (__any(need)) {
+          int r2 = 0;
+          ok = lock_lanes(w, LM_CHILD, ticket, need, r2, ctl);
+          if (need) got = r2;
+        }
         const bool allok = __all(ok);
         if (tid == 0) {
           sh.flag0 = got > 0 ? 1u : 0u;
@@ -756,6 +782,12 @@ __device__ __forceinline__ OpResult op_delete(const HeapDesc& H, u64 ticket,
       const bool big_is_l = ent_lt(Rb[K - 1], Lb[K - 1]);
       const u32 big = big_is_l ? (u32)l : (u32)r;
       const u32 small = big_is_l ? (u32)r : (u32)l;
+      early = true;
+      if (tid < 2) {
+        const u64 g = 2ull * small + tid;
+        eoc = node_exists(g, m2) ? cas_old(lock_ptr(H, (u32)g), 0, lockword(ST_INUSE, ticket))
+                                 : ~0ull;
+      }
       lds_t<Ent>* Bg = big_is_l ? Lb : Rb;
       lds_t<Ent>* Sm = big_is_l ? Rb : Lb;
       lds_t<Ent>* hi;
@@ -790,6 +822,12 @@ __device__ __forceinline__ OpResult op_delete(const HeapDesc& H, u64 ticket,
       // one live child x
       const u32 x = hl ? (u32)l : (u32)r;
       lds_t<Ent>* X = hl ? Lb : Rb;
+      early = true;
+      if (tid < 2) {
+        const u64 g = 2ull * x + tid;
+        eoc = node_exists(g, m2) ? cas_old(lock_ptr(H, (u32)g), 0, lockword(ST_INUSE, ticket))
+                                 : ~0ull;
+      }
       lds_t<Ent>* freeb = bufs[3];
       if (ent_le(X[K - 1], C[0])) {
         store_node<K, T, Ent>(cptr, X);
