@@ -76,6 +76,9 @@ def parse():
     ap.add_argument("--util-check-levels", type=int, default=10,
                     help="check every deleteMin against the oracle for heaps of up to this many "
                          "levels")
+    ap.add_argument("--phase-trace", action="store_true",
+                    help="only the root phase trace of the plain workload, with the tracing "
+                         "build (python -m paper_1906_06504_amd.build --trace); prints its JSON")
     ap.add_argument("--filter", action="store_true",
                     help="also time heap_filter on a 2^22-entry heap (k = 1024) at several "
                          "cut points; not in the default run")
@@ -101,6 +104,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.phase_trace:
+        print(json.dumps(run_phase_trace(args)))
+        return
     G.load_library()
     k = 1024
     wg = args.workgroups or DEFAULT_SHAPE["workgroups"]
@@ -1068,6 +1074,108 @@ def _paper_table_phases(G, W, ops, k, N, order, wg=128):
         % (order, res["td"]["insert_ms"], res["bu"]["insert_ms"], res["td"]["drain_ms"],
            res["bu"]["drain_ms"]))
     return res
+
+
+def run_phase_trace(args):
+    """Root phase trace of the plain workload (k = 1024, prefill 2^22, 2^24
+    keys requested, the benchmark's launch shape) with the tracing build
+    (libgheap_trace.so: thread 0 time-stamps the phases of every
+    operation's root critical section, include/gheap_trace.h).  Reports, per
+    kind of operation, the median and mean of each phase, the root hold
+    (root taken to root released), the hand-over to the next ticket and the
+    interval between root acquisitions.  Tracing adds a few stores per
+    operation, so the step time is reported beside it."""
+    import ctypes
+    import torch
+    from paper_1906_06504_amd import gheap as G
+    from paper_1906_06504_amd import workloads as W
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1906_06504_amd",
+                        "libgheap_trace.so")
+    if not os.path.exists(path):
+        raise SystemExit("the tracing build is missing: python -m paper_1906_06504_amd.build --trace")
+    lib = G.load_library(path)
+    lib.gheap_phase_trace.restype = ctypes.c_int
+    lib.gheap_phase_trace.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64]
+    pre, mix, k = W.config2(prefill=args.prefill, requested=args.requested)
+    wg = args.workgroups or 64
+    th = args.threads or 1024
+    cap = args.prefill + int(mix.n.astype(np.int64).sum()) + k
+    hz = G.clock_hz()
+    hs = G.HeapSet(k, [cap], stream=torch.cuda.Stream())
+    nops = len(mix)
+    with torch.cuda.stream(hs.stream):
+        dpre = G.ops_to_device(pre)
+        _timed_submit(hs, dpre, 1024, 0)
+        del dpre
+        snap = hs.arena.clone()
+        d = G.ops_to_device(mix)
+        dlog = G.new_log(nops)
+        times = []
+        for i in range(args.warmup + args.steps):
+            hs.arena.copy_(snap)
+            torch.cuda.synchronize()
+            if lib.gheap_phase_trace(hs.h, None, 0) != 0:
+                raise SystemExit("gheap_phase_trace reset failed")
+            times.append(_timed_submit(hs, d, wg, th, dlog))
+        tr = np.zeros(nops * 16, dtype=np.uint32)
+        if lib.gheap_phase_trace(hs.h, tr.ctypes.data_as(ctypes.c_void_p), tr.size) != 0:
+            raise SystemExit("gheap_phase_trace read failed")
+        lg = G.log_to_host(dlog, nops)
+    hs.close()
+    tr = tr.reshape(nops, 16).astype(np.int64)
+    order = np.argsort(lg["ticket"], kind="stable")
+    tr = tr[order]
+    kind = lg["kind"][order]
+    flags = lg["flags"][order].astype(np.int64)
+    us = 1e6 / hz
+
+    def d(a, b, sel):
+        x = ((tr[sel, b] - tr[sel, a]) & 0xFFFFFFFF).astype(np.float64) * us
+        return {"median": float(np.median(x)), "mean": float(np.mean(x))} if x.size else None
+
+    def has(*slots):
+        return np.all(tr[:, list(slots)] != 0, axis=1)
+
+    # operations that passed every slot of their path (slots left at the
+    # reset value, 0, belong to shorter paths: a batch that became the root,
+    # an early stop at the root)
+    full_ins = (kind == 0) & ((flags & 1) != 0) & has(0, 1, 2, 3, 4, 15)
+    part_ins = (kind == 0) & ((flags & 1) == 0) & has(0, 1, 2, 15)
+    refill = (kind == 1) & ((flags & 16) != 0) & has(0, 1, 2, 3, 4, 5, 6, 7, 15)
+    other_del = (kind == 1) & ~refill & has(0, 15)
+    out = {"workload": "plain single heap, k=1024: prefill %d keys, then a 50/50 mix of insert "
+                       "U[1,1024] and deleteMin(1024) until %d keys requested" % (args.prefill,
+                                                                                args.requested),
+           "ops": nops, "workgroups": wg, "threads": th,
+           "traced_ms_per_step": float(np.mean(times[args.warmup:])),
+           "counts": {"full_insert": int(full_ins.sum()), "partial_insert": int(part_ins.sum()),
+                      "refilling_deletemin": int(refill.sum()),
+                      "other_deletemin": int(other_del.sum())},
+           "full_insert_us": {"root_hold": d(0, 15, full_ins),
+                              "first_round_trip": d(0, 1, full_ins),
+                              "pb_merge": d(1, 2, full_ins), "root_merge": d(2, 3, full_ins),
+                              "publish": d(3, 4, full_ins), "release": d(4, 15, full_ins)},
+           "partial_insert_us": {"root_hold": d(0, 15, part_ins),
+                                 "first_round_trip": d(0, 1, part_ins),
+                                 "pb_merge": d(1, 2, part_ins),
+                                 "root_merge_and_publish": d(2, 15, part_ins)},
+           "refilling_deletemin_us": {"root_hold": d(0, 15, refill),
+                                      "root_and_pb_load": d(0, 1, refill),
+                                      "last_node_lock": d(1, 2, refill),
+                                      "last_node_load_child_tries": d(2, 3, refill),
+                                      "children_settled": d(3, 4, refill),
+                                      "children_load_pb_merge": d(4, 5, refill),
+                                      "sift_merges": d(5, 6, refill), "publish": d(6, 7, refill),
+                                      "release": d(7, 15, refill)},
+           "other_deletemin_us": {"root_hold": d(0, 15, other_del)}}
+    t0 = tr[:, 0]
+    rel = tr[:, 15]
+    hand = ((t0[1:] - rel[:-1]) & 0xFFFFFFFF).astype(np.float64) * us
+    ivl = ((t0[1:] - t0[:-1]) & 0xFFFFFFFF).astype(np.float64) * us
+    out["handover_us"] = {"median": float(np.median(hand)), "mean": float(np.mean(hand))}
+    out["root_interval_us"] = {"median": float(np.median(ivl)), "mean": float(np.mean(ivl))}
+    out["root_bound_keys_per_s"] = k / (float(np.median(ivl)) * 1e-6)
+    return out
 
 
 def run_filter(args):

@@ -1,6 +1,6 @@
 """Build libgheap.so (HIP, gfx950) in-tree with hipcc.
 
-Usage: python -m paper_1906_06504_amd.build   (or call build()).
+Usage: python -m paper_1906_06504_amd.build [--trace]   (or call build()).
 Each supported node capacity k and entry width (8 or 16 bytes) gets its own
 objects of gh_kernels.hip, gh_serve.hip and gh_bu.hip, so they compile in
 parallel.
@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgheap.so")
+LIB_TRACE = os.path.join(HERE, "libgheap_trace.so")
 KS = (32, 64, 128, 256, 512, 1024)
 ARCH = os.environ.get("GHEAP_ARCH", "gfx950")
 
@@ -37,21 +38,27 @@ def _run(cmd):
     return out
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(jobs: int | None = None, verbose: bool = False, trace: bool = False) -> str:
+    """Compile every object and link libgheap.so; with trace, the tracing
+    build libgheap_trace.so instead (every object with -DGH_PHASE_TRACE: the
+    whole-root kernels time-stamp their root phases, include/gheap_trace.h)."""
+    build_dir = BUILD + ("_trace" if trace else "")
+    lib = LIB_TRACE if trace else LIB
+    flags = COMMON + (["-DGH_PHASE_TRACE"] if trace else [])
+    os.makedirs(build_dir, exist_ok=True)
     jobs = jobs or min(8, os.cpu_count() or 4)
     tasks = []
     for k in KS:
         for eb in (8, 16):
             for name in ("gh_kernels", "gh_serve", "gh_bu"):
-                obj = os.path.join(BUILD, "%s_k%d_e%d.o" % (name, k, eb))
-                tasks.append([HIPCC] + COMMON + ["-DGH_K=%d" % k, "-DGH_ENT_BYTES=%d" % eb, "-c",
-                                                 os.path.join(CSRC, name + ".hip"), "-o", obj])
+                obj = os.path.join(build_dir, "%s_k%d_e%d.o" % (name, k, eb))
+                tasks.append([HIPCC] + flags + ["-DGH_K=%d" % k, "-DGH_ENT_BYTES=%d" % eb, "-c",
+                                                os.path.join(CSRC, name + ".hip"), "-o", obj])
     for name in ("gh_setup", "gh_filter"):
-        tasks.append([HIPCC] + COMMON + ["-c", os.path.join(CSRC, name + ".hip"),
-                                         "-o", os.path.join(BUILD, name + ".o")])
-    tasks.append([HIPCC] + COMMON + ["-x", "hip", "-c", os.path.join(CSRC, "gheap_api.cpp"),
-                                     "-o", os.path.join(BUILD, "gheap_api.o")])
+        tasks.append([HIPCC] + flags + ["-c", os.path.join(CSRC, name + ".hip"),
+                                        "-o", os.path.join(build_dir, name + ".o")])
+    tasks.append([HIPCC] + flags + ["-x", "hip", "-c", os.path.join(CSRC, "gheap_api.cpp"),
+                                    "-o", os.path.join(build_dir, "gheap_api.o")])
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         outs = list(ex.map(_run, tasks))
     if verbose:
@@ -59,11 +66,11 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
             if o:
                 print(o)
     objs = [t[t.index("-o") + 1] for t in tasks]
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = lib + ".tmp%d" % os.getpid()
     _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, trace="--trace" in sys.argv))

@@ -679,6 +679,20 @@ hipError_t launch_sssp_k<GH_K>(const SsspArgs& a) {
 
 #endif  // GH_ENT_BYTES == 8
 
+#ifdef GH_PHASE_TRACE
+template <>
+hipError_t phase_trace_k<GH_K, GH_ENT>(uint32_t* host, u64 words) {
+  if (!host) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(gh_phase_trace));
+    if (e != hipSuccess) return e;
+    return hipMemset(p, 0, sizeof(gh_phase_trace));
+  }
+  return hipMemcpyFromSymbol(host, HIP_SYMBOL(gh_phase_trace), words * sizeof(uint32_t), 0,
+                             hipMemcpyDeviceToHost);
+}
+#endif
+
 template <>
 hipError_t launch_ops_k<GH_K, GH_ENT>(const LaunchArgs& a) {
   return launch_kops_shape<GH_K, FORM_WHOLE, GH_ENT>(a);

@@ -62,6 +62,10 @@ hipError_t launch_ops_var_k(const LaunchArgs& a);
 // the operation loop with bottom-up inserts (gh_bu.hip)
 template <int K, class Ent>
 hipError_t launch_ops_bu_k(const LaunchArgs& a);
+// tracing build only (GH_PHASE_TRACE): the whole-root kernels' phase trace
+// (gh_kernels.hip): zero it (host == nullptr) or copy `words` words out
+template <int K, class Ent>
+hipError_t phase_trace_k(uint32_t* host, u64 words);
 
 // ---------------------------------------------------------------------------
 // Served form: device workspace layout

@@ -9,6 +9,9 @@
 #include <vector>
 
 #include "gh_launch.h"
+#ifdef GH_PHASE_TRACE
+#include "../../include/gheap_trace.h"
+#endif
 
 using namespace gh;
 
@@ -700,5 +703,30 @@ const char* heap_strerror(int code) {
 }
 
 uint64_t heap_clock_hz(void) { return (uint64_t)clock_mhz_of_device() * 1000000ull; }
+
+#ifdef GH_PHASE_TRACE
+int gheap_phase_trace(gh_heap_t h, uint32_t* host_out, uint64_t words) {
+  if (!h || words > (1ull << 22)) return GH_EINVAL;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return GH_EDEVICE;
+  hipError_t e = hipErrorInvalidValue;
+#define GH_TRACE_CASE(KK)                                                          \
+  case KK:                                                                          \
+    e = h->ebytes == 16 ? phase_trace_k<KK, e128>(host_out, words)                  \
+                        : phase_trace_k<KK, u64>(host_out, words);                  \
+    break;
+  switch (h->k) {
+    GH_TRACE_CASE(32)
+    GH_TRACE_CASE(64)
+    GH_TRACE_CASE(128)
+    GH_TRACE_CASE(256)
+    GH_TRACE_CASE(512)
+    GH_TRACE_CASE(1024)
+    default:
+      return GH_EINVAL;
+  }
+#undef GH_TRACE_CASE
+  return e == hipSuccess ? GH_OK : GH_EDEVICE;
+}
+#endif
 
 }  // extern "C"
