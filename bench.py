@@ -1153,12 +1153,13 @@ def run_phase_trace(args):
                       "other_deletemin": int(other_del.sum())},
            "full_insert_us": {"root_hold": d(0, 15, full_ins),
                               "first_round_trip": d(0, 1, full_ins),
-                              "pb_merge": d(1, 2, full_ins), "root_merge": d(2, 3, full_ins),
+                              "root_phase_merge": d(1, 2, full_ins),
+                              "first_path_lock": d(2, 3, full_ins),
                               "publish": d(3, 4, full_ins), "release": d(4, 15, full_ins)},
            "partial_insert_us": {"root_hold": d(0, 15, part_ins),
                                  "first_round_trip": d(0, 1, part_ins),
-                                 "pb_merge": d(1, 2, part_ins),
-                                 "root_merge_and_publish": d(2, 15, part_ins)},
+                                 "root_phase_merge": d(1, 2, part_ins),
+                                 "publish_and_release": d(2, 15, part_ins)},
            "refilling_deletemin_us": {"root_hold": d(0, 15, refill),
                                       "root_and_pb_load": d(0, 1, refill),
                                       "last_node_lock": d(1, 2, refill),

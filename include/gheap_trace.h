@@ -11,8 +11,11 @@
  * deleteMin that holds the root) to slot s of a per-operation record of 16
  * words, for operations i < 2^18:
  *   insert:    0 root taken; 1 partial buffer and root loaded, target
- *              reserved, first child locked; 2 input merged with the partial
- *              buffer; 3 root MergeAndSort done; 4 root stores published;
+ *              reserved, first try at the root's child on the insert path;
+ *              2 input, root and partial buffer merged in one pass (new
+ *              root, carry and partial buffer; stores issued); 3 that child
+ *              locked (a wait only when its first try failed); 4 root stores
+ *              published (a partial batch passes 0, 1, 2 and 15);
  *   deleteMin: 0 root taken; 1 root and partial buffer loaded; 2 last node
  *              locked; 3 last node loaded, first tries at the root's
  *              children; 4 children settled; 5 children loaded and the

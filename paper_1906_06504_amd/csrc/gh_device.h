@@ -541,6 +541,40 @@ __device__ __forceinline__ void merge_split(const lds_t<Ent>* A, int na, const l
   }
 }
 
+// The same with two split points: positions < s1 go to a[p], [s1, s2) to
+// b[p - s1], the rest to c[p - s2].
+template <int E, int T, class Ent, class SinkA, class SinkB, class SinkC>
+__device__ __forceinline__ void merge_split3(const lds_t<Ent>* A, int na, const lds_t<Ent>* B,
+                                             int nb, int s1, int s2, const SinkA& a,
+                                             const SinkB& b, const SinkC& c) {
+  const int total = na + nb;
+  for (int d = threadIdx.x * E; d < total; d += T * E) {
+    Ent v[E];
+    merge_path<E>(A, na, B, nb, d, v);
+    if (d + E <= total && d + E <= s1) {
+      a.template put_range<E>(d, v);
+    } else if (d + E <= total && d >= s1 && d + E <= s2) {
+      b.template put_range<E>(d - s1, v);
+    } else if (d + E <= total && d >= s2) {
+      c.template put_range<E>(d - s2, v);
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int p = d + e;
+        if (p < total) {
+          if (p < s1) a.put1(p, v[e]);
+          else if (p < s2) b.put1(p - s1, v[e]);
+          else c.put1(p - s2, v[e]);
+        }
+      }
+    }
+  }
+}
+
+// Entries a thread takes in a merge of up to 3K entries in one pass: a
+// power of two (even counts store 16 bytes at a time).
+constexpr int pow2_at_least(int x) { return x <= 1 ? 1 : 2 * pow2_at_least((x + 1) / 2); }
+
 // ---------------------------------------------------------------------------
 // Workgroup merge sort of up to K entries in LDS (sorts the insert batch,
 // Sec. 4.1): every thread sorts EPT entries in registers, then rounds of

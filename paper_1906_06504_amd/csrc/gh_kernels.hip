@@ -131,7 +131,7 @@ __device__ __forceinline__ u64 kn_bound(const KnapShared& ks, u32 level, u64 V, 
 // hold at least a quarter of the heap, and when the staged batches fit the
 // heap's free slots.  Returns false after a failed heap operation.
 template <int K, int T, class Ent>
-__device__ bool knap_collect(const HeapDesc& H, u64& ticket, u32& ops, lds_t<Ent>* L,
+__device__ __forceinline__ bool knap_collect(const HeapDesc& H, u64& ticket, u32& ops, lds_t<Ent>* L,
                              OpShared& sh, KnapShared& ks, Ctl* ctl) {
   typedef KnapKey<Ent> KK;
   const int tid = threadIdx.x;

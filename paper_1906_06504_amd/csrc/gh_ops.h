@@ -308,13 +308,18 @@ __device__ __forceinline__ OpResult op_insert(const HeapDesc& H, u64 ticket,
                                               const Ent* __restrict__ keys, u32 n,
                                               lds_t<Ent>* lds, OpShared& sh, Ctl* ctl) {
   constexpr int E = (2 * K) / T >= 1 ? (2 * K) / T : 1;
+  // entries a thread takes in the root phase's merge of input, root and pb
+  // (up to 3K): one pass where that needs at most max(E, 8) a thread
+  constexpr int E3a = pow2_at_least((3 * K + T - 1) / T);
+  constexpr int E3 = E3a < (E > 8 ? E : 8) ? E3a : (E > 8 ? E : 8);
   const int tid = threadIdx.x;
   OpResult res{n, 0, 0, true};
   lds_t<Ent>* b0 = lds;
   lds_t<Ent>* b1 = lds + K;
-  lds_t<Ent>* P = lds + 2 * K;   // partial buffer
-  lds_t<Ent>* F = lds + 3 * K;   // full batch / merged head
-  lds_t<Ent>* N = lds + 4 * K;   // node being merged (root first)
+  lds_t<Ent>* F = lds + 2 * K;   // the carry
+  lds_t<Ent>* N = lds + 3 * K;   // node being merged (root first)
+  lds_t<Ent>* P = lds + 4 * K;   // partial buffer, right after the root: by Property 3
+                                 // root followed by pb is one sorted run
   HeapMeta* meta = H.meta;
 
   // sort the batch before touching the heap (holds no lock)
@@ -360,16 +365,14 @@ __device__ __forceinline__ OpResult op_insert(const HeapDesc& H, u64 ticket,
     if (tid < 64) {
       const bool bad = tid == 0 && L >= 1 && lw_state(old) != ST_AVAIL &&
                        lw_state(old) != ST_REMOVED;
+      // a busy first child is waited for after the root phase's merges,
+      // before the root is released (its payload is loaded only then)
       const bool need = tid == 1 && L >= 2 && old != 0;
-      int r = 0;
-      bool ok = true;
-      if (__any(need)) ok = lock_lanes(lock_ptr(H, child1), LM_PATH, ticket, need, r, ctl);
-      else if (L >= 2) fence_acquire();
-      const bool allok = __all(ok);
+      if (tid == 1) sh.flag1 = need ? 1u : 0u;
       const bool anybad = __any(bad);
       if (tid == 0) {
         if (anybad) raise_error(ctl, ERR_STATE);
-        sh.ok = (allok && !anybad) ? 1u : 0u;
+        sh.ok = anybad ? 0u : 1u;
       }
     }
   }
@@ -377,29 +380,41 @@ __device__ __forceinline__ OpResult op_insert(const HeapDesc& H, u64 ticket,
   GH_TRACE(1);
   if (!sh.ok) { res.ok = false; return res; }
 
-  // merged = merge(sorted input, partial buffer): first K -> F, rest -> xfree
+  // The root phase in one merge.  Property 3 makes root followed by pb one
+  // sorted run, so S = merge(sorted input, root ++ pb) gives the top-down
+  // insert's results directly: the new root is S[0, K); for a partial batch
+  // the new pb is the rest; for a full batch the carry (the root-level
+  // MergeAndSort's hi half) is S[K, 2K) and the new pb S[2K, ...), the n + s
+  // - K largest of input and pb (an input entry below a root entry cannot be
+  // among them, since n <= K).  When the input is no smaller than the root
+  // the root stays as it is and only input and pb merge.
   const u32 tot = n + s;
-  merge_split<E, T>(xs, (int)n, P, (int)s, K, sink(F), sink(xfree));
-  __syncthreads();
-  GH_TRACE(2);
-
   Ent* root = slot_ptr<K, Ent>(H, 1);  // position 1
+  const HeapSink<Ent> pbsink(pb_ptr<Ent>(H), K * sizeof(Ent));
+  const bool root_moves = m >= 1 && !ent_le((Ent)N[K - 1], (Ent)xs[0]);
   if (!full) {
-    // the partial buffer keeps everything; restore Property 3 against the root
-    if (m >= 1 && !ent_le(N[K - 1], F[0])) {
-      merge_split<E, T>(N, K, F, (int)tot, K, HeapSink<Ent>(root, K * sizeof(Ent)), HeapSink<Ent>(pb_ptr<Ent>(H), K * sizeof(Ent)));
-    } else {
-      store_heap_n<K, T, Ent>(pb_ptr<Ent>(H), F, tot);
-    }
+    // the partial buffer keeps everything, Property 3 against the root
+    if (root_moves)
+      merge_split<E3, T>(xs, (int)n, N, K + (int)s, K, HeapSink<Ent>(root, K * sizeof(Ent)),
+                         pbsink);
+    else
+      merge_split<E, T>(xs, (int)n, P, (int)s, (int)tot, pbsink, pbsink);
+    GH_TRACE(2);
     publish();
     if (tid == 0) release_root_at<Stamp>(meta, ticket, m, tot, sh);
     return res;
   }
 
-  // a full batch F goes down from the root; the rest stays in the pb
+  // a full batch: the carry goes down from the root; the rest stays in the pb
   res.flags |= F_FULL;
   const u32 rest = tot - K;
-  store_heap_n<K, T, Ent>(pb_ptr<Ent>(H), xfree, rest);
+  if (root_moves)
+    merge_split3<E3, T>(xs, (int)n, N, K + (int)s, K, 2 * K,
+                        HeapSink<Ent>(root, K * sizeof(Ent)), sink(F), pbsink);
+  else
+    merge_split<E, T>(xs, (int)n, P, (int)s, K, sink(F), pbsink);
+  __syncthreads();
+  GH_TRACE(2);
   if (L == 0) {
     store_node<K, T, Ent>(root, F);
     publish();
@@ -407,16 +422,29 @@ __device__ __forceinline__ OpResult op_insert(const HeapDesc& H, u64 ticket,
     return res;
   }
 
-  // LDS buffers in play: N (node), F (carry), spare (free; xfree is read by
-  // the pb store above and stays untouched)
-  lds_t<Ent>* spare = xfree == b0 ? b1 : b0;
+  // LDS buffers in play below the root: N (node), F (carry), spare (free)
+  lds_t<Ent>* spare = xfree;
   u32 cur = 1;
   int level = 0;
   for (;;) {
     const bool at_root = cur == 1;
-    // (node, F) = MergeAndSort(node, F) with the shortcuts of Sec. 4.3
+    // (node, F) = MergeAndSort(node, F) with the shortcuts of Sec. 4.3; the
+    // root's was part of the merge above
     Ent* cur_ptr = node_ptr<K, Ent>(H, cur);
-    if (ent_le(N[K - 1], F[0])) {
+    if (at_root) {
+      // the merge is done; take the first path node now if its first try
+      // failed (parent before child: the root is still held)
+      if (sh.flag1) {
+        if (tid < 64) {
+          int r = 0;
+          const bool ok = lock_lanes(lock_ptr(H, t >> (L - 1)), LM_PATH, ticket, tid == 1, r, ctl);
+          const bool allok = __all(ok);
+          if (tid == 0) sh.ok = allok ? 1u : 0u;
+        }
+        __syncthreads();
+        if (!sh.ok) { res.ok = false; return res; }
+      }
+    } else if (ent_le(N[K - 1], F[0])) {
       // node already holds the smallest: nothing moves
     } else if (ent_le(F[K - 1], N[0])) {
       store_node<K, T, Ent>(cur_ptr, F);  // swap
