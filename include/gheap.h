@@ -198,8 +198,9 @@ typedef struct gh_reqrec {
  * layout; with many in flight the heap satisfies Properties 1-3 with the
  * same entries when the launch ends, and its layout may differ.  Inserts
  * do not overlap deleteMins in this form because a climbing insert has no
- * linearization point that deleteMins in flight would respect (see
- * DESIGN); deleteMins run in other submissions.  Log records: levels =
+ * linearization point that deleteMins in flight would respect (a deleteMin
+ * can pass a climbing batch and miss entries smaller than the ones it
+ * returns); deleteMins run in other submissions.  Log records: levels =
  * merges of the climb; flags bit 5 = the climb stopped below the root. */
 #define GH_TUNE_BOTTOM_UP 4u
 typedef struct gh_tuning {

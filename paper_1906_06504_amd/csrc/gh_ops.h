@@ -299,6 +299,129 @@ __device__ __forceinline__ bool acquire_root(const HeapDesc& H, u64 ticket, OpSh
 }
 
 // ---------------------------------------------------------------------------
+// The part of a top-down insert below the root (Sec. 3.2.2, 3.3.2): the carry
+// F goes from node `cur` on level 1 down the path to the target t (level L
+// >= 2), merging with every path node (MergeAndSort with the shortcuts of
+// Sec. 4.3), hand over hand.  On entry `cur` is locked by this operation and
+// t is reserved as TARGET(ticket); with LoadF the carry is read from the
+// target slot in the first round trip (where the root's owner left it),
+// otherwise it is in F.  N and spare are free LDS buffers.
+// ---------------------------------------------------------------------------
+template <int K, int T, class Ent>
+__device__ __forceinline__ OpResult ins_fill_target(const HeapDesc& H, u64 ticket, u32 t, int L,
+                                                    lds_t<Ent>* F, OpShared& sh, OpResult res) {
+  const int tid = threadIdx.x;
+  u64* tlock = lock_ptr(H, t);
+  store_node<K, T, Ent>(node_ptr<K, Ent>(H, t), F);
+  publish();
+  if (tid == 0) {
+    if (!cas_relaxed(tlock, lockword(ST_TARGET, ticket), lockword(ST_AVAIL, 0))) {
+      // MARKED by a deleteMin: the batch is already in the target slot
+      st_relaxed(tlock, lockword(ST_HANDED, ticket));
+      sh.flag1 = 1;
+    } else {
+      sh.flag1 = 0;
+    }
+  }
+  __syncthreads();
+  if (sh.flag1) res.flags |= F_HANDOFF;
+  res.levels = L;
+  return res;
+}
+
+template <int K, int T, class Ent, bool LoadF>
+__device__ __forceinline__ OpResult ins_descend(const HeapDesc& H, u64 ticket, u32 t, int L,
+                                                u32 cur, lds_t<Ent>* F, lds_t<Ent>* N,
+                                                lds_t<Ent>* spare, OpShared& sh, Ctl* ctl,
+                                                OpResult res) {
+  constexpr int E = (2 * K) / T >= 1 ? (2 * K) / T : 1;
+  const int tid = threadIdx.x;
+  u64* tlock = lock_ptr(H, t);
+  int level = 1;
+  for (;;) {
+    {
+      // the path node, in the same round trip a look at the target (a
+      // deleteMin that claimed it gets the carry now, before this level's
+      // merge: the carry has not entered this subtree yet) and a first try
+      // at the lock of the node after it (cur is held: parent before child)
+      const u32 nxt = t >> (L - level - 1);
+      NodeRegs<K, T, Ent> nr, fr;
+      nr.load(node_ptr<K, Ent>(H, cur));
+      if (LoadF && level == 1) fr.load(node_ptr<K, Ent>(H, t));
+      u64 tw = 0, eo = 1;
+      if (tid == 0) tw = ld_relaxed(tlock);
+      if (tid == 1 && nxt != t) eo = cas_old(lock_ptr(H, nxt), 0, lockword(ST_INUSE, ticket));
+      nr.store(N);
+      if (LoadF && level == 1) fr.store(F);
+      if (tid == 0) sh.flag0 = lw_state(tw) == ST_MARKED ? 1u : 0u;
+      if (tid == 1) sh.early = eo == 0 ? 1u : 0u;
+    }
+    __syncthreads();
+    if (sh.flag0) {
+      store_node<K, T, Ent>(node_ptr<K, Ent>(H, t), F);
+      publish();
+      if (tid == 0) {
+        if (sh.early) unlock(lock_ptr(H, t >> (L - level - 1)));
+        unlock(lock_ptr(H, cur));
+        st_relaxed(tlock, lockword(ST_HANDED, ticket));
+      }
+      res.levels = level;
+      res.flags |= F_HANDOFF;
+      return res;
+    }
+    // (node, F) = MergeAndSort(node, F) with the shortcuts of Sec. 4.3
+    Ent* cur_ptr = node_ptr<K, Ent>(H, cur);
+    if (ent_le(N[K - 1], F[0])) {
+      // node already holds the smallest: nothing moves
+    } else if (ent_le(F[K - 1], N[0])) {
+      store_node<K, T, Ent>(cur_ptr, F);  // swap
+      lds_t<Ent>* x = F; F = N; N = x;
+    } else {
+      merge_split<E, T>(N, K, F, K, K, HeapSink<Ent>(cur_ptr, K * sizeof(Ent)), sink(spare));
+      lds_t<Ent>* x = F; F = spare; spare = x;
+    }
+    ++level;
+    const u32 child = t >> (L - level);
+    // lane 0 looks whether a deleteMin claimed our target, lane 1 locks the
+    // next path node (child before parent release)
+    if (tid < 64) {
+      const bool next_is_path = child != t;
+      u64* w = (tid == 0) ? tlock : lock_ptr(H, child);
+      const u32 mode = (tid == 0) ? (u32)LM_PEEK : (u32)LM_PATH;
+      // the next path node was tried when this node was loaded
+      const bool active = tid == 0 || (tid == 1 && next_is_path && !sh.early);
+      int r = 0;
+      const bool ok = lock_lanes(w, mode, ticket, active, r, ctl);
+      const bool allok = __all(ok);
+      if (tid == 0) {
+        sh.flag0 = r == 1 ? 1u : 0u;   // MARKED seen
+        sh.ok = allok ? 1u : 0u;
+      }
+    }
+    __syncthreads();
+    if (!sh.ok) { res.ok = false; return res; }
+    if (sh.flag0) {
+      // cooperation: leave the batch in the target slot for the deleteMin
+      store_node<K, T, Ent>(node_ptr<K, Ent>(H, t), F);
+      publish();
+      if (tid == 0) {
+        if (child != t) unlock(lock_ptr(H, child));
+        unlock(lock_ptr(H, cur));
+        st_relaxed(tlock, lockword(ST_HANDED, ticket));
+      }
+      res.levels = level;
+      res.flags |= F_HANDOFF;
+      return res;
+    }
+    publish();
+    if (tid == 0) unlock(lock_ptr(H, cur));
+    if (child == t) break;
+    cur = child;
+  }
+  return ins_fill_target<K, T, Ent>(H, ticket, t, L, F, sh, res);
+}
+
+// ---------------------------------------------------------------------------
 // INS (Sec. 3.2.2 top-down insert, Sec. 3.3.2 partial batches and
 // cooperation).  `keys` holds n (1..K) entries in global memory.
 // LDS: five buffers of K entries.
@@ -422,126 +545,195 @@ __device__ __forceinline__ OpResult op_insert(const HeapDesc& H, u64 ticket,
     return res;
   }
 
-  // LDS buffers in play below the root: N (node), F (carry), spare (free)
-  lds_t<Ent>* spare = xfree;
-  u32 cur = 1;
-  int level = 0;
-  for (;;) {
-    const bool at_root = cur == 1;
-    // (node, F) = MergeAndSort(node, F) with the shortcuts of Sec. 4.3; the
-    // root's was part of the merge above
-    Ent* cur_ptr = node_ptr<K, Ent>(H, cur);
-    if (at_root) {
-      // the merge is done; take the first path node now if its first try
-      // failed (parent before child: the root is still held)
-      if (sh.flag1) {
-        if (tid < 64) {
-          int r = 0;
-          const bool ok = lock_lanes(lock_ptr(H, t >> (L - 1)), LM_PATH, ticket, tid == 1, r, ctl);
-          const bool allok = __all(ok);
-          if (tid == 0) sh.ok = allok ? 1u : 0u;
-        }
-        __syncthreads();
-        if (!sh.ok) { res.ok = false; return res; }
-      }
-    } else if (ent_le(N[K - 1], F[0])) {
-      // node already holds the smallest: nothing moves
-    } else if (ent_le(F[K - 1], N[0])) {
-      store_node<K, T, Ent>(cur_ptr, F);  // swap
-      lds_t<Ent>* x = F; F = N; N = x;
-    } else {
-      merge_split<E, T>(N, K, F, K, K, HeapSink<Ent>(cur_ptr, K * sizeof(Ent)), sink(spare));
-      lds_t<Ent>* x = F; F = spare; spare = x;
+  // The root's MergeAndSort was part of the merge above.  Take the first
+  // path node now if its first try failed (parent before child: the root is
+  // still held), then release the root.
+  if (L >= 2 && sh.flag1) {
+    if (tid < 64) {
+      int r = 0;
+      const bool ok = lock_lanes(lock_ptr(H, child1), LM_PATH, ticket, tid == 1, r, ctl);
+      const bool allok = __all(ok);
+      if (tid == 0) sh.ok = allok ? 1u : 0u;
     }
-    ++level;
-    if (at_root) GH_TRACE(3);
-    const u32 child = t >> (L - level);
-    if (!at_root) {
-      // below the root: lane 0 looks whether a deleteMin claimed our target,
-      // lane 1 locks the next path node (child before parent release)
+    __syncthreads();
+    if (!sh.ok) { res.ok = false; return res; }
+  }
+  GH_TRACE(3);
+  publish();
+  GH_TRACE(4);
+  if (tid == 0) release_root_at<Stamp>(meta, ticket, m2, rest, sh);
+  if (L == 1) return ins_fill_target<K, T, Ent>(H, ticket, t, L, F, sh, res);
+  return ins_descend<K, T, Ent, false>(H, ticket, t, L, child1, F, N, xfree, sh, ctl, res);
+}
+
+// ---------------------------------------------------------------------------
+// The sift-down of a deleteMin (Sec. 3.2.1, 3.3.2) from node c, which this
+// operation holds with cur's batch in bufs[0] (c = 1: the root, released at
+// the end of its level).  `loaded`: c's children are locked as hl / hr say
+// and loaded into bufs[1] / bufs[2].  Otherwise, with `early`, lanes 0 and 1
+// hold the result of a first try at c's children's locks in eoc.  While a
+// level merges, lanes 0 and 1 make a first try at the locks of the next
+// node's children (the next node is held), kept in eoc.
+// ---------------------------------------------------------------------------
+template <int K, int T, class Ent, bool Stamp = false>
+__device__ __forceinline__ OpResult del_sift(const HeapDesc& H, u64 ticket, u32 c, bool loaded,
+                                             bool hl, bool hr, bool early, u64 eoc,
+                                             lds_t<Ent>* (&bufs)[4], u64 m2, u64 s2,
+                                             OpShared& sh, Ctl* ctl, OpResult res) {
+  constexpr int E = (2 * K) / T >= 1 ? (2 * K) / T : 1;
+  const int tid = threadIdx.x;
+  HeapMeta* meta = H.meta;
+  lds_t<Ent>* C = bufs[0];
+  for (;;) {
+    const u64 l = 2ull * c, r = l + 1;
+    lds_t<Ent>* Lb = bufs[1];
+    lds_t<Ent>* Rb = bufs[2];
+    if (!loaded) {
+      const bool el = node_exists(l, m2), er = node_exists(r, m2);
       if (tid < 64) {
-        const bool next_is_path = child != t;
-        u64* w = (tid == 0) ? tlock : lock_ptr(H, child);
-        const u32 mode = (tid == 0) ? (u32)LM_PEEK : (u32)LM_PATH;
-        // the next path node was tried when this node was loaded
-        const bool active = tid == 0 || (tid == 1 && next_is_path && !sh.early);
-        int r = 0;
-        const bool ok = lock_lanes(w, mode, ticket, active, r, ctl);
+        const bool mine = (tid == 0 && el) || (tid == 1 && er);
+        int got = 0;
+        bool need = false;
+        if (mine) {
+          if (!early) need = true;
+          else if (eoc == 0) got = 1;
+          else if (child_view(eoc, ticket) == 0) got = 0;
+          else need = true;
+        }
+        u64* w = need ? lock_ptr(H, (u32)(tid == 0 ? l : r)) : nullptr;
+        bool ok = true;
+        if (__any(need)) {
+          int r2 = 0;
+          ok = lock_lanes(w, LM_CHILD, ticket, need, r2, ctl);
+          if (need) got = r2;
+        }
         const bool allok = __all(ok);
         if (tid == 0) {
-          sh.flag0 = r == 1 ? 1u : 0u;   // MARKED seen
+          sh.flag0 = got > 0 ? 1u : 0u;
           sh.ok = allok ? 1u : 0u;
         }
+        if (tid == 1) sh.flag1 = got > 0 ? 1u : 0u;
       }
       __syncthreads();
       if (!sh.ok) { res.ok = false; return res; }
-      if (sh.flag0) {
-        // cooperation: leave the batch in the target slot for the deleteMin
-        store_node<K, T, Ent>(node_ptr<K, Ent>(H, t), F);
-        publish();
-        if (tid == 0) {
-          if (child != t) unlock(lock_ptr(H, child));
-          unlock(lock_ptr(H, cur));
-          st_relaxed(tlock, lockword(ST_HANDED, ticket));
-        }
-        res.levels = level;
-        res.flags |= F_HANDOFF;
-        return res;
+      hl = sh.flag0;
+      hr = sh.flag1;
+      {
+        NodeRegs<K, T, Ent> lc, rc;
+        if (hl) lc.load(node_ptr<K, Ent>(H, (u32)l));
+        if (hr) rc.load(node_ptr<K, Ent>(H, (u32)r));
+        if (hl) lc.store(Lb);
+        if (hr) rc.store(Rb);
       }
+      __syncthreads();
     }
-    publish();
-    if (at_root) GH_TRACE(4);
-    if (tid == 0) {
-      if (at_root) release_root_at<Stamp>(meta, ticket, m2, rest, sh);
-      else unlock(lock_ptr(H, cur));
-    }
-    if (child == t) break;
-    cur = child;
-    {
-      // the next path node, in the same round trip a look at the target (a
-      // deleteMin that claimed it gets the carry now, before this level's
-      // merge: the carry has not entered this subtree yet) and a first try
-      // at the lock of the node after it (cur is held: parent before child)
-      const u32 nxt = t >> (L - level - 1);
-      NodeRegs<K, T, Ent> nr;
-      nr.load(node_ptr<K, Ent>(H, cur));
-      u64 tw = 0, eo = 1;
-      if (tid == 0) tw = ld_relaxed(tlock);
-      if (tid == 1 && nxt != t) eo = cas_old(lock_ptr(H, nxt), 0, lockword(ST_INUSE, ticket));
-      nr.store(N);
-      if (tid == 0) sh.flag0 = lw_state(tw) == ST_MARKED ? 1u : 0u;
-      if (tid == 1) sh.early = eo == 0 ? 1u : 0u;
-    }
-    __syncthreads();
-    if (sh.flag0) {
-      store_node<K, T, Ent>(node_ptr<K, Ent>(H, t), F);
+    loaded = false;
+    const Ent lmin = hl ? (Ent)Lb[0] : ent_max<Ent>();
+    const Ent rmin = hr ? (Ent)Rb[0] : ent_max<Ent>();
+    const Ent cmin = ent_lt(lmin, rmin) ? lmin : rmin;
+    Ent* cptr = node_ptr<K, Ent>(H, c);
+
+    if (ent_le(C[K - 1], cmin)) {
+      // the property holds: place cur and stop (early stop, Sec. 4.3)
+      store_node<K, T, Ent>(cptr, C);
       publish();
       if (tid == 0) {
-        if (sh.early) unlock(lock_ptr(H, t >> (L - level - 1)));
-        unlock(lock_ptr(H, cur));
-        st_relaxed(tlock, lockword(ST_HANDED, ticket));
+        if (hl) unlock(lock_ptr(H, (u32)l));
+        if (hr) unlock(lock_ptr(H, (u32)r));
+        if (c == 1) release_root_at<Stamp>(meta, ticket, m2, s2, sh);
+        else unlock(lock_ptr(H, c));
       }
-      res.levels = level;
-      res.flags |= F_HANDOFF;
       return res;
     }
-  }
-  // fill the target
-  store_node<K, T, Ent>(node_ptr<K, Ent>(H, t), F);
-  publish();
-  if (tid == 0) {
-    if (!cas_relaxed(tlock, lockword(ST_TARGET, ticket), lockword(ST_AVAIL, 0))) {
-      // MARKED by a deleteMin: the batch is already in the target slot
-      st_relaxed(tlock, lockword(ST_HANDED, ticket));
-      sh.flag1 = 1;
+
+    u32 next;
+    lds_t<Ent>* newcur;
+    if (hl && hr) {
+      // (hi, lo) = MergeAndSort(l, r); lo stays in the child whose max was
+      // larger (on a tie the right child counts as larger), hi merges with
+      // cur; cur's k smallest stay here
+      const bool big_is_l = ent_lt(Rb[K - 1], Lb[K - 1]);
+      const u32 big = big_is_l ? (u32)l : (u32)r;
+      const u32 small = big_is_l ? (u32)r : (u32)l;
+      early = true;
+      if (tid < 2) {
+        const u64 g = 2ull * small + tid;
+        eoc = node_exists(g, m2) ? cas_old(lock_ptr(H, (u32)g), 0, lockword(ST_INUSE, ticket))
+                                 : ~0ull;
+      }
+      lds_t<Ent>* Bg = big_is_l ? Lb : Rb;
+      lds_t<Ent>* Sm = big_is_l ? Rb : Lb;
+      lds_t<Ent>* hi;
+      lds_t<Ent>* freeb;
+      if (ent_le(Sm[K - 1], Bg[0])) {
+        hi = Sm;             // lo is the big child's batch, already in place
+        freeb = bufs[3];
+      } else {
+        merge_split<E, T>(Lb, K, Rb, K, K, sink(bufs[3]), HeapSink<Ent>(node_ptr<K, Ent>(H, big), K * sizeof(Ent)));
+        __syncthreads();
+        hi = bufs[3];
+        freeb = Lb;
+      }
+      if (ent_le(hi[K - 1], C[0])) {
+        store_node<K, T, Ent>(cptr, hi);
+        newcur = C;
+      } else {
+        merge_split<E, T>(C, K, hi, K, K, HeapSink<Ent>(cptr, K * sizeof(Ent)), sink(freeb));
+        __syncthreads();
+        newcur = freeb;
+      }
+      if (c == 1) GH_TRACE(6);
+      publish();
+      if (c == 1) GH_TRACE(7);
+      if (tid == 0) {
+        unlock(lock_ptr(H, big));
+        if (c == 1) release_root_at<Stamp>(meta, ticket, m2, s2, sh);
+        else unlock(lock_ptr(H, c));
+      }
+      next = small;
     } else {
-      sh.flag1 = 0;
+      // one live child x
+      const u32 x = hl ? (u32)l : (u32)r;
+      lds_t<Ent>* X = hl ? Lb : Rb;
+      early = true;
+      if (tid < 2) {
+        const u64 g = 2ull * x + tid;
+        eoc = node_exists(g, m2) ? cas_old(lock_ptr(H, (u32)g), 0, lockword(ST_INUSE, ticket))
+                                 : ~0ull;
+      }
+      lds_t<Ent>* freeb = bufs[3];
+      if (ent_le(X[K - 1], C[0])) {
+        store_node<K, T, Ent>(cptr, X);
+        newcur = C;
+      } else {
+        merge_split<E, T>(C, K, X, K, K, HeapSink<Ent>(cptr, K * sizeof(Ent)), sink(freeb));
+        __syncthreads();
+        newcur = freeb;
+      }
+      publish();
+      if (tid == 0) {
+        if (c == 1) release_root_at<Stamp>(meta, ticket, m2, s2, sh);
+        else unlock(lock_ptr(H, c));
+      }
+      next = x;
     }
+    ++res.levels;
+    // rotate buffers: newcur becomes C, the other three are free (in
+    // their old order; newcur is one of the four)
+    {
+      lds_t<Ent>* const a0 = bufs[0];
+      lds_t<Ent>* const a1 = bufs[1];
+      lds_t<Ent>* const a2 = bufs[2];
+      lds_t<Ent>* const a3 = bufs[3];
+      const bool n0 = newcur == a0, n1 = newcur == a1, n2 = newcur == a2;
+      bufs[0] = newcur;
+      bufs[1] = n0 ? a1 : a0;
+      bufs[2] = (n0 || n1) ? a2 : a1;
+      bufs[3] = (n0 || n1 || n2) ? a3 : a2;
+      C = bufs[0];
+    }
+    c = next;
   }
-  __syncthreads();
-  if (sh.flag1) res.flags |= F_HANDOFF;
-  res.levels = L;
-  return res;
 }
 
 // ---------------------------------------------------------------------------
@@ -734,161 +926,9 @@ __device__ __forceinline__ OpResult op_delete(const HeapDesc& H, u64 ticket,
   }
 
   // sift down; after a refill the root level's children are already locked
-  // and loaded.  While a level merges, lanes 0 and 1 make a first try at the
-  // locks of the next node's children (the next node is held), kept in eoc.
-  u32 c = 1;
-  u64 eoc = ~0ull;
-  bool early = false;
-  for (;;) {
-    const u64 l = 2ull * c, r = l + 1;
-    lds_t<Ent>* Lb = bufs[1];
-    lds_t<Ent>* Rb = bufs[2];
-    if (!loaded) {
-      const bool el = node_exists(l, m2), er = node_exists(r, m2);
-      if (tid < 64) {
-        const bool mine = (tid == 0 && el) || (tid == 1 && er);
-        int got = 0;
-        bool need = false;
-        if (mine) {
-          if (!early) need = true;
-          else if (eoc == 0) got = 1;
-          else if (child_view(eoc, ticket) == 0) got = 0;
-          else need = true;
-        }
-        u64* w = need ? lock_ptr(H, (u32)(tid == 0 ? l : r)) : nullptr;
-        bool ok = true;
-        if (__any(need)) {
-          int r2 = 0;
-          ok = lock_lanes(w, LM_CHILD, ticket, need, r2, ctl);
-          if (need) got = r2;
-        }
-        const bool allok = __all(ok);
-        if (tid == 0) {
-          sh.flag0 = got > 0 ? 1u : 0u;
-          sh.ok = allok ? 1u : 0u;
-        }
-        if (tid == 1) sh.flag1 = got > 0 ? 1u : 0u;
-      }
-      __syncthreads();
-      if (!sh.ok) { res.ok = false; return res; }
-      hl = sh.flag0;
-      hr = sh.flag1;
-      {
-        NodeRegs<K, T, Ent> lc, rc;
-        if (hl) lc.load(node_ptr<K, Ent>(H, (u32)l));
-        if (hr) rc.load(node_ptr<K, Ent>(H, (u32)r));
-        if (hl) lc.store(Lb);
-        if (hr) rc.store(Rb);
-      }
-      __syncthreads();
-    }
-    loaded = false;
-    const Ent lmin = hl ? (Ent)Lb[0] : ent_max<Ent>();
-    const Ent rmin = hr ? (Ent)Rb[0] : ent_max<Ent>();
-    const Ent cmin = ent_lt(lmin, rmin) ? lmin : rmin;
-    Ent* cptr = node_ptr<K, Ent>(H, c);
-
-    if (ent_le(C[K - 1], cmin)) {
-      // the property holds: place cur and stop (early stop, Sec. 4.3)
-      store_node<K, T, Ent>(cptr, C);
-      publish();
-      if (tid == 0) {
-        if (hl) unlock(lock_ptr(H, (u32)l));
-        if (hr) unlock(lock_ptr(H, (u32)r));
-        if (c == 1) release_root_at<Stamp>(meta, ticket, m2, s2, sh);
-        else unlock(lock_ptr(H, c));
-      }
-      return res;
-    }
-
-    u32 next;
-    lds_t<Ent>* newcur;
-    if (hl && hr) {
-      // (hi, lo) = MergeAndSort(l, r); lo stays in the child whose max was
-      // larger (on a tie the right child counts as larger), hi merges with
-      // cur; cur's k smallest stay here
-      const bool big_is_l = ent_lt(Rb[K - 1], Lb[K - 1]);
-      const u32 big = big_is_l ? (u32)l : (u32)r;
-      const u32 small = big_is_l ? (u32)r : (u32)l;
-      early = true;
-      if (tid < 2) {
-        const u64 g = 2ull * small + tid;
-        eoc = node_exists(g, m2) ? cas_old(lock_ptr(H, (u32)g), 0, lockword(ST_INUSE, ticket))
-                                 : ~0ull;
-      }
-      lds_t<Ent>* Bg = big_is_l ? Lb : Rb;
-      lds_t<Ent>* Sm = big_is_l ? Rb : Lb;
-      lds_t<Ent>* hi;
-      lds_t<Ent>* freeb;
-      if (ent_le(Sm[K - 1], Bg[0])) {
-        hi = Sm;             // lo is the big child's batch, already in place
-        freeb = bufs[3];
-      } else {
-        merge_split<E, T>(Lb, K, Rb, K, K, sink(bufs[3]), HeapSink<Ent>(node_ptr<K, Ent>(H, big), K * sizeof(Ent)));
-        __syncthreads();
-        hi = bufs[3];
-        freeb = Lb;
-      }
-      if (ent_le(hi[K - 1], C[0])) {
-        store_node<K, T, Ent>(cptr, hi);
-        newcur = C;
-      } else {
-        merge_split<E, T>(C, K, hi, K, K, HeapSink<Ent>(cptr, K * sizeof(Ent)), sink(freeb));
-        __syncthreads();
-        newcur = freeb;
-      }
-      if (c == 1) GH_TRACE(6);
-      publish();
-      if (c == 1) GH_TRACE(7);
-      if (tid == 0) {
-        unlock(lock_ptr(H, big));
-        if (c == 1) release_root_at<Stamp>(meta, ticket, m2, s2, sh);
-        else unlock(lock_ptr(H, c));
-      }
-      next = small;
-    } else {
-      // one live child x
-      const u32 x = hl ? (u32)l : (u32)r;
-      lds_t<Ent>* X = hl ? Lb : Rb;
-      early = true;
-      if (tid < 2) {
-        const u64 g = 2ull * x + tid;
-        eoc = node_exists(g, m2) ? cas_old(lock_ptr(H, (u32)g), 0, lockword(ST_INUSE, ticket))
-                                 : ~0ull;
-      }
-      lds_t<Ent>* freeb = bufs[3];
-      if (ent_le(X[K - 1], C[0])) {
-        store_node<K, T, Ent>(cptr, X);
-        newcur = C;
-      } else {
-        merge_split<E, T>(C, K, X, K, K, HeapSink<Ent>(cptr, K * sizeof(Ent)), sink(freeb));
-        __syncthreads();
-        newcur = freeb;
-      }
-      publish();
-      if (tid == 0) {
-        if (c == 1) release_root_at<Stamp>(meta, ticket, m2, s2, sh);
-        else unlock(lock_ptr(H, c));
-      }
-      next = x;
-    }
-    ++res.levels;
-    // rotate buffers: newcur becomes C, the other three are free (in
-    // their old order; newcur is one of the four)
-    {
-      lds_t<Ent>* const a0 = bufs[0];
-      lds_t<Ent>* const a1 = bufs[1];
-      lds_t<Ent>* const a2 = bufs[2];
-      lds_t<Ent>* const a3 = bufs[3];
-      const bool n0 = newcur == a0, n1 = newcur == a1, n2 = newcur == a2;
-      bufs[0] = newcur;
-      bufs[1] = n0 ? a1 : a0;
-      bufs[2] = (n0 || n1) ? a2 : a1;
-      bufs[3] = (n0 || n1 || n2) ? a3 : a2;
-      C = bufs[0];
-    }
-    c = next;
-  }
+  // and loaded
+  return del_sift<K, T, Ent, Stamp>(H, ticket, 1, loaded, hl, hr, false, ~0ull, bufs, m2, s2, sh,
+                                    ctl, res);
 }
 
 }  // namespace gh
