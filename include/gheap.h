@@ -203,6 +203,16 @@ typedef struct gh_reqrec {
  * returns); deleteMins run in other submissions.  Log records: levels =
  * merges of the climb; flags bit 5 = the climb stopped below the root. */
 #define GH_TUNE_BOTTOM_UP 4u
+/* GH_TUNE_SHARED_ROOT: a submission of whole-root operations (no other
+ * flag) launched with one workgroup runs the per-operation root protocol
+ * (ticket and node locks) like any other launch.  Without the flag such a
+ * submission runs with one operation in flight and no locks: each heap's root
+ * and partial buffer stay in the workgroup's LDS while its operations run,
+ * in list order, and its nodes are reached with caching loads and stores.
+ * The results and the heap layout are the same; a record whose seq is not
+ * its heap's next (one workgroup takes the root in list order) is refused
+ * (GH_EINVAL) instead of waiting. */
+#define GH_TUNE_SHARED_ROOT 8u
 typedef struct gh_tuning {
     uint32_t workgroups;
     uint32_t threads;

@@ -2,8 +2,8 @@
 
 Usage: python -m paper_1906_06504_amd.build [--trace]   (or call build()).
 Each supported node capacity k and entry width (8 or 16 bytes) gets its own
-objects of gh_kernels.hip, gh_serve.hip and gh_bu.hip, so they compile in
-parallel.
+objects of gh_kernels.hip, gh_serve.hip, gh_bu.hip and gh_private.hip, so they
+compile in parallel.
 """
 from __future__ import annotations
 
@@ -50,7 +50,7 @@ def build(jobs: int | None = None, verbose: bool = False, trace: bool = False) -
     tasks = []
     for k in KS:
         for eb in (8, 16):
-            for name in ("gh_kernels", "gh_serve", "gh_bu"):
+            for name in ("gh_kernels", "gh_serve", "gh_bu", "gh_private"):
                 obj = os.path.join(build_dir, "%s_k%d_e%d.o" % (name, k, eb))
                 tasks.append([HIPCC] + flags + ["-DGH_K=%d" % k, "-DGH_ENT_BYTES=%d" % eb, "-c",
                                                 os.path.join(CSRC, name + ".hip"), "-o", obj])

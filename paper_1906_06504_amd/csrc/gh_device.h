@@ -209,12 +209,15 @@ __device__ __forceinline__ void publish() {
 // region (a node or the partial buffer) whose base is the same in every
 // lane; offsets are per lane, in bytes.
 constexpr int CP_DEVICE = 16;   // cache-policy operand: device scope (sc1)
+constexpr int CP_LOCAL = 0;     // cached; coherent within one workgroup (a
+                                // heap that only that workgroup touches)
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
-struct HeapRegion {
+template <int CP = CP_DEVICE>
+struct HeapRegionT {
   __amdgpu_buffer_rsrc_t r;
-  __device__ __forceinline__ HeapRegion(const u64* base, u32 bytes) {
+  __device__ __forceinline__ HeapRegionT(const u64* base, u32 bytes) {
     const u64 a = reinterpret_cast<u64>(base);
     const u32 lo = __builtin_amdgcn_readfirstlane((u32)a);
     const u32 hi = __builtin_amdgcn_readfirstlane((u32)(a >> 32));
@@ -222,14 +225,14 @@ struct HeapRegion {
                                           bytes, 0x00020000);
   }
   __device__ __forceinline__ ulonglong2 load16(u32 off) const {
-    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, CP_DEVICE);
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, CP);
     ulonglong2 o;
     o.x = (u64)v.x | ((u64)v.y << 32);
     o.y = (u64)v.z | ((u64)v.w << 32);
     return o;
   }
   __device__ __forceinline__ u64 load8(u32 off) const {
-    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, CP_DEVICE);
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, CP);
     return (u64)v.x | ((u64)v.y << 32);
   }
   __device__ __forceinline__ void store16(u32 off, u64 a, u64 b) const {
@@ -238,13 +241,13 @@ struct HeapRegion {
     v.y = (u32)(a >> 32);
     v.z = (u32)b;
     v.w = (u32)(b >> 32);
-    __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, CP_DEVICE);
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, CP);
   }
   __device__ __forceinline__ void store8(u32 off, u64 a) const {
     u32x2 v;
     v.x = (u32)a;
     v.y = (u32)(a >> 32);
-    __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, CP_DEVICE);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, CP);
   }
   // one entry at byte offset off
   __device__ __forceinline__ void load_ent(u32 off, u64& e) const { e = load8(off); }
@@ -256,6 +259,7 @@ struct HeapRegion {
   __device__ __forceinline__ void store_ent(u32 off, u64 e) const { store8(off, e); }
   __device__ __forceinline__ void store_ent(u32 off, e128 e) const { store16(off, e.x, e.y); }
 };
+typedef HeapRegionT<CP_DEVICE> HeapRegion;
 
 __device__ __forceinline__ u64 now_ticks() { return wall_clock64(); }
 
@@ -338,10 +342,10 @@ __device__ __forceinline__ u64* lock_ptr(const HeapDesc& H, u32 c) {
 // Coalesced node transfers between heap memory and LDS (16 bytes a lane:
 // two 8-byte entries or one 16-byte entry).
 // ---------------------------------------------------------------------------
-template <int K, int T, class Ent = u64>
+template <int K, int T, class Ent = u64, int CP = CP_DEVICE>
 __device__ __forceinline__ void store_node(Ent* g, const lds_t<Ent>* __restrict__ lds) {
   constexpr int CH = K * (int)sizeof(Ent) / 16;   // 16-byte chunks per node
-  const HeapRegion R(reinterpret_cast<const u64*>(g), K * sizeof(Ent));
+  const HeapRegionT<CP> R(reinterpret_cast<const u64*>(g), K * sizeof(Ent));
   const lu64x2* l = reinterpret_cast<const lu64x2*>(lds);
   for (int c = threadIdx.x; c < CH; c += T) {
     const u64x2 v = l[c];
@@ -350,13 +354,13 @@ __device__ __forceinline__ void store_node(Ent* g, const lds_t<Ent>* __restrict_
 }
 // A node's share per thread held in registers, so that several node loads
 // (and lock atomics) can be in flight before anything is written to LDS.
-template <int K, int T, class Ent = u64>
+template <int K, int T, class Ent = u64, int CP = CP_DEVICE>
 struct NodeRegs {
   static constexpr int CH = K * (int)sizeof(Ent) / 16;   // 16-byte chunks per node
   static constexpr int C = (CH + T - 1) / T;             // chunks per thread
   ulonglong2 v[C];
   __device__ __forceinline__ void load(const Ent* g) {
-    const HeapRegion R(reinterpret_cast<const u64*>(g), K * sizeof(Ent));
+    const HeapRegionT<CP> R(reinterpret_cast<const u64*>(g), K * sizeof(Ent));
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int i = threadIdx.x + c * T;
@@ -491,9 +495,9 @@ template <class Ent>
 __device__ __forceinline__ Sink<Ent> sink(lds_t<Ent>* p) {
   return Sink<Ent>{p};
 }
-template <class Ent = u64>
+template <class Ent = u64, int CP = CP_DEVICE>
 struct HeapSink {
-  HeapRegion R;
+  HeapRegionT<CP> R;
   __device__ __forceinline__ HeapSink(Ent* p, u32 bytes)
       : R(reinterpret_cast<const u64*>(p), bytes) {}
   __device__ __forceinline__ void put1(int off, Ent x) const { R.store_ent(off * sizeof(Ent), x); }

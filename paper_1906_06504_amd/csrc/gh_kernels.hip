@@ -5,6 +5,7 @@
 // object exports gh::launch_ops_k<k, Ent>() and gh::launch_knap_k<k, Ent>(),
 // the 8-byte objects also gh::launch_sssp_k<k>().
 #include "gh_kops.h"
+#include "gh_private.h"
 
 #ifndef GH_K
 #error "compile with -DGH_K=<node capacity>"
@@ -89,7 +90,6 @@ struct KnapShared {
   u64 hsize;            // entries in the heap
   u64 gc_best;          // incumbent at the last garbage collection
   u64 gc_dropped;       // entries the collections removed
-  u64 gm, gs;           // heap shape seen by a collection
   u64 alg_bytes;        // algorithmic bytes of the instance's heap operations
   u32 gdead;            // nodes found dead by a collection
   u32 gkept;            // entries of a drained batch below the cut
@@ -131,28 +131,24 @@ __device__ __forceinline__ u64 kn_bound(const KnapShared& ks, u32 level, u64 V, 
 // hold at least a quarter of the heap, and when the staged batches fit the
 // heap's free slots.  Returns false after a failed heap operation.
 template <int K, int T, class Ent>
-__device__ __forceinline__ bool knap_collect(const HeapDesc& H, u64& ticket, u32& ops, lds_t<Ent>* L,
-                             OpShared& sh, KnapShared& ks, Ctl* ctl) {
+__device__ __forceinline__ bool knap_collect(const HeapDesc& H, PrivState& st, u64& ticket, u32& ops,
+                                             lds_t<Ent>* L, OpShared& sh, KnapShared& ks) {
   typedef KnapKey<Ent> KK;
   const int tid = threadIdx.x;
   const Ent cut = KK::cut(ks.best << 16);
   if (tid == 0) {
-    const u64 w = ld_relaxed(&H.meta->root);   // this workgroup's own last release
-    ks.gm = rw_m(w);
-    ks.gs = rw_s(w);
     ks.gdead = 0;
     ks.gc_best = ks.best;
   }
-  __syncthreads();
-  const u64 m = ks.gm;
+  const u64 m = st.m;
+  publish();   // the earlier operations' node stores are complete
+  const lds_t<Ent>* root = priv_pair<K, Ent>(L, st.pq);
   for (u64 p = tid + 1; p <= m; p += T) {
-    Ent e;
-    const HeapRegion R(reinterpret_cast<const u64*>(slot_ptr<K, Ent>(H, p)), sizeof(Ent));
-    R.load_ent(0, e);
+    const Ent e = p == 1 ? (Ent)root[0] : gptr(slot_ptr<K, Ent>(H, p))[0];
     if (!ent_lt(e, cut)) atomicAdd(&ks.gdead, 1u);
   }
   __syncthreads();
-  const u64 total = m * K + ks.gs;
+  const u64 total = m * K + st.s;
   const u64 dead_nodes = ks.gdead;
   // the drain writes at most ceil(kept / K) + 1 batches, kept <= total - dead_nodes * K
   if (dead_nodes == 0 || 4 * dead_nodes * K < total || m + (m - dead_nodes) + 2 > H.max_nodes)
@@ -160,9 +156,9 @@ __device__ __forceinline__ bool knap_collect(const HeapDesc& H, u64& ticket, u32
   Ent* stage = slot_ptr<K, Ent>(H, m + 1);
   u64 staged = 0;
   for (;;) {
-    const OpResult r = op_delete<K, T, Ent>(H, ticket++, stage + staged, (u32)K, L, sh, ctl);
+    const OpResult r = priv_delete<K, T, Ent>(H, L, st, stage + staged, sh);
+    ++ticket;
     ++ops;
-    if (!r.ok) return false;
     if (tid == 0) {
       ks.gkept = 0;
       ks.alg_bytes += op_alg_bytes<K, Ent>(1, r, sh.s);
@@ -178,12 +174,12 @@ __device__ __forceinline__ bool knap_collect(const HeapDesc& H, u64& ticket, u32
     staged += kept;
     if (kept < r.count) break;
   }
-  const OpResult rd = op_discard(H, ticket++, sh, ctl);
+  priv_discard(st);
+  ++ticket;
   ++ops;
-  if (!rd.ok) return false;
-  const OpResult rb = op_build_from<K, T, Ent>(H, ticket++, stage, staged, sh, ctl);
+  priv_build_from<K, T, Ent>(H, L, st, stage, staged);
+  ++ticket;
   ++ops;
-  if (!rb.ok) return false;
   if (tid == 0) {
     ks.gc_dropped += ks.hsize - staged;
     ks.hsize = staged;
@@ -205,7 +201,7 @@ __global__ __launch_bounds__(T) void k_knap(const HeapDesc* __restrict__ descs, 
                                             gh_knapres* __restrict__ res, u32 gc_min,
                                             Ctl* __restrict__ ctl) {
   typedef KnapKey<Ent> KK;
-  __shared__ __align__(16) Ent lds[5 * K];
+  __shared__ __align__(16) Ent lds[8 * K];
   lds_t<Ent>* const L = (lds_t<Ent>*)lds;
   __shared__ OpShared sh;
   __shared__ KnapShared ks;
@@ -291,29 +287,32 @@ __global__ __launch_bounds__(T) void k_knap(const HeapDesc* __restrict__ descs, 
     __syncthreads();
     u32 ops = 0;
     bool ok = true;
+    // the instance's heap is this workgroup's alone: it runs without locks,
+    // root and partial buffer in LDS (gh_private.h)
+    PrivState st;
+    priv_begin<K, T, Ent>(H, L, st, sh);
     for (;;) {
-      // push this round's children (at most 2K: two inserts)
+      // push this round's children (at most 2K: two inserts of K sorted
+      // entries)
       const u32 c = ks.cnt;
       for (u32 j = 0; j < c; j += K) {
         const u32 nn = c - j < (u32)K ? c - j : (u32)K;
-        OpResult r = op_insert<K, T, Ent>(H, ticket++, kids + j, nn, L, sh, ctl);
+        load_n<T>(L + 4 * K, kids + j, nn);
+        const lds_t<Ent>* xs = block_sort<K, T, Ent>(L + 4 * K, L + 5 * K, (int)nn);
+        OpResult r = priv_insert<K, T, Ent>(H, L, st, xs, nn, sh, ctl);
+        ++ticket;
         ++ops;
         if (tid == 0) {
           if (!(r.flags & F_REJECT)) ks.hsize += nn;
           ks.alg_bytes += op_alg_bytes<K, Ent>(0, r, sh.s);
         }
-        if (!r.ok) {
-          ok = false;
-          break;
-        }
         __syncthreads();
       }
-      if (!ok) break;
-      if (gc_min != 0 && ks.hsize >= gc_min && ks.gc_best != ks.best &&
-          !knap_collect<K, T, Ent>(H, ticket, ops, L, sh, ks, ctl))
-        break;
+      if (gc_min != 0 && ks.hsize >= gc_min && ks.gc_best != ks.best)
+        knap_collect<K, T, Ent>(H, st, ticket, ops, L, sh, ks);
       // take the most promising nodes
-      OpResult r = op_delete<K, T, Ent>(H, ticket++, out, (u32)K, L, sh, ctl);
+      OpResult r = priv_delete<K, T, Ent>(H, L, st, out, sh);
+      ++ticket;
       ++ops;
       if (tid == 0) {
         ks.popped_total += r.count;
@@ -326,7 +325,8 @@ __global__ __launch_bounds__(T) void k_knap(const HeapDesc* __restrict__ descs, 
       // bound left in the heap; if it cannot beat the incumbent, nothing
       // left can, and the rest of the heap is dropped unread
       if (KK::bound(out[0]) <= (ks.best << 16)) {
-        op_discard(H, ticket++, sh, ctl);
+        priv_discard(st);
+        ++ticket;
         ++ops;
         break;
       }
@@ -393,6 +393,8 @@ __global__ __launch_bounds__(T) void k_knap(const HeapDesc* __restrict__ descs, 
       // pool writes are read back by other threads after later barriers
       __syncthreads();
     }
+    // the heap's state back to its memory (empty after the last operation)
+    priv_end<K, T, Ent>(H, L, st, ticket);
     if (tid == 0) {
       gh_knapres o;
       o.best = ks.best;

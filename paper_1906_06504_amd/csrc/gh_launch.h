@@ -33,7 +33,8 @@ struct LaunchArgs {
   u32 threads;
   u32 form;         // 0: whole-root kernel; 1: general kernel (deleteMins of
                     // fewer than K entries, inserts of more than K entries);
-                    // 2: bottom-up inserts
+                    // 2: bottom-up inserts; 3: whole-root operations run by
+                    // one workgroup without locks (gh_private.hip)
   hipStream_t stream;
 };
 
@@ -62,6 +63,9 @@ hipError_t launch_ops_var_k(const LaunchArgs& a);
 // the operation loop with bottom-up inserts (gh_bu.hip)
 template <int K, class Ent>
 hipError_t launch_ops_bu_k(const LaunchArgs& a);
+// the one-workgroup operation loop (gh_private.hip)
+template <int K, class Ent>
+hipError_t launch_private_k(const LaunchArgs& a);
 // tracing build only (GH_PHASE_TRACE): the whole-root kernels' phase trace
 // (gh_kernels.hip): zero it (host == nullptr) or copy `words` words out
 template <int K, class Ent>

@@ -65,6 +65,7 @@ struct OpShared {
   u32 ok;
   u32 op;
   u32 early;           // an insert's next path node was taken by an early try
+  u64 word;            // a root word read by thread 0 for everyone
 };
 
 struct OpResult {

@@ -167,8 +167,12 @@ struct KnapF {
 template <int K, class Ent>
 struct OpsF {
   static hipError_t run(const LaunchArgs& a) {
-    return a.form == 2 ? launch_ops_bu_k<K, Ent>(a)
-                       : (a.form == 1 ? launch_ops_var_k<K, Ent>(a) : launch_ops_k<K, Ent>(a));
+    switch (a.form) {
+      case 1: return launch_ops_var_k<K, Ent>(a);
+      case 2: return launch_ops_bu_k<K, Ent>(a);
+      case 3: return launch_private_k<K, Ent>(a);
+      default: return launch_ops_k<K, Ent>(a);
+    }
   }
 };
 
@@ -263,6 +267,9 @@ int run_ops(gh_heap* h, const gh_op* d_ops, u32 nops, const OpParams& p, const v
   a.form = (fl & GH_TUNE_BOTTOM_UP) ? 2u
                                     : ((fl & (GH_TUNE_VARIABLE_DELETE | GH_TUNE_MULTI_INSERT)) ? 1u
                                                                                               : 0u);
+  // one workgroup, whole-root operations: one operation in flight, so the
+  // heaps are private to it and run without locks
+  if (a.form == 0 && wg == 1 && !(fl & GH_TUNE_SHARED_ROOT)) a.form = 3;
   a.stream = h->stream;
   if (launch_ops(h, a) != hipSuccess) return GH_EDEVICE;
   return GH_OK;

@@ -86,6 +86,7 @@ _lib = None
 GH_TUNE_VARIABLE_DELETE = 1
 GH_TUNE_MULTI_INSERT = 2
 GH_TUNE_BOTTOM_UP = 4
+GH_TUNE_SHARED_ROOT = 8
 
 
 class _Tuning(ctypes.Structure):
@@ -146,10 +147,12 @@ def load_library(path: str = LIB_PATH):
     return lib
 
 
-def _tune_flags(var_delete: bool, multi_insert: bool, bottom_up: bool = False) -> int:
+def _tune_flags(var_delete: bool, multi_insert: bool, bottom_up: bool = False,
+                shared_root: bool = False) -> int:
     return ((GH_TUNE_VARIABLE_DELETE if var_delete else 0) |
             (GH_TUNE_MULTI_INSERT if multi_insert else 0) |
-            (GH_TUNE_BOTTOM_UP if bottom_up else 0))
+            (GH_TUNE_BOTTOM_UP if bottom_up else 0) |
+            (GH_TUNE_SHARED_ROOT if shared_root else 0))
 
 
 def insert_max(k: int) -> int:
@@ -285,13 +288,17 @@ class HeapSet:
     def submit(self, ops: torch.Tensor, nops: int, d_in: torch.Tensor | None,
                d_out: torch.Tensor | None, counts: torch.Tensor | None = None,
                log: torch.Tensor | None = None, workgroups: int = 0, threads: int = 0,
-               var_delete: bool = False, multi_insert: bool = False, bottom_up: bool = False):
+               var_delete: bool = False, multi_insert: bool = False, bottom_up: bool = False,
+               shared_root: bool = False):
         """Run the op records on the set's stream.  var_delete: the records
         may hold deleteMins of fewer than k entries (n in 1..k-1);
         multi_insert: inserts of more than k entries (up to insert_max(k));
         bottom_up: every record is an insert of up to k entries, run
-        bottom-up (GH_TUNE_BOTTOM_UP)."""
-        t = _Tuning(workgroups, threads, _tune_flags(var_delete, multi_insert, bottom_up))
+        bottom-up (GH_TUNE_BOTTOM_UP); shared_root: with one workgroup, the
+        per-operation root protocol instead of the lock-free one-workgroup
+        loop (GH_TUNE_SHARED_ROOT)."""
+        t = _Tuning(workgroups, threads,
+                    _tune_flags(var_delete, multi_insert, bottom_up, shared_root))
         rc = self.lib.heap_submit(self.h, *self._op_ptrs(ops, nops, d_in, d_out, counts, log),
                                   ctypes.byref(t))
         _check(rc, "heap_submit")

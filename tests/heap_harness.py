@@ -46,7 +46,7 @@ def _is_filler(row, wide):
 
 
 def run_gpu(oplist, k, max_keys, workgroups=0, threads=0, heapset=None, nheaps=1,
-            bottom_up=False):
+            bottom_up=False, shared_root=False):
     """Submit `oplist` on a fresh heap set (or `heapset`); returns
     (heapset, out, counts[uint32], log records), out as uint64 ([n, 2] for
     16-byte entries).  Lists holding deleteMins of fewer than k entries or
@@ -62,7 +62,7 @@ def run_gpu(oplist, k, max_keys, workgroups=0, threads=0, heapset=None, nheaps=1
     var = bool(np.any(dels & (oplist.n != 0) & (oplist.n != k)))
     multi = bool(np.any((oplist.kind == W.OP_INSERT) & (oplist.n > k)))
     hs.submit(ops, n, keys, out, counts, log, workgroups=workgroups, threads=threads,
-              var_delete=var, multi_insert=multi, bottom_up=bottom_up)
+              var_delete=var, multi_insert=multi, bottom_up=bottom_up, shared_root=shared_root)
     rc = hs.sync()
     assert rc == G.GH_OK, G.strerror(rc)
     torch.cuda.synchronize()

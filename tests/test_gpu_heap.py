@@ -77,13 +77,16 @@ def test_readme_example(G):
     assert int(ns["kept"].item()) == int(np.sum(rest < np.uint64(1 << 62)))
 
 
+@pytest.mark.parametrize("shared_root", [False, True])
 @pytest.mark.parametrize("k", [32, 64, 128, 256, 512, 1024])
-def test_serialized_state_equals_oracle(G, k):
-    """One operation in flight: after a mixed trace the GPU node array and
-    partial buffer equal the oracle's exactly (same bit-reversal order)."""
+def test_serialized_state_equals_oracle(G, k, shared_root):
+    """One operation in flight (one workgroup; the lock-free one-workgroup
+    loop, or the per-operation root protocol with shared_root): after a mixed
+    trace the GPU node array and partial buffer equal the oracle's exactly
+    (same bit-reversal order)."""
     ops = W.mixed_ops(60 * k, k, seed=100 + k, first_id=0)
-    _print("serialized k=%d ops=%d" % (k, len(ops)))
-    hs, out, counts, log = run_gpu(ops, k, max_keys=60 * k, workgroups=1)
+    _print("serialized k=%d ops=%d shared_root=%s" % (k, len(ops), shared_root))
+    hs, out, counts, log = run_gpu(ops, k, max_keys=60 * k, workgroups=1, shared_root=shared_root)
     oh = replay_and_compare(ops, k, out, counts, log)
     m, s, byidx, pb = gpu_state_by_index(hs, 0, k)
     assert (m, s) == (oh.m, oh.s)
@@ -216,8 +219,9 @@ def test_repeated_entries_replay(G, k):
     assert hs.close() == G.GH_OK
 
 
+@pytest.mark.parametrize("shared_root", [False, True])
 @pytest.mark.parametrize("k", [64, 1024])
-def test_adversarial_batches_serialized(G, k):
+def test_adversarial_batches_serialized(G, k, shared_root):
     """Serialized inserts of adversarial batches through the C ABI: all-equal
     keys with distinct ids, keys interleaved with the heap's, disjoint above
     and below it, reversed, and a partial batch that straddles the partial
@@ -246,7 +250,8 @@ def test_adversarial_batches_serialized(G, k):
     kinds += [W.OP_DELETE_MIN] * 2
     sizes += [0] * 2
     ops = W.build_oplist(kinds, sizes, lambda c: keys[:c], k)
-    hs, out, counts, log = run_gpu(ops, k, max_keys=keys.size, workgroups=1)
+    hs, out, counts, log = run_gpu(ops, k, max_keys=keys.size, workgroups=1,
+                                   shared_root=shared_root)
     oh = replay_and_compare(ops, k, out, counts, log)
     assert_same_state(hs, 0, oh, k)
     assert hs.close() == G.GH_OK
