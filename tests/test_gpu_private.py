@@ -114,3 +114,23 @@ def test_private_refuses_out_of_order_seq(G):
     live = check_gpu_state(hs, 0, k)
     assert live.size == 2 * k
     assert hs.close() == G.GH_EINVAL
+
+
+def test_private_capacity_overrun_is_sticky(G):
+    """An insert that needs a node beyond max_keys in a one-workgroup
+    submission is rejected (flag 0x40, sticky GH_ENOMEM); the heap keeps the
+    entries before it and satisfies Properties 1-3."""
+    k = 64
+    ops = W.prefill_ops(10 * k, k, seed=5)
+    hs = G.HeapSet(k, [5 * k])
+    d_ops, n, keys, out, counts = G.ops_to_device(ops)
+    lg = G.new_log(n)
+    hs.submit(d_ops, n, keys, out, counts, lg, workgroups=1)
+    assert hs.sync() == G.GH_ENOMEM
+    rec = G.log_to_host(lg, n)
+    rejected = (rec["flags"].astype(np.uint32) & 0x40) != 0
+    took = int(np.argmax(rejected))        # the first rejected insert
+    assert took >= 5 and rejected[took:].all() and not rejected[:took].any()
+    live = check_gpu_state(hs, 0, k)
+    assert np.array_equal(live, np.sort(ops.keys[:took * k]))
+    assert hs.close() == G.GH_ENOMEM
