@@ -136,12 +136,14 @@ __device__ __forceinline__ bool knap_collect(const HeapDesc& H, PrivState& st, u
   typedef KnapKey<Ent> KK;
   const int tid = threadIdx.x;
   const Ent cut = KK::cut(ks.best << 16);
-  if (tid == 0) {
-    ks.gdead = 0;
-    ks.gc_best = ks.best;
-  }
+  if (tid == 0) ks.gdead = 0;
   const u64 m = st.m;
-  publish();   // the earlier operations' node stores are complete
+  // the earlier operations' node stores are complete, and every wave has
+  // evaluated the caller's condition, which reads gc_best: it may change
+  // only after this barrier, or a late wave would skip the collection that
+  // the others run and the waves would meet at each other's barriers
+  publish();
+  if (tid == 0) ks.gc_best = ks.best;
   const lds_t<Ent>* root = priv_pair<K, Ent>(L, st.pq);
   for (u64 p = tid + 1; p <= m; p += T) {
     const Ent e = p == 1 ? (Ent)root[0] : gptr(slot_ptr<K, Ent>(H, p))[0];

@@ -65,6 +65,9 @@ struct OpShared {
   u32 ok;
   u32 op;
   u32 early;           // an insert's next path node was taken by an early try
+  u32 marked;          // an insert's look at its target after a level's merge:
+                       // MARKED (a field of its own: flag0, the look made with
+                       // the node's load, may still be read by a late wave)
   u64 word;            // a root word read by thread 0 for everyone
 };
 
@@ -395,13 +398,13 @@ __device__ __forceinline__ OpResult ins_descend(const HeapDesc& H, u64 ticket, u
       const bool ok = lock_lanes(w, mode, ticket, active, r, ctl);
       const bool allok = __all(ok);
       if (tid == 0) {
-        sh.flag0 = r == 1 ? 1u : 0u;   // MARKED seen
+        sh.marked = r == 1 ? 1u : 0u;   // MARKED seen
         sh.ok = allok ? 1u : 0u;
       }
     }
     __syncthreads();
     if (!sh.ok) { res.ok = false; return res; }
-    if (sh.flag0) {
+    if (sh.marked) {
       // cooperation: leave the batch in the target slot for the deleteMin
       store_node<K, T, Ent>(node_ptr<K, Ent>(H, t), F);
       publish();

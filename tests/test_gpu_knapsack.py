@@ -84,6 +84,26 @@ def test_garbage_collection_keeps_optima(K, keytype, k):
     s.close()
 
 
+@pytest.mark.parametrize("keytype", [0, 1])
+def test_full_batch_with_collection_matches_dp(K, keytype):
+    """The benchmark's batch (512 instances) at its tuned shape, k = 256 with
+    512 threads, collecting from 4096 entries: every optimum equals the DP,
+    twice.  Eight waves a workgroup make a late wave likely; the collection
+    must start only after every wave has decided to run it (a wave that
+    skipped it once met the others at the wrong barriers and lost nodes)."""
+    inst = W.knapsack_instances(512, seed=0x5EED0004)
+    ref = np.array([oracle.knapsack_dp(w, v, c) for (w, v, c) in inst], np.int64)
+    s = K.Solver(len(inst), 256, pool_per_inst=1 << 20, keytype=keytype)
+    d = K.Instances(inst, keytype=keytype)
+    for rep in range(2):
+        res = s.run(d, workgroups=512, threads=512, gc_min=4096)
+        assert np.all(res["flags"] & 1) and not np.any(res["flags"] & 0x60)
+        bad = np.flatnonzero(res["best"].astype(np.int64) != ref)
+        assert bad.size == 0, "run %d: instances %s differ from the DP" % (rep, bad[:8].tolist())
+        assert int(res["gc_runs"].sum()) > 0
+    s.close()
+
+
 def test_values_beyond_the_8_byte_bound(K):
     """Values summing beyond 2^18: the 16-byte entry still finds the DP
     optimum; an 8-byte set refuses the instance on the device (flag bit 5,

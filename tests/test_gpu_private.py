@@ -134,3 +134,32 @@ def test_private_capacity_overrun_is_sticky(G):
     live = check_gpu_state(hs, 0, k)
     assert np.array_equal(live, np.sort(ops.keys[:took * k]))
     assert hs.close() == G.GH_ENOMEM
+
+
+@pytest.mark.parametrize("k,wide,threads", [(64, False, 0), (256, False, 512), (256, True, 512),
+                                           (256, False, 256)])
+def test_private_long_drain_equals_oracle(G, k, wide, threads):
+    """A heap of about 300 nodes built by inserts of random sizes (partial
+    batches fill the partial buffer), then deleteMins back to back until it
+    is empty and past that, in one-workgroup submissions: every output and
+    the final state equal the oracle's.  Long runs of deleteMins with no
+    insert between them are what a collection's drain does."""
+    pre = W.mixed_ops(300 * k, k, seed=95 + k, first_id=0, p_insert=1.0)
+    if wide:
+        pre = W.to_wide(pre, 96, 16)
+    total = int(pre.n.sum())
+    nd = total // k + 3
+    keys = pre.keys
+    drain = W.build_oplist([W.OP_DELETE_MIN] * nd, [0] * nd, lambda c: keys[:c], k)
+    _print("long drain k=%d wide=%d threads=%d inserts=%d entries=%d deleteMins=%d" % (
+        k, wide, threads, len(pre), total, nd))
+    hs, _, _, _ = run_gpu(pre, k, max_keys=total + k, workgroups=1, threads=threads)
+    oh = oracle.OracleHeap(k, wide=wide)
+    oh.replay(pre.kind, pre.n, pre.off, pre.keys, 1)
+    assert_same_state(hs, 0, oh, k)
+    hs, out, counts, log = run_gpu(drain, k, max_keys=total + k, workgroups=1, heapset=hs,
+                                   threads=threads)
+    oh = replay_and_compare(drain, k, out, counts, log, base_ticket=len(pre), oracle_heap=oh)
+    assert_same_state(hs, 0, oh, k)
+    assert oh.m == 0 and oh.s == 0
+    assert hs.close() == G.GH_OK
