@@ -582,7 +582,7 @@ def run_served(args):
             ms, recs = serve_once(rq)
             res = summarize(ms, recs, rq)
             res["offered_requests_per_s"] = rate
-            res["sampled_heaps_replayed_equal"] = check_served(
+            res["every_heap_replayed_equal"] = check_served(
                 pre, rq, recs, G.to_host_u64(serve_once.last_out), k, caps, H)
             out["poisson_%.1fx" % frac] = res
             log("served at %.1fx: completion p50 %.1f us p99 %.1f us; answer p50 %.1f us p99 "
@@ -638,7 +638,7 @@ def run_served(args):
         ms, recs = serve_once(reqs)
         res = summarize(ms, recs, reqs)
         res["budget_beyond_prefill"] = args.served_tight_budget
-        res["sampled_heaps_replayed_equal"] = check_served(
+        res["every_heap_replayed_equal"] = check_served(
             pre, reqs, recs, G.to_host_u64(serve_once.last_out), k, tight, H)
         out["memory_bound_saturated"] = res
         log("served, budget prefill + %d: %.3g keys/s, %d inserts waited for memory, "
@@ -652,38 +652,48 @@ def run_served(args):
     return out
 
 
-def check_served(pre, reqs, recs, gpu_out, k, caps, H, nsample=8):
-    """A sample of heaps (the largest, the smallest and evenly spaced
-    others): each heap's admitted requests replayed in ticket order on its
-    own oracle give every deleteMin's entries, and the heap never exceeds
-    its budget.  Exits on a mismatch; returns True."""
+def check_served(pre, reqs, recs, gpu_out, k, caps, H):
+    """Every heap: its admitted requests replayed in ticket order on its own
+    oracle (after its prefill) give every deleteMin's entries, and its size
+    never exceeds its budget (a running sum of the admitted requests).  One
+    replay call per heap on the host cores (ctypes releases the interpreter
+    lock).  Exits on a mismatch; returns True."""
+    import concurrent.futures as cf
     import oracle
     from paper_1906_06504_amd import gheap as G
-    from paper_1906_06504_amd import workloads as W
     oracle.build(force=False)
-    sizes = np.bincount(pre.heap.astype(np.int64), weights=pre.n.astype(np.float64),
-                        minlength=H)
-    heaps = sorted(set([int(np.argmax(sizes)), int(np.argmin(sizes))]
-                       + list(range(1, H, max(1, H // (nsample - 2))))[:nsample - 2]))
     adm = (recs["flags"] & G.REQ_ADMITTED) != 0
-    for h in heaps:
+    sizes = np.bincount(pre.heap.astype(np.int64), weights=pre.n.astype(np.float64),
+                        minlength=H).astype(np.int64)
+
+    def one(h):
         oh = oracle.OracleHeap(k)
         ps = np.flatnonzero(pre.heap == h)
         oh.replay(pre.kind[ps], pre.n[ps], pre.off[ps], pre.keys, 1)
         sel = np.flatnonzero((reqs.heap == h) & adm)
         sel = sel[np.argsort(recs["first_ticket"][sel], kind="stable")]
-        for i in sel:
-            o = int(reqs.off[i])
-            if reqs.kind[i] == W.OP_INSERT:
-                oh.insert(reqs.keys[o:o + int(reqs.n[i])])
-                if oh.size > int(caps[h]):
-                    raise SystemExit("served: heap %d over its budget" % h)
-            else:
-                want = oh.delete_min(int(reqs.n[i]) or None)
-                c = int(recs["count"][i])
-                if c != want.size or not np.array_equal(gpu_out[o:o + c], want):
-                    raise SystemExit("served: heap %d request %d differs from the oracle" % (h, i))
+        dels = reqs.kind[sel] == 1
+        coff = np.zeros(sel.size, np.uint64)
+        coff[dels] = np.arange(int(dels.sum()), dtype=np.uint64) * np.uint64(k)
+        off = np.where(dels, coff, reqs.off[sel]).astype(np.uint64)
+        out, cnt = oh.replay(reqs.kind[sel], reqs.n[sel], off, reqs.keys,
+                             max(1, int(dels.sum()) * k))
         oh.close()
+        step = np.where(dels, -cnt.astype(np.int64), reqs.n[sel].astype(np.int64))
+        if sel.size and int(sizes[h] + np.cumsum(step).max()) > int(caps[h]):
+            return "heap %d over its budget" % h
+        for j in np.flatnonzero(dels):
+            c = int(cnt[j])
+            o, g = int(off[j]), int(reqs.off[sel[j]])
+            if c != int(recs["count"][sel[j]]) or not np.array_equal(out[o:o + c],
+                                                                       gpu_out[g:g + c]):
+                return "heap %d request %d differs from the oracle" % (h, int(sel[j]))
+        return None
+
+    with cf.ThreadPoolExecutor(_host_threads()) as ex:
+        errs = [e for e in ex.map(one, range(H)) if e]
+    if errs:
+        raise SystemExit("served: %s (%d heaps differ)" % (errs[0], len(errs)))
     return True
 
 
@@ -746,6 +756,8 @@ def served_cpu_baseline(pre, reqs, recs, gpu_out, k, H):
     equal = ok1 and all(r[2] for r in rs)
     log("served cpu baseline: %.3g keys/s on 1 core (%d heaps), %.3g keys/s on %d threads "
         "(all %d heaps); outputs equal: %s" % (m1 / t1, len(sample), moved / wall, nt, H, equal))
+    if not equal:
+        raise SystemExit("served cpu baseline: a deleteMin differs from the oracle replay")
     return {"value": moved / wall, "unit": "keys/s", "cores": nt, "kind": "oracle",
             "sample": "every heap's admitted requests of the saturated run replayed in ticket "
                       "order on %d threads (prefill replay untimed); one core: %.3g keys/s over "
