@@ -444,6 +444,10 @@ def run_batched(args, wg_default, th, plain_value):
         moved = M.keys_moved(lg)
         ms = float(np.mean(times))
         alg = int(M.algorithmic_bytes(lg, k).sum())
+        eager_out = G.to_host_u64(dmix[3])
+        eager_counts = dmix[4].cpu().numpy()[:nops].astype(np.uint32)
+        check_batched(pre, mix, lg, eager_out, eager_counts, k, H)
+        log("batched leg: every heap's deleteMins equal its oracle replay")
         # graph replays of the same launch
         g = hs.submit_graph(dmix[0], nops, dmix[2], dmix[3], dmix[4], dlog, workgroups=wgb,
                             threads=th)
@@ -459,6 +463,9 @@ def run_batched(args, wg_default, th, plain_value):
             assert hs.sync() == 0
             torch.cuda.synchronize()
             gt.append(ev0.elapsed_time(ev1))
+            if not (np.array_equal(G.to_host_u64(dmix[3]), eager_out) and
+                    np.array_equal(dmix[4].cpu().numpy()[:nops].astype(np.uint32), eager_counts)):
+                raise SystemExit("batched: a graph replay's outputs differ from the eager run")
         # plain form: every heap in its own launch, one after the other
         hs.arena.copy_(snap)
         torch.cuda.synchronize()
@@ -491,6 +498,42 @@ def run_batched(args, wg_default, th, plain_value):
         % (value, ms, res["plain_one_heap_per_launch_keys_per_s"]))
     hs.close()
     return res
+
+
+def check_batched(pre, mix, lg, gpu_out, gpu_counts, k, H):
+    """Every heap of the batched form: its prefill, then its operations of
+    the timed launch in ticket order, replayed on its own oracle heap give
+    every deleteMin's entries and count.  One replay call per heap on the
+    host cores.  Exits on a mismatch."""
+    import concurrent.futures as cf
+    import oracle
+    oracle.build(force=False)
+    ph, mh = pre.heap_ids(), mix.heap_ids()
+
+    def one(h):
+        oh = oracle.OracleHeap(k)
+        ps = np.flatnonzero(ph == h)
+        oh.replay(pre.kind[ps], pre.n[ps], pre.off[ps], pre.keys, 1)
+        sel = np.flatnonzero(mh == h)
+        sel = sel[np.argsort(lg["ticket"][sel].astype(np.int64), kind="stable")]
+        dels = mix.kind[sel] == 1
+        coff = np.zeros(sel.size, np.uint64)
+        coff[dels] = np.arange(int(dels.sum()), dtype=np.uint64) * np.uint64(k)
+        off = np.where(dels, coff, mix.off[sel]).astype(np.uint64)
+        out, cnt = oh.replay(mix.kind[sel], mix.n[sel], off, mix.keys,
+                             max(1, int(dels.sum()) * k))
+        oh.close()
+        for j in np.flatnonzero(dels):
+            c = int(cnt[j])
+            o, g = int(off[j]), int(mix.off[sel[j]])
+            if c != int(gpu_counts[sel[j]]) or not np.array_equal(out[o:o + c], gpu_out[g:g + c]):
+                return "heap %d op %d differs from the oracle" % (h, int(sel[j]))
+        return None
+
+    with cf.ThreadPoolExecutor(_host_threads()) as ex:
+        errs = [e for e in ex.map(one, range(H)) if e]
+    if errs:
+        raise SystemExit("batched: %s (%d heaps differ)" % (errs[0], len(errs)))
 
 
 def run_served(args):
