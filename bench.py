@@ -935,7 +935,7 @@ def run_knapsack(args):
     # plain form: each instance alone, one launch each (a sample of 64)
     one = KS.Solver(1, k, pool_per_inst=pool, stream=torch.cuda.Stream())
     plain_ms, plain_moved = 0.0, 0
-    for i in sample:
+    for i in range(0, N, max(1, N // 64)):
         d1 = KS.Instances([inst[i]])
         one.hs.arena.copy_(one.snapshot)
         torch.cuda.synchronize()
