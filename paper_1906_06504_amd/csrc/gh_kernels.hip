@@ -203,7 +203,7 @@ __global__ __launch_bounds__(T) void k_knap(const HeapDesc* __restrict__ descs, 
                                             gh_knapres* __restrict__ res, u32 gc_min,
                                             Ctl* __restrict__ ctl) {
   typedef KnapKey<Ent> KK;
-  __shared__ __align__(16) Ent lds[8 * K];
+  __shared__ __align__(16) Ent lds[priv_lds_entries<K, T, Ent>()];
   lds_t<Ent>* const L = (lds_t<Ent>*)lds;
   __shared__ OpShared sh;
   __shared__ KnapShared ks;

@@ -23,9 +23,20 @@
 // (the ticket after the last operation run), so that the shared-root loop
 // can continue the heap in a later launch.
 //
-// LDS (8K entries): pair 0 = root [0, K) and partial buffer [K, 2K), pair 1
-// = [2K, 4K) (root followed by partial buffer is one sorted run, Property 3,
-// which the insert's one-pass merge reads), and four work buffers [4K, 8K).
+// LDS: pair 0 = root [0, K) and partial buffer [K, 2K), pair 1 = [2K, 4K)
+// (root followed by partial buffer is one sorted run, Property 3, which the
+// insert's one-pass merge reads), four work buffers [4K, 8K), and, where it
+// fits, a path buffer of priv_path_nodes() nodes from 8K on.
+//
+// The insert's descent in one merge: by Property 1 the nodes on the path
+// from level 1 down to the target, read top-down, are one sorted run, and
+// keeping at each level the K smallest of node and carry (Sec. 3.2.2) leaves
+// exactly the consecutive K-entry chunks of merge(path, carry) on the path
+// and the last chunk at the target.  So a group of path nodes is loaded in
+// one round trip and merged with the carry in one pass; the group's last K
+// outputs are the carry for the next group.  The nodes before the carry's
+// smallest entry keep their batches and are not rewritten (the shortcut of
+// Sec. 4.3); the layout is the level-by-level one.
 #pragma once
 #include "gh_launch.h"
 #include "gh_ops.h"
@@ -43,6 +54,50 @@ template <int K, class Ent>
 __device__ __forceinline__ lds_t<Ent>* priv_pair(lds_t<Ent>* lds, bool p) {
   return p ? lds + 2 * K : lds;
 }
+
+// Path nodes an insert loads in one round trip: at most priv_path_pieces()
+// 16-byte pieces a thread (registers held until the pieces are in LDS), and
+// at most 72 KB of LDS in all (eight K-entry buffers and the path buffer, so
+// that two 512-thread workgroups share a compute unit).  Below two the
+// descent goes level by level.
+template <class Ent>
+__host__ __device__ constexpr int priv_path_pieces() {
+  return 2;
+}
+template <int K, int T, class Ent>
+__host__ __device__ constexpr int priv_path_nodes() {
+  constexpr int node_bytes = K * (int)sizeof(Ent);
+  constexpr int by_regs = priv_path_pieces<Ent>() * T * 16 / node_bytes;
+  constexpr int left = 72 * 1024 - 8 * node_bytes;
+  constexpr int by_lds = left > 0 ? left / node_bytes : 0;
+  constexpr int p = by_regs < by_lds ? by_regs : by_lds;
+  return p > 16 ? 16 : p;
+}
+template <int K, int T, class Ent>
+__host__ __device__ constexpr int priv_lds_entries() {
+  return 8 * K + (priv_path_nodes<K, T, Ent>() >= 2 ? priv_path_nodes<K, T, Ent>() * K : 0);
+}
+
+// Merge output on the insert path: output chunk q of K entries is the path
+// node at level level0 + q (plain stores: the heap is this workgroup's).
+template <int K, class Ent>
+struct PathSink {
+  Ent* nodes;   // the heap's node array
+  u32 t;        // the target node
+  int L;        // the target's level
+  int level0;   // level of output chunk 0
+  __device__ __forceinline__ glob_t<Ent>* at(int off) const {
+    const u32 c = t >> (L - level0 - off / K);
+    return gptr(nodes + (u64)(bitrev_pos(c) - 1) * K) + off % K;
+  }
+  __device__ __forceinline__ void put1(int off, Ent x) const { *at(off) = x; }
+  template <int E>
+  __device__ __forceinline__ void put_range(int off, const Ent (&v)[E]) const {
+    glob_t<Ent>* g = at(off);   // E divides K: the range stays in one node
+#pragma unroll
+    for (int e = 0; e < E; ++e) g[e] = v[e];
+  }
+};
 
 // K entries from one LDS buffer to another, 16 bytes a lane.
 template <int K, int T, class Ent>
@@ -147,6 +202,51 @@ __device__ __forceinline__ OpResult priv_insert(const HeapDesc& H, lds_t<Ent>* l
   // (the node keeps the K smallest); the earlier operations' stores are
   // complete before the first node is loaded
   publish();
+  constexpr int PC = priv_path_nodes<K, T, Ent>();
+  if constexpr (PC >= 2) {
+    // groups of up to PC path nodes, each loaded in one round trip and
+    // merged with the carry in one pass (see the top of this file)
+    constexpr int CH = K * (int)sizeof(Ent) / 16;
+    constexpr int PP = priv_path_pieces<Ent>();
+    constexpr int EP = sizeof(Ent) == 16 ? 2 : 4;   // outputs a thread per merge pass
+    lds_t<Ent>* const PB = lds + 8 * K;
+    Ent* const nodes = reinterpret_cast<Ent*>(H.nodes);
+    for (int level = 1; level < L;) {
+      const int n = L - level < PC ? L - level : PC;
+      {
+        u64x2 v[PP];
+#pragma unroll
+        for (int j = 0; j < PP; ++j) {
+          const int i = tid + j * T;
+          if (i < n * CH) {
+            const int q = i / CH;
+            const u32 c = t >> (L - level - q);
+            const glob_t<u64x2>* src =
+                gptr(reinterpret_cast<const u64x2*>(nodes + (u64)(bitrev_pos(c) - 1) * K));
+            v[j] = src[i - q * CH];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < PP; ++j) {
+          const int i = tid + j * T;
+          if (i < n * CH) reinterpret_cast<lu64x2*>(PB)[i] = v[j];
+        }
+      }
+      __syncthreads();
+      int keep = 0;   // leading nodes wholly below the carry keep their batches
+      while (keep < n && ent_le((Ent)PB[(keep + 1) * K - 1], (Ent)F[0])) ++keep;
+      if (keep < n) {
+        const int na = (n - keep) * K;
+        merge_split<EP, T>(PB + keep * K, na, F, K, na,
+                           PathSink<K, Ent>{nodes, t, L, level + keep}, sink(spare));
+        __syncthreads();
+        lds_t<Ent>* x = F;
+        F = spare;
+        spare = x;
+      }
+      level += n;
+    }
+  } else {
   for (int level = 1; level < L; ++level) {
     Ent* cp = node_ptr<K, Ent>(H, t >> (L - level));
     {
@@ -169,6 +269,7 @@ __device__ __forceinline__ OpResult priv_insert(const HeapDesc& H, lds_t<Ent>* l
       spare = x;
     }
     __syncthreads();
+  }
   }
   store_node<K, T, Ent, CP_LOCAL>(node_ptr<K, Ent>(H, t), F);
   if (tid == 0) st_relaxed(lock_ptr(H, t), lockword(ST_AVAIL, 0));   // an existing node's word

@@ -31,7 +31,7 @@ __global__ __launch_bounds__(T) void k_private(const HeapDesc* __restrict__ desc
                                                OpParams direct, const Ent* __restrict__ in,
                                                Ent* __restrict__ out, u32* __restrict__ counts,
                                                gh_logrec* __restrict__ log, Ctl* __restrict__ ctl) {
-  __shared__ __align__(16) Ent lds[8 * K];
+  __shared__ __align__(16) Ent lds[priv_lds_entries<K, T, Ent>()];
   lds_t<Ent>* const L = (lds_t<Ent>*)lds;
   __shared__ OpShared sh;
   const int tid = threadIdx.x;
