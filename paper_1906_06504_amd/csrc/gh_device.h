@@ -579,16 +579,82 @@ __device__ __forceinline__ void merge_split3(const lds_t<Ent>* A, int na, const 
 // power of two (even counts store 16 bytes at a time).
 constexpr int pow2_at_least(int x) { return x <= 1 ? 1 : 2 * pow2_at_least((x + 1) / 2); }
 
+// One entry from the lane whose index differs from this lane's in `mask`
+// (a cross-lane move within the wave).
+__device__ __forceinline__ u64 ent_shfl_xor(u64 x, int mask) {
+  const int lo = __shfl_xor((int)(u32)x, mask, 64);
+  const int hi = __shfl_xor((int)(u32)(x >> 32), mask, 64);
+  return (u64)(u32)lo | ((u64)(u32)hi << 32);
+}
+__device__ __forceinline__ e128 ent_shfl_xor(e128 x, int mask) {
+  e128 r;
+  r.x = ent_shfl_xor((u64)x.x, mask);
+  r.y = ent_shfl_xor((u64)x.y, mask);
+  return r;
+}
+
+// Bitonic sorting network over the 64 lanes of a wave, one entry a lane:
+// returns this lane's entry of the ascending order (Batcher's network,
+// 21 compare-exchange stages, each a cross-lane move).
+template <class Ent>
+__device__ __forceinline__ Ent wave_sort64(Ent x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const Ent y = ent_shfl_xor(x, j);
+      const bool up = (lane & k) == 0;      // this block ascends
+      const bool low = (lane & j) == 0;     // this lane is the lower of the pair
+      const bool take_min = low == up;
+      const bool lt = ent_lt(y, x);
+      x = (take_min == lt) ? y : x;
+    }
+  }
+  return x;
+}
+
 // ---------------------------------------------------------------------------
 // Workgroup merge sort of up to K entries in LDS (sorts the insert batch,
-// Sec. 4.1): every thread sorts EPT entries in registers, then rounds of
-// merge path double the sorted run length.  A holds the n inputs; it is
-// padded with the filler to a power of two.  Returns the buffer (A or B)
+// Sec. 4.1): with K > T every thread sorts EPT = K / T entries in registers;
+// with one entry a thread each wave sorts 64 of them with wave_sort64.  Then
+// rounds of merge path double the sorted run length.  A holds the n inputs
+// (padded with the filler to a power of two); returns the buffer (A or B)
 // that holds the sorted result.
 // ---------------------------------------------------------------------------
 template <int K, int T, class Ent>
 __device__ lds_t<Ent>* block_sort(lds_t<Ent>* A, lds_t<Ent>* B, int n) {
   constexpr int EPT = (K >= T) ? (K / T) : 1;
+  if constexpr (EPT == 1) {
+    // one entry a thread: runs of 64 sorted within each wave by a bitonic
+    // network in registers (lanes past n hold the filler), then rounds of
+    // merge path from runs of 64 on
+    int np = 1;
+    while (np < n) np <<= 1;
+    const int tid = threadIdx.x;
+    const int lanes = np < 64 ? 64 : np;   // whole waves
+    if (tid < lanes) {
+      Ent x = tid < n ? (Ent)A[tid] : ent_max<Ent>();
+      x = wave_sort64(x);
+      if (tid < np) A[tid] = x;
+    }
+    __syncthreads();
+    lds_t<Ent>* src = A;
+    lds_t<Ent>* dst = B;
+    for (int w = 64; w < np; w <<= 1) {
+      if (tid < np) {
+        const int base = tid & ~(2 * w - 1);
+        Ent v[1];
+        merge_path<1>(src + base, w, src + base + w, w, tid - base, v);
+        dst[tid] = v[0];
+      }
+      __syncthreads();
+      lds_t<Ent>* t = src;
+      src = dst;
+      dst = t;
+    }
+    return src;
+  }
   int np = EPT;
   while (np < n) np <<= 1;
   for (int i = n + threadIdx.x; i < np; i += T) A[i] = ent_max<Ent>();
