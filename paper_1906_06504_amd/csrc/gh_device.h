@@ -579,18 +579,45 @@ __device__ __forceinline__ void merge_split3(const lds_t<Ent>* A, int na, const 
 // power of two (even counts store 16 bytes at a time).
 constexpr int pow2_at_least(int x) { return x <= 1 ? 1 : 2 * pow2_at_least((x + 1) / 2); }
 
-// One entry from the lane whose index differs from this lane's in `mask`
-// (a cross-lane move within the wave).
-__device__ __forceinline__ u64 ent_shfl_xor(u64 x, int mask) {
-  const int lo = __shfl_xor((int)(u32)x, mask, 64);
-  const int hi = __shfl_xor((int)(u32)(x >> 32), mask, 64);
-  return (u64)(u32)lo | ((u64)(u32)hi << 32);
+// A 32-bit word from the lane whose index differs from this lane's in bit
+// pattern J (a cross-lane move within the wave): distances 1 and 2 are quad
+// permutations and 8 a rotation by 8 within each row of 16 lanes, all DPP
+// moves of the vector unit; the others go through the LDS crossbar
+// (ds_bpermute).  Every lane of the wave must take part.
+template <int J>
+__device__ __forceinline__ u32 lane_xor32(u32 v) {
+  if constexpr (J == 1) {
+    return (u32)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);   // [1,0,3,2]
+  } else if constexpr (J == 2) {
+    return (u32)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);   // [2,3,0,1]
+  } else if constexpr (J == 8) {
+    return (u32)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false);  // row_ror:8
+  } else {
+    return (u32)__shfl_xor((int)v, J, 64);
+  }
 }
-__device__ __forceinline__ e128 ent_shfl_xor(e128 x, int mask) {
+template <int J>
+__device__ __forceinline__ u64 ent_shfl_xor(u64 x) {
+  return (u64)lane_xor32<J>((u32)x) | ((u64)lane_xor32<J>((u32)(x >> 32)) << 32);
+}
+template <int J>
+__device__ __forceinline__ e128 ent_shfl_xor(e128 x) {
   e128 r;
-  r.x = ent_shfl_xor((u64)x.x, mask);
-  r.y = ent_shfl_xor((u64)x.y, mask);
+  r.x = ent_shfl_xor<J>((u64)x.x);
+  r.y = ent_shfl_xor<J>((u64)x.y);
   return r;
+}
+
+// One compare-exchange stage of the network below: lane pairs J apart, in
+// blocks of KB lanes that ascend or descend alternately.
+template <int KB, int J, class Ent>
+__device__ __forceinline__ Ent bitonic_stage(Ent x, int lane) {
+  const Ent y = ent_shfl_xor<J>(x);
+  const bool up = (lane & KB) == 0;    // this block ascends
+  const bool low = (lane & J) == 0;    // this lane is the lower of the pair
+  const bool take_min = low == up;
+  const bool lt = ent_lt(y, x);
+  return (take_min == lt) ? y : x;
 }
 
 // Bitonic sorting network over the 64 lanes of a wave, one entry a lane:
@@ -599,18 +626,27 @@ __device__ __forceinline__ e128 ent_shfl_xor(e128 x, int mask) {
 template <class Ent>
 __device__ __forceinline__ Ent wave_sort64(Ent x) {
   const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int k = 2; k <= 64; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      const Ent y = ent_shfl_xor(x, j);
-      const bool up = (lane & k) == 0;      // this block ascends
-      const bool low = (lane & j) == 0;     // this lane is the lower of the pair
-      const bool take_min = low == up;
-      const bool lt = ent_lt(y, x);
-      x = (take_min == lt) ? y : x;
-    }
-  }
+  x = bitonic_stage<2, 1>(x, lane);
+  x = bitonic_stage<4, 2>(x, lane);
+  x = bitonic_stage<4, 1>(x, lane);
+  x = bitonic_stage<8, 4>(x, lane);
+  x = bitonic_stage<8, 2>(x, lane);
+  x = bitonic_stage<8, 1>(x, lane);
+  x = bitonic_stage<16, 8>(x, lane);
+  x = bitonic_stage<16, 4>(x, lane);
+  x = bitonic_stage<16, 2>(x, lane);
+  x = bitonic_stage<16, 1>(x, lane);
+  x = bitonic_stage<32, 16>(x, lane);
+  x = bitonic_stage<32, 8>(x, lane);
+  x = bitonic_stage<32, 4>(x, lane);
+  x = bitonic_stage<32, 2>(x, lane);
+  x = bitonic_stage<32, 1>(x, lane);
+  x = bitonic_stage<64, 32>(x, lane);
+  x = bitonic_stage<64, 16>(x, lane);
+  x = bitonic_stage<64, 8>(x, lane);
+  x = bitonic_stage<64, 4>(x, lane);
+  x = bitonic_stage<64, 2>(x, lane);
+  x = bitonic_stage<64, 1>(x, lane);
   return x;
 }
 
