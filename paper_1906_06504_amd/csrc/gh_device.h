@@ -580,20 +580,32 @@ __device__ __forceinline__ void merge_split3(const lds_t<Ent>* A, int na, const 
 constexpr int pow2_at_least(int x) { return x <= 1 ? 1 : 2 * pow2_at_least((x + 1) / 2); }
 
 // A 32-bit word from the lane whose index differs from this lane's in bit
-// pattern J (a cross-lane move within the wave): distances 1 and 2 are quad
-// permutations and 8 a rotation by 8 within each row of 16 lanes, all DPP
-// moves of the vector unit; the others go through the LDS crossbar
-// (ds_bpermute).  Every lane of the wave must take part.
+// pattern J (a cross-lane move within the wave, in registers): distances 1
+// and 2 are quad permutations, 4 a quad permutation and a half-row mirror, 8
+// a rotation by 8 within each row of 16 lanes (DPP moves of the vector
+// unit), 16 and 32 the row and half-wave swaps of gfx950 (permlane16_swap,
+// permlane32_swap).  Every lane of the wave must take part.
 template <int J>
 __device__ __forceinline__ u32 lane_xor32(u32 v) {
   if constexpr (J == 1) {
     return (u32)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);   // [1,0,3,2]
   } else if constexpr (J == 2) {
     return (u32)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);   // [2,3,0,1]
+  } else if constexpr (J == 4) {
+    // [3,2,1,0] (distance 3), then the mirror within each half row (7)
+    const int a = __builtin_amdgcn_update_dpp(0, (int)v, 0x1B, 0xF, 0xF, false);
+    return (u32)__builtin_amdgcn_update_dpp(0, a, 0x141, 0xF, 0xF, false);
   } else if constexpr (J == 8) {
     return (u32)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false);  // row_ror:8
+  } else if constexpr (J == 16) {
+    // rows of 16 swapped pairwise: the odd rows of the first result hold the
+    // even rows' values, the even rows of the second the odd rows'
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return (threadIdx.x & 16) ? r[0] : r[1];
   } else {
-    return (u32)__shfl_xor((int)v, J, 64);
+    static_assert(J == 32, "lane distances 1, 2, 4, 8, 16, 32");
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (threadIdx.x & 32) ? r[0] : r[1];
   }
 }
 template <int J>
