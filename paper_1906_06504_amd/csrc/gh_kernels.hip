@@ -361,7 +361,11 @@ __global__ __launch_bounds__(T) void k_knap(const HeapDesc* __restrict__ descs, 
         if (W + wl <= ks.cap) {
           const u64 V1 = V + vl, W1 = W + wl;
           atomicMax(reinterpret_cast<unsigned long long*>(&ks.best), (unsigned long long)V1);
-          cb[nc] = kn_bound(ks, level + 1, V1, W1);
+          // the child that takes the item has the parent's bound: the item
+          // fits, so the greedy fill from the next level with the smaller
+          // capacity stops at the same critical item with the same
+          // remainder, and the entry holds the bound exactly
+          cb[nc] = b;
           cand[nc++] = ((u64)(level + 1) << 56) | (V1 << 28) | W1;
         }
         cb[nc] = kn_bound(ks, level + 1, V, W);
